@@ -1,0 +1,58 @@
+"""Generator statistics and determinism (CPU)."""
+import numpy as np
+
+import synth
+
+
+def _w(**kw):
+    base = dict(n_shapes=80, dim=48, n_queries=6)
+    base.update(kw)
+    return synth.PRESETS["c1"].scaled(**base)
+
+
+def test_unit_norm_nonnegative_and_classes():
+    w = _w(p_dis=0.25)
+    db, scls, vcls = synth.make_db(w)
+    assert db.dtype == np.float32 and db.shape == (80 * 64, 48)
+    assert (db >= 0).all()
+    assert np.allclose(np.linalg.norm(db.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    assert (np.bincount(scls, minlength=40) == 2).all()
+    rate = float((vcls != np.repeat(scls, 64)).mean())
+    assert abs(rate - 0.25) < 0.03
+
+
+def test_deterministic_across_thread_counts():
+    w = _w()
+    a, _, _ = synth.make_db(w, threads=1)
+    b, _, _ = synth.make_db(w, threads=4)
+    assert np.array_equal(a, b)
+    q1 = synth.make_queries(w, threads=1)
+    q2 = synth.make_queries(w, threads=3)
+    for x, y in zip(q1, q2):
+        assert np.array_equal(x, y)
+
+
+def test_query_counts_range_and_offsets():
+    w = _w(m_lo=8, m_hi=64, n_queries=200)
+    q, off, cls = synth.make_queries(w)
+    cnt = np.diff(off)
+    assert cnt.min() >= 8 and cnt.max() <= 64 and len(set(cnt.tolist())) > 20
+    assert q.shape[0] == off[-1]
+
+
+def test_within_class_views_more_similar():
+    w = _w()
+    db, scls, vcls = synth.make_db(w)
+    sim = db[:640].astype(np.float64) @ db[:640].T.astype(np.float64)
+    same = vcls[:640, None] == vcls[None, :640]
+    assert sim[same].mean() > sim[~same].mean() + 0.2
+
+
+def test_kmeans_init_and_sample_and_arrivals():
+    i = synth.kmeans_init_idx(1000, 64, 0)
+    assert len(set(i.tolist())) == 64 and i.max() < 1000
+    assert np.array_equal(i, synth.kmeans_init_idx(1000, 64, 0))
+    s = synth.training_sample(10000, 500, 0)
+    assert len(set(s.tolist())) == 500
+    t = synth.poisson_arrivals(200.0, 10.0, 0)
+    assert abs(len(t) - 2000) < 200 and (np.diff(t) > 0).all()
