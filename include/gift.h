@@ -1,0 +1,133 @@
+/*
+ * gift.h -- C ABI of the GIFT search-stage library for AMD MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the search problem
+ * (Bai et al., "GIFT: A Real-time and Scalable 3D Shape Search Engine",
+ * arXiv 1604.01879, Sec. 2.3 and 2.4):
+ *
+ *   a database X = {x_1..x_N} of shapes, each a set V(x) of N_v view
+ *   features; a query x_q with its own view set; the multi-view matching
+ *   function S of Eq. 3; its inverted-file approximation of Eq. 4 with a
+ *   k-means vocabulary B = {b_1..b_K} and quantizer c(x); and the
+ *   contextual re-ranking S' of Eq. 8 evaluated through the second
+ *   inverted file (Eq. 13, 14).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers are DEVICE pointers owned by the caller unless the argument
+ *    comment says "host".  The library never allocates device memory:
+ *    every call that needs scratch space takes a caller-owned workspace
+ *    (ws, ws_bytes) whose minimum size the matching *_workspace() function
+ *    returns.  Workspace contents need not be initialised.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL is the default stream) unless it says it synchronises.
+ *  - Every call returns a gift_status.  On failure, gift_last_error()
+ *    returns a message for the calling thread.  Nothing throws across the
+ *    ABI.  No pointer is retained after a call returns.
+ *  - Views are float32 rows of `dim` values, shape-major: database view j
+ *    of shape p is row p * n_views + j.  dim must be a multiple of 32.
+ *    The paper's features are L2-normalised (Sec. 2.2); the certified
+ *    ranking below assumes unit-norm rows (to within 1e-6).
+ *  - Discrete outputs (codeword assignments, ranked ids) are defined on the
+ *    exact value of the quantity over the float32 inputs.  The kernels
+ *    compute in float32 and settle every decision that float32 rounding
+ *    could flip with a compensated (float-float) re-evaluation, so the
+ *    result equals the exact decision; equal exact values go to the lower
+ *    index.  Scores are returned as float32.
+ */
+#ifndef GIFT_H
+#define GIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gift_status;
+#define GIFT_OK            0
+#define GIFT_EINVAL       (-1)  /* bad argument (null pointer, size, range) */
+#define GIFT_EWORKSPACE   (-2)  /* workspace smaller than *_workspace()      */
+#define GIFT_EUNSUPPORTED (-3)  /* dtype, device arch or dim not supported   */
+#define GIFT_EHIP         (-4)  /* a HIP runtime call failed                 */
+#define GIFT_ECAPACITY    (-5)  /* an output or index capacity was exceeded  */
+
+/* Storage formats of database views. */
+#define GIFT_F32      0   /* float32                                          */
+#define GIFT_BF16     1   /* bfloat16 code, value = code * scale[view]         */
+#define GIFT_FP8E4M3  2   /* OCP e4m3fn code (max 448), value = code * scale   */
+
+/* Database views (Sec. 2.3: V(x_p) = {p_1..p_Nv}). */
+typedef struct gift_views {
+  const void*  data;      /* [n_shapes * n_views][dim] codes of `dtype`       */
+  int32_t      dtype;     /* GIFT_F32 / GIFT_BF16 / GIFT_FP8E4M3              */
+  int32_t      n_views;   /* N_v, 1..64                                       */
+  int64_t      n_shapes;  /* N                                                */
+  int32_t      dim;       /* d, multiple of 32                                */
+  int32_t      _pad;
+  const float* scale;     /* [n_shapes * n_views] per-view scale, or NULL for F32 */
+  const float* master;    /* float32 copy [n_shapes * n_views][dim]; required
+                             for the float32 rescore when dtype != GIFT_F32;
+                             may equal `data` when dtype == GIFT_F32          */
+} gift_views;
+
+/* A batch of query shapes with ragged view counts (V(x_q)). */
+typedef struct gift_queries {
+  const float*   views;       /* [total_views][dim] float32                   */
+  const int32_t* offsets;     /* [n_queries + 1] device, offsets[0] = 0        */
+  int32_t        n_queries;   /* B                                            */
+  int32_t        max_views;   /* host bound: max_b (offsets[b+1]-offsets[b]) */
+  int64_t        total_views; /* host: offsets[n_queries]                      */
+} gift_queries;
+
+const char* gift_version(void);
+const char* gift_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Reduced-precision storage of view features.                            */
+/* scale[v] = max_t |src[v][t]| / Fmax (Fmax = 1 for BF16, 448 for e4m3),  */
+/* dst[v][t] = round_nearest_even_saturating(src[v][t] / scale[v]) in the  */
+/* target format; an all-zero row gets scale 1.  dst is [n][dim] of 2-byte  */
+/* (BF16) or 1-byte (e4m3) codes.                                         */
+/* ---------------------------------------------------------------------- */
+gift_status gift_quantize_views(const float* src, int64_t n, int32_t dim,
+                                int32_t dtype, void* dst, float* scale,
+                                void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Exhaustive multi-view matching, Eq. 3 (Sec. 2.3):                      */
+/*   S(x_q, x_p) = (1/m) sum_{i<m} max_{j<Nv} s(q_i, p_j),                 */
+/* s = cosine similarity = dot product of the unit-norm views, m = number  */
+/* of the query's views.  Every database shape is scored in `db->dtype`    */
+/* (scales applied per pair before the max), the top `rescore_r` shapes    */
+/* by (score desc, id asc) are rescored exactly from the float32 master,   */
+/* and the top `top_k` of those are returned by (exact score desc, id asc).*/
+/*   ids    [n_queries][top_k] int32, scores [n_queries][top_k] float32    */
+/*   flags  [n_queries] int32 or NULL: bit 0 set when the returned list is  */
+/*          provably the exact top_k over all N shapes (no shape outside   */
+/*          the rescored set can belong to it, given the error bound of    */
+/*          the first-pass dtype).                                         */
+/* Requires top_k <= rescore_r <= min(1024, N).                             */
+/* ---------------------------------------------------------------------- */
+size_t gift_query_exhaustive_workspace(const gift_views* db,
+                                       const gift_queries* q,
+                                       int32_t top_k, int32_t rescore_r);
+gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
+                                  int32_t top_k, int32_t rescore_r,
+                                  int32_t* ids, float* scores, int32_t* flags,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* Full score matrix of the first pass of gift_query_exhaustive (Eq. 3 in   */
+/* db->dtype), for inspection: scores [n_queries][n_shapes] float32.        */
+size_t gift_score_exhaustive_workspace(const gift_views* db,
+                                       const gift_queries* q);
+gift_status gift_score_exhaustive(const gift_views* db, const gift_queries* q,
+                                  float* scores, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIFT_H */

@@ -1,0 +1,161 @@
+"""ctypes binding of libgift.so (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C ABI declared in
+include/gift.h.  torch tensors supply device memory and the current HIP
+stream.  If the shared library is missing, importing this module raises: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgift.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -m paper_1604_01879_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+# status codes and storage formats (include/gift.h)
+OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ECAPACITY = 0, -1, -2, -3, -4, -5
+F32, BF16, FP8E4M3 = 0, 1, 2
+_DT_BYTES = {F32: 4, BF16: 2, FP8E4M3: 1}
+_DT_TORCH = {F32: torch.float32, BF16: torch.uint16, FP8E4M3: torch.uint8}
+
+
+class GiftError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gift status {status}: {msg}")
+        self.status = status
+
+
+class gift_views(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("n_views", C.c_int32),
+                ("n_shapes", C.c_int64), ("dim", C.c_int32), ("_pad", C.c_int32),
+                ("scale", C.c_void_p), ("master", C.c_void_p)]
+
+
+class gift_queries(C.Structure):
+    _fields_ = [("views", C.c_void_p), ("offsets", C.c_void_p), ("n_queries", C.c_int32),
+                ("max_views", C.c_int32), ("total_views", C.c_int64)]
+
+
+_P = C.c_void_p
+_VP = C.POINTER(gift_views)
+_QP = C.POINTER(gift_queries)
+_sig = {
+    "gift_version": (C.c_char_p, []),
+    "gift_last_error": (C.c_char_p, []),
+    "gift_quantize_views": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P]),
+    "gift_score_exhaustive_workspace": (C.c_size_t, [_VP, _QP]),
+    "gift_score_exhaustive": (C.c_int32, [_VP, _QP, _P, _P, C.c_size_t, _P]),
+    "gift_query_exhaustive_workspace": (C.c_size_t, [_VP, _QP, C.c_int32, C.c_int32]),
+    "gift_query_exhaustive": (C.c_int32, [_VP, _QP, C.c_int32, C.c_int32, _P, _P, _P, _P,
+                                          C.c_size_t, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_sig)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(status):
+    if status != OK:
+        raise GiftError(status, _lib.gift_last_error().decode())
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def gift_version() -> str:
+    return _lib.gift_version().decode()
+
+
+class Views:
+    """Database views with their storage metadata (keeps tensors alive)."""
+
+    def __init__(self, data, n_views, dtype=F32, scale=None, master=None):
+        assert data.is_cuda and data.is_contiguous()
+        self.data, self.scale = data, scale
+        self.master = master if master is not None else (data if dtype == F32 else None)
+        self.dtype, self.n_views = dtype, int(n_views)
+        self.dim = int(data.shape[1]) if dtype == F32 else int(data.shape[1])
+        self.n_shapes = int(data.shape[0]) // self.n_views
+        self.c = gift_views(data.data_ptr(), dtype, self.n_views, self.n_shapes, self.dim, 0,
+                            scale.data_ptr() if scale is not None else None,
+                            self.master.data_ptr() if self.master is not None else None)
+
+
+class Queries:
+    """A ragged batch of query view sets (keeps tensors alive)."""
+
+    def __init__(self, views, offsets, max_views=None, offsets_host=None):
+        assert views.is_cuda and views.dtype == torch.float32 and views.is_contiguous()
+        self.views = views
+        if offsets_host is None:
+            offsets_host = offsets.cpu() if offsets.is_cuda else offsets
+        self.offsets = offsets.to(device=views.device, dtype=torch.int32).contiguous()
+        oh = offsets_host.to(torch.int64)
+        self.n_queries = int(oh.numel() - 1)
+        self.total = int(oh[-1])
+        self.max_views = int(max_views if max_views is not None else (oh[1:] - oh[:-1]).max())
+        self.c = gift_queries(views.data_ptr(), self.offsets.data_ptr(), self.n_queries,
+                              self.max_views, self.total)
+
+
+def gift_quantize_views(src, dtype, stream=None):
+    """Per-view scaled BF16 / e4m3 codes of float32 rows: (codes, scale)."""
+    n, dim = src.shape
+    codes = torch.empty((n, dim), dtype=_DT_TORCH[dtype], device=src.device)
+    scale = torch.empty(n, dtype=torch.float32, device=src.device)
+    _check(_lib.gift_quantize_views(_ptr(src), n, dim, dtype, _ptr(codes), _ptr(scale),
+                                    _stream(stream)))
+    return codes, scale
+
+
+def gift_score_exhaustive(db: Views, q: Queries, stream=None):
+    """First-pass Eq. 3 scores [B, N] float32 in the database's dtype."""
+    ws = _workspace(_lib.gift_score_exhaustive_workspace(C.byref(db.c), C.byref(q.c)),
+                    db.data.device)
+    out = torch.empty((q.n_queries, db.n_shapes), dtype=torch.float32, device=db.data.device)
+    _check(_lib.gift_score_exhaustive(C.byref(db.c), C.byref(q.c), _ptr(out), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return out
+
+
+def gift_query_exhaustive(db: Views, q: Queries, top_k, rescore_r, stream=None, ws=None):
+    """Exact top-k of Eq. 3: (ids int32 [B,k], scores f32 [B,k], flags int32 [B])."""
+    dev = db.data.device
+    need = _lib.gift_query_exhaustive_workspace(C.byref(db.c), C.byref(q.c), top_k, rescore_r)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    ids = torch.empty((q.n_queries, top_k), dtype=torch.int32, device=dev)
+    scores = torch.empty((q.n_queries, top_k), dtype=torch.float32, device=dev)
+    flags = torch.empty(q.n_queries, dtype=torch.int32, device=dev)
+    _check(_lib.gift_query_exhaustive(C.byref(db.c), C.byref(q.c), top_k, rescore_r,
+                                      _ptr(ids), _ptr(scores), _ptr(flags), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return ids, scores, flags
+
+
+def query_exhaustive_workspace(db: Views, q: Queries, top_k, rescore_r) -> int:
+    return int(_lib.gift_query_exhaustive_workspace(C.byref(db.c), C.byref(q.c), top_k,
+                                                    rescore_r))

@@ -1,0 +1,345 @@
+// Ranking of Eq. 3 / Eq. 4 scores: block-level top-r selection, the exact
+// rescore of the candidates and the final (score desc, id asc) order.
+#include "kernels.h"
+
+namespace gift {
+
+// ------------------------------------------------------------------ helpers
+// Exclusive prefix count of `flag` over the 256 threads of a block, in
+// thread order; returns the block total through `total`.
+__device__ inline int block_excl_count(bool flag, int* wsum, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[wave] = __popcll(bal);
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += wsum[w];
+    total += wsum[w];
+  }
+  __syncthreads();
+  return before + in_wave;
+}
+
+// Bitonic sort of `n` (power of two, <= 4096) 64-bit keys in LDS, ascending.
+__device__ inline void bitonic_sort_u64(uint64_t* key, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = key[i], b = key[ix];
+          if ((a > b) == up) { key[i] = b; key[ix] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ top-r
+// Key of (score desc, id asc): complement of the order-preserving bits.
+__device__ inline uint32_t desc_key(float s) { return ~float_order(s); }
+
+constexpr int MAX_R = 1024;
+
+__global__ __launch_bounds__(256) void select_top_kernel(
+    const float* __restrict__ S, int64_t n, int r, int32_t* __restrict__ out_id,
+    float* __restrict__ out_s) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh_prefix, sh_need;
+  __shared__ int wsum[4];
+  __shared__ uint64_t keys[MAX_R];
+  __shared__ int cnt_less;
+  const int b = blockIdx.x;
+  const float* row = S + (int64_t)b * n;
+  const int tid = threadIdx.x;
+
+  // Radix select of the r-th smallest 32-bit key, 8 bits per pass.
+  uint32_t prefix = 0, mask = 0, need = (uint32_t)r;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    hist[tid] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += 256) {
+      const uint32_t k = desc_key(row[i]);
+      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t cum = 0;
+      int d = 0;
+      for (; d < 255; ++d) {
+        if (cum + hist[d] >= need) break;
+        cum += hist[d];
+      }
+      sh_need = need - cum;
+      sh_prefix = prefix | ((uint32_t)d << shift);
+    }
+    __syncthreads();
+    need = sh_need;
+    prefix = sh_prefix;
+    mask |= 255u << shift;
+    __syncthreads();
+  }
+  // `prefix` is the r-th smallest key; take every smaller key and the
+  // `need` lowest ids among the keys equal to it.
+  if (tid == 0) cnt_less = 0;
+  __syncthreads();
+  const int n_less = r - (int)need;
+  int taken_eq = 0;
+  for (int64_t base = 0; base < n; base += 256) {
+    const int64_t i = base + tid;
+    uint32_t k = 0xffffffffu;
+    if (i < n) k = desc_key(row[i]);
+    const bool less = i < n && k < prefix;
+    const bool eq = i < n && k == prefix;
+    if (less) {
+      const int pos = atomicAdd(&cnt_less, 1);
+      keys[pos] = ((uint64_t)k << 32) | (uint32_t)i;
+    }
+    int tot;
+    const int pos = block_excl_count(eq, wsum, tot);
+    if (eq && taken_eq + pos < (int)need)
+      keys[n_less + taken_eq + pos] = ((uint64_t)k << 32) | (uint32_t)i;
+    taken_eq += tot;
+  }
+  __syncthreads();
+  int np2 = 1;
+  while (np2 < r) np2 <<= 1;
+  for (int i = r + tid; i < np2; i += 256) keys[i] = ~0ull;
+  __syncthreads();
+  bitonic_sort_u64(keys, np2);
+  for (int i = tid; i < r; i += 256) {
+    const uint64_t k = keys[i];
+    out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
+    out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
+  }
+}
+
+void launch_select_top(const float* S, int64_t n, int n_queries, int r,
+                       int32_t* out_id, float* out_s, hipStream_t st) {
+  if (n_queries <= 0) return;
+  hipLaunchKernelGGL(select_top_kernel, dim3(n_queries), dim3(256), 0, st, S,
+                     n, r, out_id, out_s);
+}
+
+// ------------------------------------------------------------------ rescore
+// One block per (query, candidate shape).  Phase 1: the float32 dot products
+// of up to 64 query views x 64 database views, each thread owning 4 x 4 of
+// them, with a fresh partial sum per 32-value K-tile added into a running
+// total (accumulation depth at most 32 + dim/32, which bounds the error by
+// dot_err).  Phase 2: for each query view, every database view whose float32
+// dot product lies within 2 * dot_err of the row maximum may be the true
+// maximum; those pairs are re-evaluated with the compensated dot product
+// and the exact maximum kept.  Phase 3: the compensated mean over the query
+// views, summed in ascending view order.
+constexpr int RS_LROW = 36;  // floats per LDS row (32 + 4 pad)
+
+__global__ __launch_bounds__(256) void rescore_kernel(
+    const float* __restrict__ master, int n_views, int dim,
+    const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
+    const int32_t* __restrict__ cand, int r, float dot_err,
+    float* __restrict__ s_hi, float* __restrict__ s_lo) {
+  __shared__ float qs[64 * RS_LROW];
+  __shared__ float ps[64 * RS_LROW];
+  __shared__ float rowmax[64];
+  __shared__ unsigned long long jmask[64];
+  __shared__ float mff_hi[64], mff_lo[64];
+  __shared__ float tot_hi, tot_lo;
+
+  const int64_t bc = blockIdx.x;
+  const int b = (int)(bc / r);
+  const int64_t shape = cand[bc];
+  const int q0 = qoff[b], m = qoff[b + 1] - q0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ti = tid >> 4, tj = tid & 15;  // rows 4ti..4ti+3, cols 4tj..4tj+3
+  const float* pbase = master + shape * (int64_t)n_views * dim;
+
+  if (tid == 0) { tot_hi = 0.f; tot_lo = 0.f; }
+  for (int it = 0; it * 64 < m; ++it) {
+    const int mi = min(64, m - it * 64);
+    const float* qbase = qviews + (int64_t)(q0 + it * 64) * dim;
+    float tot[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) tot[x][y] = 0.f;
+
+    for (int k0 = 0; k0 < dim; k0 += 32) {
+      __syncthreads();
+      // stage 64 x 32 of each side: 512 float4 per side, 2 per thread
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = tid + 256 * h;
+        const int row = idx >> 3, c4 = idx & 7;
+        float4 qv = make_float4(0.f, 0.f, 0.f, 0.f), pv = qv;
+        if (row < mi) qv = *reinterpret_cast<const float4*>(qbase + (int64_t)row * dim + k0 + 4 * c4);
+        if (row < n_views) pv = *reinterpret_cast<const float4*>(pbase + (int64_t)row * dim + k0 + 4 * c4);
+        *reinterpret_cast<float4*>(qs + row * RS_LROW + 4 * c4) = qv;
+        *reinterpret_cast<float4*>(ps + row * RS_LROW + 4 * c4) = pv;
+      }
+      __syncthreads();
+      float part[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) part[x][y] = 0.f;
+#pragma unroll
+      for (int k = 0; k < 32; k += 4) {
+        float4 a[4], c[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[x] = *reinterpret_cast<const float4*>(qs + (4 * ti + x) * RS_LROW + k);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) c[y] = *reinterpret_cast<const float4*>(ps + (4 * tj + y) * RS_LROW + k);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            part[x][y] = __builtin_fmaf(a[x].x, c[y].x, part[x][y]);
+            part[x][y] = __builtin_fmaf(a[x].y, c[y].y, part[x][y]);
+            part[x][y] = __builtin_fmaf(a[x].z, c[y].z, part[x][y]);
+            part[x][y] = __builtin_fmaf(a[x].w, c[y].w, part[x][y]);
+          }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) tot[x][y] += part[x][y];
+    }
+    // row maxima over valid database views, then the near-maximum masks
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      float mx = -INFINITY;
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+        if (4 * tj + y < n_views) mx = fmaxf(mx, tot[x][y]);
+      for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+      unsigned long long bits = 0;
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+        if (4 * tj + y < n_views && tot[x][y] >= mx - 2.f * dot_err)
+          bits |= 1ull << (4 * tj + y);
+      for (int o = 8; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
+      if (tj == 0) { rowmax[4 * ti + x] = mx; jmask[4 * ti + x] = bits; }
+    }
+    __syncthreads();
+    // compensated maximum per query view: one wave per view
+    for (int i = wave; i < mi; i += 4) {
+      const float* qrow = qbase + (int64_t)i * dim;
+      unsigned long long bits = jmask[i];
+      ff best = {-INFINITY, 0.f};
+      while (bits) {
+        const int j = __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const float* prow = pbase + (int64_t)j * dim;
+        float s = 0.f, c = 0.f;
+        for (int t = lane; t < dim; t += 64) dot2_step(qrow[t], prow[t], s, c);
+        const ff v = ff_wave_sum(s, c);
+        if (ff_gt(v, best)) best = v;
+      }
+      if (lane == 0) { mff_hi[i] = best.hi; mff_lo[i] = best.lo; }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ff acc = {tot_hi, tot_lo};
+      for (int i = 0; i < mi; ++i) acc = ff_add(acc, ff{mff_hi[i], mff_lo[i]});
+      tot_hi = acc.hi;
+      tot_lo = acc.lo;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ff res = {0.f, 0.f};
+    if (m > 0) res = ff_div_int(ff{tot_hi, tot_lo}, m);
+    s_hi[bc] = res.hi;
+    s_lo[bc] = res.lo;
+  }
+}
+
+void launch_rescore(const float* master, int n_views, int dim,
+                    const float* qviews, const int32_t* qoff, int n_queries,
+                    int max_m, const int32_t* cand, int r, float dot_err,
+                    float* s_hi, float* s_lo, hipStream_t st) {
+  (void)max_m;
+  const int64_t blocks = (int64_t)n_queries * r;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     master, n_views, dim, qviews, qoff, cand, r, dot_err,
+                     s_hi, s_lo);
+}
+
+// ------------------------------------------------------------------ final
+struct Cand {
+  float hi, lo;
+  int32_t id;
+};
+
+__device__ inline bool cand_before(const Cand& a, const Cand& b) {
+  if (a.hi != b.hi) return a.hi > b.hi;
+  if (a.lo != b.lo) return a.lo > b.lo;
+  return a.id < b.id;
+}
+
+__global__ __launch_bounds__(256) void final_rank_kernel(
+    const int32_t* __restrict__ cand, const float* __restrict__ first_s,
+    const float* __restrict__ s_hi, const float* __restrict__ s_lo, int r,
+    int k, int64_t n_total, float first_err, int32_t* __restrict__ ids,
+    float* __restrict__ scores, int32_t* __restrict__ flags) {
+  __shared__ Cand c[MAX_R];
+  const int b = blockIdx.x;
+  const int64_t base = (int64_t)b * r;
+  int np2 = 1;
+  while (np2 < r) np2 <<= 1;
+  for (int i = threadIdx.x; i < np2; i += 256) {
+    if (i < r) c[i] = Cand{s_hi[base + i], s_lo[base + i], cand[base + i]};
+    else c[i] = Cand{-INFINITY, -INFINITY, 0x7fffffff};
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= np2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np2; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & kk) == 0;
+          const Cand a = c[i], d = c[ix];
+          if (cand_before(d, a) == up) { c[i] = d; c[ix] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < k; i += 256) {
+    ids[(int64_t)b * k + i] = c[i].id;
+    scores[(int64_t)b * k + i] = c[i].hi;
+  }
+  if (flags != nullptr && threadIdx.x == 0) {
+    // Any shape outside the candidates has a first-pass score at most the
+    // smallest candidate's, so its exact score is below that plus the
+    // first-pass error bound.  The list is complete when that stays below
+    // the k-th exact score.
+    bool complete = (int64_t)r >= n_total;
+    if (!complete) {
+      const float kth = c[k - 1].hi;
+      const float bound = first_s[base + r - 1] + first_err;
+      complete = bound < kth - fabsf(kth) * 2.4e-7f;
+    }
+    flags[b] = complete ? 1 : 0;
+  }
+}
+
+void launch_final_rank(const int32_t* cand, const float* first_s,
+                       const float* s_hi, const float* s_lo, int n_queries,
+                       int r, int k, int64_t n_total, float first_err,
+                       int32_t* ids, float* scores, int32_t* flags,
+                       hipStream_t st) {
+  if (n_queries <= 0) return;
+  hipLaunchKernelGGL(final_rank_kernel, dim3(n_queries), dim3(256), 0, st,
+                     cand, first_s, s_hi, s_lo, r, k, n_total, first_err, ids,
+                     scores, flags);
+}
+
+}  // namespace gift

@@ -1,0 +1,205 @@
+"""GPU parity of the exhaustive path (Eq. 3) against the CPU oracle.
+
+Runs through the C ABI (ctypes binding).  Ranked ids must equal the oracle's
+float64 ranking exactly, except inside groups whose float64 scores differ by
+less than TIE (several orders are then correct; the test checks the GPU's
+choice is one of them).  Scores must agree within 1e-5 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5     # score tolerance (relative)
+TIE = 1e-9     # float64 gaps below this count as ties
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1604_01879_amd import _lib
+    return _lib
+
+
+def _data(N=300, dim=256, B=6, m=(64, 64), nv=64, p_dis=0.2, seed=0):
+    w = synth.PRESETS["c1"].scaled(n_shapes=N, dim=dim, n_queries=B, m_lo=m[0], m_hi=m[1],
+                                   n_views=nv, p_dis=p_dis, seed=seed)
+    db, _, _ = synth.make_db(w)
+    q, qoff, _ = synth.make_queries(w)
+    return w, db, q, qoff
+
+
+def _views(L, db, nv, dtype):
+    dev = torch.device("cuda:0")
+    master = torch.from_numpy(db).to(dev)
+    if dtype == L.F32:
+        return L.Views(master, nv, L.F32), None, None
+    codes, scale = L.gift_quantize_views(master, dtype)
+    return L.Views(codes, nv, dtype, scale, master), codes, scale
+
+
+def _queries(L, q, qoff):
+    dev = torch.device("cuda:0")
+    return L.Queries(torch.from_numpy(q).to(dev), torch.from_numpy(qoff),
+                     offsets_host=torch.from_numpy(qoff))
+
+
+def assert_ranked_equal(ids, scores, S_ref, k):
+    """ids/scores from the GPU for one query; S_ref the oracle's f64 row."""
+    ref_ids, ref_s = O.rank_topk(S_ref[None], k)
+    ref_ids, ref_s = ref_ids[0], ref_s[0]
+    ids = np.asarray(ids)
+    assert len(set(ids.tolist())) == k, "duplicate ids"
+    got_exact = S_ref[ids]
+    # every position holds a shape whose exact score is the exact r-th score
+    assert np.all(np.abs(got_exact - ref_s) <= TIE), (
+        f"rank mismatch at {np.flatnonzero(np.abs(got_exact - ref_s) > TIE)[:5]}")
+    # positions without a tie must carry the same id
+    gaps = np.abs(np.diff(ref_s))
+    tie = np.zeros(k, bool)
+    tie[:-1] |= gaps <= TIE
+    tie[1:] |= gaps <= TIE
+    assert np.array_equal(ids[~tie], ref_ids[~tie])
+    assert np.allclose(scores, ref_s, rtol=REL, atol=1e-7)
+
+
+@pytest.mark.parametrize("dtype_name", ["bf16", "fp8"])
+def test_quantize_bit_exact(L, dtype_name):
+    _say(f"quantize {dtype_name}")
+    rng = np.random.default_rng(1)
+    x = rng.random((333, 96)).astype(np.float32) ** 3
+    x[5] = 0.0
+    x /= np.maximum(np.linalg.norm(x, axis=1, keepdims=True), 1e-30)
+    x[7] = 0.0
+    codes_ref, scale_ref = O.quantize_views(x, dtype_name)
+    dt = L.BF16 if dtype_name == "bf16" else L.FP8E4M3
+    codes, scale = L.gift_quantize_views(torch.from_numpy(x).cuda(), dt)
+    torch.cuda.synchronize()
+    if dt == L.BF16:
+        got = codes.cpu().view(torch.bfloat16).float().numpy()
+    else:
+        got = codes.cpu().view(torch.float8_e4m3fn).float().numpy()
+    assert np.array_equal(scale.cpu().numpy(), scale_ref)
+    assert np.array_equal(got, codes_ref)
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
+def test_first_pass_scores(L, dtype_name):
+    _say(f"first pass {dtype_name}")
+    w, db, q, qoff = _data(N=150, dim=256, B=5, m=(1, 64))
+    dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
+    V, _, _ = _views(L, db, w.n_views, dt)
+    Q = _queries(L, q, qoff)
+    S = L.gift_score_exhaustive(V, Q).cpu().numpy()
+    torch.cuda.synchronize()
+    if dtype_name == "f32":
+        ref = O.exhaustive_scores(q, qoff, db, w.n_views)
+    else:
+        qc, qs = O.quantize_views(q, dtype_name)
+        dc, ds = O.quantize_views(db, dtype_name)
+        ref = O.lowprec_exhaustive_scores(qc, qs, qoff, dc, ds, w.n_views)
+    assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views"])
+def test_query_exhaustive_ranked_ids(L, dtype_name, case):
+    _say(f"query_exhaustive {dtype_name} {case}")
+    if case == "c1-like":
+        w, db, q, qoff = _data(N=400, dim=256, B=8, m=(64, 64), p_dis=0.0)
+        k, R = 10, 64
+    elif case == "ragged":
+        w, db, q, qoff = _data(N=257, dim=160, B=7, m=(1, 64), seed=3)
+        k, R = 20, 257  # R = N: every shape rescored
+    else:
+        w, db, q, qoff = _data(N=90, dim=64, B=3, m=(5, 40), nv=7, seed=5)
+        k, R = 15, 40
+    dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
+    V, _, _ = _views(L, db, w.n_views, dt)
+    Q = _queries(L, q, qoff)
+    ids, sc, flags = L.gift_query_exhaustive(V, Q, k, R)
+    torch.cuda.synchronize()
+    ids, sc, flags = ids.cpu().numpy(), sc.cpu().numpy(), flags.cpu().numpy()
+    S = O.exhaustive_scores(q, qoff, db, w.n_views)
+    for b in range(len(qoff) - 1):
+        if dtype_name == "f32" or R == w.n_shapes or flags[b]:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
+        # a complete flag is a proof: it must never be set wrongly
+        if flags[b]:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
+    if dtype_name == "f32":
+        assert flags.all()
+
+
+def test_query_exhaustive_self_queries(L):
+    """A database shape queried against its own database ranks itself first
+    with score 1 (self-maximality of Eq. 3)."""
+    _say("self queries")
+    w, db, _, _ = _data(N=200, dim=128, B=1)
+    sel = np.array([0, 17, 199])
+    q = np.concatenate([db[s * 64:(s + 1) * 64] for s in sel])
+    qoff = np.arange(4, dtype=np.int32) * 64
+    V, _, _ = _views(L, db, 64, L.F32)
+    ids, sc, _ = L.gift_query_exhaustive(V, _queries(L, q, qoff), 5, 32)
+    ids = ids.cpu().numpy()
+    assert ids[:, 0].tolist() == sel.tolist()
+    assert np.allclose(sc.cpu().numpy()[:, 0], 1.0, atol=1e-6)
+
+
+def test_query_exhaustive_permutation_invariance(L):
+    """Permuting the views inside every database shape leaves ids and scores
+    bit-identical (the maximum is order-free; the rescore sums each pair
+    over the same coordinates in the same order)."""
+    _say("view permutation")
+    w, db, q, qoff = _data(N=128, dim=128, B=4, m=(10, 64), seed=7)
+    rng = np.random.default_rng(0)
+    db2 = db.copy()
+    for p in range(w.n_shapes):
+        db2[p * 64:(p + 1) * 64] = db[p * 64 + rng.permutation(64)]
+    out = []
+    for d in (db, db2):
+        V, _, _ = _views(L, d, 64, L.F32)
+        ids, sc, _ = L.gift_query_exhaustive(V, _queries(L, q, qoff), 12, 48)
+        out.append((ids.cpu().numpy(), sc.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_batch_mix_invariance(L):
+    """A query's result is identical alone and inside a larger batch."""
+    _say("batch mix")
+    w, db, q, qoff = _data(N=220, dim=128, B=6, m=(3, 64), seed=9)
+    V, _, _ = _views(L, db, 64, L.BF16)
+    ids_all, sc_all, _ = L.gift_query_exhaustive(V, _queries(L, q, qoff), 10, 40)
+    for b in (0, 3, 5):
+        lo, hi = qoff[b], qoff[b + 1]
+        qo = np.array([0, hi - lo], np.int32)
+        ids1, sc1, _ = L.gift_query_exhaustive(V, _queries(L, q[lo:hi], qo), 10, 40)
+        assert np.array_equal(ids1.cpu().numpy()[0], ids_all.cpu().numpy()[b])
+        assert np.array_equal(sc1.cpu().numpy()[0], sc_all.cpu().numpy()[b])
+
+
+def test_invalid_arguments_rejected(L):
+    _say("invalid args")
+    w, db, q, qoff = _data(N=40, dim=64, B=2)
+    V, _, _ = _views(L, db, 64, L.F32)
+    Q = _queries(L, q, qoff)
+    with pytest.raises(L.GiftError) as e:
+        L.gift_query_exhaustive(V, Q, 10, 41)  # R > N
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.GiftError):
+        L.gift_query_exhaustive(V, Q, 11, 10)  # k > R
+    bad = L.Views(torch.zeros((64, 48), device="cuda"), 64, L.F32)  # dim % 32 != 0
+    with pytest.raises(L.GiftError) as e:
+        L.gift_query_exhaustive(bad, Q, 1, 1)
+    assert e.value.status == L.EUNSUPPORTED
