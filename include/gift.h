@@ -126,6 +126,21 @@ gift_status gift_score_exhaustive(const gift_views* db, const gift_queries* q,
                                   float* scores, void* ws, size_t ws_bytes,
                                   void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Kernel timing.  gift_profile_enable(capacity > 0) creates `capacity`   */
+/* HIP event pairs and from then on brackets each kernel launch of the    */
+/* calls above with events recorded on the launch stream (first          */
+/* `capacity` launches after a reset); capacity 0 turns timing off and    */
+/* frees the events.  gift_profile_read() waits for the recorded events  */
+/* of kernel `tag` and returns their summed duration and count.  Tags:   */
+/* 0 quantize, 1 score_tiles, 2 reduce_queries, 3 select_top, 4 rescore,  */
+/* 5 final_rank.  Host functions, not thread-safe.                        */
+/* ---------------------------------------------------------------------- */
+gift_status gift_profile_enable(int32_t capacity);
+gift_status gift_profile_reset(void);
+gift_status gift_profile_read(int32_t tag, double* total_ms, int32_t* count);
+const char* gift_profile_tag_name(int32_t tag);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,10 @@ _sig = {
     "gift_query_exhaustive_workspace": (C.c_size_t, [_VP, _QP, C.c_int32, C.c_int32]),
     "gift_query_exhaustive": (C.c_int32, [_VP, _QP, C.c_int32, C.c_int32, _P, _P, _P, _P,
                                           C.c_size_t, _P]),
+    "gift_profile_enable": (C.c_int32, [C.c_int32]),
+    "gift_profile_reset": (C.c_int32, []),
+    "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "gift_profile_tag_name": (C.c_char_p, [C.c_int32]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -159,3 +163,22 @@ def gift_query_exhaustive(db: Views, q: Queries, top_k, rescore_r, stream=None, 
 def query_exhaustive_workspace(db: Views, q: Queries, top_k, rescore_r) -> int:
     return int(_lib.gift_query_exhaustive_workspace(C.byref(db.c), C.byref(q.c), top_k,
                                                     rescore_r))
+
+
+PROFILE_TAGS = {"quantize": 0, "score_tiles": 1, "reduce_queries": 2, "select_top": 3,
+                "rescore": 4, "final_rank": 5}
+
+
+def gift_profile_enable(capacity: int):
+    _check(_lib.gift_profile_enable(int(capacity)))
+
+
+def gift_profile_reset():
+    _check(_lib.gift_profile_reset())
+
+
+def gift_profile_read(tag: str):
+    """(total ms, launch count) of the recorded launches of one kernel."""
+    tot, cnt = C.c_double(), C.c_int32()
+    _check(_lib.gift_profile_read(PROFILE_TAGS[tag], C.byref(tot), C.byref(cnt)))
+    return tot.value, cnt.value

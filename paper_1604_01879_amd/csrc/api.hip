@@ -18,6 +18,27 @@ gift_status fail(gift_status st, const char* fmt, ...) {
   return st;
 }
 
+// ---------------------------------------------------------------- profiling
+// Optional HIP-event brackets around each kernel launch, on the launch
+// stream, so a caller can read per-kernel device time.  Off by default.
+enum ProfTag { P_QUANT = 0, P_SCORE, P_REDUCE, P_SELECT, P_RESCORE, P_FINAL, P_NTAGS };
+static const char* kTagNames[P_NTAGS] = {"quantize", "score_tiles", "reduce_queries",
+                                         "select_top", "rescore", "final_rank"};
+struct ProfSlot { hipEvent_t a, b; int tag; };
+static ProfSlot* g_prof = nullptr;
+static int g_prof_cap = 0, g_prof_used = 0, g_prof_on = 0;
+
+static void prof_begin(int tag, hipStream_t st) {
+  if (!g_prof_on || g_prof_used >= g_prof_cap) return;
+  g_prof[g_prof_used].tag = tag;
+  (void)hipEventRecord(g_prof[g_prof_used].a, st);
+}
+static void prof_end(hipStream_t st) {
+  if (!g_prof_on || g_prof_used >= g_prof_cap) return;
+  (void)hipEventRecord(g_prof[g_prof_used].b, st);
+  ++g_prof_used;
+}
+
 static const double U32 = 5.9604644775390625e-08;  // 2^-24
 
 // gamma_n = n u / (1 - n u), the classic bound on an n-term float32 sum.
@@ -106,14 +127,20 @@ static gift_status first_pass(const gift_views* db, const gift_queries* q,
   const void* qv = q->views;
   const float* qs = nullptr;
   if (db->dtype != GIFT_F32) {
+    prof_begin(P_QUANT, st);
     launch_quantize(q->views, q->total_views, db->dim, db->dtype, w.qcodes, w.qscale, st);
+    prof_end(st);
     GIFT_LAUNCHED();
     qv = w.qcodes;
     qs = w.qscale;
   }
+  prof_begin(P_SCORE, st);
   gift_status s = launch_score_tiles(db, qv, qs, q->total_views, w.mbuf, q->total_views, st);
+  prof_end(st);
   if (s != GIFT_OK) return s;
+  prof_begin(P_REDUCE, st);
   launch_reduce_queries(w.mbuf, q->total_views, db->n_shapes, q->offsets, q->n_queries, w.S, st);
+  prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;
 }
@@ -127,6 +154,51 @@ extern "C" {
 const char* gift_version(void) { return "gift-mi355x 0.1 (gfx950)"; }
 
 const char* gift_last_error(void) { return g_err; }
+
+gift_status gift_profile_enable(int32_t capacity) {
+  for (int i = 0; i < g_prof_cap; ++i) {
+    (void)hipEventDestroy(g_prof[i].a);
+    (void)hipEventDestroy(g_prof[i].b);
+  }
+  delete[] g_prof;
+  g_prof = nullptr;
+  g_prof_cap = g_prof_used = g_prof_on = 0;
+  if (capacity <= 0) return GIFT_OK;
+  g_prof = new ProfSlot[capacity];
+  for (int i = 0; i < capacity; ++i) {
+    GIFT_HIP(hipEventCreate(&g_prof[i].a));
+    GIFT_HIP(hipEventCreate(&g_prof[i].b));
+    g_prof_cap = i + 1;
+  }
+  g_prof_on = 1;
+  return GIFT_OK;
+}
+
+const char* gift_profile_tag_name(int32_t tag) {
+  return (tag >= 0 && tag < P_NTAGS) ? kTagNames[tag] : "";
+}
+
+gift_status gift_profile_read(int32_t tag, double* total_ms, int32_t* count) {
+  GIFT_CHECK(total_ms && count, GIFT_EINVAL, "null outputs");
+  double tot = 0;
+  int n = 0;
+  for (int i = 0; i < g_prof_used; ++i) {
+    if (g_prof[i].tag != tag) continue;
+    GIFT_HIP(hipEventSynchronize(g_prof[i].b));
+    float ms = 0.f;
+    GIFT_HIP(hipEventElapsedTime(&ms, g_prof[i].a, g_prof[i].b));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *count = n;
+  return GIFT_OK;
+}
+
+gift_status gift_profile_reset(void) {
+  g_prof_used = 0;
+  return GIFT_OK;
+}
 
 gift_status gift_quantize_views(const float* src, int64_t n, int32_t dim,
                                 int32_t dtype, void* dst, float* scale,
@@ -183,14 +255,20 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
   if ((s = first_pass(db, q, w, st)) != GIFT_OK) return s;
+  prof_begin(P_SELECT, st);
   launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, w.cand, w.cand_s, st);
+  prof_end(st);
   GIFT_LAUNCHED();
+  prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), w.s_hi, w.s_lo, st);
+  prof_end(st);
   GIFT_LAUNCHED();
+  prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
                     db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views), ids,
                     scores, flags, st);
+  prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;
 }
