@@ -127,6 +127,95 @@ gift_status gift_score_exhaustive(const gift_views* db, const gift_queries* q,
                                   void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Quantizer c(x) with Multiple Assignment (Sec. 2.3):                     */
+/*   c(x) = argmin_k ||x - b_k||^2 over the vocabulary B = {b_1..b_K};     */
+/* words[r][a] is the a-th nearest codeword of row r of x [n][dim] by      */
+/* (exact distance, index), a < ma.  Decided on the exact distance over    */
+/* the float32 inputs (float32 MFMA distances, compensated re-evaluation   */
+/* of every codeword within the float32 error bound of the ma-th best).    */
+/* codebook [K][dim] float32, K <= 16384, ma <= min(8, K).                 */
+/* n_uncertified: device int32 or NULL; receives the number of rows with   */
+/* more than 256 codewords inside that bound (their words may then not be  */
+/* exact; 0 in practice).                                                 */
+/* ---------------------------------------------------------------------- */
+size_t gift_assign_workspace(int64_t n, int32_t dim, int32_t K, int32_t ma);
+gift_status gift_assign(const float* x, int64_t n, int32_t dim,
+                        const float* codebook, int32_t K, int32_t ma,
+                        int32_t* words, int32_t* n_uncertified,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Vocabulary by k-means (Sec. 2.3; building it is the main offline cost   */
+/* after CNN training, Sec. 3.4).  Lloyd iterations from the K training    */
+/* rows init_idx (host int64[K]): assign every row with gift_assign        */
+/* (ma = 1); each centroid becomes the float64 sum of its members in       */
+/* ascending row order divided in float64 and rounded once to float32; an  */
+/* empty cluster keeps its centroid; stop when no assignment changes or    */
+/* after max_iter updates.  codebook [K][dim] and assign [n] receive the   */
+/* final state; *iters_run (host) the number of updates.  SYNCHRONISES     */
+/* `stream` once per iteration.  Returns GIFT_ECAPACITY if an assignment   */
+/* could not be certified.                                                */
+/* ---------------------------------------------------------------------- */
+size_t gift_build_codebook_workspace(int64_t n, int32_t dim, int32_t K);
+gift_status gift_build_codebook(const float* train, int64_t n, int32_t dim,
+                                int32_t K, const int64_t* init_idx,
+                                int32_t max_iter, float* codebook,
+                                int32_t* assign, int32_t* iters_run,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* The first inverted file (Sec. 2.3, Fig. 2): K lists; list w holds, in   */
+/* ascending (shape, view) order, every database view with w among its ma  */
+/* nearest codewords, as (shape id, view index).                          */
+typedef struct gift_fif {
+  const float*   codebook;    /* [K][dim] float32                             */
+  int32_t        K;
+  int32_t        ma;          /* codewords per database view                  */
+  int64_t        n_entries;   /* = ma * n_shapes * n_views                    */
+  const int64_t* offsets;     /* [K+1]: list w is entries [offsets[w], offsets[w+1]) */
+  const int32_t* entry_shape; /* [n_entries] shape id p                        */
+  const int32_t* entry_view;  /* [n_entries] view index j in 0..n_views-1      */
+  const int32_t* view_words;  /* [n_shapes * n_views][ma] words of each view   */
+} gift_fif;
+
+/* Builds the F-IF of `db` (which needs `master`) for a codebook: fills     */
+/* offsets [K+1], entry_shape / entry_view [ma*N*Nv] and view_words          */
+/* [N*Nv][ma].  SYNCHRONISES `stream`; GIFT_ECAPACITY as gift_build_codebook. */
+size_t gift_build_fif_workspace(const gift_views* db, int32_t K, int32_t ma);
+gift_status gift_build_fif(const gift_views* db, const float* codebook,
+                           int32_t K, int32_t ma, int64_t* offsets,
+                           int32_t* entry_shape, int32_t* entry_view,
+                           int32_t* view_words, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Inverted-file matching, Eq. 4 (Sec. 2.3):                              */
+/*   S_F(x_q, x_p) = (1/m) sum_i max_j s(q_i, p_j) * delta(c(q_i), p_j),   */
+/* where a query view is hard-assigned to its nearest word c(q_i) and      */
+/* delta is 1 when that word is among the ma words of p_j; a query view    */
+/* with no matching view of p contributes 0.  Only the lists of the        */
+/* batch's words are scanned.  Ranking, rescore and flags as               */
+/* gift_query_exhaustive (the rescore evaluates Eq. 4 exactly); flags bit  */
+/* 1 marks a batch in which a query word could not be certified.           */
+/* ---------------------------------------------------------------------- */
+size_t gift_query_fif_workspace(const gift_views* db, const gift_fif* fif,
+                                const gift_queries* q, int32_t top_k,
+                                int32_t rescore_r);
+gift_status gift_query_fif(const gift_views* db, const gift_fif* fif,
+                           const gift_queries* q, int32_t top_k,
+                           int32_t rescore_r, int32_t* ids, float* scores,
+                           int32_t* flags, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* First-pass Eq. 4 scores [n_queries][n_shapes] float32 in db->dtype and,  */
+/* if qwords != NULL, the word of every query view [total_views] int32.     */
+size_t gift_score_fif_workspace(const gift_views* db, const gift_fif* fif,
+                                const gift_queries* q);
+gift_status gift_score_fif(const gift_views* db, const gift_fif* fif,
+                           const gift_queries* q, float* scores,
+                           int32_t* qwords, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing.  gift_profile_enable(capacity > 0) creates `capacity`   */
 /* HIP event pairs and from then on brackets each kernel launch of the    */
 /* calls above with events recorded on the launch stream (first          */
@@ -134,7 +223,8 @@ gift_status gift_score_exhaustive(const gift_views* db, const gift_queries* q,
 /* frees the events.  gift_profile_read() waits for the recorded events  */
 /* of kernel `tag` and returns their summed duration and count.  Tags:   */
 /* 0 quantize, 1 score_tiles, 2 reduce_queries, 3 select_top, 4 rescore,  */
-/* 5 final_rank.  Host functions, not thread-safe.                        */
+/* 5 final_rank, 6 assign, 7 group_queries, 8 fif_scan.  Host functions,   */
+/* not thread-safe.                                                       */
 /* ---------------------------------------------------------------------- */
 gift_status gift_profile_enable(int32_t capacity);
 gift_status gift_profile_reset(void);

@@ -232,13 +232,15 @@ def build_fif(db_words: np.ndarray, K: int, n_views: int):
 
 
 def fif_scores(qviews, qoff, db, n_views, codebook, offsets, entry_shape,
-               entry_view, dtype=f64):
+               entry_view, dtype=f64, qwords=None):
     """Eq. 4 through list scans: S_F[b, p].
 
     Each query view q_i is hard-assigned to its nearest word w_i = c(q_i).
     M_i(p) = max of s(q_i, p_j) over the entries (p, j) of list w_i, or 0 if
     shape p has no view in that list (READING of the Kronecker delta).
-    S_F = (1/m) sum_i M_i(p), summed in ascending i.
+    S_F = (1/m) sum_i M_i(p), summed in ascending i.  ``qwords`` may give the
+    query words (e.g. decided on float32 views while the dot products use
+    dequantised low-precision values).
     """
     db = np.asarray(db)
     n_shapes = db.shape[0] // n_views
@@ -248,7 +250,10 @@ def fif_scores(qviews, qoff, db, n_views, codebook, offsets, entry_shape,
         m = hi - lo
         if m == 0:
             continue
-        words = assign(qviews[lo:hi], codebook, 1)[:, 0]
+        if qwords is None:
+            words = assign(qviews[lo:hi], codebook, 1)[:, 0]
+        else:
+            words = np.asarray(qwords[lo:hi])
         acc = np.zeros(n_shapes, dtype=dtype)
         for i in range(m):
             w = words[i]

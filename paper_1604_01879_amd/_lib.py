@@ -44,7 +44,14 @@ class gift_queries(C.Structure):
                 ("max_views", C.c_int32), ("total_views", C.c_int64)]
 
 
+class gift_fif(C.Structure):
+    _fields_ = [("codebook", C.c_void_p), ("K", C.c_int32), ("ma", C.c_int32),
+                ("n_entries", C.c_int64), ("offsets", C.c_void_p), ("entry_shape", C.c_void_p),
+                ("entry_view", C.c_void_p), ("view_words", C.c_void_p)]
+
+
 _P = C.c_void_p
+_FP = C.POINTER(gift_fif)
 _VP = C.POINTER(gift_views)
 _QP = C.POINTER(gift_queries)
 _sig = {
@@ -56,6 +63,20 @@ _sig = {
     "gift_query_exhaustive_workspace": (C.c_size_t, [_VP, _QP, C.c_int32, C.c_int32]),
     "gift_query_exhaustive": (C.c_int32, [_VP, _QP, C.c_int32, C.c_int32, _P, _P, _P, _P,
                                           C.c_size_t, _P]),
+    "gift_assign_workspace": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
+    "gift_assign": (C.c_int32, [_P, C.c_int64, C.c_int32, _P, C.c_int32, C.c_int32, _P, _P, _P,
+                                C.c_size_t, _P]),
+    "gift_build_codebook_workspace": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32]),
+    "gift_build_codebook": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32, _P, C.c_int32, _P,
+                                        _P, C.POINTER(C.c_int32), _P, C.c_size_t, _P]),
+    "gift_build_fif_workspace": (C.c_size_t, [_VP, C.c_int32, C.c_int32]),
+    "gift_build_fif": (C.c_int32, [_VP, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P,
+                                   C.c_size_t, _P]),
+    "gift_query_fif_workspace": (C.c_size_t, [_VP, _FP, _QP, C.c_int32, C.c_int32]),
+    "gift_query_fif": (C.c_int32, [_VP, _FP, _QP, C.c_int32, C.c_int32, _P, _P, _P, _P,
+                                   C.c_size_t, _P]),
+    "gift_score_fif_workspace": (C.c_size_t, [_VP, _FP, _QP]),
+    "gift_score_fif": (C.c_int32, [_VP, _FP, _QP, _P, _P, _P, C.c_size_t, _P]),
     "gift_profile_enable": (C.c_int32, [C.c_int32]),
     "gift_profile_reset": (C.c_int32, []),
     "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -166,7 +187,7 @@ def query_exhaustive_workspace(db: Views, q: Queries, top_k, rescore_r) -> int:
 
 
 PROFILE_TAGS = {"quantize": 0, "score_tiles": 1, "reduce_queries": 2, "select_top": 3,
-                "rescore": 4, "final_rank": 5}
+                "rescore": 4, "final_rank": 5, "assign": 6, "group_queries": 7, "fif_scan": 8}
 
 
 def gift_profile_enable(capacity: int):
@@ -182,3 +203,91 @@ def gift_profile_read(tag: str):
     tot, cnt = C.c_double(), C.c_int32()
     _check(_lib.gift_profile_read(PROFILE_TAGS[tag], C.byref(tot), C.byref(cnt)))
     return tot.value, cnt.value
+
+
+# ---------------------------------------------------------------- F-IF
+def gift_assign(x, codebook, ma=1, stream=None):
+    """Words [n, ma] int32 of the rows of x (Sec. 2.3 quantizer) and the
+    device count of uncertified rows."""
+    n, dim = x.shape
+    K = int(codebook.shape[0])
+    ws = _workspace(_lib.gift_assign_workspace(n, dim, K, ma), x.device)
+    words = torch.empty((n, ma), dtype=torch.int32, device=x.device)
+    unc = torch.zeros(1, dtype=torch.int32, device=x.device)
+    _check(_lib.gift_assign(_ptr(x), n, dim, _ptr(codebook), K, ma, _ptr(words), _ptr(unc),
+                            _ptr(ws), ws.numel(), _stream(stream)))
+    return words, unc
+
+
+def gift_build_codebook(train, K, init_idx, max_iter=25, stream=None):
+    """k-means vocabulary: (codebook [K, d] f32, assign [n] i32, iterations)."""
+    n, dim = train.shape
+    init = torch.as_tensor(init_idx, dtype=torch.int64).cpu().contiguous()
+    ws = _workspace(_lib.gift_build_codebook_workspace(n, dim, K), train.device)
+    cb = torch.empty((K, dim), dtype=torch.float32, device=train.device)
+    a = torch.empty(n, dtype=torch.int32, device=train.device)
+    it = C.c_int32(0)
+    _check(_lib.gift_build_codebook(_ptr(train), n, dim, K, C.c_void_p(init.data_ptr()),
+                                    max_iter, _ptr(cb), _ptr(a), C.byref(it), _ptr(ws),
+                                    ws.numel(), _stream(stream)))
+    return cb, a, it.value
+
+
+class Fif:
+    """A first inverted file and its codebook (keeps tensors alive)."""
+
+    def __init__(self, codebook, ma, offsets, entry_shape, entry_view, view_words):
+        self.codebook, self.ma = codebook, int(ma)
+        self.K = int(codebook.shape[0])
+        self.offsets, self.entry_shape, self.entry_view = offsets, entry_shape, entry_view
+        self.view_words = view_words
+        self.c = gift_fif(codebook.data_ptr(), self.K, self.ma, int(entry_shape.numel()),
+                          offsets.data_ptr(), entry_shape.data_ptr(), entry_view.data_ptr(),
+                          view_words.data_ptr())
+
+
+def gift_build_fif(db: Views, codebook, ma=1, stream=None):
+    K = int(codebook.shape[0])
+    dev = db.data.device
+    nv = db.n_shapes * db.n_views
+    ws = _workspace(_lib.gift_build_fif_workspace(C.byref(db.c), K, ma), dev)
+    off = torch.empty(K + 1, dtype=torch.int64, device=dev)
+    es = torch.empty(nv * ma, dtype=torch.int32, device=dev)
+    ev = torch.empty(nv * ma, dtype=torch.int32, device=dev)
+    vw = torch.empty((nv, ma), dtype=torch.int32, device=dev)
+    _check(_lib.gift_build_fif(C.byref(db.c), _ptr(codebook), K, ma, _ptr(off), _ptr(es),
+                               _ptr(ev), _ptr(vw), _ptr(ws), ws.numel(), _stream(stream)))
+    return Fif(codebook, ma, off, es, ev, vw)
+
+
+def gift_query_fif(db: Views, fif: Fif, q: Queries, top_k, rescore_r, stream=None, ws=None):
+    """Exact top-k of Eq. 4: (ids, scores, flags)."""
+    dev = db.data.device
+    need = _lib.gift_query_fif_workspace(C.byref(db.c), C.byref(fif.c), C.byref(q.c), top_k,
+                                         rescore_r)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    ids = torch.empty((q.n_queries, top_k), dtype=torch.int32, device=dev)
+    scores = torch.empty((q.n_queries, top_k), dtype=torch.float32, device=dev)
+    flags = torch.empty(q.n_queries, dtype=torch.int32, device=dev)
+    _check(_lib.gift_query_fif(C.byref(db.c), C.byref(fif.c), C.byref(q.c), top_k, rescore_r,
+                               _ptr(ids), _ptr(scores), _ptr(flags), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return ids, scores, flags
+
+
+def query_fif_workspace(db: Views, fif: Fif, q: Queries, top_k, rescore_r) -> int:
+    return int(_lib.gift_query_fif_workspace(C.byref(db.c), C.byref(fif.c), C.byref(q.c),
+                                             top_k, rescore_r))
+
+
+def gift_score_fif(db: Views, fif: Fif, q: Queries, stream=None):
+    """First-pass Eq. 4 scores [B, N] and the query words [total_views]."""
+    dev = db.data.device
+    ws = _workspace(_lib.gift_score_fif_workspace(C.byref(db.c), C.byref(fif.c), C.byref(q.c)),
+                    dev)
+    out = torch.empty((q.n_queries, db.n_shapes), dtype=torch.float32, device=dev)
+    qw = torch.empty(q.total, dtype=torch.int32, device=dev)
+    _check(_lib.gift_score_fif(C.byref(db.c), C.byref(fif.c), C.byref(q.c), _ptr(out), _ptr(qw),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+    return out, qw

@@ -21,9 +21,11 @@ gift_status fail(gift_status st, const char* fmt, ...) {
 // ---------------------------------------------------------------- profiling
 // Optional HIP-event brackets around each kernel launch, on the launch
 // stream, so a caller can read per-kernel device time.  Off by default.
-enum ProfTag { P_QUANT = 0, P_SCORE, P_REDUCE, P_SELECT, P_RESCORE, P_FINAL, P_NTAGS };
+enum ProfTag { P_QUANT = 0, P_SCORE, P_REDUCE, P_SELECT, P_RESCORE, P_FINAL, P_ASSIGN,
+               P_GROUP, P_SCAN, P_NTAGS };
 static const char* kTagNames[P_NTAGS] = {"quantize", "score_tiles", "reduce_queries",
-                                         "select_top", "rescore", "final_rank"};
+                                         "select_top", "rescore", "final_rank", "assign",
+                                         "group_queries", "fif_scan"};
 struct ProfSlot { hipEvent_t a, b; int tag; };
 static ProfSlot* g_prof = nullptr;
 static int g_prof_cap = 0, g_prof_used = 0, g_prof_on = 0;
@@ -145,6 +147,135 @@ static gift_status first_pass(const gift_views* db, const gift_queries* q,
   return GIFT_OK;
 }
 
+// ---------------------------------------------------------------- quantizer
+struct AssignWs {
+  float* D;
+  float* nhi;
+  float* nlo;
+  int32_t* overflow;
+  int64_t chunk;
+};
+
+static int64_t assign_chunk(int64_t n, int K) {
+  int64_t c = ((int64_t)1 << 28) / (K > 0 ? K : 1);  // <= 1 GiB of float32 dots
+  if (c < 128) c = 128;
+  return n < c ? (n > 0 ? n : 1) : c;
+}
+
+static AssignWs carve_assign(Carver& c, int64_t n, int K) {
+  AssignWs w{};
+  w.chunk = assign_chunk(n, K);
+  w.D = c.take<float>((size_t)w.chunk * K);
+  w.nhi = c.take<float>((size_t)K);
+  w.nlo = c.take<float>((size_t)K);
+  w.overflow = c.take<int32_t>(1);
+  return w;
+}
+
+static gift_status check_codebook(const float* cb, int K, int ma, int dim) {
+  GIFT_CHECK(cb != nullptr, GIFT_EINVAL, "null codebook");
+  GIFT_CHECK(K >= 1 && K <= 16384, GIFT_EUNSUPPORTED, "K must be in 1..16384 (got %d)", K);
+  GIFT_CHECK(ma >= 1 && ma <= 8 && ma <= K, GIFT_EUNSUPPORTED, "ma must be in 1..min(8, K)");
+  GIFT_CHECK(dim >= 32 && dim % 32 == 0, GIFT_EUNSUPPORTED, "dim must be a multiple of 32");
+  return GIFT_OK;
+}
+
+// ---------------------------------------------------------------- F-IF query
+struct FifWs {
+  int32_t* qwords;
+  AssignWs as;
+  int64_t* goff;
+  int32_t* gitems;
+  void* bucket;
+  void* qcodes;
+  float* qscale;
+  uint32_t* mbuf;
+  float* S;
+  int64_t* tile_off;
+  int64_t* tcount;
+  int32_t* cand;
+  float* cand_s;
+  float* s_hi;
+  float* s_lo;
+  size_t bytes;
+};
+
+static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
+                       const gift_queries* q, int r) {
+  Carver c(base);
+  FifWs w{};
+  const int64_t tq = q->total_views;
+  w.qwords = c.take<int32_t>((size_t)tq);
+  w.as = carve_assign(c, tq, f->K);
+  w.goff = c.take<int64_t>((size_t)f->K + 1);
+  w.gitems = c.take<int32_t>((size_t)tq);
+  w.bucket = c.take<uint8_t>(bucket_sort_ws(tq, f->K));
+  if (db->dtype != GIFT_F32) {
+    w.qcodes = c.take<uint8_t>((size_t)tq * db->dim * elem_bytes(db->dtype));
+    w.qscale = c.take<float>((size_t)tq);
+  }
+  w.mbuf = c.take<uint32_t>((size_t)db->n_shapes * tq);
+  w.S = c.take<float>((size_t)q->n_queries * db->n_shapes);
+  w.tile_off = c.take<int64_t>((size_t)f->K + 1);
+  w.tcount = c.take<int64_t>((size_t)f->K);
+  if (r > 0) {
+    w.cand = c.take<int32_t>((size_t)q->n_queries * r);
+    w.cand_s = c.take<float>((size_t)q->n_queries * r);
+    w.s_hi = c.take<float>((size_t)q->n_queries * r);
+    w.s_lo = c.take<float>((size_t)q->n_queries * r);
+  }
+  w.bytes = c.bytes();
+  return w;
+}
+
+static gift_status check_fif(const gift_fif* f, const gift_views* db) {
+  GIFT_CHECK(f != nullptr && f->offsets && f->entry_shape && f->entry_view && f->view_words,
+             GIFT_EINVAL, "incomplete F-IF index");
+  gift_status s = check_codebook(f->codebook, f->K, f->ma, db->dim);
+  if (s != GIFT_OK) return s;
+  GIFT_CHECK(f->n_entries == (int64_t)f->ma * db->n_shapes * db->n_views, GIFT_EINVAL,
+             "n_entries must be ma * n_shapes * n_views");
+  return GIFT_OK;
+}
+
+// Eq. 4 first pass for every (query, shape) into w.S (float32).
+static gift_status fif_first_pass(const gift_views* db, const gift_fif* f, const gift_queries* q,
+                                  const FifWs& w, hipStream_t st) {
+  const int64_t tq = q->total_views;
+  launch_fill_i32(w.as.overflow, 1, 0, st);
+  prof_begin(P_ASSIGN, st);
+  gift_status s = launch_assign(q->views, tq, db->dim, f->codebook, f->K, 1, w.qwords, w.as.D,
+                                w.as.chunk, w.as.nhi, w.as.nlo, w.as.overflow, st);
+  prof_end(st);
+  if (s != GIFT_OK) return s;
+  prof_begin(P_GROUP, st);
+  s = launch_bucket_sort(w.qwords, tq, f->K, w.goff, 0, 1, 1, w.gitems, nullptr, w.bucket, st);
+  prof_end(st);
+  if (s != GIFT_OK) return s;
+  const void* qv = q->views;
+  const float* qs = nullptr;
+  if (db->dtype != GIFT_F32) {
+    prof_begin(P_QUANT, st);
+    launch_quantize(q->views, tq, db->dim, db->dtype, w.qcodes, w.qscale, st);
+    prof_end(st);
+    GIFT_LAUNCHED();
+    qv = w.qcodes;
+    qs = w.qscale;
+  }
+  launch_fill_i32(reinterpret_cast<int32_t*>(w.mbuf), db->n_shapes * tq, 0, st);
+  GIFT_LAUNCHED();
+  prof_begin(P_SCAN, st);
+  s = launch_fif_scan(db, f->offsets, f->entry_shape, f->entry_view, f->n_entries, f->K,
+                      w.tile_off, w.tcount, w.goff, w.gitems, qv, qs, w.mbuf, tq, st);
+  prof_end(st);
+  if (s != GIFT_OK) return s;
+  prof_begin(P_REDUCE, st);
+  launch_reduce_fif(w.mbuf, tq, db->n_shapes, q->offsets, q->n_queries, w.S, st);
+  prof_end(st);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
 }  // namespace gift
 
 using namespace gift;
@@ -261,15 +392,248 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
-                 q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), w.s_hi, w.s_lo, st);
+                 q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), nullptr, nullptr, 0,
+                 w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
-                    db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views), ids,
-                    scores, flags, st);
+                    db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views), nullptr,
+                    ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
+/* ------------------------------------------------------------ quantizer */
+size_t gift_assign_workspace(int64_t n, int32_t dim, int32_t K, int32_t ma) {
+  (void)dim;
+  (void)ma;
+  Carver c(nullptr);
+  carve_assign(c, n, K);
+  return c.bytes();
+}
+
+gift_status gift_assign(const float* x, int64_t n, int32_t dim, const float* codebook, int32_t K,
+                        int32_t ma, int32_t* words, int32_t* n_uncertified, void* ws,
+                        size_t ws_bytes, void* stream) {
+  gift_status s = check_codebook(codebook, K, ma, dim);
+  if (s != GIFT_OK) return s;
+  GIFT_CHECK(x && words && n >= 0, GIFT_EINVAL, "null input/output or n < 0");
+  const hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  AssignWs w = carve_assign(c, n, K);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= c.bytes(), GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", c.bytes(), ws_bytes);
+  int32_t* ovf = n_uncertified ? n_uncertified : w.overflow;
+  launch_fill_i32(ovf, 1, 0, st);
+  GIFT_LAUNCHED();
+  prof_begin(P_ASSIGN, st);
+  s = launch_assign(x, n, dim, codebook, K, ma, words, w.D, w.chunk, w.nhi, w.nlo, ovf, st);
+  prof_end(st);
+  return s;
+}
+
+/* ------------------------------------------------------------ codebook */
+struct KmWs {
+  float* cb2;
+  int32_t* a2;
+  int32_t* members;
+  int64_t* moff;
+  int32_t* changes;
+  int64_t* idx;
+  void* bucket;
+  AssignWs as;
+  size_t bytes;
+};
+
+static KmWs carve_km(void* base, int64_t n, int dim, int K) {
+  Carver c(base);
+  KmWs w{};
+  w.cb2 = c.take<float>((size_t)K * dim);
+  w.a2 = c.take<int32_t>((size_t)n);
+  w.members = c.take<int32_t>((size_t)n);
+  w.moff = c.take<int64_t>((size_t)K + 1);
+  w.changes = c.take<int32_t>(1);
+  w.idx = c.take<int64_t>((size_t)K);
+  w.bucket = c.take<uint8_t>(bucket_sort_ws(n, K));
+  w.as = carve_assign(c, n, K);
+  w.bytes = c.bytes();
+  return w;
+}
+
+size_t gift_build_codebook_workspace(int64_t n, int32_t dim, int32_t K) {
+  return carve_km(nullptr, n, dim, K).bytes;
+}
+
+gift_status gift_build_codebook(const float* train, int64_t n, int32_t dim, int32_t K,
+                                const int64_t* init_idx, int32_t max_iter, float* codebook,
+                                int32_t* assign, int32_t* iters_run, void* ws, size_t ws_bytes,
+                                void* stream) {
+  gift_status s = check_codebook(train, K, 1, dim);
+  if (s != GIFT_OK) return s;
+  GIFT_CHECK(train && init_idx && codebook && assign && n >= K && max_iter >= 0, GIFT_EINVAL,
+             "bad arguments (need n >= K, non-null buffers)");
+  GIFT_CHECK(n < ((int64_t)1 << 31), GIFT_ECAPACITY, "n too large");
+  for (int k = 0; k < K; ++k)
+    GIFT_CHECK(init_idx[k] >= 0 && init_idx[k] < n, GIFT_EINVAL, "init_idx[%d] out of range", k);
+  const hipStream_t st = (hipStream_t)stream;
+  KmWs w = carve_km(ws, n, dim, K);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
+  GIFT_HIP(hipMemcpyAsync(w.idx, init_idx, (size_t)K * 8, hipMemcpyHostToDevice, st));
+  launch_gather_rows(train, w.idx, K, dim, codebook, st);
+  GIFT_LAUNCHED();
+  launch_fill_i32(w.as.overflow, 1, 0, st);
+  s = launch_assign(train, n, dim, codebook, K, 1, assign, w.as.D, w.as.chunk, w.as.nhi,
+                    w.as.nlo, w.as.overflow, st);
+  if (s != GIFT_OK) return s;
+  float* cur = codebook;
+  float* nxt = w.cb2;
+  int32_t* a_cur = assign;
+  int32_t* a_nxt = w.a2;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    s = launch_bucket_sort(a_cur, n, K, w.moff, 0, 1, 1, w.members, nullptr, w.bucket, st);
+    if (s != GIFT_OK) return s;
+    launch_centroids(train, dim, K, w.moff, w.members, cur, nxt, st);
+    GIFT_LAUNCHED();
+    s = launch_assign(train, n, dim, nxt, K, 1, a_nxt, w.as.D, w.as.chunk, w.as.nhi, w.as.nlo,
+                      w.as.overflow, st);
+    if (s != GIFT_OK) return s;
+    launch_fill_i32(w.changes, 1, 0, st);
+    launch_count_changes(a_cur, a_nxt, n, w.changes, st);
+    GIFT_LAUNCHED();
+    int32_t changes = 0;
+    GIFT_HIP(hipMemcpyAsync(&changes, w.changes, 4, hipMemcpyDeviceToHost, st));
+    GIFT_HIP(hipStreamSynchronize(st));
+    float* t = cur; cur = nxt; nxt = t;
+    int32_t* ta = a_cur; a_cur = a_nxt; a_nxt = ta;
+    if (changes == 0) break;
+  }
+  if (it > max_iter) it = max_iter;
+  if (cur != codebook)
+    GIFT_HIP(hipMemcpyAsync(codebook, cur, (size_t)K * dim * 4, hipMemcpyDeviceToDevice, st));
+  if (a_cur != assign)
+    GIFT_HIP(hipMemcpyAsync(assign, a_cur, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  int32_t ovf = 0;
+  GIFT_HIP(hipMemcpyAsync(&ovf, w.as.overflow, 4, hipMemcpyDeviceToHost, st));
+  GIFT_HIP(hipStreamSynchronize(st));
+  if (iters_run) *iters_run = it;
+  GIFT_CHECK(ovf == 0, GIFT_ECAPACITY, "%d assignments had more than 256 near-tied codewords", ovf);
+  return GIFT_OK;
+}
+
+/* ------------------------------------------------------------ F-IF build */
+size_t gift_build_fif_workspace(const gift_views* db, int32_t K, int32_t ma) {
+  if (check_views(db) != GIFT_OK) return 0;
+  const int64_t nv = db->n_shapes * db->n_views;
+  Carver c(nullptr);
+  carve_assign(c, nv, K);
+  c.take<uint8_t>(bucket_sort_ws(nv * ma, K));
+  return c.bytes();
+}
+
+gift_status gift_build_fif(const gift_views* db, const float* codebook, int32_t K, int32_t ma,
+                           int64_t* offsets, int32_t* entry_shape, int32_t* entry_view,
+                           int32_t* view_words, void* ws, size_t ws_bytes, void* stream) {
+  gift_status s = check_views(db);
+  if (s != GIFT_OK) return s;
+  if ((s = check_codebook(codebook, K, ma, db->dim)) != GIFT_OK) return s;
+  GIFT_CHECK(db->master != nullptr, GIFT_EINVAL, "the quantizer needs float32 master views");
+  GIFT_CHECK(offsets && entry_shape && entry_view && view_words, GIFT_EINVAL, "null outputs");
+  const int64_t nv = db->n_shapes * db->n_views;
+  GIFT_CHECK(nv * ma < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many entries");
+  const hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  AssignWs w = carve_assign(c, nv, K);
+  void* bucket = c.take<uint8_t>(bucket_sort_ws(nv * ma, K));
+  GIFT_CHECK(ws != nullptr && ws_bytes >= c.bytes(), GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", c.bytes(), ws_bytes);
+  launch_fill_i32(w.overflow, 1, 0, st);
+  GIFT_LAUNCHED();
+  s = launch_assign(db->master, nv, db->dim, codebook, K, ma, view_words, w.D, w.chunk, w.nhi,
+                    w.nlo, w.overflow, st);
+  if (s != GIFT_OK) return s;
+  s = launch_bucket_sort(view_words, nv * ma, K, offsets, 1, ma, db->n_views, entry_shape,
+                         entry_view, bucket, st);
+  if (s != GIFT_OK) return s;
+  int32_t ovf = 0;
+  GIFT_HIP(hipMemcpyAsync(&ovf, w.overflow, 4, hipMemcpyDeviceToHost, st));
+  GIFT_HIP(hipStreamSynchronize(st));
+  GIFT_CHECK(ovf == 0, GIFT_ECAPACITY, "%d views had more than 256 near-tied codewords", ovf);
+  return GIFT_OK;
+}
+
+/* ------------------------------------------------------------ F-IF query */
+size_t gift_query_fif_workspace(const gift_views* db, const gift_fif* fif,
+                                const gift_queries* q, int32_t top_k, int32_t rescore_r) {
+  (void)top_k;
+  if (check_views(db) != GIFT_OK || check_queries(q, db->dim) != GIFT_OK || fif == nullptr)
+    return 0;
+  return carve_fif(nullptr, db, fif, q, rescore_r > 0 ? rescore_r : 1).bytes;
+}
+
+gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift_queries* q,
+                           int32_t top_k, int32_t rescore_r, int32_t* ids, float* scores,
+                           int32_t* flags, void* ws, size_t ws_bytes, void* stream) {
+  gift_status s = check_views(db);
+  if (s != GIFT_OK) return s;
+  if ((s = check_queries(q, db->dim)) != GIFT_OK) return s;
+  if ((s = check_fif(fif, db)) != GIFT_OK) return s;
+  GIFT_CHECK(ids && scores, GIFT_EINVAL, "null outputs");
+  GIFT_CHECK(top_k >= 1 && top_k <= rescore_r && rescore_r <= 1024 &&
+                 (int64_t)rescore_r <= db->n_shapes,
+             GIFT_EINVAL, "need 1 <= top_k <= rescore_r <= min(1024, N)");
+  GIFT_CHECK(db->master != nullptr, GIFT_EINVAL, "the exact rescore needs float32 master views");
+  const hipStream_t st = (hipStream_t)stream;
+  FifWs w = carve_fif(ws, db, fif, q, rescore_r);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
+  if ((s = fif_first_pass(db, fif, q, w, st)) != GIFT_OK) return s;
+  prof_begin(P_SELECT, st);
+  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, w.cand, w.cand_s, st);
+  prof_end(st);
+  GIFT_LAUNCHED();
+  prof_begin(P_RESCORE, st);
+  launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
+                 q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), w.qwords,
+                 fif->view_words, fif->ma, w.s_hi, w.s_lo, st);
+  prof_end(st);
+  GIFT_LAUNCHED();
+  prof_begin(P_FINAL, st);
+  launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
+                    db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views),
+                    w.as.overflow, ids, scores, flags, st);
+  prof_end(st);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
+size_t gift_score_fif_workspace(const gift_views* db, const gift_fif* fif,
+                                const gift_queries* q) {
+  if (check_views(db) != GIFT_OK || check_queries(q, db->dim) != GIFT_OK || fif == nullptr)
+    return 0;
+  return carve_fif(nullptr, db, fif, q, 0).bytes;
+}
+
+gift_status gift_score_fif(const gift_views* db, const gift_fif* fif, const gift_queries* q,
+                           float* scores, int32_t* qwords, void* ws, size_t ws_bytes,
+                           void* stream) {
+  gift_status s = check_views(db);
+  if (s != GIFT_OK) return s;
+  if ((s = check_queries(q, db->dim)) != GIFT_OK) return s;
+  if ((s = check_fif(fif, db)) != GIFT_OK) return s;
+  GIFT_CHECK(scores != nullptr, GIFT_EINVAL, "null scores");
+  const hipStream_t st = (hipStream_t)stream;
+  FifWs w = carve_fif(ws, db, fif, q, 0);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
+  w.S = scores;
+  if ((s = fif_first_pass(db, fif, q, w, st)) != GIFT_OK) return s;
+  if (qwords)
+    GIFT_HIP(hipMemcpyAsync(qwords, w.qwords, (size_t)q->total_views * 4,
+                            hipMemcpyDeviceToDevice, st));
   return GIFT_OK;
 }
 

@@ -1,0 +1,595 @@
+// The first inverted file (Sec. 2.3, Eq. 4, Fig. 2): quantizer c(x) with
+// Multiple Assignment, k-means vocabulary, list construction and the list
+// scan of a query batch.
+#include "kernels.h"
+#include "mfma_tile.h"
+
+namespace gift {
+
+// ------------------------------------------------------------------ GEMM
+// D[r - r0][k] = x_r . b_k in float32 on MFMA (128 x 128 block tiles).
+__global__ __launch_bounds__(256, 2) void dots_kernel(
+    const float* __restrict__ x, int64_t r0, int64_t r1, const float* __restrict__ cb,
+    int K, int dim, float* __restrict__ D, int64_t n_col_tiles) {
+  using T = TileShape<2, 2>;
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int64_t row_tile = blockIdx.x / n_col_tiles;
+  const int64_t col_tile = blockIdx.x - row_tile * n_col_tiles;
+  const int64_t rb = r0 + row_tile * T::BM;
+  const int64_t cb0 = col_tile * T::BN;
+  const int row_bytes = dim * 4;
+  const uint8_t* src[T::LOADS];
+#pragma unroll
+  for (int it = 0; it < T::LOADS; ++it) {
+    const int r = staged_row(it);
+    const uint8_t* p = nullptr;
+    if (r < T::BM) {
+      if (rb + r < r1) p = reinterpret_cast<const uint8_t*>(x + (rb + r) * dim);
+    } else {
+      const int64_t k = cb0 + (r - T::BM);
+      if (k < K) p = reinterpret_cast<const uint8_t*>(cb + k * dim);
+    }
+    src[it] = p;
+  }
+  f32x16 acc[2][2];
+  mfma_tile_mainloop<GIFT_F32, 2, 2>(lds, src, row_bytes, acc);
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t r = rb + wr * 64 + acc_row(i, e);
+        const int64_t k = cb0 + wc * 64 + acc_col(j);
+        if (r < r1 && k < K) D[(r - r0) * K + k] = acc[i][j][e];
+      }
+}
+
+// ------------------------------------------------------------------ norms
+// ||b_k||^2 as a compensated sum, one wave per codeword.
+__global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb, int K, int dim,
+                                                    float* __restrict__ nhi, float* __restrict__ nlo) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= K) return;
+  const float* b = cb + (int64_t)k * dim;
+  float s = 0.f, c = 0.f;
+  for (int t = lane; t < dim; t += 64) dot2_step(b[t], b[t], s, c);
+  const ff v = ff_wave_sum(s, c);
+  if (lane == 0) { nhi[k] = v.hi; nlo[k] = v.lo; }
+}
+
+// ------------------------------------------------------------------ select
+// One wave per row.  d^_k = ||b_k||^2 - 2 D[k] in float32 with a per-k
+// bound e_k; U = the ma-th smallest d^_k + e_k bounds the true ma-th
+// smallest distance from above, so every k with d^_k - e_k <= U may belong
+// to the exact top-ma.  Those candidates are re-evaluated with compensated
+// arithmetic and the ma smallest (distance, index) are written.
+constexpr int SEL_CAP = 256;   // candidates kept per row
+constexpr int MAX_MA = 8;
+
+__device__ inline bool dk_less(float ah, float al, int ak, float bh, float bl, int bk) {
+  if (ah != bh) return ah < bh;
+  if (al != bl) return al < bl;
+  return ak < bk;
+}
+
+__global__ __launch_bounds__(256) void assign_select_kernel(
+    const float* __restrict__ x, int64_t r0, int64_t r1, const float* __restrict__ cb,
+    int K, int dim, int ma, const float* __restrict__ D, const float* __restrict__ nhi,
+    const float* __restrict__ nlo, float gamma2, int32_t* __restrict__ words,
+    int32_t* __restrict__ overflow) {
+  __shared__ int cand[4][SEL_CAP];
+  __shared__ float chi[4][SEL_CAP], clo[4][SEL_CAP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r_raw = r0 + (int64_t)blockIdx.x * 4 + wave;
+  // an idle wave (past the last row) redoes the last row and writes nothing,
+  // so every wave reaches the block barrier below
+  const bool active = r_raw < r1;
+  const int64_t r = active ? r_raw : r1 - 1;
+  const float* xr = x + r * dim;
+  const float* Dr = D + (r - r0) * K;
+  // ||x|| with slack for its own rounding
+  float ss = 0.f;
+  for (int t = lane; t < dim; t += 64) ss = __builtin_fmaf(xr[t], xr[t], ss);
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+  const float xn = sqrtf(ss) * 1.001f + 1e-30f;
+  const float c1 = gamma2 * xn;
+  const float c2 = 2.4e-7f;  // a few float32 roundings of d^_k itself
+
+  // lane-local ma smallest upper bounds
+  float best[MAX_MA];
+#pragma unroll
+  for (int a = 0; a < MAX_MA; ++a) best[a] = INFINITY;
+  for (int k = lane; k < K; k += 64) {
+    const float dk = nhi[k] - 2.f * Dr[k];
+    const float ek = c1 * sqrtf(fmaxf(nhi[k], 0.f)) + c2 * (fabsf(dk) + 1.f);
+    float u = dk + ek;
+#pragma unroll
+    for (int a = 0; a < MAX_MA; ++a) {
+      if (a < ma && u < best[a]) { const float t = best[a]; best[a] = u; u = t; }
+    }
+  }
+  // wave-wide ma-th smallest of the upper bounds
+  float U = INFINITY;
+  int head = 0;
+  for (int a = 0; a < ma; ++a) {
+    float v = head < ma ? best[0] : INFINITY;
+#pragma unroll
+    for (int q = 0; q < MAX_MA; ++q)
+      if (q == head) v = best[q];
+    float m = v;
+    int who = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const float om = __shfl_xor(m, o, 64);
+      const int ow = __shfl_xor(who, o, 64);
+      if (om < m || (om == m && ow < who)) { m = om; who = ow; }
+    }
+    U = m;
+    if (lane == who) ++head;
+  }
+  // candidates: d^_k - e_k <= U, in ascending k
+  int n_c = 0;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    bool f = false;
+    if (k < K) {
+      const float dk = nhi[k] - 2.f * Dr[k];
+      const float ek = c1 * sqrtf(fmaxf(nhi[k], 0.f)) + c2 * (fabsf(dk) + 1.f);
+      f = dk - ek <= U;
+    }
+    const unsigned long long bal = __ballot(f);
+    const int pos = n_c + __popcll(bal & ((1ull << lane) - 1ull));
+    if (f && pos < SEL_CAP) cand[wave][pos] = k;
+    n_c += __popcll(bal);
+  }
+  if (n_c > SEL_CAP) {
+    if (lane == 0 && active) atomicAdd(overflow, 1);
+    n_c = SEL_CAP;
+  }
+  // compensated distances of the candidates
+  for (int c = 0; c < n_c; ++c) {
+    const int k = cand[wave][c];
+    const float* bk = cb + (int64_t)k * dim;
+    float s = 0.f, cc = 0.f;
+    for (int t = lane; t < dim; t += 64) dot2_step(xr[t], bk[t], s, cc);
+    const ff dot = ff_wave_sum(s, cc);
+    const ff d = ff_add(ff{nhi[k], nlo[k]}, ff{-2.f * dot.hi, -2.f * dot.lo});
+    if (lane == 0) { chi[wave][c] = d.hi; clo[wave][c] = d.lo; }
+  }
+  __syncthreads();
+  // the ma smallest by (distance, index)
+  bool used[SEL_CAP / 64];
+#pragma unroll
+  for (int q = 0; q < SEL_CAP / 64; ++q) used[q] = false;
+  for (int a = 0; a < ma; ++a) {
+    float bh = INFINITY, bl = INFINITY;
+    int bk = 0x7fffffff, bq = -1;
+#pragma unroll
+    for (int q = 0; q < SEL_CAP / 64; ++q) {
+      const int c = q * 64 + lane;
+      if (c < n_c && !used[q]) {
+        const int k = cand[wave][c];
+        if (dk_less(chi[wave][c], clo[wave][c], k, bh, bl, bk)) {
+          bh = chi[wave][c]; bl = clo[wave][c]; bk = k; bq = q;
+        }
+      }
+    }
+    int who = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const float oh = __shfl_xor(bh, o, 64), ol = __shfl_xor(bl, o, 64);
+      const int ok = __shfl_xor(bk, o, 64), ow = __shfl_xor(who, o, 64);
+      if (dk_less(oh, ol, ok, bh, bl, bk)) { bh = oh; bl = ol; bk = ok; who = ow; }
+    }
+    if (lane == who && bq >= 0) {
+#pragma unroll
+      for (int q = 0; q < SEL_CAP / 64; ++q)
+        if (q == bq) used[q] = true;
+    }
+    if (lane == 0 && active) words[r * ma + a] = bk < K ? bk : -1;
+  }
+}
+
+gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, int K, int ma,
+                          int32_t* words, float* D, int64_t chunk_rows, float* nhi, float* nlo,
+                          int32_t* overflow, hipStream_t st) {
+  if (n <= 0) return GIFT_OK;
+  hipLaunchKernelGGL(norms_kernel, dim3((K + 3) / 4), dim3(256), 0, st, cb, K, dim, nhi, nlo);
+  GIFT_LAUNCHED();
+  using T = TileShape<2, 2>;
+  static bool attr = false;
+  if (!attr) {
+    GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(dots_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)T::LDS_BYTES));
+    attr = true;
+  }
+  // accumulation depth of the MFMA dot: dim/2 steps, charged 2 roundings each
+  const double u = 5.9604644775390625e-08, nn = 2.0 * dim + 4;
+  const float gamma2 = (float)(2.0 * (nn * u / (1 - nn * u)) * 1.001);
+  const int64_t n_col_tiles = (K + T::BN - 1) / T::BN;
+  for (int64_t r0 = 0; r0 < n; r0 += chunk_rows) {
+    const int64_t r1 = r0 + chunk_rows < n ? r0 + chunk_rows : n;
+    const int64_t n_row_tiles = (r1 - r0 + T::BM - 1) / T::BM;
+    hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(n_row_tiles * n_col_tiles)), dim3(256),
+                       T::LDS_BYTES, st, x, r0, r1, cb, K, dim, D, n_col_tiles);
+    GIFT_LAUNCHED();
+    hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)((r1 - r0 + 3) / 4)), dim3(256), 0, st,
+                       x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow);
+    GIFT_LAUNCHED();
+  }
+  return GIFT_OK;
+}
+
+// ------------------------------------------------------------------ bucket sort
+// Stable counting sort of items 0..n-1 by key in [0, K): per-block key
+// histograms, a scan over blocks per key, a scan over keys, and an in-order
+// scatter by one thread per block.  Items of one key end up in ascending
+// item order.  K <= 16384.
+constexpr int BK_ITEMS = 4096;
+
+__global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* __restrict__ keys,
+                                                           int64_t n, int K, int nb,
+                                                           int32_t* __restrict__ hist) {
+  extern __shared__ int cnt[];
+  for (int k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * BK_ITEMS;
+  for (int i = threadIdx.x; i < BK_ITEMS; i += 256) {
+    const int64_t g = i0 + i;
+    if (g < n) {
+      const int k = keys[g];
+      if (k >= 0 && k < K) atomicAdd(&cnt[k], 1);  // out-of-range keys are dropped
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += 256) hist[(int64_t)k * nb + blockIdx.x] = cnt[k];
+}
+
+// hist[k][b] := exclusive prefix over b; totals[k] = row sum.
+__global__ __launch_bounds__(256) void bucket_scan_blocks_kernel(int32_t* __restrict__ hist,
+                                                                 int K, int nb,
+                                                                 int64_t* __restrict__ totals) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= K) return;
+  int32_t* h = hist + (int64_t)k * nb;
+  int64_t run = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int32_t v = h[b];
+    h[b] = (int32_t)run;
+    run += v;
+  }
+  totals[k] = run;
+}
+
+// off[0] = 0, off[k+1] = off[k] + vals[k] (single block).
+__global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int64_t* __restrict__ vals,
+                                                              int K, int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  const int per = (K + 1023) / 1024;
+  const int k0 = threadIdx.x * per;
+  int64_t s = 0;
+  for (int k = k0; k < k0 + per && k < K; ++k) s += vals[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int k = k0; k < k0 + per && k < K; ++k) {
+    off[k] = run;
+    run += vals[k];
+  }
+  if (threadIdx.x == 1023) off[K] = part[1023];
+}
+
+// In-order scatter; `mode` selects what is written per item:
+//   0: out_a[pos] = item
+//   1: F-IF entries, item e = v * ma + a: out_a = v / n_views (shape),
+//      out_b = v % n_views (view)
+__global__ __launch_bounds__(64) void bucket_scatter_kernel(
+    const int32_t* __restrict__ keys, int64_t n, int K, int nb, const int32_t* __restrict__ hist,
+    const int64_t* __restrict__ off, int mode, int ma, int n_views,
+    int32_t* __restrict__ out_a, int32_t* __restrict__ out_b) {
+  extern __shared__ int32_t pos[];
+  for (int k = threadIdx.x; k < K; k += 64) pos[k] = (int32_t)(off[k] + hist[(int64_t)k * nb + blockIdx.x]);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int64_t i0 = (int64_t)blockIdx.x * BK_ITEMS;
+  const int64_t i1 = i0 + BK_ITEMS < n ? i0 + BK_ITEMS : n;
+  for (int64_t i = i0; i < i1; ++i) {
+    const int k = keys[i];
+    if (k < 0 || k >= K) continue;
+    const int64_t p = pos[k]++;  // < n < 2^31
+    if (mode == 0) {
+      out_a[p] = (int32_t)i;
+    } else {
+      const int64_t v = i / ma;
+      out_a[p] = (int32_t)(v / n_views);
+      out_b[p] = (int32_t)(v % n_views);
+    }
+  }
+}
+
+size_t bucket_sort_ws(int64_t n, int K) {
+  const int64_t nb = (n + BK_ITEMS - 1) / BK_ITEMS;
+  return ((size_t)nb * K * 4 + 255) / 256 * 256 + ((size_t)K * 8 + 255) / 256 * 256;
+}
+
+gift_status launch_bucket_sort(const int32_t* keys, int64_t n, int K, int64_t* off,
+                               int mode, int ma, int n_views, int32_t* out_a, int32_t* out_b,
+                               void* ws, hipStream_t st) {
+  GIFT_CHECK(K >= 1 && K <= 16384, GIFT_EUNSUPPORTED, "K must be in 1..16384");
+  const int64_t nb64 = (n + BK_ITEMS - 1) / BK_ITEMS;
+  GIFT_CHECK(n < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many items");
+  const int nb = (int)(nb64 > 0 ? nb64 : 1);
+  int32_t* hist = static_cast<int32_t*>(ws);
+  int64_t* totals = reinterpret_cast<int64_t*>(static_cast<char*>(ws) +
+                                               ((size_t)nb * K * 4 + 255) / 256 * 256);
+  if (n > 0) {
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(nb), dim3(256), (size_t)K * 4, st, keys, n, K,
+                       nb, hist);
+    GIFT_LAUNCHED();
+  } else {
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(1), dim3(256), (size_t)K * 4, st, keys, 0, K, 1,
+                       hist);
+    GIFT_LAUNCHED();
+  }
+  hipLaunchKernelGGL(bucket_scan_blocks_kernel, dim3((K + 255) / 256), dim3(256), 0, st, hist, K,
+                     nb, totals);
+  GIFT_LAUNCHED();
+  hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, st, totals, K, off);
+  GIFT_LAUNCHED();
+  if (n > 0) {
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(64), (size_t)K * 4, st, keys, n, K,
+                       nb, hist, off, mode, ma, n_views, out_a, out_b);
+    GIFT_LAUNCHED();
+  }
+  return GIFT_OK;
+}
+
+// ------------------------------------------------------------------ k-means
+__global__ __launch_bounds__(256) void gather_rows_kernel(const float* __restrict__ x,
+                                                          const int64_t* __restrict__ idx,
+                                                          int K, int dim, float* __restrict__ out) {
+  const int k = blockIdx.y;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < dim; t += gridDim.x * 256)
+    out[(int64_t)k * dim + t] = x[idx[k] * dim + t];
+}
+
+// Centroid = float64 sum of the members in ascending row order, divided in
+// float64, rounded once to float32; an empty cluster keeps its centroid.
+__global__ __launch_bounds__(256) void centroid_kernel(const float* __restrict__ x, int dim,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ members,
+                                                       const float* __restrict__ old_cb,
+                                                       float* __restrict__ new_cb) {
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= dim) return;
+  const int64_t m0 = off[k], m1 = off[k + 1];
+  float out;
+  if (m1 == m0) {
+    out = old_cb[(int64_t)k * dim + t];
+  } else {
+    double s = 0.0;
+    for (int64_t m = m0; m < m1; ++m) s = s + (double)x[(int64_t)members[m] * dim + t];
+    out = (float)(s / (double)(m1 - m0));
+  }
+  new_cb[(int64_t)k * dim + t] = out;
+}
+
+__global__ __launch_bounds__(256) void count_changes_kernel(const int32_t* __restrict__ a,
+                                                            const int32_t* __restrict__ b,
+                                                            int64_t n, int32_t* __restrict__ cnt) {
+  __shared__ int part[4];
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    c += a[i] != b[i];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = part[0] + part[1] + part[2] + part[3];
+    if (tot) atomicAdd(cnt, tot);
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+void launch_gather_rows(const float* x, const int64_t* idx, int K, int dim, float* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((dim + 255) / 256, K), dim3(256), 0, st, x, idx,
+                     K, dim, out);
+}
+
+void launch_centroids(const float* x, int dim, int K, const int64_t* off, const int32_t* members,
+                      const float* old_cb, float* new_cb, hipStream_t st) {
+  hipLaunchKernelGGL(centroid_kernel, dim3((dim + 255) / 256, K), dim3(256), 0, st, x, dim, off,
+                     members, old_cb, new_cb);
+}
+
+void launch_count_changes(const int32_t* a, const int32_t* b, int64_t n, int32_t* cnt,
+                          hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(count_changes_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256),
+                     0, st, a, b, n, cnt);
+}
+
+// ------------------------------------------------------------------ list scan
+// tile_off[w+1] - tile_off[w] = ceil(|L_w| / 128) list tiles (single block).
+__global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restrict__ off, int K,
+                                                          int64_t* __restrict__ tcount) {
+  for (int w = threadIdx.x; w < K; w += 1024) tcount[w] = (off[w + 1] - off[w] + 127) / 128;
+}
+
+// One block per list tile of 128 entries and the batch's query views whose
+// word is that list: MFMA dots (entries x query views), the per-shape
+// maximum over the tile's entries (entries of a shape are contiguous), and
+// an atomic max into mbuf[shape][query view] (0 = no matching view yet).
+template <int DT>
+__global__ __launch_bounds__(256, 2) void fif_scan_kernel(
+    const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
+    int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
+    const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
+    const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
+    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    uint32_t* __restrict__ mbuf, int64_t ldm) {
+  using T = TileShape<2, 2>;
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int64_t b = blockIdx.x;
+  if (b >= tile_off[K]) return;
+  // list w with tile_off[w] <= b < tile_off[w+1]
+  int lo = 0, hi = K;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  const int w = lo;
+  const int64_t g0 = goff[w], g1 = goff[w + 1];
+  if (g0 == g1) return;
+  const int64_t e0 = loff[w] + (b - tile_off[w]) * T::BM;
+  const int64_t e1 = e0 + T::BM < loff[w + 1] ? e0 + T::BM : loff[w + 1];
+  const int ne = (int)(e1 - e0);
+  float* C = reinterpret_cast<float*>(lds);  // [128][129] after the main loop
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  for (int64_t c0 = g0; c0 < g1; c0 += T::BN) {
+    const uint8_t* src[T::LOADS];
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int r = staged_row(it);
+      const uint8_t* p = nullptr;
+      if (r < T::BM) {
+        if (r < ne) {
+          const int64_t e = e0 + r;
+          p = db + ((int64_t)ent_shape[e] * n_views + ent_view[e]) * (int64_t)row_bytes;
+        }
+      } else {
+        const int64_t c = c0 + (r - T::BM);
+        if (c < g1) p = qv + (int64_t)gitems[c] * row_bytes;
+      }
+      src[it] = p;
+    }
+    f32x16 acc[2][2];
+    mfma_tile_mainloop<DT, 2, 2>(lds, src, row_bytes, acc);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int r = wr * 64 + acc_row(i, e);
+          const int c = wc * 64 + acc_col(j);
+          float v = acc[i][j][e];
+          if (DT != GIFT_F32 && r < ne) {
+            const int64_t en = e0 + r;
+            v *= db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
+          }
+          C[r * 129 + c] = v;
+        }
+    __syncthreads();
+    {
+      const int c = threadIdx.x & 127;
+      const int half = threadIdx.x >> 7;
+      const int64_t cg = c0 + c;
+      if (cg < g1) {
+        const int qi = gitems[cg];
+        const float cs = DT != GIFT_F32 ? q_scale[qi] : 1.f;
+        const int rbeg = half * 64;
+        const int rend = rbeg + 64 < ne ? rbeg + 64 : ne;
+        int cur = -1;
+        float m = -INFINITY;
+        for (int r = rbeg; r < rend; ++r) {
+          const int shp = ent_shape[e0 + r];
+          if (shp != cur) {
+            if (cur >= 0) atomicMax(&mbuf[(int64_t)cur * ldm + qi], float_order(m * cs));
+            cur = shp;
+            m = -INFINITY;
+          }
+          m = fmaxf(m, C[r * 129 + c]);
+        }
+        if (cur >= 0) atomicMax(&mbuf[(int64_t)cur * ldm + qi], float_order(m * cs));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int32_t* ent_shape,
+                            const int32_t* ent_view, int64_t n_entries, int K,
+                            int64_t* tile_off, int64_t* tcount, const int64_t* goff,
+                            const int32_t* gitems, const void* qv, const float* qscale,
+                            uint32_t* mbuf, int64_t ldm, hipStream_t st) {
+  hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tcount);
+  GIFT_LAUNCHED();
+  hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, st, tcount, K, tile_off);
+  GIFT_LAUNCHED();
+  const int64_t bound = n_entries / 128 + K + 1;
+  GIFT_CHECK(bound < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many list tiles");
+  const size_t shmem = 128 * 129 * 4;
+  const int row_bytes = db->dim * elem_bytes(db->dtype);
+#define GIFT_SCAN_LAUNCH(DTV)                                                                  \
+  do {                                                                                         \
+    static bool attr = false;                                                                  \
+    if (!attr) {                                                                               \
+      GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fif_scan_kernel<DTV>),        \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));   \
+      attr = true;                                                                             \
+    }                                                                                          \
+    hipLaunchKernelGGL(fif_scan_kernel<DTV>, dim3((unsigned)bound), dim3(256), shmem, st,      \
+                       static_cast<const uint8_t*>(db->data), db->scale, db->n_views,          \
+                       row_bytes, loff, ent_shape, ent_view, tile_off, K, goff, gitems,        \
+                       static_cast<const uint8_t*>(qv), qscale, mbuf, ldm);                    \
+  } while (0)
+  switch (db->dtype) {
+    case GIFT_F32: GIFT_SCAN_LAUNCH(GIFT_F32); break;
+    case GIFT_BF16: GIFT_SCAN_LAUNCH(GIFT_BF16); break;
+    default: GIFT_SCAN_LAUNCH(GIFT_FP8E4M3); break;
+  }
+#undef GIFT_SCAN_LAUNCH
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
+// S[b][p] = (sum over the query's views of the decoded max, 0 where no view
+// of p shares the word) / m, summed in ascending view order.
+__global__ __launch_bounds__(256) void reduce_fif_kernel(const uint32_t* __restrict__ mbuf,
+                                                         int64_t ldm, int64_t n_shapes,
+                                                         const int32_t* __restrict__ qoff,
+                                                         float* __restrict__ S) {
+  const int b = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_shapes) return;
+  const int lo = qoff[b], hi = qoff[b + 1];
+  const uint32_t* row = mbuf + p * ldm;
+  float acc = 0.f;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t u = row[i];
+    if (u != 0u) acc += order_float(u);
+  }
+  S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
+}
+
+void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
+                       int n_queries, float* S, hipStream_t st) {
+  if (n_shapes <= 0 || n_queries <= 0) return;
+  dim3 grid((unsigned)((n_shapes + 255) / 256), (unsigned)n_queries);
+  hipLaunchKernelGGL(reduce_fif_kernel, grid, dim3(256), 0, st, mbuf, ldm, n_shapes, qoff, S);
+}
+
+}  // namespace gift

@@ -28,17 +28,49 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r,
 // Exact rescore of candidates: float32 dot products with a known error
 // bound, then a compensated re-evaluation of every view pair that float32
 // rounding could make the maximum.  Writes the float-float score.
+// With qwords != nullptr only pairs whose words match take part (Eq. 4).
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int max_m, const int32_t* cand, int r, float dot_err,
+                    const int32_t* qwords, const int32_t* view_words, int ma,
                     float* s_hi, float* s_lo, hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
 // id asc) and writes the top k; sets flags bit 0 when provably complete.
+// flags bit 1 is set when *overflow != 0 (a quantizer decision could not
+// be certified); bit 0 then stays clear.
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
                        int r, int k, int64_t n_total, float first_err,
-                       int32_t* ids, float* scores, int32_t* flags,
-                       hipStream_t st);
+                       const int32_t* overflow, int32_t* ids, float* scores,
+                       int32_t* flags, hipStream_t st);
+
+// ---- first inverted file
+// words[r][a] = the a-th nearest codeword of row r (certified, ties to the
+// lower index).  D holds chunk_rows x K floats; nhi/nlo K floats each;
+// *overflow is incremented when a row has more than 256 candidates.
+gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, int K, int ma,
+                          int32_t* words, float* D, int64_t chunk_rows, float* nhi, float* nlo,
+                          int32_t* overflow, hipStream_t st);
+size_t bucket_sort_ws(int64_t n, int K);
+// Stable counting sort of items by key; off [K+1].  mode 0 writes item
+// indices to out_a; mode 1 writes F-IF (shape, view) of item e = v*ma + a.
+gift_status launch_bucket_sort(const int32_t* keys, int64_t n, int K, int64_t* off,
+                               int mode, int ma, int n_views, int32_t* out_a, int32_t* out_b,
+                               void* ws, hipStream_t st);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_gather_rows(const float* x, const int64_t* idx, int K, int dim, float* out,
+                        hipStream_t st);
+void launch_centroids(const float* x, int dim, int K, const int64_t* off, const int32_t* members,
+                      const float* old_cb, float* new_cb, hipStream_t st);
+void launch_count_changes(const int32_t* a, const int32_t* b, int64_t n, int32_t* cnt,
+                          hipStream_t st);
+gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int32_t* ent_shape,
+                            const int32_t* ent_view, int64_t n_entries, int K,
+                            int64_t* tile_off, int64_t* tcount, const int64_t* goff,
+                            const int32_t* gitems, const void* qv, const float* qscale,
+                            uint32_t* mbuf, int64_t ldm, hipStream_t st);
+void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
+                       int n_queries, float* S, hipStream_t st);
 
 }  // namespace gift

@@ -1,0 +1,151 @@
+// MFMA main loop shared by the scoring, quantizer and list-scan kernels.
+//
+// A block of 256 threads (4 waves as 2 x 2) computes a BM x BN tile of
+// dot products rows . cols over `row_bytes` bytes per row, BM = 64*WM and
+// BN = 64*WN, each wave owning WM x WN blocks of 32 x 32.  The caller gives,
+// for every 16-byte piece this thread stages, the source row pointer
+// (nullptr reads zeros); rows 0..BM-1 are the A side, BM..BM+BN-1 the B side.
+//
+// K is staged through LDS 128 bytes of each row at a time (32 f32, 64 bf16
+// or 128 e4m3 values).  In a K-tile, lane half h reads bytes [64h, 64h + 64)
+// of its row as four 16-byte pieces.  The MFMA sums over whatever k each
+// (lane half, slot) supplies and A and B use the same assignment, so this
+// permutation of K leaves every dot product unchanged.
+//
+// Output layout (all 32x32 MFMAs): lane l holds column l % 32 of each block
+// and rows 8*(e/4) + 4*(l/32) + (e%4) for accumulator element e.
+#pragma once
+
+#include "common.h"
+
+namespace gift {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int LROW = 144;  // LDS bytes per staged row: 128 + 16 pad
+
+template <int DT>
+struct Mfma;
+
+template <>
+struct Mfma<GIFT_F32> {
+  // 16 steps of 32x32x2 per K-tile.
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].x), __builtin_bit_cast(float, b[s].x), c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].y), __builtin_bit_cast(float, b[s].y), c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].z), __builtin_bit_cast(float, b[s].z), c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].w), __builtin_bit_cast(float, b[s].w), c, 0, 0, 0);
+    }
+  }
+};
+
+template <>
+struct Mfma<GIFT_BF16> {
+  // 4 steps of 32x32x16 per K-tile.
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]), __builtin_bit_cast(bf16x8, b[s]), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<GIFT_FP8E4M3> {
+  // 2 steps of 32x32x64 (e4m3 x e4m3, unit block scales) per K-tile.
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 av = {(int)a[2 * s].x, (int)a[2 * s].y, (int)a[2 * s].z, (int)a[2 * s].w,
+                  (int)a[2 * s + 1].x, (int)a[2 * s + 1].y, (int)a[2 * s + 1].z, (int)a[2 * s + 1].w};
+      i32x8 bv = {(int)b[2 * s].x, (int)b[2 * s].y, (int)b[2 * s].z, (int)b[2 * s].w,
+                  (int)b[2 * s + 1].x, (int)b[2 * s + 1].y, (int)b[2 * s + 1].z, (int)b[2 * s + 1].w};
+      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+    }
+  }
+};
+
+template <int WM, int WN>
+struct TileShape {
+  static constexpr int BM = 2 * WM * 32;
+  static constexpr int BN = 2 * WN * 32;
+  static constexpr int ROWS = BM + BN;
+  static constexpr int LOADS = ROWS * 8 / 256;  // 16-byte pieces per thread per K-tile
+  static constexpr size_t LDS_BYTES = (size_t)ROWS * LROW;
+};
+
+// Staged row of the piece `it` of this thread.
+__device__ __forceinline__ int staged_row(int it) { return (threadIdx.x + 256 * it) >> 3; }
+
+template <int DT, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_mainloop(
+    uint8_t* lds, const uint8_t* const (&src)[TileShape<WM, WN>::LOADS], int row_bytes,
+    f32x16 (&acc)[WM][WN]) {
+  using T = TileShape<WM, WN>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5, l32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int n_kt = (row_bytes + 127) / 128;
+  uint4 pre[T::LOADS];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
+      if (src[it] != nullptr && off < row_bytes)
+        pre[it] = *reinterpret_cast<const uint4*>(src[it] + off);
+      else
+        pre[it] = make_uint4(0, 0, 0, 0);
+    }
+  };
+  gload(0);
+  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 64;
+  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + half * 64;
+  for (int kt = 0; kt < n_kt; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int idx = tid + 256 * it;
+      *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[it];
+    }
+    __syncthreads();
+    if (kt + 1 < n_kt) gload(kt + 1);
+    uint4 b[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * 16);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      uint4 a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * 16);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) Mfma<DT>::run(a, b[j], acc[i][j]);
+    }
+  }
+  __syncthreads();  // LDS may be reused by the caller's epilogue
+}
+
+// Row (within the wave's WM*32 rows) and column of accumulator element e of
+// block (i, j) held by this lane.
+__device__ __forceinline__ int acc_row(int i, int e) {
+  return i * 32 + 8 * (e >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (e & 3);
+}
+__device__ __forceinline__ int acc_col(int j) { return j * 32 + (threadIdx.x & 31); }
+
+}  // namespace gift

@@ -139,10 +139,14 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r,
 // views, summed in ascending view order.
 constexpr int RS_LROW = 36;  // floats per LDS row (32 + 4 pad)
 
+// With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
+// word of q_i is one of the `ma` words of p_j, and a query view with no such
+// pair contributes 0.
 __global__ __launch_bounds__(256) void rescore_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     const int32_t* __restrict__ cand, int r, float dot_err,
+    const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
     float* __restrict__ s_hi, float* __restrict__ s_lo) {
   __shared__ float qs[64 * RS_LROW];
   __shared__ float ps[64 * RS_LROW];
@@ -213,15 +217,30 @@ __global__ __launch_bounds__(256) void rescore_kernel(
     // row maxima over valid database views, then the near-maximum masks
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
+      const int i = 4 * ti + x;
+      int wq = -1;
+      if (qwords != nullptr && i < mi) wq = qwords[q0 + it * 64 + i];
+      bool ok[4];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int j = 4 * tj + y;
+        ok[y] = j < n_views;
+        if (ok[y] && qwords != nullptr) {
+          const int32_t* vw = view_words + (shape * n_views + j) * (int64_t)ma;
+          bool hit = false;
+          for (int a = 0; a < ma; ++a) hit |= vw[a] == wq;
+          ok[y] = hit;
+        }
+      }
       float mx = -INFINITY;
 #pragma unroll
       for (int y = 0; y < 4; ++y)
-        if (4 * tj + y < n_views) mx = fmaxf(mx, tot[x][y]);
+        if (ok[y]) mx = fmaxf(mx, tot[x][y]);
       for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
       unsigned long long bits = 0;
 #pragma unroll
       for (int y = 0; y < 4; ++y)
-        if (4 * tj + y < n_views && tot[x][y] >= mx - 2.f * dot_err)
+        if (ok[y] && tot[x][y] >= mx - 2.f * dot_err)
           bits |= 1ull << (4 * tj + y);
       for (int o = 8; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
       if (tj == 0) { rowmax[4 * ti + x] = mx; jmask[4 * ti + x] = bits; }
@@ -241,6 +260,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(
         const ff v = ff_wave_sum(s, c);
         if (ff_gt(v, best)) best = v;
       }
+      if (best.hi == -INFINITY) best = ff{0.f, 0.f};  // no matching view
       if (lane == 0) { mff_hi[i] = best.hi; mff_lo[i] = best.lo; }
     }
     __syncthreads();
@@ -263,13 +283,14 @@ __global__ __launch_bounds__(256) void rescore_kernel(
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int max_m, const int32_t* cand, int r, float dot_err,
+                    const int32_t* qwords, const int32_t* view_words, int ma,
                     float* s_hi, float* s_lo, hipStream_t st) {
   (void)max_m;
   const int64_t blocks = (int64_t)n_queries * r;
   if (blocks <= 0) return;
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                      master, n_views, dim, qviews, qoff, cand, r, dot_err,
-                     s_hi, s_lo);
+                     qwords, view_words, ma, s_hi, s_lo);
 }
 
 // ------------------------------------------------------------------ final
@@ -287,8 +308,8 @@ __device__ inline bool cand_before(const Cand& a, const Cand& b) {
 __global__ __launch_bounds__(256) void final_rank_kernel(
     const int32_t* __restrict__ cand, const float* __restrict__ first_s,
     const float* __restrict__ s_hi, const float* __restrict__ s_lo, int r,
-    int k, int64_t n_total, float first_err, int32_t* __restrict__ ids,
-    float* __restrict__ scores, int32_t* __restrict__ flags) {
+    int k, int64_t n_total, float first_err, const int32_t* __restrict__ overflow,
+    int32_t* __restrict__ ids, float* __restrict__ scores, int32_t* __restrict__ flags) {
   __shared__ Cand c[MAX_R];
   const int b = blockIdx.x;
   const int64_t base = (int64_t)b * r;
@@ -327,19 +348,20 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
       const float bound = first_s[base + r - 1] + first_err;
       complete = bound < kth - fabsf(kth) * 2.4e-7f;
     }
-    flags[b] = complete ? 1 : 0;
+    const bool ovf = overflow != nullptr && *overflow != 0;
+    flags[b] = (complete && !ovf ? 1 : 0) | (ovf ? 2 : 0);
   }
 }
 
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
                        int r, int k, int64_t n_total, float first_err,
-                       int32_t* ids, float* scores, int32_t* flags,
-                       hipStream_t st) {
+                       const int32_t* overflow, int32_t* ids, float* scores,
+                       int32_t* flags, hipStream_t st) {
   if (n_queries <= 0) return;
   hipLaunchKernelGGL(final_rank_kernel, dim3(n_queries), dim3(256), 0, st,
-                     cand, first_s, s_hi, s_lo, r, k, n_total, first_err, ids,
-                     scores, flags);
+                     cand, first_s, s_hi, s_lo, r, k, n_total, first_err, overflow,
+                     ids, scores, flags);
 }
 
 }  // namespace gift

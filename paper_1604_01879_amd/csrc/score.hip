@@ -2,12 +2,9 @@
 // for every query view, in float32, bfloat16 or e4m3 storage; plus the
 // per-view reduced-precision quantizer and the per-query mean.
 #include "kernels.h"
+#include "mfma_tile.h"
 
 namespace gift {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ quantize
 __device__ inline uint16_t bf16_rne(float y) {
@@ -65,63 +62,10 @@ void launch_quantize(const float* src, int64_t n, int dim, int dtype,
 }
 
 // ------------------------------------------------------------------ MFMA tile
-// Block tile: BM database rows x BN query views, 4 waves as 2 x 2, each wave
-// WM x WN blocks of 32 x 32.  Database rows are laid out 64 per shape (views
-// beyond n_views are masked), so a wave's WM*32 rows hold WM/2 whole shapes
-// and the per-shape max is taken inside the wave.
-//
-// K is staged through LDS 128 bytes of each row at a time (32 f32, 64 bf16 or
-// 128 e4m3 values).  In a K-tile, lane half h (lanes 32h..32h+31) reads the
-// bytes [64h, 64h + 64) of its row as four 16-byte pieces.  The MFMA sums
-// over whatever k each (lane half, slot) supplies, and A and B use the same
-// assignment, so this permutation of K leaves every dot product unchanged.
-constexpr int LROW = 144;  // LDS bytes per staged row: 128 + 16 pad
-
-template <int DT>
-struct Mfma;
-
-template <>
-struct Mfma<GIFT_F32> {
-  // 16 steps of 32x32x2 per K-tile.
-  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].x), __builtin_bit_cast(float, b[s].x), c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].y), __builtin_bit_cast(float, b[s].y), c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].z), __builtin_bit_cast(float, b[s].z), c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].w), __builtin_bit_cast(float, b[s].w), c, 0, 0, 0);
-    }
-  }
-  static constexpr int kstep = 2;  // values summed per accumulation step
-};
-
-template <>
-struct Mfma<GIFT_BF16> {
-  // 4 steps of 32x32x16 per K-tile.
-  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]), __builtin_bit_cast(bf16x8, b[s]), c, 0, 0, 0);
-  }
-  static constexpr int kstep = 16;
-};
-
-template <>
-struct Mfma<GIFT_FP8E4M3> {
-  // 2 steps of 32x32x64 (e4m3 x e4m3, unit block scales) per K-tile.
-  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      i32x8 av = {(int)a[2 * s].x, (int)a[2 * s].y, (int)a[2 * s].z, (int)a[2 * s].w,
-                  (int)a[2 * s + 1].x, (int)a[2 * s + 1].y, (int)a[2 * s + 1].z, (int)a[2 * s + 1].w};
-      i32x8 bv = {(int)b[2 * s].x, (int)b[2 * s].y, (int)b[2 * s].z, (int)b[2 * s].w,
-                  (int)b[2 * s + 1].x, (int)b[2 * s + 1].y, (int)b[2 * s + 1].z, (int)b[2 * s + 1].w};
-      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
-    }
-  }
-  static constexpr int kstep = 64;
-};
-
+// Database rows are laid out 64 per shape (views beyond n_views read zeros
+// and are masked), so a wave's WM*32 rows hold WM/2 whole shapes and the
+// per-shape max is taken inside the wave: each lane folds its 32 row values,
+// then the two lane halves are combined with one shuffle.
 template <int DT, int WM, int WN>
 __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     const uint8_t* __restrict__ db, const float* __restrict__ db_scale,
@@ -129,11 +73,8 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
     int64_t total_q, float* __restrict__ mbuf, int64_t ldm,
     int64_t n_row_tiles, int64_t n_col_tiles) {
-  constexpr int BM = 2 * WM * 32;
-  constexpr int BN = 2 * WN * 32;
-  constexpr int ROWS = BM + BN;
-  constexpr int LOADS = ROWS * 8 / 256;  // 16-byte pieces per thread per K-tile
-  constexpr int SHAPES_PER_BLOCK = BM / 64;
+  using T = TileShape<WM, WN>;
+  constexpr int SHAPES_PER_BLOCK = T::BM / 64;
   static_assert(WM % 2 == 0, "a wave must hold whole shapes");
   extern __shared__ __align__(16) uint8_t lds[];
 
@@ -155,81 +96,28 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   const int wr = wave >> 1, wc = wave & 1;
   const int half = lane >> 5, l32 = lane & 31;
   const int64_t shape0 = row_tile * SHAPES_PER_BLOCK;
-  const int64_t col0 = col_tile * BN;
+  const int64_t col0 = col_tile * T::BN;
 
-  // Source pointer of each staged row handled by this thread (nullptr = zero).
-  const uint8_t* src[LOADS];
-  int piece[LOADS];
+  const uint8_t* src[T::LOADS];
 #pragma unroll
-  for (int it = 0; it < LOADS; ++it) {
-    const int idx = tid + 256 * it;
-    const int r = idx >> 3;
-    piece[it] = idx & 7;
+  for (int it = 0; it < T::LOADS; ++it) {
+    const int r = staged_row(it);
     const uint8_t* p = nullptr;
-    if (r < BM) {
+    if (r < T::BM) {
       const int64_t shp = shape0 + (r >> 6);
       const int v = r & 63;
       if (shp < n_shapes && v < n_views) p = db + (shp * n_views + v) * (int64_t)row_bytes;
     } else {
-      const int64_t c = col0 + (r - BM);
+      const int64_t c = col0 + (r - T::BM);
       if (c < total_q) p = qv + c * (int64_t)row_bytes;
     }
     src[it] = p;
   }
-
   f32x16 acc[WM][WN];
-#pragma unroll
-  for (int i = 0; i < WM; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  mfma_tile_mainloop<DT, WM, WN>(lds, src, row_bytes, acc);
 
-  const int n_kt = (row_bytes + 127) / 128;
-  uint4 pre[LOADS];
-  auto gload = [&](int kt) {
-#pragma unroll
-    for (int it = 0; it < LOADS; ++it) {
-      const int off = kt * 128 + piece[it] * 16;
-      if (src[it] != nullptr && off < row_bytes)
-        pre[it] = *reinterpret_cast<const uint4*>(src[it] + off);
-      else
-        pre[it] = make_uint4(0, 0, 0, 0);
-    }
-  };
-  gload(0);
-  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 64;
-  const uint8_t* brow = lds + (BM + wc * WN * 32 + l32) * LROW + half * 64;
-  for (int kt = 0; kt < n_kt; ++kt) {
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < LOADS; ++it) {
-      const int idx = tid + 256 * it;
-      *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[it];
-    }
-    __syncthreads();
-    if (kt + 1 < n_kt) gload(kt + 1);
-    uint4 b[WN][4];
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * 16);
-#pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      uint4 a[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * 16);
-#pragma unroll
-      for (int j = 0; j < WN; ++j) Mfma<DT>::run(a, b[j], acc[i][j]);
-    }
-  }
-
-  // Epilogue: lane holds column l32 of each 32x32 block and rows
-  // 8*(e/4) + 4*half + (e%4) of it.  Max over the shape's valid views,
-  // scales applied per pair (row scale before the max, the positive column
-  // scale after it), then combine the two lane halves.
+  // Epilogue: max over the shape's valid views, the row scale applied
+  // before the max and the positive column scale after it.
 #pragma unroll
   for (int s = 0; s < WM / 2; ++s) {
     const int64_t shp = shape0 + wr * (WM / 2) + s;
@@ -240,7 +128,7 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int v = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+          const int v = acc_row(bi, e);
           rs[bi][e] = (shape_ok && v < n_views) ? db_scale[shp * n_views + v] : 0.f;
         }
     }
@@ -251,7 +139,7 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int v = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+          const int v = acc_row(bi, e);
           float x = acc[2 * s + bi][j][e];
           if (DT != GIFT_F32) x *= rs[bi][e];
           if (v < n_views) m = fmaxf(m, x);
@@ -270,13 +158,13 @@ template <int DT, int WM, int WN>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
                                 const float* qscale, int64_t total_q,
                                 float* mbuf, int64_t ldm, hipStream_t st) {
-  constexpr int BM = 2 * WM * 32, BN = 2 * WN * 32;
+  constexpr int BM = TileShape<WM, WN>::BM, BN = TileShape<WM, WN>::BN;
   const int row_bytes = db->dim * elem_bytes(DT);
   const int64_t n_row_tiles = (db->n_shapes + BM / 64 - 1) / (BM / 64);
   const int64_t n_col_tiles = (total_q + BN - 1) / BN;
   const int64_t blocks = n_row_tiles * n_col_tiles;
   GIFT_CHECK(blocks < (int64_t)1 << 31, GIFT_ECAPACITY, "score grid too large");
-  const size_t shmem = (size_t)(BM + BN) * LROW;
+  const size_t shmem = TileShape<WM, WN>::LDS_BYTES;
   auto kern = score_tiles_kernel<DT, WM, WN>;
   static bool attr_set = false;
   if (!attr_set) {
