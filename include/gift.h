@@ -216,6 +216,44 @@ gift_status gift_score_fif(const gift_views* db, const gift_fif* fif,
                            void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* The second inverted file (Sec. 2.4, Eq. 7, Fig. 3).  Input: for every   */
+/* database shape p its neighbour list nbr_ids / nbr_scores [N][k1] (the   */
+/* shape's top-k1 by Eq. 3 or Eq. 4, itself included; ids < 0 are padding) */
+/* which defines the sparse activation F_p[i] = S(x_p, x_i) for i in the   */
+/* list.  Output: l1 [N][2] = ||F_p||_1 as an unevaluated float pair       */
+/* hi + lo (the sigma-count that Eq. 14 pre-computes offline), and the     */
+/* postings in CSR by coordinate: post_off [N+1]; entry i lists, in        */
+/* ascending p, every shape p with a non-zero membership F_p[i] as         */
+/* (post_id = p, post_val = F_p[i]); post_id / post_val need room for N*k1 */
+/* entries, post_off[N] is the count used.                                */
+/* ---------------------------------------------------------------------- */
+size_t gift_build_sif_workspace(int64_t n_shapes);
+gift_status gift_build_sif(int64_t n_shapes, int32_t k1, const int32_t* nbr_ids,
+                           const float* nbr_scores, float* l1, int64_t* post_off,
+                           int32_t* post_id, float* post_val, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Re-ranking by Eq. 8 evaluated through the S-IF (Eq. 13 and 14):        */
+/*   S'(q, p) = sum_i min(F_q[i], F_p[i]) / (||F_q||_1 + ||F_p||_1 - num),  */
+/* the numerator taken over the coordinates where both are non-zero.  The  */
+/* query's activation is q_ids / q_scores [n_queries][k1] (ids < 0 skipped)*/
+/* plus a membership q_self[b] of the query in its own neighbour set (a    */
+/* query outside the database has no coordinate of its own, so q_self only */
+/* enters ||F_q||_1; pass 0, or q_self = NULL, for a database shape whose   */
+/* own id is in q_ids).  Returns the top_k shapes by (S' desc, id asc);    */
+/* shapes sharing no coordinate score 0 and fill the list in id order.     */
+/* S' is formed in compensated arithmetic.  flags[b] = 1, or 2 when the     */
+/* query touched more than 4096 postings and only the first were used.    */
+/* ---------------------------------------------------------------------- */
+gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
+                            const int64_t* post_off, const int32_t* post_id,
+                            const float* post_val, int32_t n_queries,
+                            int32_t k1, const int32_t* q_ids,
+                            const float* q_scores, const float* q_self,
+                            int32_t top_k, int32_t* ids, float* scores,
+                            int32_t* flags, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing.  gift_profile_enable(capacity > 0) creates `capacity`   */
 /* HIP event pairs and from then on brackets each kernel launch of the    */
 /* calls above with events recorded on the launch stream (first          */
@@ -223,7 +261,8 @@ gift_status gift_score_fif(const gift_views* db, const gift_fif* fif,
 /* frees the events.  gift_profile_read() waits for the recorded events  */
 /* of kernel `tag` and returns their summed duration and count.  Tags:   */
 /* 0 quantize, 1 score_tiles, 2 reduce_queries, 3 select_top, 4 rescore,  */
-/* 5 final_rank, 6 assign, 7 group_queries, 8 fif_scan.  Host functions,   */
+/* 5 final_rank, 6 assign, 7 group_queries, 8 fif_scan, 9 rerank_sif.      */
+/* Host functions,                                                        */
 /* not thread-safe.                                                       */
 /* ---------------------------------------------------------------------- */
 gift_status gift_profile_enable(int32_t capacity);

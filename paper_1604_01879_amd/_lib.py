@@ -77,6 +77,11 @@ _sig = {
                                    C.c_size_t, _P]),
     "gift_score_fif_workspace": (C.c_size_t, [_VP, _FP, _QP]),
     "gift_score_fif": (C.c_int32, [_VP, _FP, _QP, _P, _P, _P, C.c_size_t, _P]),
+    "gift_build_sif_workspace": (C.c_size_t, [C.c_int64]),
+    "gift_build_sif": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
+                                   _P]),
+    "gift_rerank_sif": (C.c_int32, [C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P,
+                                    C.c_int32, _P, _P, _P, _P]),
     "gift_profile_enable": (C.c_int32, [C.c_int32]),
     "gift_profile_reset": (C.c_int32, []),
     "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -187,7 +192,8 @@ def query_exhaustive_workspace(db: Views, q: Queries, top_k, rescore_r) -> int:
 
 
 PROFILE_TAGS = {"quantize": 0, "score_tiles": 1, "reduce_queries": 2, "select_top": 3,
-                "rescore": 4, "final_rank": 5, "assign": 6, "group_queries": 7, "fif_scan": 8}
+                "rescore": 4, "final_rank": 5, "assign": 6, "group_queries": 7, "fif_scan": 8,
+                "rerank_sif": 9}
 
 
 def gift_profile_enable(capacity: int):
@@ -291,3 +297,43 @@ def gift_score_fif(db: Views, fif: Fif, q: Queries, stream=None):
     _check(_lib.gift_score_fif(C.byref(db.c), C.byref(fif.c), C.byref(q.c), _ptr(out), _ptr(qw),
                                _ptr(ws), ws.numel(), _stream(stream)))
     return out, qw
+
+
+# ---------------------------------------------------------------- S-IF
+class Sif:
+    """The second inverted file (keeps tensors alive)."""
+
+    def __init__(self, n_shapes, l1, post_off, post_id, post_val):
+        self.n_shapes = int(n_shapes)
+        self.l1, self.post_off, self.post_id, self.post_val = l1, post_off, post_id, post_val
+
+    def nnz(self):
+        return int(self.post_off[-1].item())
+
+
+def gift_build_sif(nbr_ids, nbr_scores, stream=None):
+    """S-IF from neighbour lists [N, k1] (int32 ids, float32 scores)."""
+    N, k1 = nbr_ids.shape
+    dev = nbr_ids.device
+    ws = _workspace(_lib.gift_build_sif_workspace(N), dev)
+    l1 = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    off = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    pid = torch.empty(N * k1, dtype=torch.int32, device=dev)
+    pval = torch.empty(N * k1, dtype=torch.float32, device=dev)
+    _check(_lib.gift_build_sif(N, k1, _ptr(nbr_ids), _ptr(nbr_scores), _ptr(l1), _ptr(off),
+                               _ptr(pid), _ptr(pval), _ptr(ws), ws.numel(), _stream(stream)))
+    return Sif(N, l1, off, pid, pval)
+
+
+def gift_rerank_sif(sif: Sif, q_ids, q_scores, q_self, top_k, stream=None):
+    """Top-k by Eq. 8 for each query's activation: (ids, scores, flags)."""
+    B, k1 = q_ids.shape
+    dev = q_ids.device
+    ids = torch.empty((B, top_k), dtype=torch.int32, device=dev)
+    scores = torch.empty((B, top_k), dtype=torch.float32, device=dev)
+    flags = torch.empty(B, dtype=torch.int32, device=dev)
+    _check(_lib.gift_rerank_sif(sif.n_shapes, _ptr(sif.l1), _ptr(sif.post_off), _ptr(sif.post_id),
+                                _ptr(sif.post_val), B, k1, _ptr(q_ids), _ptr(q_scores),
+                                _ptr(q_self), top_k, _ptr(ids), _ptr(scores), _ptr(flags),
+                                _stream(stream)))
+    return ids, scores, flags

@@ -22,10 +22,10 @@ gift_status fail(gift_status st, const char* fmt, ...) {
 // Optional HIP-event brackets around each kernel launch, on the launch
 // stream, so a caller can read per-kernel device time.  Off by default.
 enum ProfTag { P_QUANT = 0, P_SCORE, P_REDUCE, P_SELECT, P_RESCORE, P_FINAL, P_ASSIGN,
-               P_GROUP, P_SCAN, P_NTAGS };
+               P_GROUP, P_SCAN, P_RERANK, P_NTAGS };
 static const char* kTagNames[P_NTAGS] = {"quantize", "score_tiles", "reduce_queries",
                                          "select_top", "rescore", "final_rank", "assign",
-                                         "group_queries", "fif_scan"};
+                                         "group_queries", "fif_scan", "rerank_sif"};
 struct ProfSlot { hipEvent_t a, b; int tag; };
 static ProfSlot* g_prof = nullptr;
 static int g_prof_cap = 0, g_prof_used = 0, g_prof_on = 0;
@@ -634,6 +634,54 @@ gift_status gift_score_fif(const gift_views* db, const gift_fif* fif, const gift
   if (qwords)
     GIFT_HIP(hipMemcpyAsync(qwords, w.qwords, (size_t)q->total_views * 4,
                             hipMemcpyDeviceToDevice, st));
+  return GIFT_OK;
+}
+
+/* ------------------------------------------------------------ S-IF */
+size_t gift_build_sif_workspace(int64_t n_shapes) {
+  Carver c(nullptr);
+  c.take<unsigned long long>((size_t)n_shapes);
+  c.take<unsigned long long>((size_t)n_shapes);
+  return c.bytes();
+}
+
+gift_status gift_build_sif(int64_t n_shapes, int32_t k1, const int32_t* nbr_ids,
+                           const float* nbr_scores, float* l1, int64_t* post_off,
+                           int32_t* post_id, float* post_val, void* ws, size_t ws_bytes,
+                           void* stream) {
+  GIFT_CHECK(n_shapes >= 1 && n_shapes < ((int64_t)1 << 31), GIFT_EINVAL, "n_shapes out of range");
+  GIFT_CHECK(k1 >= 1 && k1 <= 256, GIFT_EINVAL, "k1 must be in 1..256");
+  GIFT_CHECK(n_shapes * k1 < ((int64_t)1 << 31), GIFT_ECAPACITY, "n_shapes * k1 too large");
+  GIFT_CHECK(nbr_ids && nbr_scores && l1 && post_off && post_id && post_val, GIFT_EINVAL,
+             "null pointer");
+  Carver c(ws);
+  auto* cnt = c.take<unsigned long long>((size_t)n_shapes);
+  auto* fill = c.take<unsigned long long>((size_t)n_shapes);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= c.bytes(), GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", c.bytes(), ws_bytes);
+  launch_build_sif(nbr_ids, nbr_scores, n_shapes, k1, l1, post_off, post_id, post_val, cnt,
+                   fill, (hipStream_t)stream);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
+gift_status gift_rerank_sif(int64_t n_shapes, const float* l1, const int64_t* post_off,
+                            const int32_t* post_id, const float* post_val, int32_t n_queries,
+                            int32_t k1, const int32_t* q_ids, const float* q_scores,
+                            const float* q_self, int32_t top_k, int32_t* ids, float* scores,
+                            int32_t* flags, void* stream) {
+  GIFT_CHECK(n_shapes >= 1 && n_shapes < ((int64_t)1 << 31), GIFT_EINVAL, "n_shapes out of range");
+  GIFT_CHECK(k1 >= 1 && k1 <= 256, GIFT_EINVAL, "k1 must be in 1..256");
+  GIFT_CHECK(top_k >= 1 && top_k <= n_shapes, GIFT_EINVAL, "need 1 <= top_k <= n_shapes");
+  GIFT_CHECK(n_queries >= 0, GIFT_EINVAL, "n_queries < 0");
+  GIFT_CHECK(l1 && post_off && post_id && post_val && q_ids && q_scores && ids && scores,
+             GIFT_EINVAL, "null pointer");
+  const hipStream_t st = (hipStream_t)stream;
+  prof_begin(P_RERANK, st);
+  launch_rerank_sif(l1, post_off, post_id, post_val, n_shapes, q_ids, q_scores, q_self,
+                    n_queries, k1, top_k, ids, scores, flags, st);
+  prof_end(st);
+  GIFT_LAUNCHED();
   return GIFT_OK;
 }
 

@@ -73,4 +73,15 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
 void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
                        int n_queries, float* S, hipStream_t st);
 
+// ---- second inverted file
+// l1 [N][2] (compensated ||F_p||_1), post_off [N+1], post_id / post_val
+// [<= N*k1]; cnt and fill are N-entry scratch counters.
+void launch_build_sif(const int32_t* ids, const float* vals, int64_t N, int k1, float* l1,
+                      int64_t* post_off, int32_t* post_id, float* post_val,
+                      unsigned long long* cnt, unsigned long long* fill, hipStream_t st);
+void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* post_id,
+                       const float* post_val, int64_t N, const int32_t* q_id, const float* q_val,
+                       const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,
+                       int32_t* flags, hipStream_t st);
+
 }  // namespace gift

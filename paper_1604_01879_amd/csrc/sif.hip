@@ -1,0 +1,297 @@
+// The second inverted file (Sec. 2.4): sparse activations F (Eq. 7), their
+// L1 norms, the postings of Fig. 3, and re-ranking by the fuzzy Jaccard
+// similarity of Eq. 8 evaluated through Eq. 13 (numerator over shared
+// non-zero coordinates) and Eq. 14 (denominator from the L1 norms).
+#include "kernels.h"
+
+namespace gift {
+
+// ------------------------------------------------------------------ build
+// ||F_p||_1 as a compensated sum of the memberships in rank order, and the
+// per-coordinate posting counts.  Valid entries: id in [0, N), value > 0.
+__global__ __launch_bounds__(256) void sif_count_kernel(const int32_t* __restrict__ ids,
+                                                        const float* __restrict__ vals,
+                                                        int64_t N, int k1,
+                                                        float* __restrict__ l1,
+                                                        unsigned long long* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  ff acc = {0.f, 0.f};
+  for (int r = 0; r < k1; ++r) {
+    const int32_t i = ids[p * k1 + r];
+    if (i < 0 || i >= N) continue;
+    const float v = vals[p * k1 + r];
+    acc = ff_add(acc, ff{v, 0.f});
+    if (v > 0.f) atomicAdd(&cnt[i], 1ull);
+  }
+  l1[2 * p] = acc.hi;
+  l1[2 * p + 1] = acc.lo;
+}
+
+__global__ __launch_bounds__(256) void sif_scatter_kernel(const int32_t* __restrict__ ids,
+                                                          const float* __restrict__ vals,
+                                                          int64_t N, int k1,
+                                                          const int64_t* __restrict__ off,
+                                                          unsigned long long* __restrict__ fill,
+                                                          int32_t* __restrict__ post_id,
+                                                          float* __restrict__ post_val) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * k1) return;
+  const int32_t i = ids[e];
+  const float v = vals[e];
+  if (i < 0 || i >= N || !(v > 0.f)) return;
+  const int64_t pos = off[i] + (int64_t)atomicAdd(&fill[i], 1ull);
+  post_id[pos] = (int32_t)(e / k1);
+  post_val[pos] = v;
+}
+
+// Orders each posting list by shape id (lists are short: insertion sort).
+__global__ __launch_bounds__(256) void sif_sort_kernel(const int64_t* __restrict__ off, int64_t N,
+                                                       int32_t* __restrict__ post_id,
+                                                       float* __restrict__ post_val) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int64_t a = off[i], b = off[i + 1];
+  for (int64_t x = a + 1; x < b; ++x) {
+    const int32_t pid = post_id[x];
+    const float pv = post_val[x];
+    int64_t y = x - 1;
+    while (y >= a && post_id[y] > pid) {
+      post_id[y + 1] = post_id[y];
+      post_val[y + 1] = post_val[y];
+      --y;
+    }
+    post_id[y + 1] = pid;
+    post_val[y + 1] = pv;
+  }
+}
+
+// The count array doubles as int64 input of the exclusive scan.
+__global__ __launch_bounds__(1024) void scan_counts_kernel(const unsigned long long* __restrict__ cnt,
+                                                           int64_t K, int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  const int64_t per = (K + 1023) / 1024;
+  const int64_t k0 = threadIdx.x * per;
+  int64_t s = 0;
+  for (int64_t k = k0; k < k0 + per && k < K; ++k) s += (int64_t)cnt[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int64_t k = k0; k < k0 + per && k < K; ++k) {
+    off[k] = run;
+    run += (int64_t)cnt[k];
+  }
+  if (threadIdx.x == 1023) off[K] = part[1023];
+}
+
+__global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0ull;
+}
+
+void launch_build_sif(const int32_t* ids, const float* vals, int64_t N, int k1, float* l1,
+                      int64_t* post_off, int32_t* post_id, float* post_val,
+                      unsigned long long* cnt, unsigned long long* fill, hipStream_t st) {
+  const int64_t zb = (N + 255) / 256 < 65536 ? (N + 255) / 256 : 65536;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)zb), dim3(256), 0, st, cnt, N);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)zb), dim3(256), 0, st, fill, N);
+  hipLaunchKernelGGL(sif_count_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, ids,
+                     vals, N, k1, l1, cnt);
+  hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(1024), 0, st, cnt, N, post_off);
+  hipLaunchKernelGGL(sif_scatter_kernel, dim3((unsigned)((N * k1 + 255) / 256)), dim3(256), 0,
+                     st, ids, vals, N, k1, post_off, fill, post_id, post_val);
+  hipLaunchKernelGGL(sif_sort_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                     post_off, N, post_id, post_val);
+}
+
+// ------------------------------------------------------------------ rerank
+// One block per query.  F_q has memberships q_val at coordinates q_id (ids
+// < 0 skipped) plus q_self for the query itself, which has no coordinate and
+// only enters ||F_q||_1.  The postings of the query's coordinates are
+// expanded into LDS as (shape, min(F_q[i], F_p[i])) pairs, sorted by
+// (shape, expansion order); each shape's pairs are summed (Eq. 13), the
+// score S' = num / (||F_q||_1 + ||F_p||_1 - num) (Eq. 14) is formed in
+// compensated arithmetic, and the shapes are ranked by (S' desc, id asc);
+// shapes sharing no coordinate score 0 and fill the list in id order.
+constexpr int SIF_CAP = 4096;  // expanded postings per query
+
+struct SCand {
+  float hi, lo;
+  int32_t id;
+};
+
+__device__ inline bool scand_before(const SCand& a, const SCand& b) {
+  if (a.hi != b.hi) return a.hi > b.hi;
+  if (a.lo != b.lo) return a.lo > b.lo;
+  return a.id < b.id;
+}
+
+// (a.hi + a.lo) / (b.hi + b.lo) for b > 0.
+__device__ inline ff ff_div(ff a, ff b) {
+#pragma clang fp contract(off)
+  const float q1 = a.hi / b.hi;
+  float p, e;
+  two_prod(q1, b.hi, p, e);
+  // remainder a - q1 * b
+  float r = ((a.hi - p) - e) + a.lo;
+  r = r - q1 * b.lo;
+  const float q2 = r / b.hi;
+  return ff_norm(q1, q2);
+}
+
+__global__ __launch_bounds__(256) void rerank_sif_kernel(
+    const float* __restrict__ l1, const int64_t* __restrict__ post_off,
+    const int32_t* __restrict__ post_id, const float* __restrict__ post_val, int64_t N,
+    const int32_t* __restrict__ q_id, const float* __restrict__ q_val,
+    const float* __restrict__ q_self, int k1, int k, int32_t* __restrict__ out_id,
+    float* __restrict__ out_s, int32_t* __restrict__ flags) {
+  __shared__ int64_t pre[257];
+  __shared__ float Ahi, Alo;
+  __shared__ int overflow;
+  __shared__ int wsum[4];
+  extern __shared__ __align__(16) uint8_t sm[];
+  uint64_t* key = reinterpret_cast<uint64_t*>(sm);                // (shape << 32) | slot
+  float* pv = reinterpret_cast<float*>(sm + 8 * SIF_CAP);           // min value per slot
+  SCand* cand = reinterpret_cast<SCand*>(sm + 12 * SIF_CAP);
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int32_t* qi = q_id + (int64_t)b * k1;
+  const float* qv = q_val + (int64_t)b * k1;
+
+  if (tid == 0) {
+    ff A = {q_self != nullptr ? q_self[b] : 0.f, 0.f};
+    int64_t run = 0;
+    for (int r = 0; r < k1; ++r) {
+      pre[r] = run;
+      const int32_t i = qi[r];
+      if (i >= 0 && i < N) {
+        A = ff_add(A, ff{qv[r], 0.f});
+        if (qv[r] > 0.f) run += post_off[i + 1] - post_off[i];
+      }
+    }
+    pre[k1] = run;
+    overflow = run > SIF_CAP;
+    Ahi = A.hi;
+    Alo = A.lo;
+  }
+  __syncthreads();
+  const int L = (int)(pre[k1] < SIF_CAP ? pre[k1] : SIF_CAP);
+  for (int s = tid; s < L; s += 256) {
+    int lo = 0, hi = k1;  // r with pre[r] <= s < pre[r+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= s) lo = mid; else hi = mid;
+    }
+    const int64_t e = post_off[qi[lo]] + (s - pre[lo]);
+    key[s] = ((uint64_t)(uint32_t)post_id[e] << 32) | (uint32_t)s;
+    pv[s] = fminf(qv[lo], post_val[e]);
+  }
+  int np2 = 1;
+  while (np2 < L) np2 <<= 1;
+  for (int s = L + tid; s < np2; s += 256) key[s] = ~0ull;
+  __syncthreads();
+  for (int kk = 2; kk <= np2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < np2; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & kk) == 0;
+          const uint64_t x = key[i], y = key[ix];
+          if ((x > y) == up) { key[i] = y; key[ix] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // one candidate per distinct shape, in ascending shape order
+  int base_u = 0;
+  for (int s0 = 0; s0 < L; s0 += 256) {
+    const int s = s0 + tid;
+    const bool start = s < L && (s == 0 || (key[s] >> 32) != (key[s - 1] >> 32));
+    const int lane = tid & 63, wave = tid >> 6;
+    const unsigned long long bal = __ballot(start);
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) before += wsum[w];
+      tot += wsum[w];
+    }
+    const int u = base_u + before + __popcll(bal & ((1ull << lane) - 1ull));
+    if (start) {
+      const int32_t p = (int32_t)(key[s] >> 32);
+      ff num = {0.f, 0.f};
+      for (int t = s; t < L && (key[t] >> 32) == (uint64_t)(uint32_t)p; ++t)
+        num = ff_add(num, ff{pv[(uint32_t)key[t]], 0.f});
+      // denominator ||F_q||_1 + ||F_p||_1 - num (Eq. 14)
+      ff den = ff_add(ff{Ahi, Alo}, ff{l1[2 * (int64_t)p], l1[2 * (int64_t)p + 1]});
+      den = ff_add(den, ff{-num.hi, -num.lo});
+      const ff sc = ff_div(num, den);
+      cand[u] = SCand{sc.hi, sc.lo, p};
+    }
+    base_u += tot;
+    __syncthreads();
+  }
+  const int U = base_u;
+  // candidate ids are ascending here; remember them for the zero padding
+  // by sorting a copy of the ids into `key` (already ascending by shape)
+  for (int i = tid; i < U; i += 256) key[i] = (uint64_t)(uint32_t)cand[i].id;
+  int np2u = 1;
+  while (np2u < U) np2u <<= 1;
+  for (int i = U + tid; i < np2u; i += 256) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
+  __syncthreads();
+  for (int kk = 2; kk <= np2u; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < np2u; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & kk) == 0;
+          const SCand x = cand[i], y = cand[ix];
+          if (scand_before(y, x) == up) { cand[i] = y; cand[ix] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int kp = k < U ? k : U;
+  for (int i = tid; i < kp; i += 256) {
+    out_id[(int64_t)b * k + i] = cand[i].id;
+    out_s[(int64_t)b * k + i] = cand[i].hi;
+  }
+  if (tid == 0) {
+    // zero-score shapes in id order, skipping the candidates
+    int pos = kp, c = 0;
+    for (int64_t id = 0; pos < k && id < N; ++id) {
+      while (c < U && (int64_t)key[c] < id) ++c;
+      if (c < U && (int64_t)key[c] == id) continue;
+      out_id[(int64_t)b * k + pos] = (int32_t)id;
+      out_s[(int64_t)b * k + pos] = 0.f;
+      ++pos;
+    }
+    if (flags != nullptr) flags[b] = overflow ? 2 : 1;
+  }
+}
+
+void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* post_id,
+                       const float* post_val, int64_t N, const int32_t* q_id, const float* q_val,
+                       const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,
+                       int32_t* flags, hipStream_t st) {
+  if (B <= 0) return;
+  const size_t shmem = (size_t)SIF_CAP * (8 + 4 + sizeof(SCand));
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rerank_sif_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    attr = true;
+  }
+  hipLaunchKernelGGL(rerank_sif_kernel, dim3(B), dim3(256), shmem, st, l1, post_off, post_id,
+                     post_val, N, q_id, q_val, q_self, k1, k, out_id, out_s, flags);
+}
+
+}  // namespace gift

@@ -1,0 +1,159 @@
+"""GPU parity of the second inverted file (Sec. 2.4: Eq. 7, 8, 13, 14)
+against the CPU oracle."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from test_gpu_exhaustive import assert_ranked_equal
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1604_01879_amd import _lib
+    return _lib
+
+
+def _random_lists(rng, N, k1, crisp=False, pad=0):
+    ids = np.empty((N, k1), np.int32)
+    sc = np.empty((N, k1), np.float32)
+    for p in range(N):
+        others = rng.choice(np.delete(np.arange(N), p), size=k1 - 1, replace=False)
+        ids[p] = [p] + others.tolist()
+        sc[p] = [1.0] + sorted(rng.random(k1 - 1).astype(np.float32).tolist(), reverse=True)
+    if crisp:
+        sc[:] = 1.0
+    if pad:
+        ids[:pad, -1] = -1  # padding entries
+    return ids, sc
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def test_build_sif_matches_oracle(L):
+    _say("build_sif")
+    rng = np.random.default_rng(0)
+    N, k1 = 700, 12
+    ids, sc = _random_lists(rng, N, k1, pad=30)
+    sc[5, 3] = 0.0  # a zero membership has no posting
+    S = L.gift_build_sif(_t(ids), _t(sc))
+    torch.cuda.synchronize()
+    l1, po, pid, pv = O.build_sif(ids, sc.astype(np.float64), N)
+    g = S.l1.cpu().numpy().astype(np.float64)
+    assert np.allclose(g[:, 0] + g[:, 1], l1, rtol=0, atol=1e-12)
+    assert np.array_equal(S.post_off.cpu().numpy(), po)
+    nnz = int(po[-1])
+    assert np.array_equal(S.post_id.cpu().numpy()[:nnz], pid)
+    assert np.array_equal(S.post_val.cpu().numpy()[:nnz].astype(np.float64), pv)
+
+
+def test_rerank_golden_hand_example(L):
+    _say("rerank golden")
+    g = json.load(open(os.path.join(GOLD, "sif_4shape.json")))
+    ids = np.array(g["nbr_ids"], np.int32)
+    sc = np.array(g["nbr_scores"], np.float32)
+    S = L.gift_build_sif(_t(ids), _t(sc))
+    out_ids, out_s, fl = L.gift_rerank_sif(S, _t(ids), _t(sc), None, 4)
+    torch.cuda.synchronize()
+    out_ids, out_s = out_ids.cpu().numpy(), out_s.cpu().numpy()
+    Sp = np.array(g["S_prime"])
+    for p in range(4):
+        ref_ids, ref_s = O.rank_topk(Sp[p][None], 4)
+        assert out_ids[p].tolist() == ref_ids[0].tolist()
+        assert np.allclose(out_s[p], ref_s[0], atol=1e-6)
+    assert (fl.cpu().numpy() == 1).all()
+
+
+@pytest.mark.parametrize("crisp", [False, True])
+def test_rerank_matches_oracle(L, crisp):
+    _say(f"rerank crisp={crisp}")
+    rng = np.random.default_rng(3 if crisp else 4)
+    N, k1, k = 400, 16, 50
+    ids, sc = _random_lists(rng, N, k1, crisp=crisp)
+    S = L.gift_build_sif(_t(ids), _t(sc))
+    l1, po, pid, pv = O.build_sif(ids, sc.astype(np.float64), N)
+    # database shapes as queries (self in the list) and outside queries
+    qsel = np.arange(0, N, 37)
+    q_ids = ids[qsel]
+    q_sc = sc[qsel]
+    oi = rng.choice(N, size=(5, k1 - 1), replace=False) if False else np.stack(
+        [rng.choice(N, size=k1 - 1, replace=False) for _ in range(5)]).astype(np.int32)
+    os_ = np.sort(rng.random((5, k1 - 1)).astype(np.float32), axis=1)[:, ::-1].copy()
+    if crisp:
+        os_[:] = 1.0
+    q_ids2 = np.concatenate([oi, -np.ones((5, 1), np.int32)], axis=1)
+    q_sc2 = np.concatenate([os_, np.zeros((5, 1), np.float32)], axis=1)
+    all_ids = np.concatenate([q_ids, q_ids2]).astype(np.int32)
+    all_sc = np.concatenate([q_sc, q_sc2]).astype(np.float32)
+    self_m = np.concatenate([np.zeros(len(qsel)), np.ones(5)]).astype(np.float32)
+    gi, gs, fl = L.gift_rerank_sif(S, _t(all_ids), _t(all_sc), _t(self_m), k)
+    torch.cuda.synchronize()
+    gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
+    for b in range(len(all_ids)):
+        _, _, Sref = O.rerank_sif(l1, po, pid, pv, all_ids[b], all_sc[b].astype(np.float64),
+                                  float(self_m[b]), k)
+        assert_ranked_equal(gi[b], gs[b], Sref, k)
+    # S'(x, x) = 1 for database shapes queried with their own list
+    assert np.allclose(gs[:len(qsel), 0], 1.0, atol=1e-6)
+    assert (gi[:len(qsel), 0] == qsel).all()
+
+
+def test_sif_end_to_end_after_exhaustive(L):
+    """Neighbour lists from the exhaustive path (database shapes as queries),
+    S-IF built from them, out-of-database queries re-ranked with their own
+    top-(k1 - 1) plus the self membership S(q, q).  The oracle runs the same
+    pipeline from its own float64 scores; ranks must agree except where the
+    float64 re-ranking scores are closer than the membership rounding."""
+    _say("sif end to end")
+    w = synth.PRESETS["c1"].scaled(n_shapes=240, dim=64, n_queries=4, m_lo=10, m_hi=64,
+                                   p_dis=0.2)
+    db, _, _ = synth.make_db(w)
+    q, qoff, _ = synth.make_queries(w)
+    k1, k = 10, 30
+    nv = w.n_views
+    # GPU
+    master = _t(db)
+    V = L.Views(master, nv, L.F32)
+    Qdb = L.Queries(master, torch.arange(0, w.n_shapes + 1, dtype=torch.int32) * nv)
+    nid, nsc, _ = L.gift_query_exhaustive(V, Qdb, k1, 64)
+    Sg = L.gift_build_sif(nid, nsc)
+    Q = L.Queries(_t(q), torch.from_numpy(qoff))
+    qi, qs, _ = L.gift_query_exhaustive(V, Q, k1 - 1, 64)
+    one = torch.ones(w.n_queries, dtype=torch.float32, device=DEV)
+    gi, gs, _ = L.gift_rerank_sif(Sg, qi, qs, one, k)
+    torch.cuda.synchronize()
+    # oracle
+    Sdb = O.exhaustive_scores(db, np.arange(w.n_shapes + 1) * nv, db, nv)
+    oid, osc = O.rank_topk(Sdb, k1)
+    assert np.array_equal(nid.cpu().numpy(), oid)
+    l1, po, pid, pv = O.build_sif(oid, osc, w.n_shapes)
+    Sq = O.exhaustive_scores(q, qoff, db, nv)
+    qid_o, qsc_o = O.rank_topk(Sq, k1 - 1)
+    assert np.array_equal(qi.cpu().numpy(), qid_o)
+    selfs = O.self_score(q, qoff)
+    gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
+    for b in range(w.n_queries):
+        _, _, Sref = O.rerank_sif(l1, po, pid, pv, qid_o[b], qsc_o[b], selfs[b], k)
+        ref_ids, ref_s = O.rank_topk(Sref[None], k)
+        assert np.allclose(gs[b], ref_s[0], atol=2e-6)
+        gaps = np.abs(np.diff(ref_s[0]))
+        firm = np.ones(k, bool)
+        firm[:-1] &= gaps > 1e-5
+        firm[1:] &= gaps > 1e-5
+        assert np.array_equal(gi[b][firm], ref_ids[0][firm])
