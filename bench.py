@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="queries timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
+    ap.add_argument("--fif-steps", type=int, default=5)
+    ap.add_argument("--kmeans-iters", type=int, default=10)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -80,6 +83,12 @@ def main():
     log("database resident in HBM (f32 master + bf16 + fp8 codes)")
 
     k, R = args.top_k, args.rescore
+    tuning = {}
+    for name in ("bf16", "fp8"):
+        if name == args.dtype or (name == "fp8" and args.fp8_steps):
+            bt, bg, ms = L.gift_autotune_score(views[name], Q, [0, 1], [8, 16, 32], reps=2)
+            tuning[name] = {"tile": bt, "group": bg, "ms_grid": ms.round(2).tolist()}
+            log(f"autotuned {name}: tile {bt} group {bg}")
 
     def run(name, steps, warmup, prof=False):
         V = views[name]
@@ -164,6 +173,7 @@ def main():
                                 + (" (all queries certified complete)" if exact_ok else " (NOT all certified)"),
                    "complete_flags": int(main_run["flags"].sum())},
         "kernels_ms": main_run["kern"],
+        "autotune": tuning,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "score_tiles",
@@ -178,6 +188,13 @@ def main():
         f8 = recall(fp8_run["ids"], exact_ids, min(100, k))
         result["fp8_path"] = {"queries_per_s": round(B * args.fp8_steps / fp8_run["total"], 2),
                               "recall_at100_mean": f8[0], "recall_at100_min": f8[1]}
+
+    if args.fif:
+        try:
+            result["fif_path"] = fif_leg(L, torch, w, master, views, Q, q_np, qoff_np,
+                                         exact_ids, args)
+        except Exception as e:  # the headline stands on its own
+            result["fif_path"] = {"error": repr(e)}
 
     if args.cpu_sample > 0:
         import oracle as O
@@ -198,6 +215,108 @@ def main():
         result["recall"]["fp32_path_ids_equal_fp64_oracle_sample"] = bool(
             np.array_equal(exact_ids[:ns], ids64))
     print(json.dumps(result))
+
+
+def fif_leg(L, torch, w, master, views, Q, q_np, qoff_np, exact_ids, args):
+    """F-IF (Eq. 4) + S-IF (Eq. 8) on the same database, float32 storage."""
+    import synth
+    dev = master.device
+    out = {}
+    K = w.K
+    init = synth.kmeans_init_idx(w.n_shapes * w.n_views, K, w.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cb, _, iters = L.gift_build_codebook(master, K, init, args.kmeans_iters)
+    torch.cuda.synchronize()
+    out["codebook"] = {"K": K, "train_views": w.n_shapes * w.n_views, "iterations": iters,
+                       "max_iter": args.kmeans_iters, "seconds": round(time.perf_counter() - t0, 3)}
+    log(f"k-means K={K}: {iters} iterations in {out['codebook']['seconds']}s")
+    V = views["f32"]
+    B = w.n_queries
+    per_ma = {}
+    fif_ma1 = None
+    for ma in (1, 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = L.gift_build_fif(V, cb, ma)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        lens = (F.offsets[1:] - F.offsets[:-1]).cpu().numpy()
+        ws = torch.empty(L.query_fif_workspace(V, F, Q, args.top_k, args.rescore),
+                         dtype=torch.uint8, device=dev)
+        L.gift_query_fif(V, F, Q, args.top_k, args.rescore, ws=ws)
+        torch.cuda.synchronize()
+        L.gift_profile_enable(64 * args.fif_steps)
+        t0 = time.perf_counter()
+        for _ in range(args.fif_steps):
+            res = L.gift_query_fif(V, F, Q, args.top_k, args.rescore, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.fif_steps
+        kern = {}
+        for tag in L.PROFILE_TAGS:
+            ms, n = L.gift_profile_read(tag)
+            if n:
+                kern[tag] = {"avg_ms": ms / n, "launches": n}
+        L.gift_profile_enable(0)
+        ids = res[0].cpu().numpy()
+        # pairs scanned and list bytes touched (each touched list read once per batch)
+        _, qw = L.gift_score_fif(V, F, Q)
+        qw = qw.cpu().numpy()
+        words, counts = np.unique(qw, return_counts=True)
+        pairs = int((lens[words] * counts).sum())
+        list_bytes = int(lens[words].sum()) * w.dim * 4
+        scan_ms = kern.get("fif_scan", {}).get("avg_ms", float("nan"))
+        per_ma[f"ma{ma}"] = {
+            "build_seconds": round(tb, 3), "list_len_mean": float(lens.mean()),
+            "list_len_max": int(lens.max()), "queries_per_s": round(B / dt, 2),
+            "ms_per_batch": round(dt * 1e3, 3), "pairs_scanned_per_query": pairs / B,
+            "scan_gflop_per_batch": 2.0 * pairs * w.dim / 1e9,
+            "scan_tflops": 2.0 * pairs * w.dim / (scan_ms * 1e-3) / 1e12,
+            "scan_list_GBps": list_bytes / (scan_ms * 1e-3) / 1e9,
+            "recall_at100_vs_eq3": recall(ids, exact_ids, min(100, args.top_k))[0],
+            "kernels_ms": kern}
+        log(f"F-IF ma={ma}: {B / dt:.1f} q/s, scan {scan_ms:.2f} ms")
+        if ma == 1:
+            fif_ma1 = F
+    out["per_ma"] = per_ma
+    # S-IF from every database shape's top-k1 by Eq. 4 (MA = 1), then re-rank
+    k1 = 20
+    F = fif_ma1
+    nbr_i, nbr_s = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = 1024
+    for s0 in range(0, w.n_shapes, chunk):
+        s1 = min(w.n_shapes, s0 + chunk)
+        offs = torch.arange(0, s1 - s0 + 1, dtype=torch.int32) * w.n_views
+        Qd = L.Queries(master[s0 * w.n_views:s1 * w.n_views], offs)
+        i_, s_, _ = L.gift_query_fif(V, F, Qd, k1, 64)
+        nbr_i.append(i_)
+        nbr_s.append(s_)
+    nbr_i = torch.cat(nbr_i).contiguous()
+    nbr_s = torch.cat(nbr_s).contiguous()
+    S = L.gift_build_sif(nbr_i, nbr_s)
+    torch.cuda.synchronize()
+    tsif = time.perf_counter() - t0
+    qi, qs, _ = L.gift_query_fif(V, F, Q, k1 - 1, 64)
+    one = torch.ones(B, dtype=torch.float32, device=dev)
+    L.gift_rerank_sif(S, qi, qs, one, args.top_k)
+    torch.cuda.synchronize()
+    L.gift_profile_enable(64)
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.gift_rerank_sif(S, qi, qs, one, args.top_k)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ms, n = L.gift_profile_read("rerank_sif")
+    L.gift_profile_enable(0)
+    out["sif"] = {"k1": k1, "build_seconds_incl_neighbour_queries": round(tsif, 3),
+                  "postings": S.nnz(), "rerank_ms_per_batch": round(dt * 1e3, 4),
+                  "rerank_kernel_ms": ms / max(n, 1), "queries_per_batch": B,
+                  "rerank_queries_per_s": round(B / dt, 1)}
+    log(f"S-IF: {S.nnz()} postings, rerank {dt * 1e3:.3f} ms per {B} queries")
+    return out
 
 
 if __name__ == "__main__":

@@ -254,6 +254,27 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
                             int32_t* flags, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Tuning of the first-pass scorer (host, process-wide, not thread-safe).  */
+/* tile: 0 = 256 database rows x 128 query views per block, 1 = 256 x 256  */
+/* (BF16 / FP8 only; float32 uses 128 x 128); group: number of database    */
+/* row tiles that share one sweep over the query tiles in the launch order */
+/* (blocks go to the 8 XCDs round-robin, so multiples of 8 keep each       */
+/* database tile on one XCD).  gift_autotune_score times every (tile,      */
+/* group) pair of the given lists on this workload (reps launches each,   */
+/* HIP events on `stream`; SYNCHRONISES), writes the average ms per launch */
+/* to ms_out [n_tiles][n_groups] (may be NULL), selects the fastest pair   */
+/* and returns it.  Workspace as gift_score_exhaustive.                    */
+/* ---------------------------------------------------------------------- */
+gift_status gift_set_score_tuning(int32_t dtype, int32_t tile, int32_t group);
+gift_status gift_get_score_tuning(int32_t dtype, int32_t* tile, int32_t* group);
+gift_status gift_autotune_score(const gift_views* db, const gift_queries* q,
+                                const int32_t* tiles, int32_t n_tiles,
+                                const int32_t* groups, int32_t n_groups,
+                                int32_t reps, float* ms_out,
+                                int32_t* best_tile, int32_t* best_group,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing.  gift_profile_enable(capacity > 0) creates `capacity`   */
 /* HIP event pairs and from then on brackets each kernel launch of the    */
 /* calls above with events recorded on the launch stream (first          */

@@ -82,6 +82,11 @@ _sig = {
                                    _P]),
     "gift_rerank_sif": (C.c_int32, [C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P,
                                     C.c_int32, _P, _P, _P, _P]),
+    "gift_set_score_tuning": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
+    "gift_get_score_tuning": (C.c_int32, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gift_autotune_score": (C.c_int32, [_VP, _QP, _P, C.c_int32, _P, C.c_int32, C.c_int32, _P,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P,
+                                        C.c_size_t, _P]),
     "gift_profile_enable": (C.c_int32, [C.c_int32]),
     "gift_profile_reset": (C.c_int32, []),
     "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -337,3 +342,30 @@ def gift_rerank_sif(sif: Sif, q_ids, q_scores, q_self, top_k, stream=None):
                                 _ptr(q_self), top_k, _ptr(ids), _ptr(scores), _ptr(flags),
                                 _stream(stream)))
     return ids, scores, flags
+
+
+# ---------------------------------------------------------------- tuning
+def gift_set_score_tuning(dtype, tile, group):
+    _check(_lib.gift_set_score_tuning(dtype, tile, group))
+
+
+def gift_get_score_tuning(dtype):
+    t, g = C.c_int32(), C.c_int32()
+    _check(_lib.gift_get_score_tuning(dtype, C.byref(t), C.byref(g)))
+    return t.value, g.value
+
+
+def gift_autotune_score(db: Views, q: Queries, tiles, groups, reps=2, stream=None):
+    """Times every (tile, group) pair on this workload and selects the best.
+    Returns (best_tile, best_group, ms [len(tiles), len(groups)])."""
+    import numpy as np
+    ti = (C.c_int32 * len(tiles))(*tiles)
+    gr = (C.c_int32 * len(groups))(*groups)
+    ms = (C.c_float * (len(tiles) * len(groups)))()
+    bt, bg = C.c_int32(), C.c_int32()
+    ws = _workspace(_lib.gift_score_exhaustive_workspace(C.byref(db.c), C.byref(q.c)),
+                    db.data.device)
+    _check(_lib.gift_autotune_score(C.byref(db.c), C.byref(q.c), ti, len(tiles), gr, len(groups),
+                                    reps, ms, C.byref(bt), C.byref(bg), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return bt.value, bg.value, np.array(ms[:], dtype=np.float32).reshape(len(tiles), len(groups))

@@ -47,9 +47,10 @@ static const double U32 = 5.9604644775390625e-08;  // 2^-24
 static double gamma_n(double n) { return n * U32 / (1.0 - n * U32); }
 
 // Bound on |float32 dot - exact dot| of two unit-norm views in the rescore
-// kernel: a fresh partial sum per 32 values, added into a running total.
+// kernel: 16 MFMA steps of two products per 32-value K-tile (charged two
+// roundings each) into a fresh block, added into a running total.
 static float rescore_dot_err(int dim) {
-  return (float)(gamma_n(32.0 + dim / 32 + 1) * 1.0001);
+  return (float)(gamma_n(2.0 * 16 + dim / 32 + 2) * 1.0001);
 }
 
 // Bound on |first-pass score - exact Eq. 3 score| for unit-norm views.
@@ -635,6 +636,78 @@ gift_status gift_score_fif(const gift_views* db, const gift_fif* fif, const gift
     GIFT_HIP(hipMemcpyAsync(qwords, w.qwords, (size_t)q->total_views * 4,
                             hipMemcpyDeviceToDevice, st));
   return GIFT_OK;
+}
+
+/* ------------------------------------------------------------ tuning */
+gift_status gift_set_score_tuning(int32_t dtype, int32_t tile, int32_t group) {
+  return set_score_tuning(dtype, tile, group);
+}
+
+gift_status gift_get_score_tuning(int32_t dtype, int32_t* tile, int32_t* group) {
+  GIFT_CHECK(dtype >= 0 && dtype <= 2 && tile && group, GIFT_EINVAL, "bad arguments");
+  get_score_tuning(dtype, tile, group);
+  return GIFT_OK;
+}
+
+gift_status gift_autotune_score(const gift_views* db, const gift_queries* q, const int32_t* tiles,
+                                int32_t n_tiles, const int32_t* groups, int32_t n_groups,
+                                int32_t reps, float* ms_out, int32_t* best_tile,
+                                int32_t* best_group, void* ws, size_t ws_bytes, void* stream) {
+  gift_status s = check_views(db);
+  if (s != GIFT_OK) return s;
+  if ((s = check_queries(q, db->dim)) != GIFT_OK) return s;
+  GIFT_CHECK(tiles && groups && n_tiles >= 1 && n_groups >= 1 && reps >= 1 && best_tile &&
+                 best_group, GIFT_EINVAL, "bad arguments");
+  const hipStream_t st = (hipStream_t)stream;
+  ExhaustiveWs w = carve_exhaustive(ws, db, q, 0);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
+  int keep_tile = 0, keep_group = 8;
+  get_score_tuning(db->dtype, &keep_tile, &keep_group);
+  const void* qv = q->views;
+  const float* qs = nullptr;
+  if (db->dtype != GIFT_F32) {
+    launch_quantize(q->views, q->total_views, db->dim, db->dtype, w.qcodes, w.qscale, st);
+    GIFT_LAUNCHED();
+    qv = w.qcodes;
+    qs = w.qscale;
+  }
+  hipEvent_t e0, e1;
+  GIFT_HIP(hipEventCreate(&e0));
+  GIFT_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  *best_tile = keep_tile;
+  *best_group = keep_group;
+  for (int a = 0; a < n_tiles; ++a)
+    for (int g = 0; g < n_groups; ++g) {
+      s = set_score_tuning(db->dtype, tiles[a], groups[g]);
+      if (s == GIFT_OK) s = launch_score_tiles(db, qv, qs, q->total_views, w.mbuf, q->total_views, st);
+      if (s == GIFT_OK) GIFT_HIP(hipEventRecord(e0, st));
+      for (int r = 0; s == GIFT_OK && r < reps; ++r)
+        s = launch_score_tiles(db, qv, qs, q->total_views, w.mbuf, q->total_views, st);
+      float ms = 0.f;
+      if (s == GIFT_OK) {
+        GIFT_HIP(hipEventRecord(e1, st));
+        GIFT_HIP(hipEventSynchronize(e1));
+        GIFT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+      }
+      if (s != GIFT_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        set_score_tuning(db->dtype, keep_tile, keep_group);
+        return s;
+      }
+      if (ms_out) ms_out[a * n_groups + g] = ms;
+      if (ms < best) {
+        best = ms;
+        *best_tile = tiles[a];
+        *best_group = groups[g];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return set_score_tuning(db->dtype, *best_tile, *best_group);
 }
 
 /* ------------------------------------------------------------ S-IF */

@@ -16,6 +16,11 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
                                const float* qscale, int64_t total_q,
                                float* mbuf, int64_t ldm, hipStream_t st);
 
+// Tile shape (0 or 1) per storage dtype and launch-order group of the
+// first-pass scorer.
+gift_status set_score_tuning(int dtype, int tile, int group);
+void get_score_tuning(int dtype, int* tile, int* group);
+
 // S[b][p] = (sum_{i in query b} mbuf[p][i]) / m_b.
 void launch_reduce_queries(const float* mbuf, int64_t ldm, int64_t n_shapes,
                            const int32_t* qoff, int n_queries, float* S,

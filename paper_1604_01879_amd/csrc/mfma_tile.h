@@ -29,6 +29,10 @@ constexpr int LROW = 144;  // LDS bytes per staged row: 128 + 16 pad
 template <int DT>
 struct Mfma;
 
+struct Pair32 {
+  uint4 lo, hi;
+};
+
 template <>
 struct Mfma<GIFT_F32> {
   // 16 steps of 32x32x2 per K-tile.
@@ -59,11 +63,10 @@ struct Mfma<GIFT_FP8E4M3> {
   __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      i32x8 av = {(int)a[2 * s].x, (int)a[2 * s].y, (int)a[2 * s].z, (int)a[2 * s].w,
-                  (int)a[2 * s + 1].x, (int)a[2 * s + 1].y, (int)a[2 * s + 1].z, (int)a[2 * s + 1].w};
-      i32x8 bv = {(int)b[2 * s].x, (int)b[2 * s].y, (int)b[2 * s].z, (int)b[2 * s].w,
-                  (int)b[2 * s + 1].x, (int)b[2 * s + 1].y, (int)b[2 * s + 1].z, (int)b[2 * s + 1].w};
-      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+      const Pair32 ap = {a[2 * s], a[2 * s + 1]}, bp = {b[2 * s], b[2 * s + 1]};
+      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(__builtin_bit_cast(i32x8, ap),
+                                                          __builtin_bit_cast(i32x8, bp), c, 0, 0,
+                                                          0, 127, 0, 127);
     }
   }
 };
@@ -139,6 +142,86 @@ __device__ __forceinline__ void mfma_tile_mainloop(
     }
   }
   __syncthreads();  // LDS may be reused by the caller's epilogue
+}
+
+// Same tile with two LDS stages and global loads issued two K-tiles ahead
+// (two register sets), so one barrier per K-tile and about two K-tiles of
+// MFMA work to hide each load.  Needs 2 * LDS_BYTES of shared memory.
+template <int DT, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_mainloop_db(
+    uint8_t* lds, const uint8_t* const (&src)[TileShape<WM, WN>::LOADS], int row_bytes,
+    f32x16 (&acc)[WM][WN]) {
+  using T = TileShape<WM, WN>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5, l32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int n_kt = (row_bytes + 127) / 128;
+  uint4 pre0[T::LOADS], pre1[T::LOADS];
+  auto gload = [&](uint4 (&pre)[T::LOADS], int kt) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
+      if (src[it] != nullptr && off < row_bytes)
+        pre[it] = *reinterpret_cast<const uint4*>(src[it] + off);
+      else
+        pre[it] = make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto lstore = [&](const uint4 (&pre)[T::LOADS], uint8_t* buf) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int idx = tid + 256 * it;
+      *reinterpret_cast<uint4*>(buf + (idx >> 3) * LROW + (idx & 7) * 16) = pre[it];
+    }
+  };
+  auto compute = [&](const uint8_t* buf) {
+    const uint8_t* arow = buf + (wr * WM * 32 + l32) * LROW + half * 64;
+    const uint8_t* brow = buf + (T::BM + wc * WN * 32 + l32) * LROW + half * 64;
+    uint4 b[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * 16);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      uint4 a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * 16);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) Mfma<DT>::run(a, b[j], acc[i][j]);
+    }
+  };
+  uint8_t* buf0 = lds;
+  uint8_t* buf1 = lds + T::LDS_BYTES;
+  gload(pre0, 0);
+  if (n_kt > 1) gload(pre1, 1);
+  lstore(pre0, buf0);
+  __syncthreads();
+  for (int kt = 0; kt < n_kt; kt += 2) {
+    // buf0 holds tile kt; pre1 holds tile kt + 1
+    if (kt + 2 < n_kt) gload(pre0, kt + 2);
+    compute(buf0);
+    if (kt + 1 < n_kt) lstore(pre1, buf1);
+    __syncthreads();
+    if (kt + 1 >= n_kt) break;
+    // buf1 holds tile kt + 1; pre0 holds tile kt + 2
+    if (kt + 3 < n_kt) gload(pre1, kt + 3);
+    compute(buf1);
+    if (kt + 2 < n_kt) lstore(pre0, buf0);
+    __syncthreads();
+  }
 }
 
 // Row (within the wave's WM*32 rows) and column of accumulator element e of

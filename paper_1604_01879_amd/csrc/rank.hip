@@ -1,6 +1,7 @@
 // Ranking of Eq. 3 / Eq. 4 scores: block-level top-r selection, the exact
 // rescore of the candidates and the final (score desc, id asc) order.
 #include "kernels.h"
+#include "mfma_tile.h"
 
 namespace gift {
 
@@ -128,31 +129,31 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r,
 }
 
 // ------------------------------------------------------------------ rescore
-// One block per (query, candidate shape).  Phase 1: the float32 dot products
-// of up to 64 query views x 64 database views, each thread owning 4 x 4 of
-// them, with a fresh partial sum per 32-value K-tile added into a running
-// total (accumulation depth at most 32 + dim/32, which bounds the error by
-// dot_err).  Phase 2: for each query view, every database view whose float32
-// dot product lies within 2 * dot_err of the row maximum may be the true
-// maximum; those pairs are re-evaluated with the compensated dot product
-// and the exact maximum kept.  Phase 3: the compensated mean over the query
-// views, summed in ascending view order.
-constexpr int RS_LROW = 36;  // floats per LDS row (32 + 4 pad)
-
+// One block (two waves) per (query, candidate shape).  Phase 1: the float32
+// dot products of the candidate's views (rows, 64) with up to 64 query views
+// (columns) on MFMA, 32 x 32 blocks: wave w owns query views 32w..32w+31 and
+// both row blocks.  Each 32-value K-tile is accumulated into a fresh
+// register block and then added into a running total, which bounds the
+// accumulation depth by 2*16 + dim/32 roundings (dot_err).  The lane that
+// holds query view i holds 32 of its row values, so the maximum over the
+// candidate's valid views and the mask of views within 2 * dot_err of it
+// need one cross-half shuffle.  Phase 2: every masked pair is re-evaluated
+// with the compensated dot product and the exact maximum kept.  Phase 3:
+// the compensated mean over the query views in ascending order.
 // With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
 // word of q_i is one of the `ma` words of p_j, and a query view with no such
 // pair contributes 0.
-__global__ __launch_bounds__(256) void rescore_kernel(
+__global__ __launch_bounds__(128, 2) void rescore_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
     float* __restrict__ s_hi, float* __restrict__ s_lo) {
-  __shared__ float qs[64 * RS_LROW];
-  __shared__ float ps[64 * RS_LROW];
-  __shared__ float rowmax[64];
+  constexpr int ROWS = 128;  // 64 candidate views + 64 query views
+  __shared__ __align__(16) uint8_t lds[ROWS * LROW];
   __shared__ unsigned long long jmask[64];
   __shared__ float mff_hi[64], mff_lo[64];
+  __shared__ int32_t vw[64 * 8];
   __shared__ float tot_hi, tot_lo;
 
   const int64_t bc = blockIdx.x;
@@ -160,100 +161,114 @@ __global__ __launch_bounds__(256) void rescore_kernel(
   const int64_t shape = cand[bc];
   const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ti = tid >> 4, tj = tid & 15;  // rows 4ti..4ti+3, cols 4tj..4tj+3
+  const int half = lane >> 5, l32 = lane & 31;
   const float* pbase = master + shape * (int64_t)n_views * dim;
+  const int row_bytes = dim * 4;
 
+  if (qwords != nullptr)
+    for (int x = tid; x < n_views * ma; x += 128) vw[x] = view_words[shape * n_views * ma + x];
   if (tid == 0) { tot_hi = 0.f; tot_lo = 0.f; }
   for (int it = 0; it * 64 < m; ++it) {
     const int mi = min(64, m - it * 64);
     const float* qbase = qviews + (int64_t)(q0 + it * 64) * dim;
-    float tot[4][4];
+    // staging pointers: 8 pieces per thread per K-tile
+    const uint8_t* src[8];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) tot[x][y] = 0.f;
-
-    for (int k0 = 0; k0 < dim; k0 += 32) {
-      __syncthreads();
-      // stage 64 x 32 of each side: 512 float4 per side, 2 per thread
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = tid + 256 * h;
-        const int row = idx >> 3, c4 = idx & 7;
-        float4 qv = make_float4(0.f, 0.f, 0.f, 0.f), pv = qv;
-        if (row < mi) qv = *reinterpret_cast<const float4*>(qbase + (int64_t)row * dim + k0 + 4 * c4);
-        if (row < n_views) pv = *reinterpret_cast<const float4*>(pbase + (int64_t)row * dim + k0 + 4 * c4);
-        *reinterpret_cast<float4*>(qs + row * RS_LROW + 4 * c4) = qv;
-        *reinterpret_cast<float4*>(ps + row * RS_LROW + 4 * c4) = pv;
+    for (int p = 0; p < 8; ++p) {
+      const int row = (tid + 128 * p) >> 3;
+      const uint8_t* ptr = nullptr;
+      if (row < 64) {
+        if (row < n_views) ptr = reinterpret_cast<const uint8_t*>(pbase + (int64_t)row * dim);
+      } else if (row - 64 < mi) {
+        ptr = reinterpret_cast<const uint8_t*>(qbase + (int64_t)(row - 64) * dim);
       }
-      __syncthreads();
-      float part[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) part[x][y] = 0.f;
-#pragma unroll
-      for (int k = 0; k < 32; k += 4) {
-        float4 a[4], c[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) a[x] = *reinterpret_cast<const float4*>(qs + (4 * ti + x) * RS_LROW + k);
-#pragma unroll
-        for (int y = 0; y < 4; ++y) c[y] = *reinterpret_cast<const float4*>(ps + (4 * tj + y) * RS_LROW + k);
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            part[x][y] = __builtin_fmaf(a[x].x, c[y].x, part[x][y]);
-            part[x][y] = __builtin_fmaf(a[x].y, c[y].y, part[x][y]);
-            part[x][y] = __builtin_fmaf(a[x].z, c[y].z, part[x][y]);
-            part[x][y] = __builtin_fmaf(a[x].w, c[y].w, part[x][y]);
-          }
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) tot[x][y] += part[x][y];
+      src[p] = ptr;
     }
-    // row maxima over valid database views, then the near-maximum masks
+    f32x16 tot[2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = 4 * ti + x;
-      int wq = -1;
-      if (qwords != nullptr && i < mi) wq = qwords[q0 + it * 64 + i];
-      bool ok[4];
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int j = 4 * tj + y;
-        ok[y] = j < n_views;
-        if (ok[y] && qwords != nullptr) {
-          const int32_t* vw = view_words + (shape * n_views + j) * (int64_t)ma;
+      for (int e = 0; e < 16; ++e) tot[bi][e] = 0.f;
+    const uint8_t* arow = lds + l32 * LROW + half * 64;
+    const uint8_t* brow = lds + (64 + wave * 32 + l32) * LROW + half * 64;
+    for (int k0 = 0; k0 < row_bytes; k0 += 128) {
+      uint4 pre[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int off = k0 + ((tid + 128 * p) & 7) * 16;
+        pre[p] = src[p] != nullptr ? *reinterpret_cast<const uint4*>(src[p] + off)
+                                   : make_uint4(0, 0, 0, 0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int idx = tid + 128 * p;
+        *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[p];
+      }
+      __syncthreads();
+      uint4 bq[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) bq[s4] = *reinterpret_cast<const uint4*>(brow + s4 * 16);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        uint4 a[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          a[s4] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + s4 * 16);
+        f32x16 part;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[e] = 0.f;
+        Mfma<GIFT_F32>::run(a, bq, part);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tot[bi][e] += part[e];
+      }
+    }
+    // per query view (this lane's column): maximum over valid views and the
+    // mask of views that may hold the exact maximum
+    const int i = wave * 32 + l32;
+    int wq = -1;
+    if (qwords != nullptr && i < mi) wq = qwords[q0 + it * 64 + i];
+    float mx = -INFINITY;
+    unsigned valid = 0u;  // bit (bi*16 + e)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+        bool ok = j < n_views;
+        if (ok && qwords != nullptr) {
           bool hit = false;
-          for (int a = 0; a < ma; ++a) hit |= vw[a] == wq;
-          ok[y] = hit;
+          for (int a2 = 0; a2 < ma; ++a2) hit |= vw[j * ma + a2] == wq;
+          ok = hit;
+        }
+        if (ok) {
+          valid |= 1u << (bi * 16 + e);
+          mx = fmaxf(mx, tot[bi][e]);
         }
       }
-      float mx = -INFINITY;
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    unsigned long long bits = 0ull;
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
-        if (ok[y]) mx = fmaxf(mx, tot[x][y]);
-      for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-      unsigned long long bits = 0;
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
-        if (ok[y] && tot[x][y] >= mx - 2.f * dot_err)
-          bits |= 1ull << (4 * tj + y);
-      for (int o = 8; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
-      if (tj == 0) { rowmax[4 * ti + x] = mx; jmask[4 * ti + x] = bits; }
-    }
+      for (int e = 0; e < 16; ++e) {
+        const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+        if (((valid >> (bi * 16 + e)) & 1u) && tot[bi][e] >= mx - 2.f * dot_err)
+          bits |= 1ull << j;
+      }
+    const unsigned lo_b = (unsigned)bits, hi_b = (unsigned)(bits >> 32);
+    bits |= (unsigned long long)__shfl_xor(lo_b, 32, 64) |
+            ((unsigned long long)__shfl_xor(hi_b, 32, 64) << 32);
+    if (half == 0) jmask[i] = i < mi ? bits : 0ull;
     __syncthreads();
     // compensated maximum per query view: one wave per view
-    for (int i = wave; i < mi; i += 4) {
-      const float* qrow = qbase + (int64_t)i * dim;
-      unsigned long long bits = jmask[i];
+    for (int iv = wave; iv < mi; iv += 2) {
+      const float* qrow = qbase + (int64_t)iv * dim;
+      unsigned long long bb = jmask[iv];
       ff best = {-INFINITY, 0.f};
-      while (bits) {
-        const int j = __builtin_ctzll(bits);
-        bits &= bits - 1;
+      while (bb) {
+        const int j = __builtin_ctzll(bb);
+        bb &= bb - 1;
         const float* prow = pbase + (int64_t)j * dim;
         float s = 0.f, c = 0.f;
         for (int t = lane; t < dim; t += 64) dot2_step(qrow[t], prow[t], s, c);
@@ -261,12 +276,12 @@ __global__ __launch_bounds__(256) void rescore_kernel(
         if (ff_gt(v, best)) best = v;
       }
       if (best.hi == -INFINITY) best = ff{0.f, 0.f};  // no matching view
-      if (lane == 0) { mff_hi[i] = best.hi; mff_lo[i] = best.lo; }
+      if (lane == 0) { mff_hi[iv] = best.hi; mff_lo[iv] = best.lo; }
     }
     __syncthreads();
     if (tid == 0) {
       ff acc = {tot_hi, tot_lo};
-      for (int i = 0; i < mi; ++i) acc = ff_add(acc, ff{mff_hi[i], mff_lo[i]});
+      for (int iv = 0; iv < mi; ++iv) acc = ff_add(acc, ff{mff_hi[iv], mff_lo[iv]});
       tot_hi = acc.hi;
       tot_lo = acc.lo;
     }
@@ -288,7 +303,7 @@ void launch_rescore(const float* master, int n_views, int dim,
   (void)max_m;
   const int64_t blocks = (int64_t)n_queries * r;
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(128), 0, st,
                      master, n_views, dim, qviews, qoff, cand, r, dot_err,
                      qwords, view_words, ma, s_hi, s_lo);
 }

@@ -72,15 +72,16 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     int64_t n_shapes, int n_views, int row_bytes,
     const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
     int64_t total_q, float* __restrict__ mbuf, int64_t ldm,
-    int64_t n_row_tiles, int64_t n_col_tiles) {
+    int64_t n_row_tiles, int64_t n_col_tiles, int64_t GROUP) {
   using T = TileShape<WM, WN>;
   constexpr int SHAPES_PER_BLOCK = T::BM / 64;
   static_assert(WM % 2 == 0, "a wave must hold whole shapes");
   extern __shared__ __align__(16) uint8_t lds[];
 
-  // Tile order: GROUP consecutive row tiles share each column sweep, so the
-  // blocks on one XCD (ids equal mod 8) keep re-using one database tile.
-  constexpr int64_t GROUP = 8;
+  // Tile order: GROUP consecutive row tiles share each column sweep.  Blocks
+  // are dealt to the 8 XCDs round-robin, so with GROUP a multiple of 8 the
+  // blocks of one XCD keep to GROUP/8 database tiles while they sweep the
+  // query tiles, and the database tiles stay in that XCD's L2.
   const int64_t id = blockIdx.x;
   const int64_t per_group = GROUP * n_col_tiles;
   const int64_t g = id / per_group;
@@ -154,6 +155,26 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   }
 }
 
+// Tuning knobs: tile shape per storage dtype (0: 256 x 128 database rows x
+// query views, 1: 256 x 256; float32 always 128 x 128) and the row-tile
+// group of the launch order.
+static int g_tile[3] = {0, 1, 1};
+static int64_t g_group[3] = {8, 8, 8};
+
+gift_status set_score_tuning(int dtype, int tile, int group) {
+  GIFT_CHECK(dtype >= 0 && dtype <= 2, GIFT_EINVAL, "bad dtype");
+  GIFT_CHECK(tile == 0 || tile == 1, GIFT_EINVAL, "tile must be 0 or 1");
+  GIFT_CHECK(group >= 1 && group <= 1024, GIFT_EINVAL, "group must be in 1..1024");
+  if (dtype != GIFT_F32) g_tile[dtype] = tile;
+  g_group[dtype] = group;
+  return GIFT_OK;
+}
+
+void get_score_tuning(int dtype, int* tile, int* group) {
+  *tile = g_tile[dtype];
+  *group = (int)g_group[dtype];
+}
+
 template <int DT, int WM, int WN>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
                                 const float* qscale, int64_t total_q,
@@ -176,7 +197,7 @@ static gift_status launch_tiles(const gift_views* db, const void* qv,
                      static_cast<const uint8_t*>(db->data), db->scale,
                      db->n_shapes, db->n_views, row_bytes,
                      static_cast<const uint8_t*>(qv), qscale, total_q, mbuf,
-                     ldm, n_row_tiles, n_col_tiles);
+                     ldm, n_row_tiles, n_col_tiles, g_group[DT]);
   GIFT_LAUNCHED();
   return GIFT_OK;
 }
@@ -187,8 +208,14 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
   if (total_q <= 0 || db->n_shapes <= 0) return GIFT_OK;
   switch (db->dtype) {
     case GIFT_F32: return launch_tiles<GIFT_F32, 2, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
-    case GIFT_BF16: return launch_tiles<GIFT_BF16, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
-    case GIFT_FP8E4M3: return launch_tiles<GIFT_FP8E4M3, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
+    case GIFT_BF16:
+      if (g_tile[GIFT_BF16] == 1)
+        return launch_tiles<GIFT_BF16, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);
+      return launch_tiles<GIFT_BF16, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
+    case GIFT_FP8E4M3:
+      if (g_tile[GIFT_FP8E4M3] == 1)
+        return launch_tiles<GIFT_FP8E4M3, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);
+      return launch_tiles<GIFT_FP8E4M3, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
   }
   return fail(GIFT_EUNSUPPORTED, "unknown dtype %d", db->dtype);
 }
