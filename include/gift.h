@@ -254,6 +254,50 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
                             int32_t* flags, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batch plans for the F-IF path (Eq. 4, then the exact rescore and        */
+/* ranking of gift_query_fif).  A plan fixes the database, the index and   */
+/* capacities (max_queries, max_views in total, max_views_per_query) and   */
+/* binds caller-owned device buffers: q_views [max_views][dim] float32 and */
+/* q_offsets [max_queries + 1] (the batch input, written by the caller     */
+/* before each run; q_offsets[0] = 0), and the outputs ids / scores        */
+/* [max_queries][top_k] and flags [max_queries] (NULL allowed).  The first */
+/* pass runs as ONE persistent kernel whose blocks take work items         */
+/* (quantize, clear, dot tiles, word selection, grouping, list tiles,      */
+/* per-query means) in order from a device queue; it is followed by the    */
+/* selection, rescore and final-ranking kernels, and the whole sequence is */
+/* captured once into a HIP graph.  gift_fif_plan_run(n_queries, n_views)  */
+/* launches that graph for a batch occupying the first n_queries slots and  */
+/* n_views rows; outputs of unused slots are unspecified.  Results equal   */
+/* those of gift_query_fif on the same batch.  blocks_per_cu (1 or 2) sets */
+/* the persistent grid.  Create SYNCHRONISES `stream` (which must be a     */
+/* non-default stream not being captured); run is asynchronous.  A plan is */
+/* not thread-safe and its runs on different streams must not overlap.     */
+/* gift_fif_plan_error (SYNCHRONISES) returns 1 if a queue wait of the     */
+/* last run hit its spin limit (results invalid), else 0.                  */
+/* ---------------------------------------------------------------------- */
+typedef struct gift_fif_plan gift_fif_plan;
+size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,
+                               int32_t max_queries, int64_t max_views,
+                               int32_t top_k, int32_t rescore_r);
+gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif,
+                                 int32_t max_queries, int64_t max_views,
+                                 int32_t max_views_per_query, int32_t top_k,
+                                 int32_t rescore_r, const float* q_views,
+                                 int32_t* q_offsets, int32_t* ids,
+                                 float* scores, int32_t* flags,
+                                 int32_t blocks_per_cu, void* ws,
+                                 size_t ws_bytes, void* stream,
+                                 gift_fif_plan** plan);
+gift_status gift_fif_plan_run(gift_fif_plan* plan, int32_t n_queries,
+                              int64_t n_views, void* stream);
+/* The same sequence launched kernel by kernel (no graph), for comparison. */
+gift_status gift_fif_plan_run_eager(gift_fif_plan* plan, int32_t n_queries,
+                                    int64_t n_views, void* stream);
+gift_status gift_fif_plan_error(gift_fif_plan* plan, int32_t* err,
+                                void* stream);
+gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
+
+/* ---------------------------------------------------------------------- */
 /* Tuning of the first-pass scorer (host, process-wide, not thread-safe).  */
 /* tile: 0 = 256 database rows x 128 query views per block, 1 = 256 x 256  */
 /* (BF16 / FP8 only; float32 uses 128 x 128); group: number of database    */

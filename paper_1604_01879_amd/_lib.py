@@ -87,6 +87,15 @@ _sig = {
     "gift_autotune_score": (C.c_int32, [_VP, _QP, _P, C.c_int32, _P, C.c_int32, C.c_int32, _P,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P,
                                         C.c_size_t, _P]),
+    "gift_fif_plan_workspace": (C.c_size_t, [_VP, _FP, C.c_int32, C.c_int64, C.c_int32,
+                                             C.c_int32]),
+    "gift_fif_plan_create": (C.c_int32, [_VP, _FP, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                         C.c_int32, _P, _P, _P, _P, _P, C.c_int32, _P,
+                                         C.c_size_t, _P, C.POINTER(C.c_void_p)]),
+    "gift_fif_plan_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
+    "gift_fif_plan_run_eager": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
+    "gift_fif_plan_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), _P]),
+    "gift_fif_plan_destroy": (C.c_int32, [C.c_void_p]),
     "gift_profile_enable": (C.c_int32, [C.c_int32]),
     "gift_profile_reset": (C.c_int32, []),
     "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -369,3 +378,56 @@ def gift_autotune_score(db: Views, q: Queries, tiles, groups, reps=2, stream=Non
                                     reps, ms, C.byref(bt), C.byref(bg), _ptr(ws), ws.numel(),
                                     _stream(stream)))
     return bt.value, bg.value, np.array(ms[:], dtype=np.float32).reshape(len(tiles), len(groups))
+
+
+# ---------------------------------------------------------------- plans
+class FifPlan:
+    """A captured F-IF batch plan with its own input/output buffers.
+
+    Fill ``views[:n_views]`` and ``offsets[:n_queries + 1]`` (device) and call
+    ``run(n_queries, n_views)``; results land in ``ids``, ``scores``,
+    ``flags``.  The plan captures on (and by default runs on) its own
+    non-default stream."""
+
+    def __init__(self, db: Views, fif: Fif, max_queries, max_views, max_views_per_query, top_k,
+                 rescore_r, blocks_per_cu=2, stream=None):
+        dev = db.data.device
+        self.db, self.fif = db, fif
+        self.max_queries, self.max_views, self.top_k = max_queries, max_views, top_k
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.views = torch.zeros((max_views, db.dim), dtype=torch.float32, device=dev)
+        self.offsets = torch.zeros(max_queries + 1, dtype=torch.int32, device=dev)
+        self.ids = torch.zeros((max_queries, top_k), dtype=torch.int32, device=dev)
+        self.scores = torch.zeros((max_queries, top_k), dtype=torch.float32, device=dev)
+        self.flags = torch.zeros(max_queries, dtype=torch.int32, device=dev)
+        need = _lib.gift_fif_plan_workspace(C.byref(db.c), C.byref(fif.c), max_queries,
+                                            max_views, top_k, rescore_r)
+        self.ws = _workspace(need, dev)
+        torch.cuda.synchronize(dev)
+        self.handle = C.c_void_p()
+        _check(_lib.gift_fif_plan_create(C.byref(db.c), C.byref(fif.c), max_queries, max_views,
+                                         max_views_per_query, top_k, rescore_r,
+                                         _ptr(self.views), _ptr(self.offsets), _ptr(self.ids),
+                                         _ptr(self.scores), _ptr(self.flags), blocks_per_cu,
+                                         _ptr(self.ws), self.ws.numel(), _stream(self.stream),
+                                         C.byref(self.handle)))
+
+    def run(self, n_queries, n_views, stream=None, eager=False):
+        f = _lib.gift_fif_plan_run_eager if eager else _lib.gift_fif_plan_run
+        _check(f(self.handle, n_queries, n_views, _stream(stream or self.stream)))
+
+    def error(self, stream=None):
+        e = C.c_int32()
+        _check(_lib.gift_fif_plan_error(self.handle, C.byref(e), _stream(stream or self.stream)))
+        return e.value
+
+    def close(self):
+        if self.handle:
+            _lib.gift_fif_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -64,6 +64,9 @@ static float first_pass_err(int dtype, int dim, int max_m) {
   return (float)(e * 1.001);
 }
 
+float rescore_dot_error(int dim) { return rescore_dot_err(dim); }
+float first_pass_error(int dtype, int dim, int max_m) { return first_pass_err(dtype, dim, max_m); }
+
 static gift_status check_views(const gift_views* db) {
   GIFT_CHECK(db != nullptr && db->data != nullptr, GIFT_EINVAL, "null database views");
   GIFT_CHECK(db->dtype == GIFT_F32 || db->dtype == GIFT_BF16 || db->dtype == GIFT_FP8E4M3,

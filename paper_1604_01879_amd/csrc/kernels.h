@@ -78,6 +78,52 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
 void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
                        int n_queries, float* S, hipStream_t st);
 
+// ---- persistent batch of the F-IF first pass
+enum BatchPhase { BP_Q = 0, BP_FILL, BP_GEMM, BP_SEL, BP_PRE, BP_SCAT, BP_SCAN, BP_RED, BP_END };
+struct BatchArgs {
+  const uint8_t* db;
+  const float* db_scale;
+  int n_views, row_bytes;
+  int64_t n_shapes;
+  const float* cb;
+  const float* nhi;
+  const float* nlo;
+  int K, dim;
+  const int64_t* loff;
+  const int32_t* ent_shape;
+  const int32_t* ent_view;
+  const int64_t* tile_off;
+  const float* qviews;
+  int32_t* qoff;
+  int Bmax;
+  int64_t Vmax;
+  const int32_t* desc;  // {n_queries, n_views} of the current batch
+  uint8_t* qcodes;
+  float* qscale;
+  float* D;
+  int32_t* qwords;
+  int32_t* counts;
+  int64_t* goff;
+  int32_t* fillc;
+  int32_t* gitems;
+  uint32_t* mbuf;
+  float* S;
+  int32_t* overflow;
+  unsigned long long* ctrl;  // head, done, error, spare
+  float gamma2;
+  int64_t gemm_col_tiles;
+  int64_t first[9];          // first item of each phase, then the total
+};
+void launch_batch_reset(const BatchArgs& a, hipStream_t st);
+gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st);
+gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo, hipStream_t st);
+gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64_t* tile_off,
+                              hipStream_t st);
+float assign_gamma2(int dim);
+// error bounds of the rescore dot product and of the first pass (api.hip)
+float rescore_dot_error(int dim);
+float first_pass_error(int dtype, int dim, int max_m);
+
 // ---- second inverted file
 // l1 [N][2] (compensated ||F_p||_1), post_off [N+1], post_id / post_val
 // [<= N*k1]; cnt and fill are N-entry scratch counters.

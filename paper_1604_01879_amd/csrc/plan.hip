@@ -1,0 +1,327 @@
+// Batch plans: the whole F-IF query path of a ragged batch (Eq. 4 first
+// pass in one persistent kernel, then selection, exact rescore and final
+// ranking) captured once into a HIP graph and replayed per batch.
+#include <string.h>
+
+#include "kernels.h"
+
+namespace gift {
+
+struct PlanWs {
+  float* nhi;
+  float* nlo;
+  int64_t* tcount;
+  int64_t* tile_off;
+  int32_t* desc;
+  uint8_t* qcodes;
+  float* qscale;
+  float* D;
+  int32_t* qwords;
+  int32_t* counts;
+  int64_t* goff;
+  int32_t* fillc;
+  int32_t* gitems;
+  uint32_t* mbuf;
+  float* S;
+  int32_t* overflow;
+  unsigned long long* ctrl;
+  int32_t* cand;
+  float* cand_s;
+  float* s_hi;
+  float* s_lo;
+  size_t bytes;
+};
+
+static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, int Bmax,
+                         int64_t Vmax, int r) {
+  Carver c(base);
+  PlanWs w{};
+  w.nhi = c.take<float>((size_t)f->K);
+  w.nlo = c.take<float>((size_t)f->K);
+  w.tcount = c.take<int64_t>((size_t)f->K);
+  w.tile_off = c.take<int64_t>((size_t)f->K + 1);
+  w.desc = c.take<int32_t>(4);
+  if (db->dtype != GIFT_F32) {
+    w.qcodes = c.take<uint8_t>((size_t)Vmax * db->dim * elem_bytes(db->dtype));
+    w.qscale = c.take<float>((size_t)Vmax);
+  }
+  w.D = c.take<float>((size_t)Vmax * f->K);
+  w.qwords = c.take<int32_t>((size_t)Vmax);
+  w.counts = c.take<int32_t>((size_t)f->K);
+  w.goff = c.take<int64_t>((size_t)f->K + 1);
+  w.fillc = c.take<int32_t>((size_t)f->K);
+  w.gitems = c.take<int32_t>((size_t)Vmax);
+  w.mbuf = c.take<uint32_t>((size_t)db->n_shapes * Vmax);
+  w.S = c.take<float>((size_t)Bmax * db->n_shapes);
+  w.overflow = c.take<int32_t>(1);
+  w.ctrl = c.take<unsigned long long>(4);
+  w.cand = c.take<int32_t>((size_t)Bmax * r);
+  w.cand_s = c.take<float>((size_t)Bmax * r);
+  w.s_hi = c.take<float>((size_t)Bmax * r);
+  w.s_lo = c.take<float>((size_t)Bmax * r);
+  w.bytes = c.bytes();
+  return w;
+}
+
+}  // namespace gift
+
+struct gift_fif_plan {
+  gift::BatchArgs args;
+  gift::PlanWs ws;
+  gift_views db;
+  int Bmax, max_m, top_k, r;
+  int64_t Vmax;
+  int grid;
+  const float* qviews;
+  int32_t* qoff;
+  int32_t* ids;
+  float* scores;
+  int32_t* flags;
+  const int32_t* view_words;
+  int ma;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int64_t items[gift::BP_END];
+};
+
+namespace gift {
+
+static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
+  launch_batch_reset(p->args, st);
+  GIFT_LAUNCHED();
+  gift_status s = launch_fif_batch(p->args, p->db.dtype, p->grid, st);
+  if (s != GIFT_OK) return s;
+  launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, p->ws.cand, p->ws.cand_s, st);
+  GIFT_LAUNCHED();
+  launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->max_m,
+                 p->ws.cand, p->r, rescore_dot_error(p->db.dim), p->ws.qwords, p->view_words,
+                 p->ma, p->ws.s_hi, p->ws.s_lo, st);
+  GIFT_LAUNCHED();
+  launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
+                    p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim, p->max_m),
+                    p->ws.overflow, p->ids, p->scores, p->flags, st);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
+}  // namespace gift
+
+using namespace gift;
+
+extern "C" {
+
+size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif, int32_t max_queries,
+                               int64_t max_views, int32_t top_k, int32_t rescore_r) {
+  (void)top_k;
+  if (db == nullptr || fif == nullptr || max_queries < 1 || max_views < 1 || rescore_r < 1)
+    return 0;
+  return carve_plan(nullptr, db, fif, max_queries, max_views, rescore_r).bytes;
+}
+
+gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int32_t max_queries,
+                                 int64_t max_views, int32_t max_views_per_query, int32_t top_k,
+                                 int32_t rescore_r, const float* q_views, int32_t* q_offsets,
+                                 int32_t* ids, float* scores, int32_t* flags,
+                                 int32_t blocks_per_cu, void* ws, size_t ws_bytes, void* stream,
+                                 gift_fif_plan** plan) {
+  GIFT_CHECK(plan != nullptr, GIFT_EINVAL, "null plan pointer");
+  *plan = nullptr;
+  GIFT_CHECK(db && fif && db->data && db->master && fif->codebook && fif->offsets &&
+                 fif->entry_shape && fif->entry_view && fif->view_words,
+             GIFT_EINVAL, "incomplete database or index (the plan needs float32 master views)");
+  GIFT_CHECK(db->n_views >= 1 && db->n_views <= 64 && db->dim >= 32 && db->dim % 32 == 0,
+             GIFT_EUNSUPPORTED, "n_views must be 1..64 and dim a multiple of 32");
+  GIFT_CHECK(db->dtype == GIFT_F32 || db->scale != nullptr, GIFT_EINVAL, "missing scales");
+  GIFT_CHECK(fif->K >= 1 && fif->K <= 16384 && fif->ma >= 1 && fif->ma <= 8, GIFT_EUNSUPPORTED,
+             "K must be 1..16384 and ma 1..8");
+  GIFT_CHECK(fif->n_entries == (int64_t)fif->ma * db->n_shapes * db->n_views, GIFT_EINVAL,
+             "n_entries must be ma * n_shapes * n_views");
+  GIFT_CHECK(max_queries >= 1 && max_views >= 1 && max_views < ((int64_t)1 << 31) &&
+                 max_views_per_query >= 1,
+             GIFT_EINVAL, "bad capacities");
+  GIFT_CHECK(top_k >= 1 && top_k <= rescore_r && rescore_r <= 1024 &&
+                 (int64_t)rescore_r <= db->n_shapes,
+             GIFT_EINVAL, "need 1 <= top_k <= rescore_r <= min(1024, N)");
+  GIFT_CHECK(q_views && q_offsets && ids && scores, GIFT_EINVAL, "null batch buffers");
+  GIFT_CHECK(blocks_per_cu >= 1 && blocks_per_cu <= 2, GIFT_EINVAL, "blocks_per_cu must be 1 or 2");
+  const hipStream_t st = (hipStream_t)stream;
+  PlanWs w = carve_plan(ws, db, fif, max_queries, max_views, rescore_r);
+  GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
+             "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
+
+  auto* p = new gift_fif_plan();
+  p->ws = w;
+  p->db = *db;
+  p->Bmax = max_queries;
+  p->Vmax = max_views;
+  p->max_m = max_views_per_query;
+  p->top_k = top_k;
+  p->r = rescore_r;
+  p->qviews = q_views;
+  p->qoff = q_offsets;
+  p->ids = ids;
+  p->scores = scores;
+  p->flags = flags;
+  p->view_words = fif->view_words;
+  p->ma = fif->ma;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete p;
+    return fail(GIFT_EHIP, "cannot query the device");
+  }
+  p->grid = n_cu * blocks_per_cu;
+
+  // once per plan: codebook norms and list-tile offsets
+  gift_status s = launch_norms(fif->codebook, fif->K, db->dim, w.nhi, w.nlo, st);
+  if (s == GIFT_OK) s = launch_list_tiles(fif->offsets, fif->K, w.tcount, w.tile_off, st);
+  int64_t n_tiles = 0;
+  if (s == GIFT_OK && (hipMemcpyAsync(&n_tiles, w.tile_off + fif->K, 8, hipMemcpyDeviceToHost, st) !=
+                           hipSuccess ||
+                       hipStreamSynchronize(st) != hipSuccess))
+    s = fail(GIFT_EHIP, "reading the list-tile count failed");
+  if (s != GIFT_OK) {
+    delete p;
+    return s;
+  }
+
+  BatchArgs& a = p->args;
+  memset(&a, 0, sizeof(a));
+  a.db = static_cast<const uint8_t*>(db->data);
+  a.db_scale = db->scale;
+  a.n_views = db->n_views;
+  a.row_bytes = db->dim * elem_bytes(db->dtype);
+  a.n_shapes = db->n_shapes;
+  a.cb = fif->codebook;
+  a.nhi = w.nhi;
+  a.nlo = w.nlo;
+  a.K = fif->K;
+  a.dim = db->dim;
+  a.loff = fif->offsets;
+  a.ent_shape = fif->entry_shape;
+  a.ent_view = fif->entry_view;
+  a.tile_off = w.tile_off;
+  a.qviews = q_views;
+  a.qoff = q_offsets;
+  a.Bmax = max_queries;
+  a.Vmax = max_views;
+  a.desc = w.desc;
+  a.qcodes = w.qcodes;
+  a.qscale = w.qscale;
+  a.D = w.D;
+  a.qwords = w.qwords;
+  a.counts = w.counts;
+  a.goff = w.goff;
+  a.fillc = w.fillc;
+  a.gitems = w.gitems;
+  a.mbuf = w.mbuf;
+  a.S = w.S;
+  a.overflow = w.overflow;
+  a.ctrl = w.ctrl;
+  a.gamma2 = assign_gamma2(db->dim);
+  a.gemm_col_tiles = (fif->K + 127) / 128;
+  const int64_t n_items[BP_END] = {
+      db->dtype == GIFT_F32 ? 0 : (max_views + 63) / 64,          // Q
+      (db->n_shapes + 15) / 16,                                    // FILL
+      ((max_views + 127) / 128) * a.gemm_col_tiles,                // GEMM
+      (max_views + 3) / 4,                                         // SEL
+      1,                                                           // PRE
+      (max_views + 255) / 256,                                     // SCAT
+      n_tiles,                                                     // SCAN
+      (int64_t)max_queries * ((db->n_shapes + 255) / 256)};        // RED
+  int64_t acc = 0;
+  for (int i = 0; i < BP_END; ++i) {
+    a.first[i] = acc;
+    p->items[i] = n_items[i];
+    acc += n_items[i];
+  }
+  a.first[BP_END] = acc;
+
+  // an empty batch run eagerly once (sets kernel attributes, checks launches)
+  {
+    const int32_t zero[2] = {0, 0};
+    if (hipMemcpyAsync(w.desc, zero, sizeof(zero), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(q_offsets, zero, 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+      delete p;
+      return fail(GIFT_EHIP, "plan initialisation copy failed");
+    }
+    s = enqueue_plan(p, st);
+    if (s == GIFT_OK && hipStreamSynchronize(st) != hipSuccess)
+      s = fail(GIFT_EHIP, "plan warm-up failed");
+    if (s != GIFT_OK) {
+      delete p;
+      return s;
+    }
+  }
+
+  // capture the batch into a graph
+  hipStreamCaptureStatus cs;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    delete p;
+    return fail(GIFT_EINVAL, "the plan stream must not be capturing");
+  }
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete p;
+    return fail(GIFT_EHIP, "hipStreamBeginCapture failed");
+  }
+  s = enqueue_plan(p, st);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &g);
+  if (s != GIFT_OK || ec != hipSuccess || g == nullptr) {
+    if (g) (void)hipGraphDestroy(g);
+    delete p;
+    return s != GIFT_OK ? s : fail(GIFT_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+  }
+  p->graph = g;
+  if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete p;
+    return fail(GIFT_EHIP, "graph instantiation failed");
+  }
+  *plan = p;
+  return GIFT_OK;
+}
+
+gift_status gift_fif_plan_run(gift_fif_plan* p, int32_t n_queries, int64_t n_views,
+                              void* stream) {
+  GIFT_CHECK(p != nullptr, GIFT_EINVAL, "null plan");
+  GIFT_CHECK(n_queries >= 0 && n_queries <= p->Bmax && n_views >= 0 && n_views <= p->Vmax,
+             GIFT_ECAPACITY, "batch of %d queries / %lld views exceeds the plan (%d / %lld)",
+             n_queries, (long long)n_views, p->Bmax, (long long)p->Vmax);
+  const hipStream_t st = (hipStream_t)stream;
+  const int32_t desc[2] = {n_queries, (int32_t)n_views};
+  // pageable source: the runtime stages it before returning, so `desc` may go
+  GIFT_HIP(hipMemcpyAsync(p->ws.desc, desc, sizeof(desc), hipMemcpyHostToDevice, st));
+  GIFT_HIP(hipGraphLaunch(p->exec, st));
+  return GIFT_OK;
+}
+
+gift_status gift_fif_plan_run_eager(gift_fif_plan* p, int32_t n_queries, int64_t n_views,
+                                    void* stream) {
+  GIFT_CHECK(p != nullptr, GIFT_EINVAL, "null plan");
+  GIFT_CHECK(n_queries >= 0 && n_queries <= p->Bmax && n_views >= 0 && n_views <= p->Vmax,
+             GIFT_ECAPACITY, "batch exceeds the plan");
+  const hipStream_t st = (hipStream_t)stream;
+  const int32_t desc[2] = {n_queries, (int32_t)n_views};
+  GIFT_HIP(hipMemcpyAsync(p->ws.desc, desc, sizeof(desc), hipMemcpyHostToDevice, st));
+  return enqueue_plan(p, st);
+}
+
+gift_status gift_fif_plan_error(gift_fif_plan* p, int32_t* err, void* stream) {
+  GIFT_CHECK(p != nullptr && err != nullptr, GIFT_EINVAL, "null argument");
+  unsigned long long e = 0;
+  GIFT_HIP(hipMemcpyAsync(&e, p->ws.ctrl + 2, 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  GIFT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  *err = (int32_t)e;
+  return GIFT_OK;
+}
+
+gift_status gift_fif_plan_destroy(gift_fif_plan* p) {
+  if (p == nullptr) return GIFT_OK;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
+  return GIFT_OK;
+}
+
+}  // extern "C"

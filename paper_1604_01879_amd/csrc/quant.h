@@ -1,0 +1,54 @@
+// Per-view scaled reduced-precision codes (shared by the standalone
+// quantizer and the batch kernel).
+#pragma once
+
+#include "common.h"
+
+namespace gift {
+
+__device__ inline uint16_t bf16_rne(float y) {
+  uint32_t u = __builtin_bit_cast(uint32_t, y);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP e4m3fn, round to nearest even, saturating at 448.
+__device__ inline uint8_t e4m3_rne_sat(float y) {
+  uint32_t sgn = (__builtin_bit_cast(uint32_t, y) >> 24) & 0x80u;
+  float a = fabsf(y);
+  if (!(a < 448.f)) return (uint8_t)(sgn | 0x7eu);
+  if (a < 0.015625f) {                 // below 2^-6: step 2^-9
+    int q = (int)rintf(a * 512.f);     // exact scaling, ties to even
+    return (uint8_t)(sgn | (uint32_t)q);  // q == 8 encodes 2^-6 exactly
+  }
+  uint32_t u = __builtin_bit_cast(uint32_t, a);
+  u += 0x7ffffu + ((u >> 20) & 1u);    // keep 3 mantissa bits, ties to even
+  int e = (int)((u >> 23) & 0xffu) - 127;
+  uint32_t m = (u >> 20) & 7u;
+  return (uint8_t)(sgn | (uint32_t)((e + 7) << 3) | m);
+}
+
+// One wave quantizes view v: scale = max|x| / Fmax (1 for an all-zero
+// view), code = round(x / scale).
+__device__ inline void quantize_view_wave(const float* __restrict__ src, int64_t v, int dim,
+                                          int dtype, uint8_t* __restrict__ dst,
+                                          float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const float* x = src + v * dim;
+  float amax = 0.f;
+  for (int t = lane; t < dim; t += 64) amax = fmaxf(amax, fabsf(x[t]));
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  const float fmax_ = dtype == GIFT_BF16 ? 1.0f : 448.0f;
+  float s = amax / fmax_;
+  if (s == 0.f) s = 1.f;
+  if (lane == 0) scale[v] = s;
+  if (dtype == GIFT_BF16) {
+    uint16_t* d = reinterpret_cast<uint16_t*>(dst) + v * dim;
+    for (int t = lane; t < dim; t += 64) d[t] = bf16_rne(x[t] / s);
+  } else {
+    uint8_t* d = dst + v * dim;
+    for (int t = lane; t < dim; t += 64) d[t] = e4m3_rne_sat(x[t] / s);
+  }
+}
+
+}  // namespace gift

@@ -1,0 +1,138 @@
+"""GPU tests of the batch plan: the F-IF path as one persistent kernel plus
+ranking kernels captured in a HIP graph.  Its results must equal those of
+gift_query_fif on the same batch (and so the oracle's), for every replay."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from test_gpu_exhaustive import assert_ranked_equal
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1604_01879_amd import _lib
+    return _lib
+
+
+def _setup(L, dtype, n_shapes=260, dim=128, K=24, ma=2, B=9, seed=0):
+    w = synth.PRESETS["c1"].scaled(n_shapes=n_shapes, dim=dim, n_queries=B, m_lo=1, m_hi=64,
+                                   p_dis=0.2, seed=seed)
+    db, _, _ = synth.make_db(w)
+    q, qoff, _ = synth.make_queries(w)
+    cb = db[synth.kmeans_init_idx(db.shape[0], K, 3)]
+    master = torch.from_numpy(db).to(DEV)
+    V32 = L.Views(master, w.n_views, L.F32)
+    F = L.gift_build_fif(V32, torch.from_numpy(cb).to(DEV), ma)
+    if dtype == L.F32:
+        V = V32
+    else:
+        codes, scale = L.gift_quantize_views(master, dtype)
+        V = L.Views(codes, w.n_views, dtype, scale, master)
+    return w, db, q, qoff, cb, V, F
+
+
+def _load(plan, q, qoff):
+    n_q = len(qoff) - 1
+    plan.views[:qoff[-1]] = torch.from_numpy(q).to(DEV)
+    plan.offsets[:n_q + 1] = torch.from_numpy(qoff).to(DEV)
+    torch.cuda.synchronize()  # the plan runs on its own stream
+    return n_q, int(qoff[-1])
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16"])
+def test_plan_equals_query_fif(L, dtype_name):
+    _say(f"plan vs query_fif {dtype_name}")
+    dt = {"f32": L.F32, "bf16": L.BF16}[dtype_name]
+    w, db, q, qoff, cb, V, F = _setup(L, dt)
+    k, R = 15, 60
+    plan = L.FifPlan(V, F, max_queries=12, max_views=12 * 64, max_views_per_query=64, top_k=k,
+                     rescore_r=R)
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, *O.build_fif(O.assign(db, cb, 2), 24,
+                                                                w.n_views))
+    # full batch, then a smaller one (fewer queries and views) on the same plan
+    for sub in (len(qoff) - 1, 4):
+        qo = qoff[:sub + 1]
+        qq = q[:qo[-1]]
+        Q = L.Queries(torch.from_numpy(qq).to(DEV), torch.from_numpy(qo))
+        ref_ids, ref_sc, ref_fl = L.gift_query_fif(V, F, Q, k, R)
+        n_q, n_v = _load(plan, qq, qo)
+        for eager in (False, True):
+            plan.run(n_q, n_v, eager=eager)
+            plan.stream.synchronize()
+            assert plan.error() == 0
+            ids = plan.ids[:n_q].cpu().numpy()
+            sc = plan.scores[:n_q].cpu().numpy()
+            assert np.array_equal(ids, ref_ids.cpu().numpy())
+            assert np.array_equal(sc, ref_sc.cpu().numpy())
+            assert np.array_equal(plan.flags[:n_q].cpu().numpy(), ref_fl.cpu().numpy())
+            for b in range(n_q):
+                assert_ranked_equal(ids[b], sc[b], S[b], k)
+    plan.close()
+
+
+def test_plan_replays_with_eager_work_between(L):
+    _say("plan replays")
+    w, db, q, qoff, cb, V, F = _setup(L, L.F32, seed=4)
+    k, R = 10, 40
+    plan = L.FifPlan(V, F, max_queries=9, max_views=9 * 64, max_views_per_query=64, top_k=k,
+                     rescore_r=R)
+    n_q, n_v = _load(plan, q, qoff)
+    plan.run(n_q, n_v)
+    plan.stream.synchronize()
+    first = (plan.ids.clone(), plan.scores.clone())
+    Q = L.Queries(torch.from_numpy(q).to(DEV), torch.from_numpy(qoff))
+    for _ in range(4):
+        L.gift_query_fif(V, F, Q, k, R)  # eager work on another stream in between
+        torch.cuda.synchronize()
+        plan.run(n_q, n_v)
+        plan.stream.synchronize()
+        assert torch.equal(plan.ids, first[0])
+        assert torch.equal(plan.scores, first[1])
+    plan.close()
+
+
+def test_plan_alone_and_in_the_mix(L):
+    """A query's result is identical when it runs alone and when it shares
+    the batch with others."""
+    _say("plan alone vs mix")
+    w, db, q, qoff, cb, V, F = _setup(L, L.BF16, seed=6, B=8)
+    k, R = 12, 48
+    plan = L.FifPlan(V, F, max_queries=8, max_views=8 * 64, max_views_per_query=64, top_k=k,
+                     rescore_r=R)
+    n_q, n_v = _load(plan, q, qoff)
+    plan.run(n_q, n_v)
+    plan.stream.synchronize()
+    mix_ids, mix_sc = plan.ids[:n_q].cpu().numpy(), plan.scores[:n_q].cpu().numpy()
+    for b in (0, 5, 7):
+        lo, hi = qoff[b], qoff[b + 1]
+        _load(plan, q[lo:hi], np.array([0, hi - lo], np.int32))
+        plan.run(1, int(hi - lo))
+        plan.stream.synchronize()
+        assert np.array_equal(plan.ids[0].cpu().numpy(), mix_ids[b])
+        assert np.array_equal(plan.scores[0].cpu().numpy(), mix_sc[b])
+    plan.close()
+
+
+def test_plan_rejects_oversized_batch(L):
+    _say("plan capacity")
+    w, db, q, qoff, cb, V, F = _setup(L, L.F32, B=3)
+    plan = L.FifPlan(V, F, max_queries=3, max_views=100, max_views_per_query=64, top_k=5,
+                     rescore_r=20)
+    with pytest.raises(L.GiftError) as e:
+        plan.run(4, 50)
+    assert e.value.status == L.ECAPACITY
+    with pytest.raises(L.GiftError):
+        plan.run(2, 101)
+    plan.close()
