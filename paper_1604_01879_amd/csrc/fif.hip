@@ -657,9 +657,7 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   if (threadIdx.x == 0) *a.overflow = 0;
   const int32_t last = a.qoff[n_q];
   for (int b = n_q + 1 + threadIdx.x; b <= a.Bmax; b += 256) a.qoff[b] = last;
-  if (threadIdx.x == 0) {  // views the offsets may address, for the clamps below
-    a.ctrl[3] = (unsigned long long)(last < a.desc[1] ? last : a.desc[1]);
-  }
+
 }
 
 template <int DT>
