@@ -53,6 +53,11 @@ def main():
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
     ap.add_argument("--fif-steps", type=int, default=5)
     ap.add_argument("--kmeans-iters", type=int, default=10)
+    ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
+                    help="c3: exhaustive precision headline (default); c4: batched F-IF + "
+                         "S-IF plan; c5: continuous-batching serving")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rates", default="200,500,1000")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -63,6 +68,10 @@ def main():
     import torch
     import synth
     from paper_1604_01879_amd import _lib as L
+
+    if args.workload in ("c4", "c5"):
+        print(json.dumps(scale_bench(args)))
+        return
 
     dev = torch.device("cuda:0")
     w = synth.PRESETS["c3"].scaled(n_shapes=args.shapes, n_queries=args.queries)
@@ -215,6 +224,146 @@ def main():
         result["recall"]["fp32_path_ids_equal_fp64_oracle_sample"] = bool(
             np.array_equal(exact_ids[:ns], ids64))
     print(json.dumps(result))
+
+
+def _resident_db(w, torch, L, dtype):
+    """Generates the database in chunks straight into HBM: float32 master and
+    the reduced-precision codes."""
+    import synth
+    dev = torch.device("cuda:0")
+    nv = w.n_shapes * w.n_views
+    master = torch.empty((nv, w.dim), dtype=torch.float32, device=dev)
+    host, _, _ = synth.make_db(w)
+    step = 1 << 20
+    for r0 in range(0, nv, step):
+        master[r0:r0 + step].copy_(torch.from_numpy(host[r0:r0 + step]))
+    del host
+    codes, scale = L.gift_quantize_views(master, dtype)
+    torch.cuda.synchronize()
+    return master, L.Views(codes, w.n_views, dtype, scale, master)
+
+
+def _build_index(w, torch, L, master, V, k1, log_prefix):
+    """k-means codebook on a seeded sample of 64*K views, F-IF (MA = 1), and
+    the S-IF from every database shape's top-k1 by Eq. 4."""
+    import synth
+    dev = master.device
+    t0 = time.time()
+    nv = w.n_shapes * w.n_views
+    sample = synth.training_sample(nv, 64 * w.K, w.seed)
+    train = master[torch.from_numpy(sample).to(dev)].contiguous()
+    init = synth.kmeans_init_idx(train.shape[0], w.K, w.seed)
+    cb, _, iters = L.gift_build_codebook(train, w.K, init, 10)
+    del train
+    F = L.gift_build_fif(L.Views(master, w.n_views, L.F32), cb, 1)
+    torch.cuda.synchronize()
+    t_fif = time.time() - t0
+    log(f"{log_prefix}: codebook ({iters} iterations) + F-IF in {t_fif:.1f}s")
+    t0 = time.time()
+    chunk = max(1, min(512, int(6e9 // (w.n_shapes * w.n_views * 4))))  # mbuf <= 6 GB
+    ids, scs = [], []
+    for s0 in range(0, w.n_shapes, chunk):
+        s1 = min(w.n_shapes, s0 + chunk)
+        offs = torch.arange(0, s1 - s0 + 1, dtype=torch.int32) * w.n_views
+        Qd = L.Queries(master[s0 * w.n_views:s1 * w.n_views], offs)
+        i_, s_, _ = L.gift_query_fif(V, F, Qd, k1, 64)
+        ids.append(i_)
+        scs.append(s_)
+    S = L.gift_build_sif(torch.cat(ids).contiguous(), torch.cat(scs).contiguous())
+    torch.cuda.synchronize()
+    t_sif = time.time() - t0
+    log(f"{log_prefix}: S-IF ({S.nnz()} postings) in {t_sif:.1f}s")
+    return cb, F, S, {"codebook_iterations": iters, "codebook_train_views": int(len(sample)),
+                      "fif_build_seconds": round(t_fif, 2), "sif_build_seconds": round(t_sif, 2),
+                      "sif_postings": S.nnz()}
+
+
+def scale_bench(args):
+    import torch
+    import synth
+    from paper_1604_01879_amd import _lib as L
+    from paper_1604_01879_amd.serve import Server, replay_trace
+    dev = torch.device("cuda:0")
+    w = synth.PRESETS[args.workload]
+    dtype = L.BF16 if args.workload == "c4" else L.FP8E4M3
+    t0 = time.time()
+    master, V = _resident_db(w, torch, L, dtype)
+    log(f"{args.workload}: {w.n_shapes} x {w.n_views} x {w.dim} resident in {time.time() - t0:.1f}s")
+    k1 = 20
+    cb, F, S, build = _build_index(w, torch, L, master, V, k1, args.workload)
+    q, qoff, _ = synth.make_queries(w)
+    if args.workload == "c4":
+        B, nvq = w.n_queries, int(qoff[-1])
+        out = {}
+        for bpc in (1, 2):
+            plan = L.FifPlan(V, F, B, nvq, w.m_hi, k1 - 1, 64, blocks_per_cu=bpc)
+            plan.views[:nvq].copy_(torch.from_numpy(q))
+            plan.offsets.copy_(torch.from_numpy(qoff))
+            torch.cuda.synchronize()
+            one = torch.ones(B, dtype=torch.float32, device=dev)
+            with torch.cuda.stream(plan.stream):
+                plan.run(B, nvq)
+                plan.stream.synchronize()
+                L.gift_profile_enable(64 * args.steps)
+                t1 = time.perf_counter()
+                for _ in range(args.steps):
+                    plan.run(B, nvq)
+                    res = L.gift_rerank_sif(S, plan.ids, plan.scores, one, args.top_k,
+                                            stream=plan.stream)
+                plan.stream.synchronize()
+                dt = (time.perf_counter() - t1) / args.steps
+                rr_ms, rr_n = L.gift_profile_read("rerank_sif")
+                L.gift_profile_enable(0)
+                t1 = time.perf_counter()
+                plan.run(B, nvq, eager=True)
+                plan.stream.synchronize()
+                t_eager = time.perf_counter() - t1
+            err = plan.error()
+            out[f"blocks_per_cu_{bpc}"] = {"ms_per_batch": round(dt * 1e3, 3),
+                                           "queries_per_s": round(B / dt, 1),
+                                           "eager_first_pass_ms": round(t_eager * 1e3, 3),
+                                           "rerank_ms": rr_ms / max(rr_n, 1), "queue_error": err}
+            log(f"c4 plan bpc={bpc}: {dt * 1e3:.2f} ms per batch of {B}")
+            plan.close()
+        best = max(out.values(), key=lambda v: v["queries_per_s"])
+        return {"metric": "queries/s, batched F-IF (one persistent kernel in a HIP graph) + "
+                          "S-IF re-rank, 50k x 64-view BF16 DB",
+                "value": best["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+                "steps": args.steps, "higher_is_better": True, "dtype": "bf16",
+                "data": "synthetic", "config": {"workload": "c4: 50,000 shapes x 64 x 4096 BF16, "
+                "K=8192 (k-means on 524,288 sampled views), k1=20, 1,024 queries with 12..64 "
+                "views per batch", "queries_per_batch": B, "views_per_batch": nvq},
+                "build": build, "plans": out}
+    # c5: continuous batching under Poisson load
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    srv = Server(V, F, S, top_k=args.top_k, k1=k1, rescore_r=64, max_queries=64,
+                 max_views=64 * 64, max_slots=3)
+    queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
+    for v in queries[:8]:
+        srv.submit(v).result()
+    runs = {}
+    for rate in rates:
+        arr = synth.poisson_arrivals(rate, args.serve_seconds, w.seed + int(rate))
+        qs = [queries[i % len(queries)] for i in range(len(arr))]
+        b0 = srv.batches
+        _, lat, wall = replay_trace(srv, qs, arr)
+        runs[str(int(rate))] = {"offered_qps": rate, "completed": len(arr),
+                                "achieved_qps": round(len(arr) / wall, 1),
+                                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                "batches": srv.batches - b0}
+        log(f"c5 serve {rate} qps: p50 {runs[str(int(rate))]['p50_ms']} ms, "
+            f"p99 {runs[str(int(rate))]['p99_ms']} ms")
+    n_slots = srv.n_slots
+    srv.close()
+    top = runs[str(int(rates[-1]))]
+    return {"metric": "serving queries/s and p50/p99 ms, F-IF + S-IF, 200k x 64-view FP8 DB",
+            "value": top["achieved_qps"], "unit": "queries/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "fp8", "data": "synthetic",
+            "config": {"workload": "c5: 200,000 shapes x 64 x 1024 e4m3, K=8192, k1=20, Poisson "
+                       f"arrivals {args.serve_rates} q/s for {args.serve_seconds}s each, "
+                       "8..64 views per query", "slots": n_slots},
+            "build": build, "serving": runs}
 
 
 def fif_leg(L, torch, w, master, views, Q, q_np, qoff_np, exact_ids, args):
