@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
     ap.add_argument("--fif-steps", type=int, default=5)
     ap.add_argument("--kmeans-iters", type=int, default=10)
-    ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy"], default="c3",
                     help="c3: exhaustive precision headline (default); c4: batched F-IF + "
                          "S-IF plan; c5: continuous-batching serving")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -69,6 +69,21 @@ def main():
     import synth
     from paper_1604_01879_amd import _lib as L
 
+    if args.workload == "copy":
+        # a plain device copy of known size: calibrates the HBM byte counters
+        n = 1 << 30  # float32 elements, 4 GiB each way
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"workload": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "copies": args.steps + 1, "GBps": round(8 * n / dt / 1e9, 1)}))
+        return
     if args.workload in ("c4", "c5"):
         print(json.dumps(scale_bench(args)))
         return

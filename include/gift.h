@@ -233,6 +233,30 @@ gift_status gift_build_sif(int64_t n_shapes, int32_t k1, const int32_t* nbr_ids,
                            int32_t* post_id, float* post_val, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* Neighbour augmentation (Sec. 2.4.1, Eq. 10): sparse activation rows     */
+/* replaced by the mean of the rows of their top-k2 neighbours,            */
+/*   F_b := (1 / n_b) * sum over members i of F_i.                         */
+/* The table nbr_ids / nbr_scores [N][k1] holds F_i of every database shape */
+/* as a list (ids < 0 are padding).  Member j of output row b is table row */
+/* members[b][j] (ids < 0 skipped; a database shape lists itself first, so */
+/* k2 = 1 leaves it unchanged); when own_ids / own_scores [n_rows][k_own]  */
+/* are given, that list is one more member (a query outside the database). */
+/* n_b = number of members.  The right-hand side uses the un-augmented     */
+/* rows.  Output rows out_ids / out_scores [n_rows][k_out] list the        */
+/* coordinates in ascending id with their averaged memberships, padded     */
+/* with (-1, 0) (rows longer than k_out are cut); n_members [n_rows] (or    */
+/* NULL) receives n_b, so a query's self membership becomes q_self / n_b.  */
+/* Requires k2 * k1 + k_own <= 1024.                                       */
+gift_status gift_augment_neighbours(int64_t n_shapes, int32_t k1,
+                                   const int32_t* nbr_ids,
+                                   const float* nbr_scores, int32_t n_rows,
+                                   const int32_t* members, int32_t k2,
+                                   const int32_t* own_ids,
+                                   const float* own_scores, int32_t k_own,
+                                   int32_t* out_ids, float* out_scores,
+                                   int32_t k_out, int32_t* n_members,
+                                   void* stream);
+
 /* Re-ranking by Eq. 8 evaluated through the S-IF (Eq. 13 and 14):        */
 /*   S'(q, p) = sum_i min(F_q[i], F_p[i]) / (||F_q||_1 + ||F_p||_1 - num),  */
 /* the numerator taken over the coordinates where both are non-zero.  The  */

@@ -80,6 +80,9 @@ _sig = {
     "gift_build_sif_workspace": (C.c_size_t, [C.c_int64]),
     "gift_build_sif": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
                                    _P]),
+    "gift_augment_neighbours": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P,
+                                            C.c_int32, _P, _P, C.c_int32, _P, _P, C.c_int32, _P,
+                                            _P]),
     "gift_rerank_sif": (C.c_int32, [C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P,
                                     C.c_int32, _P, _P, _P, _P]),
     "gift_set_score_tuning": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
@@ -431,3 +434,20 @@ class FifPlan:
             self.close()
         except Exception:
             pass
+
+
+def gift_augment_neighbours(nbr_ids, nbr_scores, members, own_ids=None, own_scores=None,
+                            k_out=None, stream=None):
+    """Eq. 10 rows: (ids [n, k_out], scores [n, k_out], n_members [n])."""
+    N, k1 = nbr_ids.shape
+    n_rows, k2 = members.shape
+    k_own = int(own_ids.shape[1]) if own_ids is not None else 0
+    k_out = k_out or (k2 * k1 + k_own)
+    dev = nbr_ids.device
+    oi = torch.empty((n_rows, k_out), dtype=torch.int32, device=dev)
+    os_ = torch.empty((n_rows, k_out), dtype=torch.float32, device=dev)
+    nm = torch.empty(n_rows, dtype=torch.int32, device=dev)
+    _check(_lib.gift_augment_neighbours(N, k1, _ptr(nbr_ids), _ptr(nbr_scores), n_rows,
+                                        _ptr(members), k2, _ptr(own_ids), _ptr(own_scores), k_own,
+                                        _ptr(oi), _ptr(os_), k_out, _ptr(nm), _stream(stream)))
+    return oi, os_, nm

@@ -741,6 +741,27 @@ gift_status gift_build_sif(int64_t n_shapes, int32_t k1, const int32_t* nbr_ids,
   return GIFT_OK;
 }
 
+gift_status gift_augment_neighbours(int64_t n_shapes, int32_t k1, const int32_t* nbr_ids,
+                                   const float* nbr_scores, int32_t n_rows,
+                                   const int32_t* members, int32_t k2, const int32_t* own_ids,
+                                   const float* own_scores, int32_t k_own, int32_t* out_ids,
+                                   float* out_scores, int32_t k_out, int32_t* n_members,
+                                   void* stream) {
+  GIFT_CHECK(n_shapes >= 1 && n_shapes < ((int64_t)1 << 31), GIFT_EINVAL, "n_shapes out of range");
+  GIFT_CHECK(k1 >= 1 && k2 >= 1 && n_rows >= 0, GIFT_EINVAL, "bad sizes");
+  GIFT_CHECK(own_ids == nullptr || (own_scores != nullptr && k_own >= 1), GIFT_EINVAL,
+             "own row needs scores and k_own >= 1");
+  const int total = k2 * k1 + (own_ids ? k_own : 0);
+  GIFT_CHECK(total <= 1024, GIFT_EUNSUPPORTED, "k2 * k1 + k_own must be <= 1024");
+  GIFT_CHECK(k_out >= 1, GIFT_EINVAL, "k_out must be >= 1");
+  GIFT_CHECK(nbr_ids && nbr_scores && members && out_ids && out_scores, GIFT_EINVAL,
+             "null pointer");
+  launch_augment(nbr_ids, nbr_scores, n_shapes, k1, members, k2, own_ids, own_scores, k_own,
+                 n_rows, out_ids, out_scores, k_out, n_members, (hipStream_t)stream);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
 gift_status gift_rerank_sif(int64_t n_shapes, const float* l1, const int64_t* post_off,
                             const int32_t* post_id, const float* post_val, int32_t n_queries,
                             int32_t k1, const int32_t* q_ids, const float* q_scores,

@@ -278,6 +278,102 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   }
 }
 
+// ------------------------------------------------------------------ augment
+// Neighbour augmentation (Eq. 10): output row b is the mean of its member
+// rows, F_b := (1/n) sum over the valid members i of F_i, where member j of
+// row b is table row members[b][j] (ids < 0 skipped) and, when own_ids is
+// given, the row's own list counts as one more member.  One block per row:
+// the (id, value) pairs of all members are gathered into LDS, sorted by
+// (id, member), summed per id in that order and divided by n; the result is
+// written in ascending id, padded with (-1, 0).
+constexpr int AUG_CAP = 1024;
+
+__global__ __launch_bounds__(256) void augment_kernel(
+    const int32_t* __restrict__ t_ids, const float* __restrict__ t_val, int64_t N, int k1,
+    const int32_t* __restrict__ members, int k2, const int32_t* __restrict__ own_ids,
+    const float* __restrict__ own_val, int k_own, int32_t* __restrict__ out_ids,
+    float* __restrict__ out_val, int k_out, int32_t* __restrict__ n_members) {
+  __shared__ uint64_t key[AUG_CAP];  // (id << 32) | slot
+  __shared__ float val[AUG_CAP];
+  __shared__ int nmem;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    int n = own_ids != nullptr ? 1 : 0;
+    for (int j = 0; j < k2; ++j) {
+      const int32_t m = members[(int64_t)b * k2 + j];
+      if (m >= 0 && m < N) ++n;
+    }
+    nmem = n;
+  }
+  __syncthreads();
+  // slot order: members in order, then the own row
+  const int total = k2 * k1 + (own_ids != nullptr ? k_own : 0);
+  for (int s = tid; s < total; s += 256) {
+    int32_t id = -1;
+    float v = 0.f;
+    if (s < k2 * k1) {
+      const int32_t m = members[(int64_t)b * k2 + s / k1];
+      if (m >= 0 && m < N) {
+        id = t_ids[(int64_t)m * k1 + s % k1];
+        v = t_val[(int64_t)m * k1 + s % k1];
+      }
+    } else {
+      id = own_ids[(int64_t)b * k_own + (s - k2 * k1)];
+      v = own_val[(int64_t)b * k_own + (s - k2 * k1)];
+    }
+    key[s] = (id >= 0 && id < N) ? (((uint64_t)(uint32_t)id << 32) | (uint32_t)s) : ~0ull;
+    val[s] = v;
+  }
+  int np2 = 1;
+  while (np2 < total) np2 <<= 1;
+  for (int s = total + tid; s < np2; s += 256) key[s] = ~0ull;
+  __syncthreads();
+  for (int kk = 2; kk <= np2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < np2; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & kk) == 0;
+          const uint64_t x = key[i], y = key[ix];
+          if ((x > y) == up) { key[i] = y; key[ix] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const float nf = nmem > 0 ? (float)nmem : 1.f;
+    int o = 0;
+    for (int s = 0; s < total && key[s] != ~0ull;) {
+      const uint32_t id = (uint32_t)(key[s] >> 32);
+      float sum = 0.f;
+      int t = s;
+      for (; t < total && key[t] != ~0ull && (uint32_t)(key[t] >> 32) == id; ++t)
+        sum += val[(uint32_t)key[t]];
+      if (o < k_out) {
+        out_ids[(int64_t)b * k_out + o] = (int32_t)id;
+        out_val[(int64_t)b * k_out + o] = sum / nf;
+      }
+      ++o;
+      s = t;
+    }
+    for (; o < k_out; ++o) {
+      out_ids[(int64_t)b * k_out + o] = -1;
+      out_val[(int64_t)b * k_out + o] = 0.f;
+    }
+    if (n_members != nullptr) n_members[b] = nmem;
+  }
+}
+
+void launch_augment(const int32_t* t_ids, const float* t_val, int64_t N, int k1,
+                    const int32_t* members, int k2, const int32_t* own_ids, const float* own_val,
+                    int k_own, int n_rows, int32_t* out_ids, float* out_val, int k_out,
+                    int32_t* n_members, hipStream_t st) {
+  if (n_rows <= 0) return;
+  hipLaunchKernelGGL(augment_kernel, dim3(n_rows), dim3(256), 0, st, t_ids, t_val, N, k1,
+                     members, k2, own_ids, own_val, k_own, out_ids, out_val, k_out, n_members);
+}
+
 void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* post_id,
                        const float* post_val, int64_t N, const int32_t* q_id, const float* q_val,
                        const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,

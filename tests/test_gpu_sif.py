@@ -157,3 +157,49 @@ def test_sif_end_to_end_after_exhaustive(L):
         firm[:-1] &= gaps > 1e-5
         firm[1:] &= gaps > 1e-5
         assert np.array_equal(gi[b][firm], ref_ids[0][firm])
+
+
+def test_neighbour_augmentation_matches_oracle(L):
+    """Eq. 10 on database rows (members = each shape's own top-k2, itself
+    first) and on outside queries (their own list is one more member)."""
+    _say("neighbour augmentation")
+    rng = np.random.default_rng(21)
+    N, k1, k2 = 150, 10, 4
+    ids, sc = _random_lists(rng, N, k1)
+    F = np.zeros((N, N))
+    for p in range(N):
+        F[p, ids[p]] = sc[p]
+    oi, os_, nm = L.gift_augment_neighbours(_t(ids), _t(sc), _t(ids[:, :k2].copy()))
+    torch.cuda.synchronize()
+    ref = O.neighbour_augment(F, ids, k2)
+    oi, os_ = oi.cpu().numpy(), os_.cpu().numpy()
+    assert (nm.cpu().numpy() == k2).all()
+    for p in range(N):
+        got = np.zeros(N)
+        valid = oi[p] >= 0
+        got[oi[p][valid]] = os_[p][valid]
+        assert list(oi[p][valid]) == sorted(oi[p][valid])
+        assert np.allclose(got, ref[p], rtol=1e-6, atol=1e-7)
+    # k2 = 1: unchanged rows
+    oi1, os1, _ = L.gift_augment_neighbours(_t(ids), _t(sc), _t(ids[:, :1].copy()), k_out=k1)
+    for p in range(0, N, 7):
+        order = np.argsort(ids[p])
+        assert np.array_equal(oi1.cpu().numpy()[p], ids[p][order])
+        assert np.array_equal(os1.cpu().numpy()[p], sc[p][order])
+    # outside queries: own list + top-(k2-1) database neighbours
+    qi = np.stack([rng.choice(N, size=k1, replace=False) for _ in range(5)]).astype(np.int32)
+    qv = np.sort(rng.random((5, k1)).astype(np.float32), axis=1)[:, ::-1].copy()
+    mem = qi[:, :k2 - 1].copy()
+    gi, gs, gn = L.gift_augment_neighbours(_t(ids), _t(sc), _t(mem), _t(qi), _t(qv))
+    gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
+    assert (gn.cpu().numpy() == k2).all()
+    for b in range(5):
+        dense = np.zeros(N)
+        dense[qi[b]] += qv[b]
+        for i in mem[b]:
+            dense += F[i]
+        dense /= k2
+        got = np.zeros(N)
+        valid = gi[b] >= 0
+        got[gi[b][valid]] = gs[b][valid]
+        assert np.allclose(got, dense, rtol=1e-6, atol=1e-7)
