@@ -257,6 +257,23 @@ gift_status gift_augment_neighbours(int64_t n_shapes, int32_t k1,
                                    int32_t k_out, int32_t* n_members,
                                    void* stream);
 
+/* Aggregated contextual activation (Sec. 2.4, Eq. 9): the element-wise    */
+/* generalised mean with exponent alpha of two sparse activations of the   */
+/* same shapes from two similarity measures,                               */
+/*   F = ((F1^alpha + F2^alpha) / 2)^(1/alpha),                            */
+/* over the union of each row's coordinates (a coordinate missing from one */
+/* row contributes 0).  Rows ids1/scores1 [n_rows][k_a] and ids2/scores2    */
+/* [n_rows][k_b] (ids < 0 skipped, ids distinct within a row); output       */
+/* [n_rows][k_out] in ascending id, padded with (-1, 0).  Neighbour        */
+/* co-augmentation (Eq. 11) is gift_augment_neighbours with the other      */
+/* measure's neighbour ids as members.  alpha > 0; k_a + k_b <= 1024.      */
+gift_status gift_fuse_activations(int32_t n_rows, const int32_t* ids1,
+                                  const float* scores1, int32_t k_a,
+                                  const int32_t* ids2, const float* scores2,
+                                  int32_t k_b, float alpha, int32_t* out_ids,
+                                  float* out_scores, int32_t k_out,
+                                  void* stream);
+
 /* Re-ranking by Eq. 8 evaluated through the S-IF (Eq. 13 and 14):        */
 /*   S'(q, p) = sum_i min(F_q[i], F_p[i]) / (||F_q||_1 + ||F_p||_1 - num),  */
 /* the numerator taken over the coordinates where both are non-zero.  The  */

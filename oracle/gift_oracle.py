@@ -26,7 +26,7 @@ __all__ = [
     "fif_scores", "fif_scores_literal", "build_sif", "rerank_sif",
     "rerank_sif_dense", "jaccard_dense", "quantize_views", "dequantize",
     "lowprec_exhaustive_scores", "recall_at_k", "self_score",
-    "neighbour_augment",
+    "neighbour_augment", "fuse_activations", "co_augment",
 ]
 
 
@@ -402,6 +402,19 @@ def neighbour_augment(F: np.ndarray, nbr_ids: np.ndarray, k2: int) -> np.ndarray
             out[q] += F[i]
         out[q] /= len(nb)
     return out
+
+
+def co_augment(F1: np.ndarray, F2: np.ndarray, nbr1: np.ndarray, nbr2: np.ndarray, k2: int):
+    """Eq. 11: each measure's rows averaged over the other measure's top-k2
+    neighbours (Jacobi, un-augmented right-hand sides)."""
+    return neighbour_augment(F1, nbr2, k2), neighbour_augment(F2, nbr1, k2)
+
+
+def fuse_activations(F1: np.ndarray, F2: np.ndarray, alpha: float) -> np.ndarray:
+    """Eq. 9: element-wise generalised mean with exponent alpha of two
+    activations, ((F1^a + F2^a) / 2)^(1/a), with 0^a = 0 for a > 0."""
+    a = float(alpha)
+    return ((np.power(F1, a) + np.power(F2, a)) / 2.0) ** (1.0 / a)
 
 
 # --------------------------------------------------------------------------

@@ -83,6 +83,8 @@ _sig = {
     "gift_augment_neighbours": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P,
                                             C.c_int32, _P, _P, C.c_int32, _P, _P, C.c_int32, _P,
                                             _P]),
+    "gift_fuse_activations": (C.c_int32, [C.c_int32, _P, _P, C.c_int32, _P, _P, C.c_int32,
+                                          C.c_float, _P, _P, C.c_int32, _P]),
     "gift_rerank_sif": (C.c_int32, [C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P,
                                     C.c_int32, _P, _P, _P, _P]),
     "gift_set_score_tuning": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
@@ -451,3 +453,15 @@ def gift_augment_neighbours(nbr_ids, nbr_scores, members, own_ids=None, own_scor
                                         _ptr(members), k2, _ptr(own_ids), _ptr(own_scores), k_own,
                                         _ptr(oi), _ptr(os_), k_out, _ptr(nm), _stream(stream)))
     return oi, os_, nm
+
+
+def gift_fuse_activations(ids1, sc1, ids2, sc2, alpha=0.5, k_out=None, stream=None):
+    """Eq. 9 rows: (ids [n, k_out], scores [n, k_out])."""
+    n, k_a = ids1.shape
+    k_b = int(ids2.shape[1])
+    k_out = k_out or (k_a + k_b)
+    oi = torch.empty((n, k_out), dtype=torch.int32, device=ids1.device)
+    os_ = torch.empty((n, k_out), dtype=torch.float32, device=ids1.device)
+    _check(_lib.gift_fuse_activations(n, _ptr(ids1), _ptr(sc1), k_a, _ptr(ids2), _ptr(sc2), k_b,
+                                      float(alpha), _ptr(oi), _ptr(os_), k_out, _stream(stream)))
+    return oi, os_

@@ -762,6 +762,21 @@ gift_status gift_augment_neighbours(int64_t n_shapes, int32_t k1, const int32_t*
   return GIFT_OK;
 }
 
+gift_status gift_fuse_activations(int32_t n_rows, const int32_t* ids1, const float* scores1,
+                                 int32_t k_a, const int32_t* ids2, const float* scores2,
+                                 int32_t k_b, float alpha, int32_t* out_ids, float* out_scores,
+                                 int32_t k_out, void* stream) {
+  GIFT_CHECK(n_rows >= 0 && k_a >= 1 && k_b >= 1 && k_a + k_b <= 1024 && k_out >= 1,
+             GIFT_EINVAL, "bad sizes (k_a + k_b <= 1024)");
+  GIFT_CHECK(alpha > 0.f, GIFT_EINVAL, "alpha must be > 0");
+  GIFT_CHECK(ids1 && scores1 && ids2 && scores2 && out_ids && out_scores, GIFT_EINVAL,
+             "null pointer");
+  launch_fuse(ids1, scores1, k_a, ids2, scores2, k_b, alpha, n_rows, out_ids, out_scores, k_out,
+              (hipStream_t)stream);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
 gift_status gift_rerank_sif(int64_t n_shapes, const float* l1, const int64_t* post_off,
                             const int32_t* post_id, const float* post_val, int32_t n_queries,
                             int32_t k1, const int32_t* q_ids, const float* q_scores,

@@ -134,6 +134,9 @@ void launch_augment(const int32_t* t_ids, const float* t_val, int64_t N, int k1,
                     const int32_t* members, int k2, const int32_t* own_ids, const float* own_val,
                     int k_own, int n_rows, int32_t* out_ids, float* out_val, int k_out,
                     int32_t* n_members, hipStream_t st);
+void launch_fuse(const int32_t* i1, const float* v1, int k_a, const int32_t* i2, const float* v2,
+                 int k_b, float alpha, int n_rows, int32_t* out_ids, float* out_val, int k_out,
+                 hipStream_t st);
 void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* post_id,
                        const float* post_val, int64_t N, const int32_t* q_id, const float* q_val,
                        const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,

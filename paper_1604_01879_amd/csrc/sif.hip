@@ -374,6 +374,78 @@ void launch_augment(const int32_t* t_ids, const float* t_val, int64_t N, int k1,
                      members, k2, own_ids, own_val, k_own, out_ids, out_val, k_out, n_members);
 }
 
+// ------------------------------------------------------------------ fusion
+// Eq. 9: aggregated contextual activation of two measures, the element-wise
+// generalised mean ((F1^a + F2^a) / 2)^(1/a) over the union of the two
+// rows' coordinates (a coordinate missing from one row has membership 0
+// there).  One block per row; ids are distinct within a row.
+__global__ __launch_bounds__(256) void fuse_kernel(
+    const int32_t* __restrict__ i1, const float* __restrict__ v1, int k_a,
+    const int32_t* __restrict__ i2, const float* __restrict__ v2, int k_b, float alpha,
+    int32_t* __restrict__ out_ids, float* __restrict__ out_val, int k_out) {
+  __shared__ uint64_t key[AUG_CAP];  // (id << 32) | slot
+  __shared__ float val[AUG_CAP];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int total = k_a + k_b;
+  for (int s = tid; s < total; s += 256) {
+    const int32_t id = s < k_a ? i1[(int64_t)b * k_a + s] : i2[(int64_t)b * k_b + (s - k_a)];
+    const float v = s < k_a ? v1[(int64_t)b * k_a + s] : v2[(int64_t)b * k_b + (s - k_a)];
+    key[s] = id >= 0 ? (((uint64_t)(uint32_t)id << 32) | (uint32_t)s) : ~0ull;
+    val[s] = v;
+  }
+  int np2 = 1;
+  while (np2 < total) np2 <<= 1;
+  for (int s = total + tid; s < np2; s += 256) key[s] = ~0ull;
+  __syncthreads();
+  for (int kk = 2; kk <= np2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < np2; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool up = (i & kk) == 0;
+          const uint64_t x = key[i], y = key[ix];
+          if ((x > y) == up) { key[i] = y; key[ix] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const float inv_a = 1.f / alpha;
+    int o = 0;
+    for (int s = 0; s < total && key[s] != ~0ull;) {
+      const uint32_t id = (uint32_t)(key[s] >> 32);
+      float a = 0.f, c = 0.f;
+      int t = s;
+      for (; t < total && key[t] != ~0ull && (uint32_t)(key[t] >> 32) == id; ++t) {
+        const uint32_t slot = (uint32_t)key[t];
+        if ((int)slot < k_a) a = val[slot]; else c = val[slot];
+      }
+      const float pa = a > 0.f ? powf(a, alpha) : 0.f;
+      const float pc = c > 0.f ? powf(c, alpha) : 0.f;
+      const float m = 0.5f * (pa + pc);
+      if (o < k_out) {
+        out_ids[(int64_t)b * k_out + o] = (int32_t)id;
+        out_val[(int64_t)b * k_out + o] = m > 0.f ? powf(m, inv_a) : 0.f;
+      }
+      ++o;
+      s = t;
+    }
+    for (; o < k_out; ++o) {
+      out_ids[(int64_t)b * k_out + o] = -1;
+      out_val[(int64_t)b * k_out + o] = 0.f;
+    }
+  }
+}
+
+void launch_fuse(const int32_t* i1, const float* v1, int k_a, const int32_t* i2, const float* v2,
+                 int k_b, float alpha, int n_rows, int32_t* out_ids, float* out_val, int k_out,
+                 hipStream_t st) {
+  if (n_rows <= 0) return;
+  hipLaunchKernelGGL(fuse_kernel, dim3(n_rows), dim3(256), 0, st, i1, v1, k_a, i2, v2, k_b,
+                     alpha, out_ids, out_val, k_out);
+}
+
 void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* post_id,
                        const float* post_val, int64_t N, const int32_t* q_id, const float* q_val,
                        const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,

@@ -203,3 +203,31 @@ def test_neighbour_augmentation_matches_oracle(L):
         valid = gi[b] >= 0
         got[gi[b][valid]] = gs[b][valid]
         assert np.allclose(got, dense, rtol=1e-6, atol=1e-7)
+
+
+def test_fusion_and_co_augmentation_match_oracle(L):
+    """Eq. 11 (co-augmentation through gift_augment_neighbours with the other
+    measure's neighbours) followed by Eq. 9 (alpha = 0.5 and 1)."""
+    _say("fusion")
+    rng = np.random.default_rng(24)
+    N, k1, k2 = 120, 8, 3
+    i1, s1 = _random_lists(rng, N, k1)
+    i2, s2 = _random_lists(rng, N, k1)
+    F1 = np.zeros((N, N))
+    F2 = np.zeros((N, N))
+    for p in range(N):
+        F1[p, i1[p]] = s1[p]
+        F2[p, i2[p]] = s2[p]
+    A1, A2 = O.co_augment(F1, F2, i1, i2, k2)
+    a1i, a1s, _ = L.gift_augment_neighbours(_t(i1), _t(s1), _t(i2[:, :k2].copy()))
+    a2i, a2s, _ = L.gift_augment_neighbours(_t(i2), _t(s2), _t(i1[:, :k2].copy()))
+    for alpha in (0.5, 1.0):
+        fi, fs = L.gift_fuse_activations(a1i, a1s, a2i, a2s, alpha)
+        torch.cuda.synchronize()
+        ref = O.fuse_activations(A1, A2, alpha)
+        fi, fs = fi.cpu().numpy(), fs.cpu().numpy()
+        for p in range(N):
+            got = np.zeros(N)
+            valid = fi[p] >= 0
+            got[fi[p][valid]] = fs[p][valid]
+            assert np.allclose(got, ref[p], rtol=2e-6, atol=1e-7)

@@ -355,3 +355,38 @@ def test_recall_metric():
     a = np.array([[1, 2, 3, 4]])
     b = np.array([[4, 3, 9, 8]])
     assert O.recall_at_k(a, b, 4) == (0.5, 0.5)
+
+
+# ---------------------------------------------------------------- Eq. 9 / 11
+def test_fusion_generalised_mean_closed_forms():
+    rng = np.random.default_rng(22)
+    a = rng.random(50)
+    b = rng.random(50)
+    # alpha = 1 is the arithmetic mean
+    assert np.allclose(O.fuse_activations(a, b, 1.0), (a + b) / 2)
+    # equal inputs are a fixed point for any alpha
+    assert np.allclose(O.fuse_activations(a, a, 0.5), a)
+    # alpha = 0.5 written out: ((sqrt a + sqrt b) / 2)^2
+    assert np.allclose(O.fuse_activations(a, b, 0.5), ((np.sqrt(a) + np.sqrt(b)) / 2) ** 2)
+    # one side zero: a / 2^(1/alpha)
+    assert np.allclose(O.fuse_activations(a, np.zeros(50), 0.5), a / 4)
+    # the generalised mean lies between min and max and grows with alpha
+    lo = O.fuse_activations(a, b, 0.5)
+    hi = O.fuse_activations(a, b, 1.0)
+    assert (lo <= hi + 1e-15).all()
+    assert (lo >= np.minimum(a, b) - 1e-15).all() and (hi <= np.maximum(a, b) + 1e-15).all()
+
+
+def test_co_augmentation_swaps_neighbour_sets():
+    rng = np.random.default_rng(23)
+    N = 12
+    F1 = rng.random((N, N))
+    F2 = rng.random((N, N))
+    n1 = np.stack([np.concatenate([[p], rng.permutation(np.delete(np.arange(N), p))])
+                   for p in range(N)])
+    n2 = np.stack([np.concatenate([[p], rng.permutation(np.delete(np.arange(N), p))])
+                   for p in range(N)])
+    A1, A2 = O.co_augment(F1, F2, n1, n2, 3)
+    for p in range(N):
+        assert np.allclose(A1[p], F1[n2[p, :3]].mean(0))
+        assert np.allclose(A2[p], F2[n1[p, :3]].mean(0))
