@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
     ap.add_argument("--fif-steps", type=int, default=5)
     ap.add_argument("--kmeans-iters", type=int, default=10)
-    ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy", "sweep"], default="c3",
                     help="c3: exhaustive precision headline (default); c4: batched F-IF + "
                          "S-IF plan; c5: continuous-batching serving")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -86,6 +86,9 @@ def main():
         return
     if args.workload in ("c4", "c5"):
         print(json.dumps(scale_bench(args)))
+        return
+    if args.workload == "sweep":
+        print(json.dumps(sweep_bench(args)))
         return
 
     dev = torch.device("cuda:0")
@@ -379,6 +382,48 @@ def scale_bench(args):
                        f"arrivals {args.serve_rates} q/s for {args.serve_seconds}s each, "
                        "8..64 views per query", "slots": n_slots},
             "build": build, "serving": runs}
+
+
+def sweep_bench(args):
+    """F-IF vocabulary size x Multiple Assignment sweep (the shape of the
+    paper's Fig. 5): recall of Eq. 4 against exact Eq. 3 and time per query."""
+    import torch
+    import synth
+    from paper_1604_01879_amd import _lib as L
+    dev = torch.device("cuda:0")
+    w = synth.PRESETS["sweep"]
+    db, _, _ = synth.make_db(w)
+    q, qoff, _ = synth.make_queries(w)
+    master = torch.from_numpy(db).to(dev)
+    V = L.Views(master, w.n_views, L.F32)
+    Q = L.Queries(torch.from_numpy(q).to(dev), torch.from_numpy(qoff))
+    k, R, B = w.top_k, 64, w.n_queries
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps
+
+    (ex_ids, _, _), t_ex = timed(lambda: L.gift_query_exhaustive(V, Q, k, R))
+    ex_ids = ex_ids.cpu().numpy()
+    rows = []
+    for K in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        init = synth.kmeans_init_idx(db.shape[0], K, w.seed)
+        cb, _, it = L.gift_build_codebook(master, K, init, 10)
+        for ma in (1, 2, 3):
+            F = L.gift_build_fif(V, cb, ma)
+            (ids, _, _), t = timed(lambda: L.gift_query_fif(V, F, Q, k, R))
+            rec = recall(ids.cpu().numpy(), ex_ids, k)
+            rows.append({"K": K, "MA": ma, "kmeans_iters": it, "recall_at_k_vs_eq3": rec[0],
+                         "ms_per_query": round(t / B * 1e3, 4)})
+            log(f"sweep K={K} MA={ma}: recall {rec[0]:.3f}, {t / B * 1e3:.3f} ms/query")
+    return {"workload": "sweep: F-IF K x MA, 4,096 shapes (40 classes, 8 viewpoint sub-centres "
+                        "each) x 64 views x 256-d, 256 queries, top-20",
+            "exhaustive_ms_per_query": round(t_ex / B * 1e3, 4), "rows": rows}
 
 
 def fif_leg(L, torch, w, master, views, Q, q_np, qoff_np, exact_ids, args):

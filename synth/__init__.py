@@ -28,7 +28,7 @@ import numpy as np
 
 # Order in which child seed streams are spawned from SeedSequence(seed).
 _STREAMS = ("centres", "db_classes", "db_noise", "q_classes", "q_counts",
-            "q_noise", "kmeans_init", "arrivals")
+            "q_noise", "kmeans_init", "arrivals", "subcentres")
 _CHUNK = 2048  # views per noise chunk; each chunk has its own seed
 
 
@@ -49,6 +49,8 @@ class Workload:
     ma: tuple              # multiple-assignment values exercised
     top_k: int
     seed: int = 0
+    n_sub: int = 0         # per-class viewpoint sub-centres (0: none)
+    sub_sigma: float = 0.5  # scale of the sub-centre offsets
 
     def scaled(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -68,6 +70,10 @@ PRESETS = {
     "c4": Workload("c4", 50000, 100, 64, 4096, 0.3, 0.2, 1024, 12, 64, 8192, (1,), 100),
     # Serving: 200,000 shapes (200 classes) x 1024-d, 8..64 query views.
     "c5": Workload("c5", 200000, 200, 64, 1024, 0.3, 0.2, 1024, 8, 64, 8192, (1,), 100),
+    # F-IF K x MA sweep (shape of the paper's Fig. 5): 4,096 shapes with 8
+    # viewpoint sub-centres per class, 256-d, 256 queries, top-20.
+    "sweep": Workload("sweep", 4096, 40, 64, 256, 0.3, 0.1, 256, 64, 64, 256, (1, 2, 3), 20,
+                      0, 8, 0.8),
 }
 
 
@@ -90,6 +96,25 @@ def class_centres(w: Workload) -> np.ndarray:
     """Per-class centres mu_c ~ N(0, I_d), float32 [C, d]."""
     rng = np.random.Generator(np.random.PCG64(_streams(w.seed)["centres"]))
     return rng.standard_normal((w.n_classes, w.dim), dtype=np.float32)
+
+
+def subcentre_offsets(w: Workload) -> np.ndarray:
+    """Per (class, viewpoint) offsets nu ~ sub_sigma * N(0, I_d), float32
+    [C, n_sub, d]: view j of a shape is drawn around mu_class + nu[class,
+    j mod n_sub], so views taken from the same viewpoint agree across the
+    shapes of a class (the structure an inverted file can exploit)."""
+    rng = np.random.Generator(np.random.PCG64(_streams(w.seed)["subcentres"]))
+    nu = rng.standard_normal((w.n_classes, max(1, w.n_sub), w.dim), dtype=np.float32)
+    return (nu * np.float32(w.sub_sigma)).astype(np.float32)
+
+
+def _centre_table(w: Workload):
+    """Centres indexed by class * n_sub + viewpoint (or by class alone)."""
+    mu = class_centres(w)
+    if w.n_sub <= 0:
+        return mu
+    nu = subcentre_offsets(w)
+    return (mu[:, None, :] + nu).reshape(w.n_classes * w.n_sub, w.dim)
 
 
 def _view_classes(rng, base_cls: np.ndarray, n_views: int, C: int, p_dis: float):
@@ -140,7 +165,7 @@ def make_db(w: Workload, out: np.ndarray | None = None, threads=None):
     ``out`` may be a preallocated float32 array (e.g. pinned host memory).
     """
     st = _streams(w.seed)
-    centres = class_centres(w)
+    centres = _centre_table(w)
     shape_cls = (np.arange(w.n_shapes) % w.n_classes).astype(np.int32)
     rng = np.random.Generator(np.random.PCG64(st["db_classes"]))
     vclass = _view_classes(rng, shape_cls, w.n_views, w.n_classes, w.p_dis)
@@ -148,7 +173,11 @@ def make_db(w: Workload, out: np.ndarray | None = None, threads=None):
     if out is None:
         out = np.empty((nv, w.dim), dtype=np.float32)
     assert out.shape == (nv, w.dim) and out.dtype == np.float32
-    _fill_views(out, vclass, centres, w.sigma, w.seed, 1, threads)
+    rows = vclass
+    if w.n_sub > 0:
+        vpt = (np.arange(nv) % w.n_views) % w.n_sub
+        rows = (vclass * w.n_sub + vpt).astype(np.int32)
+    _fill_views(out, rows, centres, w.sigma, w.seed, 1, threads)
     return out, shape_cls, vclass
 
 
@@ -165,7 +194,7 @@ def make_queries(w: Workload, threads=None):
     Returns (views float32 [sum m, d], offsets int32 [B+1], classes int32 [B]).
     """
     st = _streams(w.seed)
-    centres = class_centres(w)
+    centres = _centre_table(w)
     rng = np.random.Generator(np.random.PCG64(st["q_classes"]))
     qcls = rng.integers(0, w.n_classes, size=w.n_queries, dtype=np.int32)
     counts = query_counts(w)
@@ -177,7 +206,11 @@ def make_queries(w: Workload, threads=None):
         shift = rng.integers(1, w.n_classes, size=vclass.shape[0], dtype=np.int32)
         vclass = np.where(dis, (vclass + shift) % w.n_classes, vclass).astype(np.int32)
     out = np.empty((int(offsets[-1]), w.dim), dtype=np.float32)
-    _fill_views(out, vclass, centres, w.sigma, w.seed, 2, threads)
+    rows = vclass
+    if w.n_sub > 0:
+        vpt = (np.arange(int(offsets[-1])) - np.repeat(offsets[:-1], counts)) % w.n_sub
+        rows = (vclass * w.n_sub + vpt).astype(np.int32)
+    _fill_views(out, rows, centres, w.sigma, w.seed, 2, threads)
     return out, offsets, qcls
 
 

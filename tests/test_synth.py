@@ -56,3 +56,22 @@ def test_kmeans_init_and_sample_and_arrivals():
     assert len(set(s.tolist())) == 500
     t = synth.poisson_arrivals(200.0, 10.0, 0)
     assert abs(len(t) - 2000) < 200 and (np.diff(t) > 0).all()
+
+
+def test_subcentres_group_views_by_viewpoint():
+    w = synth.PRESETS["c1"].scaled(n_shapes=80, dim=48, n_queries=4, n_sub=4, sub_sigma=1.0)
+    db, scls, vcls = synth.make_db(w)
+    assert np.allclose(np.linalg.norm(db.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    x = db.astype(np.float64)
+    # shapes 0 and 40 share class 0: same-viewpoint views are closer than
+    # other-viewpoint views of the same class
+    a, b = x[0:64], x[40 * 64:41 * 64]
+    sim = a @ b.T
+    vp = np.arange(64) % 4
+    same = vp[:, None] == vp[None, :]
+    cls_ok = (vcls[0:64][:, None] == 0) & (vcls[40 * 64:41 * 64][None, :] == 0)
+    assert sim[same & cls_ok].mean() > sim[~same & cls_ok].mean() + 0.05
+    # without sub-centres the preset data is unchanged
+    base, _, _ = synth.make_db(synth.PRESETS["c1"].scaled(n_shapes=10, dim=32))
+    again, _, _ = synth.make_db(synth.PRESETS["c1"].scaled(n_shapes=10, dim=32, n_sub=0))
+    assert np.array_equal(base, again)
