@@ -146,19 +146,24 @@ def main():
         return dict(total=total, lat=np.array(lat), ids=ids, scores=sc, flags=flags, kern=kern)
 
     main_run = run(args.dtype, args.steps, args.warmup, prof=True)
-    ref_run = main_run if args.dtype == "f32" else run("f32", args.fp32_steps, 1, prof=True)
+    if args.dtype == "f32":
+        ref_run = main_run
+    elif args.fp32_steps > 0:
+        ref_run = run("f32", args.fp32_steps, 1, prof=True)
+    else:
+        ref_run = None
     fp8_run = run("fp8", args.fp8_steps, 1) if args.dtype != "fp8" and args.fp8_steps else None
 
     B = w.n_queries
     qps = B * args.steps / main_run["total"]
     ms_step = main_run["total"] / args.steps * 1e3
-    exact_ids = ref_run["ids"]
-    exact_ok = bool(ref_run["flags"].all())
+    exact_ids = ref_run["ids"] if ref_run is not None else main_run["ids"]
+    exact_ok = bool(ref_run["flags"].all()) if ref_run is not None else False
     r100 = recall(main_run["ids"], exact_ids, 100 if k >= 100 else k)
     r10 = recall(main_run["ids"], exact_ids, min(10, k))
     # score error of the returned list against the exact (float32-certified) scores
     err = 0.0
-    for b in range(B):
+    for b in range(B if ref_run is not None else 0):
         ref = dict(zip(exact_ids[b].tolist(), ref_run["scores"][b].tolist()))
         for i, s in zip(main_run["ids"][b].tolist(), main_run["scores"][b].tolist()):
             if i in ref:
@@ -206,7 +211,7 @@ def main():
                      "kernel": "score_tiles",
                      "algorithmic_flops_per_launch": flops},
     }
-    if ref_run is not main_run:
+    if ref_run is not None and ref_run is not main_run:
         f32_qps = B * args.fp32_steps / ref_run["total"]
         result["fp32_path"] = {"queries_per_s": round(f32_qps, 2),
                                "speedup_of_headline": round(qps / f32_qps, 2),
@@ -216,7 +221,7 @@ def main():
         result["fp8_path"] = {"queries_per_s": round(B * args.fp8_steps / fp8_run["total"], 2),
                               "recall_at100_mean": f8[0], "recall_at100_min": f8[1]}
 
-    if args.fif:
+    if args.fif and ref_run is not None:
         try:
             result["fif_path"] = fif_leg(L, torch, w, master, views, Q, q_np, qoff_np,
                                          exact_ids, args)
