@@ -605,22 +605,33 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
 }
 
 // S[b][p] = (sum over the query's views of the decoded max, 0 where no view
-// of p shares the word) / m, summed in ascending view order.
+// of p shares the word) / m, summed in ascending view order; staged through
+// LDS as reduce_queries_kernel.
 __global__ __launch_bounds__(256) void reduce_fif_kernel(const uint32_t* __restrict__ mbuf,
                                                          int64_t ldm, int64_t n_shapes,
                                                          const int32_t* __restrict__ qoff,
                                                          float* __restrict__ S) {
+  __shared__ uint32_t tile[256 * 65];
   const int b = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n_shapes) return;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lo = qoff[b], hi = qoff[b + 1];
-  const uint32_t* row = mbuf + p * ldm;
   float acc = 0.f;
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t u = row[i];
-    if (u != 0u) acc += order_float(u);
+  for (int c0 = lo; c0 < hi; c0 += 64) {
+    const int w = hi - c0 < 64 ? hi - c0 : 64;
+    __syncthreads();
+    for (int r = wave; r < 256; r += 4) {
+      const int64_t p = p0 + r;
+      if (p < n_shapes && lane < w) tile[r * 65 + lane] = mbuf[p * ldm + c0 + lane];
+    }
+    __syncthreads();
+    for (int i = 0; i < w; ++i) {
+      const uint32_t u = tile[tid * 65 + i];
+      if (u != 0u) acc += order_float(u);
+    }
   }
-  S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
+  const int64_t p = p0 + tid;
+  if (p < n_shapes) S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
 }
 
 void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,

@@ -185,19 +185,31 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
 }
 
 // ------------------------------------------------------------------ mean
-// S[b][p] = (sum over the query's views, ascending) / m.  One thread per
-// (query, shape); consecutive threads take consecutive shapes.
+// S[b][p] = (sum over the query's views, ascending) / m.  One block per
+// (256 shapes, query): the query's columns of the 256 mbuf rows are staged
+// through LDS 64 at a time with one wave reading one 256-byte row segment
+// (coalesced), then each thread sums its shape's values in view order.
 __global__ __launch_bounds__(256) void reduce_queries_kernel(
     const float* __restrict__ mbuf, int64_t ldm, int64_t n_shapes,
     const int32_t* __restrict__ qoff, float* __restrict__ S) {
+  __shared__ float tile[256 * 65];
   const int b = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n_shapes) return;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lo = qoff[b], hi = qoff[b + 1];
-  const float* row = mbuf + p * ldm;
   float acc = 0.f;
-  for (int i = lo; i < hi; ++i) acc += row[i];
-  S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
+  for (int c0 = lo; c0 < hi; c0 += 64) {
+    const int w = hi - c0 < 64 ? hi - c0 : 64;
+    __syncthreads();
+    for (int r = wave; r < 256; r += 4) {
+      const int64_t p = p0 + r;
+      if (p < n_shapes && lane < w) tile[r * 65 + lane] = mbuf[p * ldm + c0 + lane];
+    }
+    __syncthreads();
+    for (int i = 0; i < w; ++i) acc += tile[tid * 65 + i];
+  }
+  const int64_t p = p0 + tid;
+  if (p < n_shapes) S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
 }
 
 void launch_reduce_queries(const float* mbuf, int64_t ldm, int64_t n_shapes,
