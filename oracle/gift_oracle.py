@@ -26,7 +26,8 @@ __all__ = [
     "fif_scores", "fif_scores_literal", "build_sif", "rerank_sif",
     "rerank_sif_dense", "jaccard_dense", "quantize_views", "dequantize",
     "lowprec_exhaustive_scores", "recall_at_k", "self_score",
-    "neighbour_augment", "fuse_activations", "co_augment",
+    "neighbour_augment", "fuse_activations", "co_augment", "quantize_views_mx",
+    "dequantize_mx",
 ]
 
 
@@ -478,6 +479,53 @@ def quantize_views(x: np.ndarray, fmt: str):
     y = (X / scale[:, None]).astype(f32)
     codes = _round_bf16(y) if fmt == "bf16" else _round_e4m3(y)
     return codes, scale
+
+
+_E2M1 = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0], dtype=f64)
+
+
+def _round_e2m1(y: np.ndarray) -> np.ndarray:
+    """Round to the nearest FP4 E2M1 value (ties to even mantissa; grid
+    index parity equals mantissa parity), saturating at +-6."""
+    y = np.asarray(y, dtype=f64)
+    a = np.minimum(np.abs(y), 6.0)
+    g = _E2M1
+    hi = np.clip(np.searchsorted(g, a, side="left"), 0, len(g) - 1)
+    lo = np.clip(hi - 1, 0, len(g) - 1)
+    dlo, dhi = a - g[lo], g[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
+    r = np.where(a == g[hi], g[hi], np.where(pick_hi, g[hi], g[lo]))
+    return (np.sign(y) * r).astype(f32)
+
+
+_MX = {"mxfp8": (8, _round_e4m3), "mxfp4": (2, _round_e2m1)}
+
+
+def quantize_views_mx(x: np.ndarray, fmt: str):
+    """Block-scaled storage with one shared power-of-two scale per 32
+    consecutive values of a view (OCP microscaling): the block exponent is
+    floor(log2(max |x| of the block)) - emax of the element format (8 for
+    e4m3, 2 for e2m1), clamped to [-127, 127] (-127 for an all-zero block),
+    stored as E8M0 = exponent + 127; elements are x / 2^exponent rounded to
+    the element format (nearest, ties to even, saturating).  Returns (codes
+    as float32 values [n, d], e8m0 uint8 [n, d/32])."""
+    emax, rnd = _MX[fmt]
+    X = np.asarray(x, dtype=f32)
+    n, d = X.shape
+    blocks = X.reshape(n, d // 32, 32).astype(f64)
+    amax = np.abs(blocks).max(axis=2)
+    mant, ex = np.frexp(amax)                  # amax = mant * 2^ex, mant in [0.5, 1)
+    e = np.where(amax > 0, ex - 1 - emax, -127).clip(-127, 127)
+    y = blocks / np.ldexp(1.0, e)[:, :, None]  # exact: division by a power of two
+    codes = rnd(y).reshape(n, d)
+    return codes, (e + 127).astype(np.uint8)
+
+
+def dequantize_mx(codes, e8m0):
+    c = np.asarray(codes, dtype=f64)
+    n, d = c.shape
+    scale = np.ldexp(1.0, np.asarray(e8m0, dtype=np.int64) - 127)
+    return (c.reshape(n, d // 32, 32) * scale[:, :, None]).reshape(n, d)
 
 
 def dequantize(codes, scale):

@@ -390,3 +390,35 @@ def test_co_augmentation_swaps_neighbour_sets():
     for p in range(N):
         assert np.allclose(A1[p], F1[n2[p, :3]].mean(0))
         assert np.allclose(A2[p], F2[n1[p, :3]].mean(0))
+
+
+# ---------------------------------------------------------------- MX storage
+def test_mx_element_rounding_hand_cases():
+    from oracle.gift_oracle import _round_e2m1
+    t = np.array([0.25, 0.75, 1.25, 1.75, 2.5, 3.5, 5.0, 7.0, -2.6, 0.2], np.float32)
+    # ties to even mantissa: 0.25 -> 0, 0.75 -> 1.0, 1.25 -> 1.0, 1.75 -> 2.0,
+    # 2.5 -> 2.0, 3.5 -> 4.0, 5.0 -> 4.0; saturation 7 -> 6
+    assert _round_e2m1(t).tolist() == [0.0, 1.0, 1.0, 2.0, 2.0, 4.0, 4.0, 6.0, -3.0, 0.0]
+
+
+def test_mx_block_scales_and_error():
+    rng = np.random.default_rng(30)
+    x = (rng.random((20, 128)) ** 2).astype(np.float32)
+    x[3, :32] = 0.0                      # an all-zero block
+    x[4, 32:64] = 2.0 ** -5              # a power-of-two block
+    for fmt, emax, rel in (("mxfp8", 8, 2.0 ** -3), ("mxfp4", 2, 2.0 ** -1)):
+        codes, e = O.quantize_views_mx(x, fmt)
+        assert e.shape == (20, 4) and e.dtype == np.uint8
+        assert e[3, 0] == 0 and np.all(codes[3, :32] == 0)
+        # a block of 2^-5 has exponent -5 - emax, and codes 2^emax
+        assert e[4, 1] == 127 - 5 - emax
+        assert np.all(codes[4, 32:64] == 2.0 ** emax)
+        # largest code of a non-zero block lies in [2^emax, 2^(emax+1)]
+        blk = np.abs(codes.reshape(20, 4, 32)).max(axis=2)
+        nz = blk > 0
+        assert (blk[nz] >= 2.0 ** emax).all() and (blk[nz] <= 2.0 ** (emax + 1)).all()
+        # element error within half a step of the format relative to the block max
+        deq = O.dequantize_mx(codes, e)
+        bmax = np.abs(x.reshape(20, 4, 32)).max(axis=2, keepdims=True)
+        err = np.abs(deq.reshape(20, 4, 32) - x.reshape(20, 4, 32))
+        assert (err <= rel * bmax + 1e-30).all()
