@@ -57,6 +57,9 @@ typedef int32_t gift_status;
 #define GIFT_F32      0   /* float32                                          */
 #define GIFT_BF16     1   /* bfloat16 code, value = code * scale[view]         */
 #define GIFT_FP8E4M3  2   /* OCP e4m3fn code (max 448), value = code * scale   */
+#define GIFT_MXFP8    3   /* e4m3 codes, one E8M0 scale byte per 32 values     */
+#define GIFT_MXFP4    4   /* e2m1 codes (two per byte, even index in the low
+                             nibble), one E8M0 scale byte per 32 values       */
 
 /* Database views (Sec. 2.3: V(x_p) = {p_1..p_Nv}). */
 typedef struct gift_views {
@@ -66,7 +69,10 @@ typedef struct gift_views {
   int64_t      n_shapes;  /* N                                                */
   int32_t      dim;       /* d, multiple of 32                                */
   int32_t      _pad;
-  const float* scale;     /* [n_shapes * n_views] per-view scale, or NULL for F32 */
+  const void*  scale;     /* BF16 / FP8: float32 per view [n_shapes*n_views];
+                             MX: uint8 E8M0 [n_shapes*n_views][dim/32], the
+                             value of a code is code * 2^(e8m0 - 127);
+                             NULL for F32                                     */
   const float* master;    /* float32 copy [n_shapes * n_views][dim]; required
                              for the float32 rescore when dtype != GIFT_F32;
                              may equal `data` when dtype == GIFT_F32          */
@@ -86,13 +92,19 @@ const char* gift_last_error(void);
 
 /* ---------------------------------------------------------------------- */
 /* Reduced-precision storage of view features.                            */
-/* scale[v] = max_t |src[v][t]| / Fmax (Fmax = 1 for BF16, 448 for e4m3),  */
-/* dst[v][t] = round_nearest_even_saturating(src[v][t] / scale[v]) in the  */
-/* target format; an all-zero row gets scale 1.  dst is [n][dim] of 2-byte  */
-/* (BF16) or 1-byte (e4m3) codes.                                         */
+/* BF16 / FP8: scale[v] = max_t |src[v][t]| / Fmax (Fmax = 1 for BF16, 448 */
+/* for e4m3), dst[v][t] = round_nearest_even_saturating(src[v][t] /        */
+/* scale[v]); an all-zero row gets scale 1.  dst is [n][dim] of 2-byte     */
+/* (BF16) or 1-byte (e4m3) codes; `scale` is float32 [n].                  */
+/* MX (microscaling, per 32 consecutive values of a view): exponent e =    */
+/* floor(log2(block max |x|)) - emax (emax 8 for e4m3, 2 for e2m1),        */
+/* clamped to [-127, 127] (-127 for an all-zero block), scale byte e + 127 */
+/* into `scale` (uint8 [n][dim/32]); codes round(x / 2^e) to the element   */
+/* format (nearest, ties to even, saturating).  dst is [n][dim] bytes      */
+/* (MXFP8) or [n][dim/2] bytes (MXFP4).  dim must be a multiple of 32.     */
 /* ---------------------------------------------------------------------- */
 gift_status gift_quantize_views(const float* src, int64_t n, int32_t dim,
-                                int32_t dtype, void* dst, float* scale,
+                                int32_t dtype, void* dst, void* scale,
                                 void* stream);
 
 /* ---------------------------------------------------------------------- */

@@ -22,9 +22,9 @@ _lib = C.CDLL(LIB_PATH)
 
 # status codes and storage formats (include/gift.h)
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ECAPACITY = 0, -1, -2, -3, -4, -5
-F32, BF16, FP8E4M3 = 0, 1, 2
-_DT_BYTES = {F32: 4, BF16: 2, FP8E4M3: 1}
-_DT_TORCH = {F32: torch.float32, BF16: torch.uint16, FP8E4M3: torch.uint8}
+F32, BF16, FP8E4M3, MXFP8, MXFP4 = 0, 1, 2, 3, 4
+_DT_TORCH = {F32: torch.float32, BF16: torch.uint16, FP8E4M3: torch.uint8, MXFP8: torch.uint8,
+             MXFP4: torch.uint8}
 
 
 class GiftError(RuntimeError):
@@ -146,7 +146,7 @@ class Views:
         self.data, self.scale = data, scale
         self.master = master if master is not None else (data if dtype == F32 else None)
         self.dtype, self.n_views = dtype, int(n_views)
-        self.dim = int(data.shape[1]) if dtype == F32 else int(data.shape[1])
+        self.dim = int(data.shape[1]) * (2 if dtype == MXFP4 else 1)
         self.n_shapes = int(data.shape[0]) // self.n_views
         self.c = gift_views(data.data_ptr(), dtype, self.n_views, self.n_shapes, self.dim, 0,
                             scale.data_ptr() if scale is not None else None,
@@ -171,10 +171,16 @@ class Queries:
 
 
 def gift_quantize_views(src, dtype, stream=None):
-    """Per-view scaled BF16 / e4m3 codes of float32 rows: (codes, scale)."""
+    """Reduced-precision codes of float32 rows: (codes, scale).  BF16 / e4m3:
+    per-view float32 scale [n]; MX: uint8 E8M0 [n, dim/32] and codes of
+    dim (MXFP8) or dim/2 (MXFP4) bytes per row."""
     n, dim = src.shape
-    codes = torch.empty((n, dim), dtype=_DT_TORCH[dtype], device=src.device)
-    scale = torch.empty(n, dtype=torch.float32, device=src.device)
+    width = dim // 2 if dtype == MXFP4 else dim
+    codes = torch.empty((n, width), dtype=_DT_TORCH[dtype], device=src.device)
+    if dtype in (MXFP8, MXFP4):
+        scale = torch.empty((n, dim // 32), dtype=torch.uint8, device=src.device)
+    else:
+        scale = torch.empty(n, dtype=torch.float32, device=src.device)
     _check(_lib.gift_quantize_views(_ptr(src), n, dim, dtype, _ptr(codes), _ptr(scale),
                                     _stream(stream)))
     return codes, scale

@@ -59,6 +59,9 @@ static float rescore_dot_err(int dim) {
 // 2 u_s + u_s^2 relative; the MFMA accumulation is charged 2*dim roundings;
 // the mean over at most max_m views adds gamma_(max_m + 1).
 static float first_pass_err(int dtype, int dim, int max_m) {
+  // MX element errors are relative to the block maximum, not the element
+  // (saturation can cost an eighth of it): no useful bound, so never certify
+  if (dtype == GIFT_MXFP8 || dtype == GIFT_MXFP4) return 4.f;
   double us = dtype == GIFT_BF16 ? 1.0 / 256 : dtype == GIFT_FP8E4M3 ? 1.0 / 16 : 0.0;
   double e = (2 * us + us * us) + gamma_n(2.0 * dim + 4) + gamma_n(max_m + 2.0);
   return (float)(e * 1.001);
@@ -69,8 +72,12 @@ float first_pass_error(int dtype, int dim, int max_m) { return first_pass_err(dt
 
 static gift_status check_views(const gift_views* db) {
   GIFT_CHECK(db != nullptr && db->data != nullptr, GIFT_EINVAL, "null database views");
-  GIFT_CHECK(db->dtype == GIFT_F32 || db->dtype == GIFT_BF16 || db->dtype == GIFT_FP8E4M3,
-             GIFT_EUNSUPPORTED, "unsupported dtype %d", db->dtype);
+  GIFT_CHECK(db->dtype >= GIFT_F32 && db->dtype <= GIFT_MXFP4, GIFT_EUNSUPPORTED,
+             "unsupported dtype %d", db->dtype);
+  GIFT_CHECK(db->dtype != GIFT_MXFP8 || db->dim % 128 == 0, GIFT_EUNSUPPORTED,
+             "MXFP8 storage needs dim a multiple of 128");
+  GIFT_CHECK(db->dtype != GIFT_MXFP4 || db->dim % 256 == 0, GIFT_EUNSUPPORTED,
+             "MXFP4 storage needs dim a multiple of 256");
   GIFT_CHECK(db->n_views >= 1 && db->n_views <= 64, GIFT_EUNSUPPORTED,
              "n_views must be in 1..64 (got %d)", db->n_views);
   GIFT_CHECK(db->n_shapes >= 1 && db->n_shapes < ((int64_t)1 << 31), GIFT_EINVAL,
@@ -96,7 +103,7 @@ static gift_status check_queries(const gift_queries* q, int dim) {
 
 struct ExhaustiveWs {
   void* qcodes;
-  float* qscale;
+  void* qscale;
   float* mbuf;
   float* S;
   int32_t* cand;
@@ -112,8 +119,9 @@ static ExhaustiveWs carve_exhaustive(void* base, const gift_views* db,
   ExhaustiveWs w{};
   const int64_t tq = q->total_views;
   if (db->dtype != GIFT_F32) {
-    w.qcodes = c.take<uint8_t>((size_t)tq * db->dim * elem_bytes(db->dtype));
-    w.qscale = c.take<float>((size_t)tq);
+    w.qcodes = c.take<uint8_t>((size_t)tq * row_bytes_of(db->dtype, db->dim));
+    w.qscale = is_mx(db->dtype) ? (void*)c.take<uint8_t>((size_t)tq * (db->dim / 32))
+                                : (void*)c.take<float>((size_t)tq);
   }
   w.mbuf = c.take<float>((size_t)db->n_shapes * tq);
   w.S = c.take<float>((size_t)q->n_queries * db->n_shapes);
@@ -131,7 +139,7 @@ static ExhaustiveWs carve_exhaustive(void* base, const gift_views* db,
 static gift_status first_pass(const gift_views* db, const gift_queries* q,
                               const ExhaustiveWs& w, hipStream_t st) {
   const void* qv = q->views;
-  const float* qs = nullptr;
+  const void* qs = nullptr;
   if (db->dtype != GIFT_F32) {
     prof_begin(P_QUANT, st);
     launch_quantize(q->views, q->total_views, db->dim, db->dtype, w.qcodes, w.qscale, st);
@@ -215,7 +223,7 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
   w.gitems = c.take<int32_t>((size_t)tq);
   w.bucket = c.take<uint8_t>(bucket_sort_ws(tq, f->K));
   if (db->dtype != GIFT_F32) {
-    w.qcodes = c.take<uint8_t>((size_t)tq * db->dim * elem_bytes(db->dtype));
+    w.qcodes = c.take<uint8_t>((size_t)tq * row_bytes_of(db->dtype, db->dim));
     w.qscale = c.take<float>((size_t)tq);
   }
   w.mbuf = c.take<uint32_t>((size_t)db->n_shapes * tq);
@@ -233,6 +241,8 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
 }
 
 static gift_status check_fif(const gift_fif* f, const gift_views* db) {
+  GIFT_CHECK(!is_mx(db->dtype), GIFT_EUNSUPPORTED,
+             "the F-IF scan reads float32, BF16 or FP8 storage (MX is exhaustive-only)");
   GIFT_CHECK(f != nullptr && f->offsets && f->entry_shape && f->entry_view && f->view_words,
              GIFT_EINVAL, "incomplete F-IF index");
   gift_status s = check_codebook(f->codebook, f->K, f->ma, db->dim);
@@ -336,12 +346,14 @@ gift_status gift_profile_reset(void) {
 }
 
 gift_status gift_quantize_views(const float* src, int64_t n, int32_t dim,
-                                int32_t dtype, void* dst, float* scale,
+                                int32_t dtype, void* dst, void* scale,
                                 void* stream) {
   GIFT_CHECK(src && dst && scale, GIFT_EINVAL, "null pointer");
   GIFT_CHECK(n >= 0 && dim >= 1, GIFT_EINVAL, "bad size");
-  GIFT_CHECK(dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3, GIFT_EUNSUPPORTED,
-             "quantize target must be BF16 or FP8E4M3");
+  GIFT_CHECK(dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3 || dtype == GIFT_MXFP8 ||
+                 dtype == GIFT_MXFP4,
+             GIFT_EUNSUPPORTED, "quantize target must be BF16, FP8E4M3, MXFP8 or MXFP4");
+  GIFT_CHECK(!is_mx(dtype) || dim % 32 == 0, GIFT_EUNSUPPORTED, "MX storage needs dim % 32 == 0");
   launch_quantize(src, n, dim, dtype, dst, scale, (hipStream_t)stream);
   GIFT_LAUNCHED();
   return GIFT_OK;
@@ -668,7 +680,7 @@ gift_status gift_autotune_score(const gift_views* db, const gift_queries* q, con
   int keep_tile = 0, keep_group = 8;
   get_score_tuning(db->dtype, &keep_tile, &keep_group);
   const void* qv = q->views;
-  const float* qs = nullptr;
+  const void* qs = nullptr;
   if (db->dtype != GIFT_F32) {
     launch_quantize(q->views, q->total_views, db->dim, db->dtype, w.qcodes, w.qscale, st);
     GIFT_LAUNCHED();

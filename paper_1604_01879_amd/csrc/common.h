@@ -46,6 +46,16 @@ struct Carver {
   size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
+// Bytes of one stored row of `dim` values.
+inline int64_t row_bytes_of(int dtype, int64_t dim) {
+  switch (dtype) {
+    case GIFT_F32: return 4 * dim;
+    case GIFT_BF16: return 2 * dim;
+    case GIFT_MXFP4: return dim / 2;
+    default: return dim;  // e4m3 and MX e4m3
+  }
+}
+inline bool is_mx(int dtype) { return dtype == GIFT_MXFP8 || dtype == GIFT_MXFP4; }
 inline int elem_bytes(int dtype) {
   return dtype == GIFT_F32 ? 4 : dtype == GIFT_BF16 ? 2 : 1;
 }

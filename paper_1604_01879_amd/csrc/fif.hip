@@ -580,7 +580,7 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
   const int64_t bound = n_entries / 128 + K + 1;
   GIFT_CHECK(bound < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many list tiles");
   const size_t shmem = 128 * 129 * 4;
-  const int row_bytes = db->dim * elem_bytes(db->dtype);
+  const int row_bytes = (int)row_bytes_of(db->dtype, db->dim);
 #define GIFT_SCAN_LAUNCH(DTV)                                                                  \
   do {                                                                                         \
     static bool attr = false;                                                                  \
@@ -590,7 +590,8 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
       attr = true;                                                                             \
     }                                                                                          \
     hipLaunchKernelGGL(fif_scan_kernel<DTV>, dim3((unsigned)bound), dim3(256), shmem, st,      \
-                       static_cast<const uint8_t*>(db->data), db->scale, db->n_views,          \
+                       static_cast<const uint8_t*>(db->data),                                  \
+                       static_cast<const float*>(db->scale), db->n_views,                       \
                        row_bytes, loff, ent_shape, ent_view, tile_off, K, goff, gitems,        \
                        static_cast<const uint8_t*>(qv), qscale, mbuf, ldm);                    \
   } while (0)

@@ -6,14 +6,15 @@
 namespace gift {
 
 // Per-view scaled reduced-precision codes (BF16 or e4m3).
+// scale: float32 per view (BF16 / FP8) or uint8 E8M0 per 32 values (MX).
 void launch_quantize(const float* src, int64_t n, int dim, int dtype,
-                     void* dst, float* scale, hipStream_t st);
+                     void* dst, void* scale, hipStream_t st);
 
 // Eq. 3 first pass: for every database shape p and every query view c,
 // mbuf[p * ldm + c] = max_j s(q_c, p_j) (scales applied for BF16/FP8).
 // qv/qscale hold the query views in the same dtype as the database.
 gift_status launch_score_tiles(const gift_views* db, const void* qv,
-                               const float* qscale, int64_t total_q,
+                               const void* qscale, int64_t total_q,
                                float* mbuf, int64_t ldm, hipStream_t st);
 
 // Tile shape (0 or 1) per storage dtype and launch-order group of the

@@ -224,6 +224,118 @@ __device__ __forceinline__ void mfma_tile_mainloop_db(
   }
 }
 
+// Block-scaled (MX) operands: each lane supplies 32 consecutive K values of
+// its row and one E8M0 scale byte for them per MFMA step.  FMT is the
+// operand-format code of the scaled MFMA (0: e4m3, 4: e2m1).  Per 128-byte
+// K-tile a lane half covers 64 bytes: 2 steps of 32 e4m3 bytes, or 4 steps
+// of 16 e2m1 bytes.  `sa`/`sb` hold the lane's scale bytes for the tile's
+// steps, step s in byte s.
+template <int FMT>
+struct MfmaMx;
+
+template <>
+struct MfmaMx<0> {
+  static constexpr int STEPS = 2;
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], uint32_t sa,
+                                             uint32_t sb, f32x16& c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const Pair32 ap = {a[2 * s], a[2 * s + 1]}, bp = {b[2 * s], b[2 * s + 1]};
+      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+          __builtin_bit_cast(i32x8, ap), __builtin_bit_cast(i32x8, bp), c, 0, 0, 0,
+          (int)((sa >> (8 * s)) & 0xffu), 0, (int)((sb >> (8 * s)) & 0xffu));
+    }
+  }
+};
+
+template <>
+struct MfmaMx<4> {
+  static constexpr int STEPS = 4;
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], uint32_t sa,
+                                             uint32_t sb, f32x16& c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const Pair32 ap = {a[s], make_uint4(0, 0, 0, 0)}, bp = {b[s], make_uint4(0, 0, 0, 0)};
+      c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+          __builtin_bit_cast(i32x8, ap), __builtin_bit_cast(i32x8, bp), c, 4, 4, 0,
+          (int)((sa >> (8 * s)) & 0xffu), 0, (int)((sb >> (8 * s)) & 0xffu));
+    }
+  }
+};
+
+// The tile of mfma_tile_mainloop for MX operands.  sa_row[i] / sb_row[j]
+// point at the E8M0 bytes of the row / column this lane supplies in block
+// i / j (row_bytes must be a multiple of 128).
+template <int FMT, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_mainloop_mx(
+    uint8_t* lds, const uint8_t* const (&src)[TileShape<WM, WN>::LOADS], int row_bytes,
+    const uint8_t* const (&sa_row)[WM], const uint8_t* const (&sb_row)[WN],
+    f32x16 (&acc)[WM][WN]) {
+  using T = TileShape<WM, WN>;
+  constexpr int STEPS = MfmaMx<FMT>::STEPS;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5, l32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int n_kt = row_bytes / 128;
+  uint4 pre[T::LOADS];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
+      pre[it] = src[it] != nullptr ? *reinterpret_cast<const uint4*>(src[it] + off)
+                                   : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sload = [&](const uint8_t* row, int kt) -> uint32_t {
+    const int b0 = kt * 2 * STEPS + half * STEPS;  // first scale byte of this lane half
+    if (STEPS == 2) return *reinterpret_cast<const uint16_t*>(row + b0);
+    return *reinterpret_cast<const uint32_t*>(row + b0);
+  };
+  gload(0);
+  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 64;
+  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + half * 64;
+  for (int kt = 0; kt < n_kt; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int idx = tid + 256 * it;
+      *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[it];
+    }
+    __syncthreads();
+    if (kt + 1 < n_kt) gload(kt + 1);
+    uint32_t sb[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) sb[j] = sload(sb_row[j], kt);
+    uint4 b[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * 16);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const uint32_t sa = sload(sa_row[i], kt);
+      uint4 a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * 16);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) MfmaMx<FMT>::run(a, b[j], sa, sb[j], acc[i][j]);
+    }
+  }
+  __syncthreads();
+}
+
 // Row (within the wave's WM*32 rows) and column of accumulator element e of
 // block (i, j) held by this lane.
 __device__ __forceinline__ int acc_row(int i, int e) {

@@ -28,6 +28,56 @@ __device__ inline uint8_t e4m3_rne_sat(float y) {
   return (uint8_t)(sgn | (uint32_t)((e + 7) << 3) | m);
 }
 
+// FP4 e2m1 (values 0, 0.5, 1, 1.5, 2, 3, 4, 6), nearest, ties to even,
+// saturating; 4-bit code s:e(2):m(1).
+__device__ inline uint8_t e2m1_rne_sat(float y) {
+  const uint32_t sgn = (__builtin_bit_cast(uint32_t, y) >> 28) & 0x8u;
+  const float a = fabsf(y);
+  if (!(a < 6.f)) return (uint8_t)(sgn | 0x7u);
+  if (a < 1.f) {                       // step 0.5: codes 0, 1 (0.5), 2 (1.0)
+    const int q = (int)rintf(a * 2.f);
+    return (uint8_t)(sgn | (uint32_t)q);
+  }
+  uint32_t u = __builtin_bit_cast(uint32_t, a);
+  u += 0x1fffffu + ((u >> 22) & 1u);   // keep 1 mantissa bit, ties to even
+  const int e = (int)((u >> 23) & 0xffu) - 127;  // 0..2 (6 stays below the cut)
+  const uint32_t m = (u >> 22) & 1u;
+  return (uint8_t)(sgn | (uint32_t)((e + 1) << 1) | m);
+}
+
+// One wave quantizes view v in MX form: each lane takes whole 32-value
+// blocks.  Block exponent floor(log2(amax)) - emax, clamped to [-127, 127].
+__device__ inline void quantize_view_mx_wave(const float* __restrict__ src, int64_t v, int dim,
+                                             int dtype, uint8_t* __restrict__ dst,
+                                             uint8_t* __restrict__ e8m0) {
+  const int lane = threadIdx.x & 63;
+  const int nblk = dim / 32;
+  const int emax = dtype == GIFT_MXFP8 ? 8 : 2;
+  const float* x = src + v * dim;
+  for (int b = lane; b < nblk; b += 64) {
+    float amax = 0.f;
+    for (int t = 0; t < 32; ++t) amax = fmaxf(amax, fabsf(x[b * 32 + t]));
+    int e = -127;
+    if (amax > 0.f) {
+      int ex;
+      (void)frexpf(amax, &ex);           // amax = m * 2^ex, m in [0.5, 1)
+      e = ex - 1 - emax;
+      e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    }
+    e8m0[v * nblk + b] = (uint8_t)(e + 127);
+    if (dtype == GIFT_MXFP8) {
+      for (int t = 0; t < 32; ++t)
+        dst[v * dim + b * 32 + t] = e4m3_rne_sat(ldexpf(x[b * 32 + t], -e));
+    } else {
+      for (int t = 0; t < 32; t += 2) {
+        const uint8_t lo = e2m1_rne_sat(ldexpf(x[b * 32 + t], -e));
+        const uint8_t hi = e2m1_rne_sat(ldexpf(x[b * 32 + t + 1], -e));
+        dst[(v * dim + b * 32 + t) / 2] = (uint8_t)(lo | (hi << 4));
+      }
+    }
+  }
+}
+
 // One wave quantizes view v: scale = max|x| / Fmax (1 for an all-zero
 // view), code = round(x / scale).
 __device__ inline void quantize_view_wave(const float* __restrict__ src, int64_t v, int dim,

@@ -17,12 +17,24 @@ __global__ __launch_bounds__(256) void quantize_kernel(
   quantize_view_wave(src, v, dim, dtype, dst, scale);
 }
 
+__global__ __launch_bounds__(256) void quantize_mx_kernel(
+    const float* __restrict__ src, int64_t n, int dim, int dtype,
+    uint8_t* __restrict__ dst, uint8_t* __restrict__ e8m0) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  quantize_view_mx_wave(src, v, dim, dtype, dst, e8m0);
+}
+
 void launch_quantize(const float* src, int64_t n, int dim, int dtype,
-                     void* dst, float* scale, hipStream_t st) {
+                     void* dst, void* scale, hipStream_t st) {
   if (n <= 0) return;
   dim3 grid((unsigned)((n + 3) / 4));
-  hipLaunchKernelGGL(quantize_kernel, grid, dim3(256), 0, st, src, n, dim,
-                     dtype, static_cast<uint8_t*>(dst), scale);
+  if (is_mx(dtype))
+    hipLaunchKernelGGL(quantize_mx_kernel, grid, dim3(256), 0, st, src, n, dim, dtype,
+                       static_cast<uint8_t*>(dst), static_cast<uint8_t*>(scale));
+  else
+    hipLaunchKernelGGL(quantize_kernel, grid, dim3(256), 0, st, src, n, dim,
+                       dtype, static_cast<uint8_t*>(dst), static_cast<float*>(scale));
 }
 
 // ------------------------------------------------------------------ MFMA tile
@@ -32,11 +44,15 @@ void launch_quantize(const float* src, int64_t n, int dim, int dtype,
 // then the two lane halves are combined with one shuffle.
 template <int DT, int WM, int WN>
 __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
-    const uint8_t* __restrict__ db, const float* __restrict__ db_scale,
+    const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v,
     int64_t n_shapes, int n_views, int row_bytes,
-    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    const uint8_t* __restrict__ qv, const void* __restrict__ q_scale_v,
     int64_t total_q, float* __restrict__ mbuf, int64_t ldm,
     int64_t n_row_tiles, int64_t n_col_tiles, int64_t GROUP) {
+  constexpr bool MX = DT == GIFT_MXFP8 || DT == GIFT_MXFP4;
+  constexpr bool SCALED = DT == GIFT_BF16 || DT == GIFT_FP8E4M3;  // per-view scales
+  const float* db_scale = static_cast<const float*>(db_scale_v);
+  const float* q_scale = static_cast<const float*>(q_scale_v);
   using T = TileShape<WM, WN>;
   constexpr int SHAPES_PER_BLOCK = T::BM / 64;
   static_assert(WM % 2 == 0, "a wave must hold whole shapes");
@@ -79,7 +95,31 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     src[it] = p;
   }
   f32x16 acc[WM][WN];
-  mfma_tile_mainloop<DT, WM, WN>(lds, src, row_bytes, acc);
+  if constexpr (MX) {
+    // E8M0 rows of the row / column this lane supplies in each block
+    const int nblk = (DT == GIFT_MXFP4 ? 2 * row_bytes : row_bytes) / 32;
+    const uint8_t* de8 = static_cast<const uint8_t*>(db_scale_v);
+    const uint8_t* qe8 = static_cast<const uint8_t*>(q_scale_v);
+    const uint8_t* sa_row[WM];
+    const uint8_t* sb_row[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const int r = wr * WM * 32 + i * 32 + l32;
+      const int64_t shp = shape0 + (r >> 6);
+      const int v = r & 63;
+      const bool ok = shp < n_shapes && v < n_views;
+      sa_row[i] = de8 + (ok ? (shp * n_views + v) * (int64_t)nblk : 0);
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int64_t c = col0 + wc * WN * 32 + j * 32 + l32;
+      sb_row[j] = qe8 + (c < total_q ? c * (int64_t)nblk : 0);
+    }
+    mfma_tile_mainloop_mx<DT == GIFT_MXFP8 ? 0 : 4, WM, WN>(lds, src, row_bytes, sa_row, sb_row,
+                                                            acc);
+  } else {
+    mfma_tile_mainloop<DT, WM, WN>(lds, src, row_bytes, acc);
+  }
 
   // Epilogue: max over the shape's valid views, the row scale applied
   // before the max and the positive column scale after it.
@@ -88,7 +128,7 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     const int64_t shp = shape0 + wr * (WM / 2) + s;
     const bool shape_ok = shp < n_shapes;
     float rs[2][16];
-    if (DT != GIFT_F32) {
+    if (SCALED) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -106,13 +146,13 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
         for (int e = 0; e < 16; ++e) {
           const int v = acc_row(bi, e);
           float x = acc[2 * s + bi][j][e];
-          if (DT != GIFT_F32) x *= rs[bi][e];
+          if (SCALED) x *= rs[bi][e];
           if (v < n_views) m = fmaxf(m, x);
         }
       m = fmaxf(m, __shfl_xor(m, 32, 64));
       const int64_t c = col0 + wc * WN * 32 + j * 32 + l32;
       if (half == 0 && shape_ok && c < total_q) {
-        if (DT != GIFT_F32) m *= q_scale[c];
+        if (SCALED) m *= q_scale[c];
         mbuf[shp * ldm + c] = m;
       }
     }
@@ -122,14 +162,16 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
 // Tuning knobs: tile shape per storage dtype (0: 256 x 128 database rows x
 // query views, 1: 256 x 256; float32 always 128 x 128) and the row-tile
 // group of the launch order.
-static int g_tile[3] = {0, 1, 1};
-static int64_t g_group[3] = {8, 8, 8};
+static int g_tile[5] = {0, 1, 1, 0, 0};
+static int64_t g_group[5] = {8, 8, 8, 8, 8};
 
 gift_status set_score_tuning(int dtype, int tile, int group) {
-  GIFT_CHECK(dtype >= 0 && dtype <= 2, GIFT_EINVAL, "bad dtype");
+  GIFT_CHECK(dtype >= 0 && dtype <= 4, GIFT_EINVAL, "bad dtype");
   GIFT_CHECK(tile == 0 || tile == 1, GIFT_EINVAL, "tile must be 0 or 1");
+  GIFT_CHECK(tile == 0 || (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3), GIFT_EUNSUPPORTED,
+             "tile 1 is for BF16 / FP8 storage");
   GIFT_CHECK(group >= 1 && group <= 1024, GIFT_EINVAL, "group must be in 1..1024");
-  if (dtype != GIFT_F32) g_tile[dtype] = tile;
+  if (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3) g_tile[dtype] = tile;
   g_group[dtype] = group;
   return GIFT_OK;
 }
@@ -141,10 +183,10 @@ void get_score_tuning(int dtype, int* tile, int* group) {
 
 template <int DT, int WM, int WN>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
-                                const float* qscale, int64_t total_q,
+                                const void* qscale, int64_t total_q,
                                 float* mbuf, int64_t ldm, hipStream_t st) {
   constexpr int BM = TileShape<WM, WN>::BM, BN = TileShape<WM, WN>::BN;
-  const int row_bytes = db->dim * elem_bytes(DT);
+  const int row_bytes = (int)row_bytes_of(DT, db->dim);
   const int64_t n_row_tiles = (db->n_shapes + BM / 64 - 1) / (BM / 64);
   const int64_t n_col_tiles = (total_q + BN - 1) / BN;
   const int64_t blocks = n_row_tiles * n_col_tiles;
@@ -167,7 +209,7 @@ static gift_status launch_tiles(const gift_views* db, const void* qv,
 }
 
 gift_status launch_score_tiles(const gift_views* db, const void* qv,
-                               const float* qscale, int64_t total_q,
+                               const void* qscale, int64_t total_q,
                                float* mbuf, int64_t ldm, hipStream_t st) {
   if (total_q <= 0 || db->n_shapes <= 0) return GIFT_OK;
   switch (db->dtype) {
@@ -180,6 +222,10 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
       if (g_tile[GIFT_FP8E4M3] == 1)
         return launch_tiles<GIFT_FP8E4M3, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);
       return launch_tiles<GIFT_FP8E4M3, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
+    case GIFT_MXFP8:
+      return launch_tiles<GIFT_MXFP8, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
+    case GIFT_MXFP4:
+      return launch_tiles<GIFT_MXFP4, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
   }
   return fail(GIFT_EUNSUPPORTED, "unknown dtype %d", db->dtype);
 }

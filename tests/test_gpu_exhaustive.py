@@ -203,3 +203,54 @@ def test_invalid_arguments_rejected(L):
     with pytest.raises(L.GiftError) as e:
         L.gift_query_exhaustive(bad, Q, 1, 1)
     assert e.value.status == L.EUNSUPPORTED
+
+
+_E2M1_VALUES = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0, -0.0, -0.5, -1.0, -1.5, -2.0,
+                         -3.0, -4.0, -6.0], np.float32)
+
+
+def _decode_mx(L, codes, dtype):
+    c = codes.cpu()
+    if dtype == L.MXFP8:
+        return c.view(torch.float8_e4m3fn).float().numpy()
+    b = c.numpy()
+    out = np.empty((b.shape[0], b.shape[1] * 2), np.float32)
+    out[:, 0::2] = _E2M1_VALUES[b & 15]
+    out[:, 1::2] = _E2M1_VALUES[b >> 4]
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_mx_quantize_bit_exact(L, fmt):
+    _say(f"mx quantize {fmt}")
+    dt = L.MXFP8 if fmt == "mxfp8" else L.MXFP4
+    rng = np.random.default_rng(31)
+    x = (rng.random((97, 256)).astype(np.float32) ** 3)
+    x[3, :32] = 0.0
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    codes_ref, e_ref = O.quantize_views_mx(x, fmt)
+    codes, e = L.gift_quantize_views(torch.from_numpy(x).cuda(), dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(e.cpu().numpy(), e_ref)
+    assert np.array_equal(_decode_mx(L, codes, dt), codes_ref)
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_mx_first_pass_and_ranking(L, fmt):
+    _say(f"mx first pass {fmt}")
+    dt = L.MXFP8 if fmt == "mxfp8" else L.MXFP4
+    w, db, q, qoff = _data(N=180, dim=256, B=5, m=(3, 64), seed=12)
+    master = torch.from_numpy(db).to("cuda:0")
+    codes, e = L.gift_quantize_views(master, dt)
+    V = L.Views(codes, w.n_views, dt, e, master)
+    Q = _queries(L, q, qoff)
+    S = L.gift_score_exhaustive(V, Q).cpu().numpy()
+    qc, qe = O.quantize_views_mx(q, fmt)
+    dc, de = O.quantize_views_mx(db, fmt)
+    ref = O.exhaustive_scores(O.dequantize_mx(qc, qe), qoff, O.dequantize_mx(dc, de), w.n_views)
+    assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
+    # with every shape rescored the ranking is the exact one
+    ids, sc, _ = L.gift_query_exhaustive(V, Q, 15, w.n_shapes)
+    Sx = O.exhaustive_scores(q, qoff, db, w.n_views)
+    for b in range(len(qoff) - 1):
+        assert_ranked_equal(ids.cpu().numpy()[b], sc.cpu().numpy()[b], Sx[b], 15)
