@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2,
                     help="steps of the plain float32 path (reference and speedup)")
     ap.add_argument("--fp8-steps", type=int, default=3)
+    ap.add_argument("--mx-steps", type=int, default=3,
+                    help="steps of the MX block-scaled FP8 / FP4 paths (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
@@ -101,9 +103,9 @@ def main():
     log(f"generated {w.n_shapes} x {w.n_views} x {w.dim} in {time.time() - t0:.1f}s")
     master = db_host.to(dev, non_blocking=False)
     Q = L.Queries(torch.from_numpy(q_np).to(dev), torch.from_numpy(qoff_np))
-    dts = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}
+    dts = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3, "mxfp8": L.MXFP8, "mxfp4": L.MXFP4}
     views = {"f32": L.Views(master, w.n_views, L.F32)}
-    for name in ("bf16", "fp8"):
+    for name in ("bf16", "fp8") + (("mxfp8", "mxfp4") if args.mx_steps else ()):
         codes, scale = L.gift_quantize_views(master, dts[name])
         views[name] = L.Views(codes, w.n_views, dts[name], scale, master)
     torch.cuda.synchronize()
@@ -216,6 +218,12 @@ def main():
         result["fp32_path"] = {"queries_per_s": round(f32_qps, 2),
                                "speedup_of_headline": round(qps / f32_qps, 2),
                                "kernels_ms": ref_run["kern"]}
+    if args.mx_steps and ref_run is not None:
+        for name in ("mxfp8", "mxfp4"):
+            mr = run(name, args.mx_steps, 1)
+            rr = recall(mr["ids"], exact_ids, min(100, k))
+            result[f"{name}_path"] = {"queries_per_s": round(B * args.mx_steps / mr["total"], 2),
+                                      "recall_at100_mean": rr[0], "recall_at100_min": rr[1]}
     if fp8_run is not None:
         f8 = recall(fp8_run["ids"], exact_ids, min(100, k))
         result["fp8_path"] = {"queries_per_s": round(B * args.fp8_steps / fp8_run["total"], 2),
