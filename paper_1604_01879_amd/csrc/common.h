@@ -29,6 +29,10 @@ gift_status fail(gift_status st, const char* fmt, ...);
 // Launch-error check after a kernel launch.
 #define GIFT_LAUNCHED() GIFT_HIP(hipGetLastError())
 
+// Allows `kernel` `bytes` of dynamic LDS on the current device (once per
+// kernel and device; thread-safe).
+gift_status ensure_dynamic_lds(const void* kernel, size_t bytes);
+
 // ---------------------------------------------------------------- workspace
 // Carves 256-byte aligned sub-buffers out of one caller-owned workspace.
 // With base == nullptr it only measures.

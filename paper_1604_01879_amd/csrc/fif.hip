@@ -226,11 +226,9 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
   hipLaunchKernelGGL(norms_kernel, dim3((K + 3) / 4), dim3(256), 0, st, cb, K, dim, nhi, nlo);
   GIFT_LAUNCHED();
   using T = TileShape<2, 2>;
-  static bool attr = false;
-  if (!attr) {
-    GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(dots_kernel),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)T::LDS_BYTES));
-    attr = true;
+  {
+    const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(dots_kernel), T::LDS_BYTES);
+    if (s != GIFT_OK) return s;
   }
   // accumulation depth of the MFMA dot: dim/2 steps, charged 2 roundings each
   const double u = 5.9604644775390625e-08, nn = 2.0 * dim + 4;
@@ -583,12 +581,9 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
   const int row_bytes = (int)row_bytes_of(db->dtype, db->dim);
 #define GIFT_SCAN_LAUNCH(DTV)                                                                  \
   do {                                                                                         \
-    static bool attr = false;                                                                  \
-    if (!attr) {                                                                               \
-      GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fif_scan_kernel<DTV>),        \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));   \
-      attr = true;                                                                             \
-    }                                                                                          \
+    const gift_status s_ = ensure_dynamic_lds(                                                 \
+        reinterpret_cast<const void*>(fif_scan_kernel<DTV>), shmem);                           \
+    if (s_ != GIFT_OK) return s_;                                                              \
     hipLaunchKernelGGL(fif_scan_kernel<DTV>, dim3((unsigned)bound), dim3(256), shmem, st,      \
                        static_cast<const uint8_t*>(db->data),                                  \
                        static_cast<const float*>(db->scale), db->n_views,                       \
@@ -816,12 +811,9 @@ gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_
   const size_t shmem = 128 * 129 * 4;  // the largest phase: the scan's C tile
 #define GIFT_BATCH_LAUNCH(DTV)                                                                 \
   do {                                                                                         \
-    static bool attr = false;                                                                  \
-    if (!attr) {                                                                               \
-      GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fif_batch_kernel<DTV>),       \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));   \
-      attr = true;                                                                             \
-    }                                                                                          \
+    const gift_status s_ = ensure_dynamic_lds(                                                 \
+        reinterpret_cast<const void*>(fif_batch_kernel<DTV>), shmem);                          \
+    if (s_ != GIFT_OK) return s_;                                                              \
     hipLaunchKernelGGL(fif_batch_kernel<DTV>, dim3(grid), dim3(256), shmem, st, a);            \
   } while (0)
   switch (dtype) {

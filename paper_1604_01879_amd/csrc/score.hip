@@ -193,11 +193,9 @@ static gift_status launch_tiles(const gift_views* db, const void* qv,
   GIFT_CHECK(blocks < (int64_t)1 << 31, GIFT_ECAPACITY, "score grid too large");
   const size_t shmem = TileShape<WM, WN>::LDS_BYTES;
   auto kern = score_tiles_kernel<DT, WM, WN>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    GIFT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    attr_set = true;
+  {
+    const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), shmem);
+    if (s != GIFT_OK) return s;
   }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), shmem, st,
                      static_cast<const uint8_t*>(db->data), db->scale,

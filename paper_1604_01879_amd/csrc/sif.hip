@@ -452,12 +452,7 @@ void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* 
                        int32_t* flags, hipStream_t st) {
   if (B <= 0) return;
   const size_t shmem = (size_t)SIF_CAP * (8 + 4 + sizeof(SCand));
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rerank_sif_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    attr = true;
-  }
+  (void)ensure_dynamic_lds(reinterpret_cast<const void*>(rerank_sif_kernel), shmem);
   hipLaunchKernelGGL(rerank_sif_kernel, dim3(B), dim3(256), shmem, st, l1, post_off, post_id,
                      post_val, N, q_id, q_val, q_self, k1, k, out_id, out_s, flags);
 }
