@@ -653,8 +653,16 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, cons
 // of phase p first waits until every item numbered below the first item of
 // p has finished (one `done` counter).  Those items were all taken before
 // this one by blocks that are running, and the earliest unfinished item
-// never waits, so the queue always drains.  A wait that exceeds its spin
-// limit sets the error word and the item is skipped, so every block exits.
+// never waits, so the queue always drains.  A wait that exceeds its
+// wall-clock limit sets the error word; from then on every wait and every
+// item is skipped, so every block exits.
+//
+// Memory ordering across blocks (the L2 of each XCD is private): every
+// thread of an item that produces data for later items makes its writes
+// visible at device scope (release fence) before the block barrier that
+// precedes the `done` increment.  A waiting item polls `done` with relaxed
+// loads, so the poll does not invalidate caches, and thread 0 takes one
+// device-scope acquire fence after the wait, before the block barrier.
 
 __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   // counters, word counts, and the offsets of unused query slots
@@ -664,7 +672,25 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   if (threadIdx.x == 0) *a.overflow = 0;
   const int32_t last = a.qoff[n_q];
   for (int b = n_q + 1 + threadIdx.x; b <= a.Bmax; b += 256) a.qoff[b] = last;
+}
 
+// Thread 0 of a block: waits until *done >= need.  Returns 0, or the error
+// word when it is (or becomes) set, or 1 after setting it when the wait
+// exceeds `ticks` of the constant-rate wall clock.
+__device__ int wait_done(const unsigned long long* done, unsigned long long* err,
+                         unsigned long long need, int64_t ticks) {
+  const long long t0 = wall_clock64();
+  for (int polls = 0;; ++polls) {
+    if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return 0;
+    const int e = (int)__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e != 0) return e;
+    if (wall_clock64() - t0 > ticks) {
+      __hip_atomic_fetch_or(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 1;
+    }
+    if (polls < 64) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(32);
+  }
 }
 
 template <int DT>
@@ -679,6 +705,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   unsigned long long* err = a.ctrl + 2;
   const int n_q = a.desc[0];
   const int64_t n_v = a.desc[1];
+  int acquired = -1;  // thread 0: last phase whose inputs this block acquired
   for (;;) {
     if (tid == 0) sh_item = (int64_t)atomicAdd(head, 1ull);
     __syncthreads();
@@ -691,21 +718,16 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     const bool needs_wait = ph == BP_SEL || ph == BP_PRE || ph == BP_SCAT || ph == BP_SCAN ||
                             ph == BP_RED;
     if (tid == 0) {
-      if (needs_wait) {
-        const unsigned long long need = (unsigned long long)a.first[ph];
-        unsigned long long spins = 0;
-        while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          if (++spins > (1ull << 26)) {
-            atomicOr(err, 1ull);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(8);
-        }
+      int e = (int)__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // phases only grow within a block: one wait and one acquire per phase
+      if (needs_wait && ph > acquired && e == 0) {
+        e = wait_done(done, err, (unsigned long long)a.first[ph], a.wait_ticks);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        acquired = ph;
       }
-      sh_err = (int)__hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      sh_err = e;
     }
     __syncthreads();
-    __threadfence();
     if (!sh_err) {
       switch (ph) {
         case BP_Q: {
@@ -795,11 +817,10 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           break;
       }
     }
+    // the per-query means are read only after the kernel
+    if (ph != BP_RED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      atomicAdd(done, 1ull);
-    }
+    if (tid == 0) __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -112,6 +112,7 @@ struct BatchArgs {
   int32_t* overflow;
   unsigned long long* ctrl;  // head, done, error, spare
   float gamma2;
+  int64_t wait_ticks;        // wall-clock ticks a phase wait may take
   int64_t gemm_col_tiles;
   int64_t first[9];          // first item of each phase, then the total
 };

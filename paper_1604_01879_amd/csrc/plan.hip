@@ -172,6 +172,12 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
     return fail(GIFT_EHIP, "cannot query the device");
   }
   p->grid = n_cu * blocks_per_cu;
+  int clock_khz = 0;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      clock_khz <= 0) {
+    delete p;
+    return fail(GIFT_EHIP, "cannot query the wall-clock rate");
+  }
 
   // once per plan: codebook norms and list-tile offsets
   gift_status s = launch_norms(fif->codebook, fif->K, db->dim, w.nhi, w.nlo, st);
@@ -220,6 +226,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.overflow = w.overflow;
   a.ctrl = w.ctrl;
   a.gamma2 = assign_gamma2(db->dim);
+  a.wait_ticks = (int64_t)clock_khz * 1000 * 5;  // five seconds per phase wait
   a.gemm_col_tiles = (fif->K + 127) / 128;
   const int64_t n_items[BP_END] = {
       db->dtype == GIFT_F32 ? 0 : (max_views + 63) / 64,          // Q

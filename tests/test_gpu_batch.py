@@ -56,9 +56,12 @@ def test_plan_equals_query_fif(L, dtype_name):
     _say(f"plan vs query_fif {dtype_name}")
     dt = {"f32": L.F32, "bf16": L.BF16}[dtype_name]
     w, db, q, qoff, cb, V, F = _setup(L, dt)
+    torch.cuda.synchronize()
+    _say("index built")
     k, R = 15, 60
     plan = L.FifPlan(V, F, max_queries=12, max_views=12 * 64, max_views_per_query=64, top_k=k,
                      rescore_r=R)
+    _say("plan created")
     S = O.fif_scores(q, qoff, db, w.n_views, cb, *O.build_fif(O.assign(db, cb, 2), 24,
                                                                 w.n_views))
     # full batch, then a smaller one (fewer queries and views) on the same plan
@@ -67,10 +70,13 @@ def test_plan_equals_query_fif(L, dtype_name):
         qq = q[:qo[-1]]
         Q = L.Queries(torch.from_numpy(qq).to(DEV), torch.from_numpy(qo))
         ref_ids, ref_sc, ref_fl = L.gift_query_fif(V, F, Q, k, R)
+        torch.cuda.synchronize()
+        _say(f"query_fif {sub} queries done")
         n_q, n_v = _load(plan, qq, qo)
         for eager in (False, True):
             plan.run(n_q, n_v, eager=eager)
             plan.stream.synchronize()
+            _say(f"plan run eager={eager} done")
             assert plan.error() == 0
             ids = plan.ids[:n_q].cpu().numpy()
             sc = plan.scores[:n_q].cpu().numpy()
