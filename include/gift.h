@@ -26,6 +26,9 @@
  *    ABI.  No pointer is retained after a call returns.
  *  - Views are float32 rows of `dim` values, shape-major: database view j
  *    of shape p is row p * n_views + j.  dim must be a multiple of 32.
+ *    Arrays of rows (views, master views, query views, codebooks, training
+ *    rows) must be 16-byte aligned and scale arrays 4-byte aligned;
+ *    otherwise a call returns GIFT_EINVAL.
  *    The paper's features are L2-normalised (Sec. 2.2); the certified
  *    ranking below assumes unit-norm rows (to within 1e-6).
  *  - Discrete outputs (codeword assignments, ranked ids) are defined on the

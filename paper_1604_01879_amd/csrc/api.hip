@@ -86,8 +86,15 @@ static float first_pass_err(int dtype, int dim, int max_m) {
 float rescore_dot_error(int dim) { return rescore_dot_err(dim); }
 float first_pass_error(int dtype, int dim, int max_m) { return first_pass_err(dtype, dim, max_m); }
 
+// Rows are read with 16-byte vector loads and scales with 4-byte loads.
+static bool aligned(const void* p, uintptr_t a) {
+  return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
+}
+
 static gift_status check_views(const gift_views* db) {
   GIFT_CHECK(db != nullptr && db->data != nullptr, GIFT_EINVAL, "null database views");
+  GIFT_CHECK(aligned(db->data, 16) && aligned(db->master, 16) && aligned(db->scale, 4),
+             GIFT_EINVAL, "views and master views must be 16-byte aligned, scales 4-byte");
   GIFT_CHECK(db->dtype >= GIFT_F32 && db->dtype <= GIFT_MXFP4, GIFT_EUNSUPPORTED,
              "unsupported dtype %d", db->dtype);
   GIFT_CHECK(db->dtype != GIFT_MXFP8 || db->dim % 128 == 0, GIFT_EUNSUPPORTED,
@@ -109,6 +116,7 @@ static gift_status check_queries(const gift_queries* q, int dim) {
   (void)dim;
   GIFT_CHECK(q != nullptr && q->views != nullptr && q->offsets != nullptr, GIFT_EINVAL,
              "null queries");
+  GIFT_CHECK(aligned(q->views, 16), GIFT_EINVAL, "query views must be 16-byte aligned");
   GIFT_CHECK(q->n_queries >= 1, GIFT_EINVAL, "n_queries must be >= 1");
   GIFT_CHECK(q->total_views >= 1 && q->total_views < ((int64_t)1 << 31), GIFT_EINVAL,
              "total_views out of range");
@@ -202,6 +210,7 @@ static AssignWs carve_assign(Carver& c, int64_t n, int K) {
 
 static gift_status check_codebook(const float* cb, int K, int ma, int dim) {
   GIFT_CHECK(cb != nullptr, GIFT_EINVAL, "null codebook");
+  GIFT_CHECK(aligned(cb, 16), GIFT_EINVAL, "codebook and training rows must be 16-byte aligned");
   GIFT_CHECK(K >= 1 && K <= 16384, GIFT_EUNSUPPORTED, "K must be in 1..16384 (got %d)", K);
   GIFT_CHECK(ma >= 1 && ma <= 8 && ma <= K, GIFT_EUNSUPPORTED, "ma must be in 1..min(8, K)");
   GIFT_CHECK(dim >= 32 && dim % 32 == 0, GIFT_EUNSUPPORTED, "dim must be a multiple of 32");
@@ -452,6 +461,7 @@ gift_status gift_assign(const float* x, int64_t n, int32_t dim, const float* cod
   gift_status s = check_codebook(codebook, K, ma, dim);
   if (s != GIFT_OK) return s;
   GIFT_CHECK(x && words && n >= 0, GIFT_EINVAL, "null input/output or n < 0");
+  GIFT_CHECK(aligned(x, 16), GIFT_EINVAL, "input rows must be 16-byte aligned");
   const hipStream_t st = (hipStream_t)stream;
   Carver c(ws);
   AssignWs w = carve_assign(c, n, K);

@@ -224,18 +224,31 @@ __device__ __forceinline__ void mfma_tile_mainloop_db(
   }
 }
 
-// Block-scaled (MX) operands: each lane supplies 32 consecutive K values of
-// its row and one E8M0 scale byte for them per MFMA step.  FMT is the
-// operand-format code of the scaled MFMA (0: e4m3, 4: e2m1).  Per 128-byte
-// K-tile a lane half covers 64 bytes: 2 steps of 32 e4m3 bytes, or 4 steps
-// of 16 e2m1 bytes.  `sa`/`sb` hold the lane's scale bytes for the tile's
-// steps, step s in byte s.
+// Block-scaled (MX) operands, one E8M0 scale byte per lane per MFMA step;
+// FMT is the operand-format code of the scaled MFMA (0: e4m3, 4: e2m1).
+//   e4m3: a step covers two 32-value blocks X, Y of the row.  The lane of
+//     half h supplies X[16h, 16h+16) then Y[16h, 16h+16) and the scale of
+//     block h of the pair (its partner lane carries the other one).  Per
+//     128-byte K-tile: steps over blocks (0, 1) and (2, 3); lane half h reads
+//     the pieces at bytes 16h, 32 + 16h, 64 + 16h, 96 + 16h.
+//   e2m1: a lane supplies one whole 32-value block (16 bytes) with its own
+//     scale; half h covers bytes [64h, 64h + 64) in 4 steps.
+// `sa`/`sb` hold the lane's scale bytes for the tile's steps, step s in
+// byte s.
 template <int FMT>
 struct MfmaMx;
 
 template <>
 struct MfmaMx<0> {
   static constexpr int STEPS = 2;
+  // byte offset of the lane half's first piece and the stride between pieces
+  __device__ static __forceinline__ int piece0(int half) { return 16 * half; }
+  static constexpr int PIECE_STRIDE = 32;
+  // scale byte of step s for this lane half: block 2s + half of the K-tile
+  __device__ static __forceinline__ uint32_t scales(const uint8_t* row, int kt, int half) {
+    const uint8_t* p = row + kt * 4 + half;
+    return (uint32_t)p[0] | ((uint32_t)p[2] << 8);
+  }
   __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], uint32_t sa,
                                              uint32_t sb, f32x16& c) {
 #pragma unroll
@@ -251,6 +264,12 @@ struct MfmaMx<0> {
 template <>
 struct MfmaMx<4> {
   static constexpr int STEPS = 4;
+  __device__ static __forceinline__ int piece0(int half) { return 64 * half; }
+  static constexpr int PIECE_STRIDE = 16;
+  // scale byte of step s for this lane half: block 4 half + s of the K-tile
+  __device__ static __forceinline__ uint32_t scales(const uint8_t* row, int kt, int half) {
+    return *reinterpret_cast<const uint32_t*>(row + kt * 8 + half * 4);
+  }
   __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], uint32_t sa,
                                              uint32_t sb, f32x16& c) {
 #pragma unroll
@@ -272,7 +291,6 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
     const uint8_t* const (&sa_row)[WM], const uint8_t* const (&sb_row)[WN],
     f32x16 (&acc)[WM][WN]) {
   using T = TileShape<WM, WN>;
-  constexpr int STEPS = MfmaMx<FMT>::STEPS;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -297,13 +315,12 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
     }
   };
   auto sload = [&](const uint8_t* row, int kt) -> uint32_t {
-    const int b0 = kt * 2 * STEPS + half * STEPS;  // first scale byte of this lane half
-    if (STEPS == 2) return *reinterpret_cast<const uint16_t*>(row + b0);
-    return *reinterpret_cast<const uint32_t*>(row + b0);
+    return MfmaMx<FMT>::scales(row, kt, half);
   };
   gload(0);
-  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 64;
-  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + half * 64;
+  constexpr int PS = MfmaMx<FMT>::PIECE_STRIDE;
+  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + MfmaMx<FMT>::piece0(half);
+  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + MfmaMx<FMT>::piece0(half);
   for (int kt = 0; kt < n_kt; ++kt) {
     __syncthreads();
 #pragma unroll
@@ -321,14 +338,14 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
     for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * 16);
+        b[j][s] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + s * PS);
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
       const uint32_t sa = sload(sa_row[i], kt);
       uint4 a[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * 16);
+        a[s] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + s * PS);
 #pragma unroll
       for (int j = 0; j < WN; ++j) MfmaMx<FMT>::run(a, b[j], sa, sb[j], acc[i][j]);
     }

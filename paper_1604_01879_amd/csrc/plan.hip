@@ -144,6 +144,10 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
                  (int64_t)rescore_r <= db->n_shapes,
              GIFT_EINVAL, "need 1 <= top_k <= rescore_r <= min(1024, N)");
   GIFT_CHECK(q_views && q_offsets && ids && scores, GIFT_EINVAL, "null batch buffers");
+  GIFT_CHECK((reinterpret_cast<uintptr_t>(q_views) & 15) == 0 &&
+                 (reinterpret_cast<uintptr_t>(db->data) & 15) == 0 &&
+                 (reinterpret_cast<uintptr_t>(db->master) & 15) == 0,
+             GIFT_EINVAL, "views must be 16-byte aligned");
   GIFT_CHECK(blocks_per_cu >= 1 && blocks_per_cu <= 2, GIFT_EINVAL, "blocks_per_cu must be 1 or 2");
   const hipStream_t st = (hipStream_t)stream;
   PlanWs w = carve_plan(ws, db, fif, max_queries, max_views, rescore_r);

@@ -261,17 +261,36 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
             ((unsigned long long)__shfl_xor(hi_b, 32, 64) << 32);
     if (half == 0) jmask[i] = i < mi ? bits : 0ull;
     __syncthreads();
-    // compensated maximum per query view: one wave per view
+    // compensated maximum per query view: one wave per view.  Lane l
+    // takes the float4 pieces l, l + 64, ... of the rows, 8 pieces of each
+    // row in flight per batch (dim is a multiple of 32, so the piece count
+    // is a multiple of 8).
+    const int n4 = dim >> 2;
     for (int iv = wave; iv < mi; iv += 2) {
-      const float* qrow = qbase + (int64_t)iv * dim;
+      const float4* q4 = reinterpret_cast<const float4*>(qbase + (int64_t)iv * dim);
       unsigned long long bb = jmask[iv];
       ff best = {-INFINITY, 0.f};
       while (bb) {
         const int j = __builtin_ctzll(bb);
         bb &= bb - 1;
-        const float* prow = pbase + (int64_t)j * dim;
+        const float4* p4 = reinterpret_cast<const float4*>(pbase + (int64_t)j * dim);
         float s = 0.f, c = 0.f;
-        for (int t = lane; t < dim; t += 64) dot2_step(qrow[t], prow[t], s, c);
+        for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
+          float4 qa[8], pa[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int u = u0 + 64 * k;
+            qa[k] = u < n4 ? q4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            pa[k] = u < n4 ? p4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            dot2_step(qa[k].x, pa[k].x, s, c);
+            dot2_step(qa[k].y, pa[k].y, s, c);
+            dot2_step(qa[k].z, pa[k].z, s, c);
+            dot2_step(qa[k].w, pa[k].w, s, c);
+          }
+        }
         const ff v = ff_wave_sum(s, c);
         if (ff_gt(v, best)) best = v;
       }

@@ -203,6 +203,18 @@ def test_invalid_arguments_rejected(L):
     with pytest.raises(L.GiftError) as e:
         L.gift_query_exhaustive(bad, Q, 1, 1)
     assert e.value.status == L.EUNSUPPORTED
+    # rows that start 4 bytes past a 16-byte boundary are refused, not read
+    flat = torch.zeros(db.size + 4, dtype=torch.float32, device="cuda")
+    shifted = flat[1:1 + db.size].view(db.shape)
+    assert shifted.data_ptr() % 16 == 4
+    with pytest.raises(L.GiftError) as e:
+        L.gift_query_exhaustive(L.Views(shifted, 64, L.F32), Q, 1, 1)
+    assert e.value.status == L.EINVAL
+    qflat = torch.zeros(q.size + 4, dtype=torch.float32, device="cuda")
+    Qs = L.Queries(qflat[1:1 + q.size].view(q.shape), torch.from_numpy(qoff))
+    with pytest.raises(L.GiftError) as e:
+        L.gift_query_exhaustive(V, Qs, 1, 1)
+    assert e.value.status == L.EINVAL
 
 
 _E2M1_VALUES = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0, -0.0, -0.5, -1.0, -1.5, -2.0,
