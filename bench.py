@@ -58,6 +58,10 @@ def main():
     ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy", "sweep"], default="c3",
                     help="c3: exhaustive precision headline (default); c4: batched F-IF + "
                          "S-IF plan; c5: continuous-batching serving")
+    ap.add_argument("--tune", default="",
+                    help="fixed score tuning 'tile,group' for BF16 and FP8 instead of the "
+                         "autotuner (e.g. 1,32), so that profiled launches are all the timed "
+                         "configuration")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rates", default="200,500,1000")
     args = ap.parse_args()
@@ -115,6 +119,11 @@ def main():
     tuning = {}
     for name in ("bf16", "fp8"):
         if name == args.dtype or (name == "fp8" and args.fp8_steps):
+            if args.tune:
+                bt, bg = (int(x) for x in args.tune.split(","))
+                L.gift_set_score_tuning(dts[name], bt, bg)
+                tuning[name] = {"tile": bt, "group": bg, "fixed": True}
+                continue
             bt, bg, ms = L.gift_autotune_score(views[name], Q, [0, 1], [8, 16, 32], reps=2)
             tuning[name] = {"tile": bt, "group": bg, "ms_grid": ms.round(2).tolist()}
             log(f"autotuned {name}: tile {bt} group {bg}")
@@ -309,6 +318,10 @@ def _build_index(w, torch, L, master, V, k1, log_prefix):
                       "sif_postings": S.nnz()}
 
 
+_PHASES = ("quantize", "clear", "codeword_dots", "word_select", "word_offsets", "grouping",
+           "active_tiles", "list_scan", "query_mean")
+
+
 def scale_bench(args):
     import torch
     import synth
@@ -350,10 +363,12 @@ def scale_bench(args):
                 plan.stream.synchronize()
                 t_eager = time.perf_counter() - t1
             err = plan.error()
+            phases = dict(zip(_PHASES, (round(x / 1e3, 3) for x in plan.phase_us())))
             out[f"blocks_per_cu_{bpc}"] = {"ms_per_batch": round(dt * 1e3, 3),
                                            "queries_per_s": round(B / dt, 1),
                                            "eager_first_pass_ms": round(t_eager * 1e3, 3),
-                                           "rerank_ms": rr_ms / max(rr_n, 1), "queue_error": err}
+                                           "rerank_ms": rr_ms / max(rr_n, 1), "queue_error": err,
+                                           "phase_block_ms": phases}
             log(f"c4 plan bpc={bpc}: {dt * 1e3:.2f} ms per batch of {B}")
             plan.close()
         best = max(out.values(), key=lambda v: v["queries_per_s"])
@@ -365,7 +380,33 @@ def scale_bench(args):
                 "K=8192 (k-means on 524,288 sampled views), k1=20, 1,024 queries with 12..64 "
                 "views per batch", "queries_per_batch": B, "views_per_batch": nvq},
                 "build": build, "plans": out}
-    # c5: continuous batching under Poisson load
+    # c5: first the cost of one batch by size on a plan alone, then
+    # continuous batching under Poisson load
+    by_size = {}
+    plan = L.FifPlan(V, F, 64, 64 * 64, w.m_hi, k1 - 1, 64)
+    one = torch.ones(64, dtype=torch.float32, device=dev)
+    for nb in (1, 4, 16, 64):
+        nv = int(qoff[nb])
+        plan.views[:nv].copy_(torch.from_numpy(q[:nv]))
+        plan.offsets[:nb + 1].copy_(torch.from_numpy(qoff[:nb + 1]))
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(plan.stream):
+            plan.run(nb, nv)
+            L.gift_rerank_sif(S, plan.ids[:nb], plan.scores[:nb], one[:nb], args.top_k,
+                              stream=plan.stream)
+            ev0.record(plan.stream)
+            for _ in range(5):
+                plan.run(nb, nv)
+                L.gift_rerank_sif(S, plan.ids[:nb], plan.scores[:nb], one[:nb], args.top_k,
+                                  stream=plan.stream)
+            ev1.record(plan.stream)
+        plan.stream.synchronize()
+        by_size[str(nb)] = {"views": nv, "ms_per_batch": round(ev0.elapsed_time(ev1) / 5, 3),
+                            "phase_block_ms": dict(zip(_PHASES, (round(x / 1e3, 3)
+                                                                 for x in plan.phase_us())))}
+        log(f"c5 plan alone: {nb} queries in {by_size[str(nb)]['ms_per_batch']} ms")
+    plan.close()
     rates = [float(r) for r in args.serve_rates.split(",")]
     srv = Server(V, F, S, top_k=args.top_k, k1=k1, rescore_r=64, max_queries=64,
                  max_views=64 * 64, max_slots=3)
@@ -394,7 +435,7 @@ def scale_bench(args):
             "config": {"workload": "c5: 200,000 shapes x 64 x 1024 e4m3, K=8192, k1=20, Poisson "
                        f"arrivals {args.serve_rates} q/s for {args.serve_seconds}s each, "
                        "8..64 views per query", "slots": n_slots},
-            "build": build, "serving": runs}
+            "build": build, "plan_alone_by_batch": by_size, "serving": runs}
 
 
 def sweep_bench(args):

@@ -329,7 +329,12 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* non-default stream not being captured); run is asynchronous.  A plan is */
 /* not thread-safe and its runs on different streams must not overlap.     */
 /* gift_fif_plan_error (SYNCHRONISES) returns 1 if a queue wait of the     */
-/* last run hit its spin limit (results invalid), else 0.                  */
+/* last run hit its time limit (results invalid), else 0.                  */
+/* gift_fif_plan_phase_us (SYNCHRONISES) writes, for the last run, the     */
+/* block-microseconds spent in each phase of the persistent kernel (sum    */
+/* over blocks of the wall time from taking an item to finishing it):      */
+/* out[9] = quantize, clear, codeword dots, word selection, word offsets,  */
+/* grouping, active-tile listing, list scan, per-query mean.               */
 /* ---------------------------------------------------------------------- */
 typedef struct gift_fif_plan gift_fif_plan;
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,
@@ -351,6 +356,8 @@ gift_status gift_fif_plan_run_eager(gift_fif_plan* plan, int32_t n_queries,
                                     int64_t n_views, void* stream);
 gift_status gift_fif_plan_error(gift_fif_plan* plan, int32_t* err,
                                 void* stream);
+gift_status gift_fif_plan_phase_us(gift_fif_plan* plan, double* out /* host [9] */,
+                                   void* stream);
 gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
 
 /* ---------------------------------------------------------------------- */

@@ -62,11 +62,17 @@ static const double U32 = 5.9604644775390625e-08;  // 2^-24
 // gamma_n = n u / (1 - n u), the classic bound on an n-term float32 sum.
 static double gamma_n(double n) { return n * U32 / (1.0 - n * U32); }
 
-// Bound on |float32 dot - exact dot| of two unit-norm views in the rescore
-// kernel: 16 MFMA steps of two products per 32-value K-tile (charged two
-// roundings each) into a fresh block, added into a running total.
+// Bound on |approximate dot - exact dot| of two unit-norm views in the
+// rescore kernel.  Splitting x = hi + lo + r (bfloat16 hi, lo; |x - hi| <=
+// 2^-8 |x|, |r| <= 2^-16 |x|) and dropping lo.lo', hi.r', r.hi' and smaller
+// terms costs at most 3.02 * 2^-16 sum |x y|.  Per 32-value K-tile, 6 BF16
+// MFMAs of 16 products each (charged 17 roundings each) go into a fresh
+// block that is added into a running total; the summed terms are at most
+// 1.02 sum |x y|.  sum |x y| <= 1 for unit-norm views.  The absolute term
+// covers values small enough for their low parts to be denormal.
 static float rescore_dot_err(int dim) {
-  return (float)(gamma_n(2.0 * 16 + dim / 32 + 2) * 1.0001);
+  const double split = 3.02 / 65536.0;
+  return (float)((split + 1.02 * gamma_n(6.0 * 17 + dim / 32 + 2)) * 1.0001 + 1e-25);
 }
 
 // Bound on |first-pass score - exact Eq. 3 score| for unit-norm views.
@@ -305,11 +311,11 @@ static gift_status fif_first_pass(const gift_views* db, const gift_fif* f, const
   GIFT_LAUNCHED();
   prof_begin(P_SCAN, st);
   s = launch_fif_scan(db, f->offsets, f->entry_shape, f->entry_view, f->n_entries, f->K,
-                      w.tile_off, w.tcount, w.goff, w.gitems, qv, qs, w.mbuf, tq, st);
+                      w.tile_off, w.tcount, w.goff, w.gitems, qv, qs, w.mbuf, db->n_shapes, st);
   prof_end(st);
   if (s != GIFT_OK) return s;
   prof_begin(P_REDUCE, st);
-  launch_reduce_fif(w.mbuf, tq, db->n_shapes, q->offsets, q->n_queries, w.S, st);
+  launch_reduce_fif(w.mbuf, db->n_shapes, db->n_shapes, q->offsets, q->n_queries, w.S, st);
   prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;
@@ -428,19 +434,19 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
   if ((s = first_pass(db, q, w, st)) != GIFT_OK) return s;
   prof_begin(P_SELECT, st);
-  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, w.cand, w.cand_s, st);
+  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), nullptr, nullptr, 0,
-                 w.s_hi, w.s_lo, st);
+                 nullptr, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
                     db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views), nullptr,
-                    ids, scores, flags, st);
+                    nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;
@@ -634,19 +640,19 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
   if ((s = fif_first_pass(db, fif, q, w, st)) != GIFT_OK) return s;
   prof_begin(P_SELECT, st);
-  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, w.cand, w.cand_s, st);
+  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->max_views, w.cand, rescore_r, rescore_dot_err(db->dim), w.qwords,
-                 fif->view_words, fif->ma, w.s_hi, w.s_lo, st);
+                 fif->view_words, fif->ma, nullptr, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
                     db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views),
-                    w.as.overflow, ids, scores, flags, st);
+                    w.as.overflow, nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;

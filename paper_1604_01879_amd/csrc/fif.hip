@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb
 // arithmetic and the ma smallest (distance, index) are written.
 constexpr int SEL_CAP = 256;   // candidates kept per row
 constexpr int MAX_MA = 8;
+constexpr int SEL_UNROLL = 8;  // codewords per lane with loads in flight together
 
 __device__ inline bool dk_less(float ah, float al, int ak, float bh, float bl, int bk) {
   if (ah != bh) return ah < bh;
@@ -104,25 +105,52 @@ __device__ void select_rows(const float* __restrict__ x, int64_t r0, int64_t r1,
   const int64_t r = active ? r_raw : r1 - 1;
   const float* xr = x + r * dim;
   const float* Dr = D + (r - r0) * K;
-  // ||x|| with slack for its own rounding
+  // ||x|| with slack for its own rounding (lane l: float4 pieces l, l + 64,
+  // ...; dim is a multiple of 32, so the piece count is a multiple of 8)
+  const int n4 = dim >> 2;
+  const float4* x4 = reinterpret_cast<const float4*>(xr);
   float ss = 0.f;
-  for (int t = lane; t < dim; t += 64) ss = __builtin_fmaf(xr[t], xr[t], ss);
+  for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
+    float4 xa[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      xa[k] = u0 + 64 * k < n4 ? x4[u0 + 64 * k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ss = __builtin_fmaf(xa[k].x, xa[k].x, ss);
+      ss = __builtin_fmaf(xa[k].y, xa[k].y, ss);
+      ss = __builtin_fmaf(xa[k].z, xa[k].z, ss);
+      ss = __builtin_fmaf(xa[k].w, xa[k].w, ss);
+    }
+  }
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
   const float xn = sqrtf(ss) * 1.001f + 1e-30f;
   const float c1 = gamma2 * xn;
   const float c2 = 2.4e-7f;  // a few float32 roundings of d^_k itself
 
-  // lane-local ma smallest upper bounds
+  // lane-local ma smallest upper bounds; SEL_UNROLL codewords per lane are
+  // loaded before any is used, so their loads overlap
   float best[MAX_MA];
 #pragma unroll
   for (int a = 0; a < MAX_MA; ++a) best[a] = INFINITY;
-  for (int k = lane; k < K; k += 64) {
-    const float dk = nhi[k] - 2.f * Dr[k];
-    const float ek = c1 * sqrtf(fmaxf(nhi[k], 0.f)) + c2 * (fabsf(dk) + 1.f);
-    float u = dk + ek;
+  for (int k0 = lane; k0 < K; k0 += 64 * SEL_UNROLL) {
+    float dv[SEL_UNROLL], nv[SEL_UNROLL];
 #pragma unroll
-    for (int a = 0; a < MAX_MA; ++a) {
-      if (a < ma && u < best[a]) { const float t = best[a]; best[a] = u; u = t; }
+    for (int t = 0; t < SEL_UNROLL; ++t) {
+      const int k = k0 + 64 * t;
+      dv[t] = k < K ? Dr[k] : 0.f;
+      nv[t] = k < K ? nhi[k] : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < SEL_UNROLL; ++t) {
+      if (k0 + 64 * t >= K) continue;
+      const float dk = nv[t] - 2.f * dv[t];
+      const float ek = c1 * sqrtf(fmaxf(nv[t], 0.f)) + c2 * (fabsf(dk) + 1.f);
+      float u = dk + ek;
+#pragma unroll
+      for (int a = 0; a < MAX_MA; ++a) {
+        if (a < ma && u < best[a]) { const float tt = best[a]; best[a] = u; u = tt; }
+      }
     }
   }
   // wave-wide ma-th smallest of the upper bounds
@@ -145,29 +173,55 @@ __device__ void select_rows(const float* __restrict__ x, int64_t r0, int64_t r1,
   }
   // candidates: d^_k - e_k <= U, in ascending k
   int n_c = 0;
-  for (int k0 = 0; k0 < K; k0 += 64) {
-    const int k = k0 + lane;
-    bool f = false;
-    if (k < K) {
-      const float dk = nhi[k] - 2.f * Dr[k];
-      const float ek = c1 * sqrtf(fmaxf(nhi[k], 0.f)) + c2 * (fabsf(dk) + 1.f);
-      f = dk - ek <= U;
+  for (int kb = 0; kb < K; kb += 64 * SEL_UNROLL) {
+    float dv[SEL_UNROLL], nv[SEL_UNROLL];
+#pragma unroll
+    for (int t = 0; t < SEL_UNROLL; ++t) {
+      const int k = kb + 64 * t + lane;
+      dv[t] = k < K ? Dr[k] : 0.f;
+      nv[t] = k < K ? nhi[k] : 0.f;
     }
-    const unsigned long long bal = __ballot(f);
-    const int pos = n_c + __popcll(bal & ((1ull << lane) - 1ull));
-    if (f && pos < SEL_CAP) cand[wave][pos] = k;
-    n_c += __popcll(bal);
+#pragma unroll
+    for (int t = 0; t < SEL_UNROLL; ++t) {
+      const int k = kb + 64 * t + lane;
+      bool f = false;
+      if (k < K) {
+        const float dk = nv[t] - 2.f * dv[t];
+        const float ek = c1 * sqrtf(fmaxf(nv[t], 0.f)) + c2 * (fabsf(dk) + 1.f);
+        f = dk - ek <= U;
+      }
+      const unsigned long long bal = __ballot(f);
+      const int pos = n_c + __popcll(bal & ((1ull << lane) - 1ull));
+      if (f && pos < SEL_CAP) cand[wave][pos] = k;
+      n_c += __popcll(bal);
+    }
   }
   if (n_c > SEL_CAP) {
     if (lane == 0 && active) atomicAdd(overflow, 1);
     n_c = SEL_CAP;
   }
-  // compensated distances of the candidates
+  // compensated distances of the candidates, 8 float4 pieces of each row
+  // in flight per lane
   for (int c = 0; c < n_c; ++c) {
     const int k = cand[wave][c];
-    const float* bk = cb + (int64_t)k * dim;
+    const float4* b4 = reinterpret_cast<const float4*>(cb + (int64_t)k * dim);
     float s = 0.f, cc = 0.f;
-    for (int t = lane; t < dim; t += 64) dot2_step(xr[t], bk[t], s, cc);
+    for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
+      float4 xa[8], ba[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int u = u0 + 64 * q;
+        xa[q] = u < n4 ? x4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        ba[q] = u < n4 ? b4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dot2_step(xa[q].x, ba[q].x, s, cc);
+        dot2_step(xa[q].y, ba[q].y, s, cc);
+        dot2_step(xa[q].z, ba[q].z, s, cc);
+        dot2_step(xa[q].w, ba[q].w, s, cc);
+      }
+    }
     const ff dot = ff_wave_sum(s, cc);
     const ff d = ff_add(ff{nhi[k], nlo[k]}, ff{-2.f * dot.hi, -2.f * dot.lo});
     if (lane == 0) { chi[wave][c] = d.hi; clo[wave][c] = d.lo; }
@@ -464,24 +518,18 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 // One block per list tile of 128 entries and the batch's query views whose
 // word is that list: MFMA dots (entries x query views), the per-shape
 // maximum over the tile's entries (entries of a shape are contiguous), and
-// an atomic max into mbuf[shape][query view] (0 = no matching view yet).
+// an atomic max into mbuf[query view][shape] (row stride ldn; 0 = no
+// matching view yet).
+// Tile b of list w (tile_off[w] <= b < tile_off[w + 1]).
 template <int DT>
-__device__ void scan_tile(
+__device__ void scan_list_tile(
     const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
     int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
-    const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
+    const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int w,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
     const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
-    uint32_t* __restrict__ mbuf, int64_t ldm, int64_t b, uint8_t* lds) {
+    uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds) {
   using T = TileShape<2, 2>;
-  if (b >= tile_off[K]) return;
-  // list w with tile_off[w] <= b < tile_off[w+1]
-  int lo = 0, hi = K;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (tile_off[mid] <= b) lo = mid; else hi = mid;
-  }
-  const int w = lo;
   const int64_t g0 = goff[w], g1 = goff[w + 1];
   if (g0 == g1) return;
   const int64_t e0 = loff[w] + (b - tile_off[w]) * T::BM;
@@ -540,17 +588,37 @@ __device__ void scan_tile(
         for (int r = rbeg; r < rend; ++r) {
           const int shp = ent_shape[e0 + r];
           if (shp != cur) {
-            if (cur >= 0) atomicMax(&mbuf[(int64_t)cur * ldm + qi], float_order(m * cs));
+            if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
             cur = shp;
             m = -INFINITY;
           }
           m = fmaxf(m, C[r * 129 + c]);
         }
-        if (cur >= 0) atomicMax(&mbuf[(int64_t)cur * ldm + qi], float_order(m * cs));
+        if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
       }
     }
     __syncthreads();
   }
+}
+
+// Tile b of the concatenated lists: finds its list, then as scan_list_tile.
+template <int DT>
+__device__ void scan_tile(
+    const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
+    int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
+    const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
+    const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
+    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds) {
+  if (b >= tile_off[K]) return;
+  // list w with tile_off[w] <= b < tile_off[w+1]
+  int lo = 0, hi = K;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  scan_list_tile<DT>(db, db_scale, n_views, row_bytes, loff, ent_shape, ent_view, tile_off, lo,
+                     goff, gitems, qv, q_scale, mbuf, ldn, b, lds);
 }
 
 template <int DT>
@@ -560,17 +628,17 @@ __global__ __launch_bounds__(256, 2) void fif_scan_kernel(
     const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
     const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
-    uint32_t* __restrict__ mbuf, int64_t ldm) {
+    uint32_t* __restrict__ mbuf, int64_t ldn) {
   extern __shared__ __align__(16) uint8_t lds[];
   scan_tile<DT>(db, db_scale, n_views, row_bytes, loff, ent_shape, ent_view, tile_off, K, goff,
-                gitems, qv, q_scale, mbuf, ldm, blockIdx.x, lds);
+                gitems, qv, q_scale, mbuf, ldn, blockIdx.x, lds);
 }
 
 gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int32_t* ent_shape,
                             const int32_t* ent_view, int64_t n_entries, int K,
                             int64_t* tile_off, int64_t* tcount, const int64_t* goff,
                             const int32_t* gitems, const void* qv, const float* qscale,
-                            uint32_t* mbuf, int64_t ldm, hipStream_t st) {
+                            uint32_t* mbuf, int64_t ldn, hipStream_t st) {
   hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tcount);
   GIFT_LAUNCHED();
   hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, st, tcount, K, tile_off);
@@ -588,7 +656,7 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
                        static_cast<const uint8_t*>(db->data),                                  \
                        static_cast<const float*>(db->scale), db->n_views,                       \
                        row_bytes, loff, ent_shape, ent_view, tile_off, K, goff, gitems,        \
-                       static_cast<const uint8_t*>(qv), qscale, mbuf, ldm);                    \
+                       static_cast<const uint8_t*>(qv), qscale, mbuf, ldn);                    \
   } while (0)
   switch (db->dtype) {
     case GIFT_F32: GIFT_SCAN_LAUNCH(GIFT_F32); break;
@@ -601,40 +669,42 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
 }
 
 // S[b][p] = (sum over the query's views of the decoded max, 0 where no view
-// of p shares the word) / m, summed in ascending view order; staged through
-// LDS as reduce_queries_kernel.
-__global__ __launch_bounds__(256) void reduce_fif_kernel(const uint32_t* __restrict__ mbuf,
-                                                         int64_t ldm, int64_t n_shapes,
-                                                         const int32_t* __restrict__ qoff,
-                                                         float* __restrict__ S) {
-  __shared__ uint32_t tile[256 * 65];
-  const int b = blockIdx.y;
-  const int64_t p0 = (int64_t)blockIdx.x * 256;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lo = qoff[b], hi = qoff[b + 1];
+// of p shares the word) / m, summed in ascending view order.  mbuf rows are
+// query views, so each step reads 256 consecutive shapes.
+__device__ __forceinline__ float fif_mean(const uint32_t* __restrict__ mbuf, int64_t ldn,
+                                          int64_t p, int lo, int hi) {
   float acc = 0.f;
-  for (int c0 = lo; c0 < hi; c0 += 64) {
-    const int w = hi - c0 < 64 ? hi - c0 : 64;
-    __syncthreads();
-    for (int r = wave; r < 256; r += 4) {
-      const int64_t p = p0 + r;
-      if (p < n_shapes && lane < w) tile[r * 65 + lane] = mbuf[p * ldm + c0 + lane];
-    }
-    __syncthreads();
-    for (int i = 0; i < w; ++i) {
-      const uint32_t u = tile[tid * 65 + i];
-      if (u != 0u) acc += order_float(u);
-    }
+  int i = lo;
+  for (; i + 4 <= hi; i += 4) {
+    uint32_t u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = mbuf[(int64_t)(i + t) * ldn + p];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (u[t] != 0u) acc += order_float(u[t]);
   }
-  const int64_t p = p0 + tid;
-  if (p < n_shapes) S[(int64_t)b * n_shapes + p] = hi > lo ? acc / (float)(hi - lo) : 0.f;
+  for (; i < hi; ++i) {
+    const uint32_t u = mbuf[(int64_t)i * ldn + p];
+    if (u != 0u) acc += order_float(u);
+  }
+  return hi > lo ? acc / (float)(hi - lo) : 0.f;
 }
 
-void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
+__global__ __launch_bounds__(256) void reduce_fif_kernel(const uint32_t* __restrict__ mbuf,
+                                                         int64_t ldn, int64_t n_shapes,
+                                                         const int32_t* __restrict__ qoff,
+                                                         float* __restrict__ S) {
+  const int b = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_shapes) return;
+  S[(int64_t)b * n_shapes + p] = fif_mean(mbuf, ldn, p, qoff[b], qoff[b + 1]);
+}
+
+void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, const int32_t* qoff,
                        int n_queries, float* S, hipStream_t st) {
   if (n_shapes <= 0 || n_queries <= 0) return;
   dim3 grid((unsigned)((n_shapes + 255) / 256), (unsigned)n_queries);
-  hipLaunchKernelGGL(reduce_fif_kernel, grid, dim3(256), 0, st, mbuf, ldm, n_shapes, qoff, S);
+  hipLaunchKernelGGL(reduce_fif_kernel, grid, dim3(256), 0, st, mbuf, ldn, n_shapes, qoff, S);
 }
 
 // ------------------------------------------------------------------ batch
@@ -642,20 +712,26 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, cons
 // (assign + group + scan + reduce) from a device work queue.  Items are
 // numbered phase by phase:
 //   Q    quantize query views to the storage format (BF16/FP8 only)
-//   FILL clear mbuf for the batch's views
+//   FILL clear rows [0, n_v) of mbuf
 //   GEMM query view x codeword dot tiles (MFMA)
 //   SEL  certified nearest word of 4 query views; count views per word
-//   PRE  exclusive scan of the word counts (one item)
+//   PRE  word offsets of the groups and of the active list tiles (one item)
 //   SCAT place every query view in its word's group
-//   SCAN one list tile against its word's query views (as fif_scan)
-//   RED  per-query mean over its views for 256 shapes
-// Blocks take items in increasing order from an atomic counter.  An item
-// of phase p first waits until every item numbered below the first item of
-// p has finished (one `done` counter).  Those items were all taken before
-// this one by blocks that are running, and the earliest unfinished item
-// never waits, so the queue always drains.  A wait that exceeds its
-// wall-clock limit sets the error word; from then on every wait and every
-// item is skipped, so every block exits.
+//   TILE list the tiles of every list whose word has query views
+//   SCAN one active list tile against its word's query views
+//   RED  per-query mean over its views for BATCH_RED_SHAPES shapes
+// The item counts of Q..TILE follow from the batch's view count, which every
+// block reads at start; SCAN has one item per active tile (counted by PRE)
+// and RED one per (query, shape chunk), so a batch costs what its queries
+// touch, not what the plan could hold.  Blocks take items in increasing
+// order from an atomic counter.  An item of phase p first waits until every
+// item numbered below the first item of p has finished (one `done`
+// counter); an item at or past the first SCAN item first waits for all of
+// Q..TILE, and then knows the SCAN and RED ranges.  The items waited for
+// were all taken before by blocks that are running, and the earliest
+// unfinished item never waits, so the queue always drains.  A wait that
+// exceeds its wall-clock limit sets the error word; from then on every wait
+// and every item is skipped, so every block exits.
 //
 // Memory ordering across blocks (the L2 of each XCD is private): every
 // thread of an item that produces data for later items makes its writes
@@ -668,6 +744,7 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   // counters, word counts, and the offsets of unused query slots
   const int n_q = a.desc[0];
   for (int i = threadIdx.x; i < 4; i += 256) a.ctrl[i] = 0ull;
+  for (int i = threadIdx.x; i < BP_END; i += 256) a.phase_ticks[i] = 0ull;
   for (int k = threadIdx.x; k < a.K; k += 256) a.counts[k] = 0;
   if (threadIdx.x == 0) *a.overflow = 0;
   const int32_t last = a.qoff[n_q];
@@ -693,90 +770,178 @@ __device__ int wait_done(const unsigned long long* done, unsigned long long* err
   }
 }
 
+// tile_word[b] = the list that tile b of the concatenated lists belongs to.
+__global__ __launch_bounds__(256) void tile_word_kernel(const int64_t* __restrict__ tile_off,
+                                                        int K, int32_t* __restrict__ tile_word) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= K) return;
+  for (int64_t b = tile_off[w]; b < tile_off[w + 1]; ++b) tile_word[b] = w;
+}
+
 template <int DT>
 __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int64_t sh_item;
+  __shared__ int64_t sh_nact;
   __shared__ int sh_err;
   const int tid = threadIdx.x;
-  const int64_t total = a.first[BP_END];
   unsigned long long* head = a.ctrl;
   unsigned long long* done = a.ctrl + 1;
   unsigned long long* err = a.ctrl + 2;
+  unsigned long long* n_active_w = a.ctrl + 3;  // active list tiles, written by PRE
   const int n_q = a.desc[0];
   const int64_t n_v = a.desc[1];
-  int acquired = -1;  // thread 0: last phase whose inputs this block acquired
+  // first items of Q..TILE and of SCAN, from the batch's view count
+  int64_t first[BP_SCAN + 1];
+  {
+    const int64_t n_items[BP_SCAN] = {
+        DT == GIFT_F32 ? 0 : (n_v + 63) / 64,                                   // Q
+        (n_v * a.n_shapes + BATCH_FILL_WORDS - 1) / BATCH_FILL_WORDS,           // FILL
+        ((n_v + 127) / 128) * a.gemm_col_tiles,                                 // GEMM
+        (n_v + 3) / 4,                                                          // SEL
+        1,                                                                      // PRE
+        (n_v + 255) / 256,                                                      // SCAT
+        (int64_t)(a.K + 255) / 256};                                            // TILE
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < BP_SCAN; ++i) {
+      first[i] = acc;
+      acc += n_items[i];
+    }
+    first[BP_SCAN] = acc;
+  }
+  const int64_t red_chunks = (a.n_shapes + BATCH_RED_SHAPES - 1) / BATCH_RED_SHAPES;
+  const int64_t n_red = (int64_t)n_q * red_chunks;
+  int64_t n_active = -1;  // active list tiles, once this block has waited for PRE
+  int acquired = -1;      // thread 0: last phase whose inputs this block acquired
+  long long t_item = 0;   // thread 0: wall clock when the item was taken
   for (;;) {
-    if (tid == 0) sh_item = (int64_t)atomicAdd(head, 1ull);
+    if (tid == 0) {
+      sh_item = (int64_t)atomicAdd(head, 1ull);
+      t_item = wall_clock64();
+    }
     __syncthreads();
     const int64_t item = sh_item;
     __syncthreads();
-    if (item >= total) break;
-    int ph = 0;
-    while (ph + 1 < BP_END && item >= a.first[ph + 1]) ++ph;
-    const int64_t j = item - a.first[ph];
-    const bool needs_wait = ph == BP_SEL || ph == BP_PRE || ph == BP_SCAT || ph == BP_SCAN ||
+    int ph;
+    int64_t j, need = 0;
+    if (item < first[BP_SCAN]) {
+      ph = 0;
+      while (ph + 1 < BP_SCAN && item >= first[ph + 1]) ++ph;
+      j = item - first[ph];
+      need = first[ph];
+    } else {
+      if (n_active < 0) {
+        // the SCAN and RED ranges are known once Q..TILE have finished
+        if (tid == 0) {
+          int e = (int)__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (e == 0) e = wait_done(done, err, (unsigned long long)first[BP_SCAN], a.wait_ticks);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          acquired = BP_SCAN;
+          sh_nact = e == 0 ? (int64_t)__hip_atomic_load(n_active_w, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                           : 0;
+        }
+        __syncthreads();
+        n_active = sh_nact;
+      }
+      if (item < first[BP_SCAN] + n_active) {
+        ph = BP_SCAN;
+        j = item - first[BP_SCAN];
+      } else if (item < first[BP_SCAN] + n_active + n_red) {
+        ph = BP_RED;
+        j = item - first[BP_SCAN] - n_active;
+        need = first[BP_SCAN] + n_active;
+      } else {
+        break;
+      }
+    }
+    const bool needs_wait = ph == BP_SEL || ph == BP_PRE || ph == BP_SCAT || ph == BP_TILE ||
                             ph == BP_RED;
     if (tid == 0) {
       int e = (int)__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // phases only grow within a block: one wait and one acquire per phase
       if (needs_wait && ph > acquired && e == 0) {
-        e = wait_done(done, err, (unsigned long long)a.first[ph], a.wait_ticks);
+        e = wait_done(done, err, (unsigned long long)need, a.wait_ticks);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         acquired = ph;
       }
       sh_err = e;
     }
     __syncthreads();
+    // whether the item stored data that later items read with plain loads
+    bool wrote = false;
     if (!sh_err) {
       switch (ph) {
         case BP_Q: {
           const int wave = tid >> 6;
           for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4)
             quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, a.qscale);
+          wrote = true;
           break;
         }
         case BP_FILL: {
-          const int64_t p0 = j * 16, p1 = p0 + 16 < a.n_shapes ? p0 + 16 : a.n_shapes;
-          for (int64_t p = p0; p < p1; ++p)
-            for (int64_t c = tid; c < n_v; c += 256) a.mbuf[p * a.Vmax + c] = 0u;
+          // rows [0, n_v) of mbuf, BATCH_FILL_WORDS words per item
+          const int64_t e0 = j * BATCH_FILL_WORDS, lim = n_v * a.n_shapes;
+          const int64_t e1 = e0 + BATCH_FILL_WORDS < lim ? e0 + BATCH_FILL_WORDS : lim;
+          for (int64_t e = e0 + 4 * tid; e < e1; e += 1024) {
+            if (e + 4 <= e1)
+              *reinterpret_cast<uint4*>(a.mbuf + e) = make_uint4(0u, 0u, 0u, 0u);
+            else
+              for (int64_t t = e; t < e1; ++t) a.mbuf[t] = 0u;
+          }
+          wrote = true;
           break;
         }
         case BP_GEMM: {
           const int64_t rt = j / a.gemm_col_tiles;
-          if (rt * 128 < n_v)
-            dots_tile(a.qviews, 0, n_v, a.cb, a.K, a.dim, a.D, rt, j - rt * a.gemm_col_tiles, lds);
+          dots_tile(a.qviews, 0, n_v, a.cb, a.K, a.dim, a.D, rt, j - rt * a.gemm_col_tiles, lds);
+          wrote = true;
           break;
         }
         case BP_SEL:
-          if (j * 4 < n_v)
-            select_rows(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo, a.gamma2,
-                        a.qwords, a.overflow, a.counts, j, lds);
+          select_rows(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo, a.gamma2,
+                      a.qwords, a.overflow, a.counts, j, lds);
+          wrote = true;
           break;
         case BP_PRE: {
+          // group offsets (goff) and active-tile offsets (act_off) over words
           int64_t* part = reinterpret_cast<int64_t*>(lds);
+          int64_t* tpart = part + 256;
           const int per = (a.K + 255) / 256;
           const int k0 = tid * per;
-          int64_t sum = 0;
-          for (int k = k0; k < k0 + per && k < a.K; ++k) sum += a.counts[k];
+          int64_t sum = 0, tsum = 0;
+          for (int k = k0; k < k0 + per && k < a.K; ++k) {
+            const int c = a.counts[k];
+            sum += c;
+            if (c > 0) tsum += a.tile_off[k + 1] - a.tile_off[k];
+          }
           part[tid] = sum;
+          tpart[tid] = tsum;
           __syncthreads();
           if (tid == 0) {
-            int64_t run = 0;
+            int64_t run = 0, trun = 0;
             for (int t = 0; t < 256; ++t) {
-              const int64_t v = part[t];
+              const int64_t v = part[t], tv = tpart[t];
               part[t] = run;
+              tpart[t] = trun;
               run += v;
+              trun += tv;
             }
             a.goff[a.K] = run;
+            *n_active_w = (unsigned long long)trun;
           }
           __syncthreads();
-          int64_t run = part[tid];
+          int64_t run = part[tid], trun = tpart[tid];
           for (int k = k0; k < k0 + per && k < a.K; ++k) {
+            const int c = a.counts[k];
             a.goff[k] = run;
-            run += a.counts[k];
+            a.act_off[k] = (int32_t)trun;
+            run += c;
+            if (c > 0) trun += a.tile_off[k + 1] - a.tile_off[k];
             a.fillc[k] = 0;
           }
+          wrote = true;
           break;
         }
         case BP_SCAT:
@@ -784,43 +949,52 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
             const int w = a.qwords[v];
             if (w >= 0 && w < a.K) a.gitems[a.goff[w] + atomicAdd(&a.fillc[w], 1)] = (int32_t)v;
           }
+          wrote = true;
           break;
-        case BP_SCAN:
-          scan_tile<DT>(a.db, a.db_scale, a.n_views, a.row_bytes, a.loff, a.ent_shape,
-                        a.ent_view, a.tile_off, a.K, a.goff, a.gitems,
-                        DT == GIFT_F32 ? reinterpret_cast<const uint8_t*>(a.qviews) : a.qcodes,
-                        a.qscale, a.mbuf, a.Vmax, j, lds);
-          break;
-        case BP_RED: {
-          const int64_t nchunk = (a.n_shapes + 255) / 256;
-          const int b = (int)(j / nchunk);
-          const int64_t p = (j - (int64_t)b * nchunk) * 256 + tid;
-          if (p < a.n_shapes) {
-            float res = 0.f;
-            if (b < n_q) {
-              const int64_t lim = (int64_t)n_v;
-              const int lo = (int)(a.qoff[b] < 0 ? 0 : (a.qoff[b] > lim ? lim : a.qoff[b]));
-              const int hi = (int)(a.qoff[b + 1] < lo ? lo : (a.qoff[b + 1] > lim ? lim : a.qoff[b + 1]));
-              const uint32_t* row = a.mbuf + p * a.Vmax;
-              float acc = 0.f;
-              for (int i = lo; i < hi; ++i) {
-                const uint32_t u = row[i];
-                if (u != 0u) acc += order_float(u);
-              }
-              res = hi > lo ? acc / (float)(hi - lo) : 0.f;
-            }
-            a.S[(int64_t)b * a.n_shapes + p] = res;
+        case BP_TILE: {
+          const int w = (int)(j * 256) + tid;
+          if (w < a.K && a.counts[w] > 0) {
+            const int64_t b0 = a.tile_off[w], b1 = a.tile_off[w + 1];
+            int32_t* dst = a.act_tile + a.act_off[w];
+            for (int64_t b = b0; b < b1; ++b) dst[b - b0] = (int32_t)b;
           }
+          wrote = true;
+          break;
+        }
+        case BP_SCAN: {
+          const int64_t b = a.act_tile[j];
+          scan_list_tile<DT>(a.db, a.db_scale, a.n_views, a.row_bytes, a.loff, a.ent_shape,
+                             a.ent_view, a.tile_off, a.tile_word[b], a.goff, a.gitems,
+                             DT == GIFT_F32 ? reinterpret_cast<const uint8_t*>(a.qviews)
+                                            : a.qcodes,
+                             a.qscale, a.mbuf, a.n_shapes, b, lds);
+          break;
+        }
+        case BP_RED: {
+          // BATCH_RED_SHAPES shapes of one query of the batch
+          const int b = (int)(j / red_chunks);
+          const int64_t lim = (int64_t)n_v;
+          const int lo = (int)(a.qoff[b] < 0 ? 0 : (a.qoff[b] > lim ? lim : a.qoff[b]));
+          const int hi = (int)(a.qoff[b + 1] < lo ? lo : (a.qoff[b + 1] > lim ? lim : a.qoff[b + 1]));
+          const int64_t p0 = (j - (int64_t)b * red_chunks) * BATCH_RED_SHAPES;
+          for (int64_t p = p0 + tid; p < p0 + BATCH_RED_SHAPES && p < a.n_shapes; p += 256)
+            a.S[(int64_t)b * a.n_shapes + p] = fif_mean(a.mbuf, a.n_shapes, p, lo, hi);
           break;
         }
         default:
           break;
       }
     }
-    // the per-query means are read only after the kernel
-    if (ph != BP_RED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Release what later items read with plain loads.  The list scan writes
+    // only through device-scope atomics (as the queue counters do) and the
+    // per-query means are read only after the kernel.
+    if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.phase_ticks[ph], (unsigned long long)(wall_clock64() - t_item),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -845,6 +1019,11 @@ gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_
 #undef GIFT_BATCH_LAUNCH
   GIFT_LAUNCHED();
   return GIFT_OK;
+}
+
+void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStream_t st) {
+  hipLaunchKernelGGL(tile_word_kernel, dim3((K + 255) / 256), dim3(256), 0, st, tile_off, K,
+                     tile_word);
 }
 
 gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo, hipStream_t st) {

@@ -27,8 +27,10 @@ void launch_reduce_queries(const float* mbuf, int64_t ldm, int64_t n_shapes,
                            const int32_t* qoff, int n_queries, float* S,
                            hipStream_t st);
 
-// Top-r of each row of S [B][N] by (score desc, id asc), sorted.
-void launch_select_top(const float* S, int64_t n, int n_queries, int r,
+// Top-r of each row of S [B][N] by (score desc, id asc), sorted.  In this
+// and the next two launchers, rows (queries) b >= *active are skipped when
+// `active` is not null (batch plans sized for more queries than a batch).
+void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
                        int32_t* out_id, float* out_s, hipStream_t st);
 
 // Exact rescore of candidates: float32 dot products with a known error
@@ -39,7 +41,7 @@ void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int max_m, const int32_t* cand, int r, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    float* s_hi, float* s_lo, hipStream_t st);
+                    const int32_t* active, float* s_hi, float* s_lo, hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
 // id asc) and writes the top k; sets flags bit 0 when provably complete.
@@ -48,8 +50,8 @@ void launch_rescore(const float* master, int n_views, int dim,
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
                        int r, int k, int64_t n_total, float first_err,
-                       const int32_t* overflow, int32_t* ids, float* scores,
-                       int32_t* flags, hipStream_t st);
+                       const int32_t* overflow, const int32_t* active, int32_t* ids,
+                       float* scores, int32_t* flags, hipStream_t st);
 
 // ---- first inverted file
 // words[r][a] = the a-th nearest codeword of row r (certified, ties to the
@@ -75,12 +77,16 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
                             const int32_t* ent_view, int64_t n_entries, int K,
                             int64_t* tile_off, int64_t* tcount, const int64_t* goff,
                             const int32_t* gitems, const void* qv, const float* qscale,
-                            uint32_t* mbuf, int64_t ldm, hipStream_t st);
-void launch_reduce_fif(const uint32_t* mbuf, int64_t ldm, int64_t n_shapes, const int32_t* qoff,
+                            uint32_t* mbuf, int64_t ldn, hipStream_t st);
+// mbuf is [query view][shape] with row stride ldn (F-IF scan and reduce).
+void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, const int32_t* qoff,
                        int n_queries, float* S, hipStream_t st);
 
 // ---- persistent batch of the F-IF first pass
-enum BatchPhase { BP_Q = 0, BP_FILL, BP_GEMM, BP_SEL, BP_PRE, BP_SCAT, BP_SCAN, BP_RED, BP_END };
+enum BatchPhase { BP_Q = 0, BP_FILL, BP_GEMM, BP_SEL, BP_PRE, BP_SCAT, BP_TILE, BP_SCAN, BP_RED,
+                  BP_END };
+constexpr int64_t BATCH_FILL_WORDS = (int64_t)1 << 18;  // mbuf words cleared per FILL item
+constexpr int64_t BATCH_RED_SHAPES = 1024;            // shapes of one query per RED item
 struct BatchArgs {
   const uint8_t* db;
   const float* db_scale;
@@ -94,6 +100,7 @@ struct BatchArgs {
   const int32_t* ent_shape;
   const int32_t* ent_view;
   const int64_t* tile_off;
+  const int32_t* tile_word;  // list of each tile of the concatenated lists
   const float* qviews;
   int32_t* qoff;
   int Bmax;
@@ -107,20 +114,23 @@ struct BatchArgs {
   int64_t* goff;
   int32_t* fillc;
   int32_t* gitems;
+  int32_t* act_off;          // [K] first active-tile slot of each word
+  int32_t* act_tile;         // active list tiles of the batch
   uint32_t* mbuf;
   float* S;
   int32_t* overflow;
   unsigned long long* ctrl;  // head, done, error, spare
+  unsigned long long* phase_ticks;  // [BP_END] wall-clock ticks per phase
   float gamma2;
   int64_t wait_ticks;        // wall-clock ticks a phase wait may take
   int64_t gemm_col_tiles;
-  int64_t first[9];          // first item of each phase, then the total
 };
 void launch_batch_reset(const BatchArgs& a, hipStream_t st);
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st);
 gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo, hipStream_t st);
 gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64_t* tile_off,
                               hipStream_t st);
+void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStream_t st);
 float assign_gamma2(int dim);
 // error bounds of the rescore dot product and of the first pass (api.hip)
 float rescore_dot_error(int dim);

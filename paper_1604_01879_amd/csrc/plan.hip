@@ -12,6 +12,9 @@ struct PlanWs {
   float* nlo;
   int64_t* tcount;
   int64_t* tile_off;
+  int32_t* tile_word;
+  int32_t* act_off;
+  int32_t* act_tile;
   int32_t* desc;
   uint8_t* qcodes;
   float* qscale;
@@ -25,6 +28,7 @@ struct PlanWs {
   float* S;
   int32_t* overflow;
   unsigned long long* ctrl;
+  unsigned long long* phase_ticks;
   int32_t* cand;
   float* cand_s;
   float* s_hi;
@@ -40,6 +44,11 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.nlo = c.take<float>((size_t)f->K);
   w.tcount = c.take<int64_t>((size_t)f->K);
   w.tile_off = c.take<int64_t>((size_t)f->K + 1);
+  // list tiles: at most n_entries / 128 + K of them
+  const size_t max_tiles = (size_t)(f->n_entries / 128 + f->K + 1);
+  w.tile_word = c.take<int32_t>(max_tiles);
+  w.act_off = c.take<int32_t>((size_t)f->K);
+  w.act_tile = c.take<int32_t>(max_tiles);
   w.desc = c.take<int32_t>(4);
   if (db->dtype != GIFT_F32) {
     w.qcodes = c.take<uint8_t>((size_t)Vmax * row_bytes_of(db->dtype, db->dim));
@@ -55,6 +64,7 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.S = c.take<float>((size_t)Bmax * db->n_shapes);
   w.overflow = c.take<int32_t>(1);
   w.ctrl = c.take<unsigned long long>(4);
+  w.phase_ticks = c.take<unsigned long long>(BP_END);
   w.cand = c.take<int32_t>((size_t)Bmax * r);
   w.cand_s = c.take<float>((size_t)Bmax * r);
   w.s_hi = c.take<float>((size_t)Bmax * r);
@@ -81,7 +91,7 @@ struct gift_fif_plan {
   int ma;
   hipGraph_t graph;
   hipGraphExec_t exec;
-  int64_t items[gift::BP_END];
+  int clock_khz;
 };
 
 namespace gift {
@@ -91,15 +101,18 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   GIFT_LAUNCHED();
   gift_status s = launch_fif_batch(p->args, p->db.dtype, p->grid, st);
   if (s != GIFT_OK) return s;
-  launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, p->ws.cand, p->ws.cand_s, st);
+  // query slots past the batch (desc[0]) are skipped by every ranking kernel
+  const int32_t* active = p->ws.desc;
+  launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, active, p->ws.cand, p->ws.cand_s,
+                    st);
   GIFT_LAUNCHED();
   launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->max_m,
                  p->ws.cand, p->r, rescore_dot_error(p->db.dim), p->ws.qwords, p->view_words,
-                 p->ma, p->ws.s_hi, p->ws.s_lo, st);
+                 p->ma, active, p->ws.s_hi, p->ws.s_lo, st);
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
                     p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim, p->max_m),
-                    p->ws.overflow, p->ids, p->scores, p->flags, st);
+                    p->ws.overflow, active, p->ids, p->scores, p->flags, st);
   GIFT_LAUNCHED();
   return GIFT_OK;
 }
@@ -137,6 +150,8 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
              "K must be 1..16384 and ma 1..8");
   GIFT_CHECK(fif->n_entries == (int64_t)fif->ma * db->n_shapes * db->n_views, GIFT_EINVAL,
              "n_entries must be ma * n_shapes * n_views");
+  GIFT_CHECK(fif->n_entries / 128 + fif->K + 1 < ((int64_t)1 << 31), GIFT_ECAPACITY,
+             "too many list tiles");
   GIFT_CHECK(max_queries >= 1 && max_views >= 1 && max_views < ((int64_t)1 << 31) &&
                  max_views_per_query >= 1,
              GIFT_EINVAL, "bad capacities");
@@ -186,11 +201,10 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   // once per plan: codebook norms and list-tile offsets
   gift_status s = launch_norms(fif->codebook, fif->K, db->dim, w.nhi, w.nlo, st);
   if (s == GIFT_OK) s = launch_list_tiles(fif->offsets, fif->K, w.tcount, w.tile_off, st);
-  int64_t n_tiles = 0;
-  if (s == GIFT_OK && (hipMemcpyAsync(&n_tiles, w.tile_off + fif->K, 8, hipMemcpyDeviceToHost, st) !=
-                           hipSuccess ||
-                       hipStreamSynchronize(st) != hipSuccess))
-    s = fail(GIFT_EHIP, "reading the list-tile count failed");
+  if (s == GIFT_OK) {
+    launch_tile_word(w.tile_off, fif->K, w.tile_word, st);
+    if (hipGetLastError() != hipSuccess) s = fail(GIFT_EHIP, "tile map launch failed");
+  }
   if (s != GIFT_OK) {
     delete p;
     return s;
@@ -212,6 +226,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.ent_shape = fif->entry_shape;
   a.ent_view = fif->entry_view;
   a.tile_off = w.tile_off;
+  a.tile_word = w.tile_word;
   a.qviews = q_views;
   a.qoff = q_offsets;
   a.Bmax = max_queries;
@@ -225,29 +240,17 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.goff = w.goff;
   a.fillc = w.fillc;
   a.gitems = w.gitems;
+  a.act_off = w.act_off;
+  a.act_tile = w.act_tile;
   a.mbuf = w.mbuf;
   a.S = w.S;
   a.overflow = w.overflow;
   a.ctrl = w.ctrl;
+  a.phase_ticks = w.phase_ticks;
   a.gamma2 = assign_gamma2(db->dim);
   a.wait_ticks = (int64_t)clock_khz * 1000 * 5;  // five seconds per phase wait
+  p->clock_khz = clock_khz;
   a.gemm_col_tiles = (fif->K + 127) / 128;
-  const int64_t n_items[BP_END] = {
-      db->dtype == GIFT_F32 ? 0 : (max_views + 63) / 64,          // Q
-      (db->n_shapes + 15) / 16,                                    // FILL
-      ((max_views + 127) / 128) * a.gemm_col_tiles,                // GEMM
-      (max_views + 3) / 4,                                         // SEL
-      1,                                                           // PRE
-      (max_views + 255) / 256,                                     // SCAT
-      n_tiles,                                                     // SCAN
-      (int64_t)max_queries * ((db->n_shapes + 255) / 256)};        // RED
-  int64_t acc = 0;
-  for (int i = 0; i < BP_END; ++i) {
-    a.first[i] = acc;
-    p->items[i] = n_items[i];
-    acc += n_items[i];
-  }
-  a.first[BP_END] = acc;
 
   // an empty batch run eagerly once (sets kernel attributes, checks launches)
   {
@@ -325,6 +328,16 @@ gift_status gift_fif_plan_error(gift_fif_plan* p, int32_t* err, void* stream) {
   GIFT_HIP(hipMemcpyAsync(&e, p->ws.ctrl + 2, 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
   GIFT_HIP(hipStreamSynchronize((hipStream_t)stream));
   *err = (int32_t)e;
+  return GIFT_OK;
+}
+
+gift_status gift_fif_plan_phase_us(gift_fif_plan* p, double* out, void* stream) {
+  GIFT_CHECK(p != nullptr && out != nullptr, GIFT_EINVAL, "null argument");
+  unsigned long long t[BP_END];
+  GIFT_HIP(hipMemcpyAsync(t, p->ws.phase_ticks, sizeof(t), hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+  GIFT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  for (int i = 0; i < BP_END; ++i) out[i] = (double)t[i] * 1000.0 / (double)p->clock_khz;
   return GIFT_OK;
 }
 

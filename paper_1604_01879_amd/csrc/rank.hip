@@ -2,12 +2,17 @@
 // rescore of the candidates and the final (score desc, id asc) order.
 #include "kernels.h"
 #include "mfma_tile.h"
+#include "quant.h"
 
 namespace gift {
 
 // ------------------------------------------------------------------ helpers
-// Exclusive prefix count of `flag` over the 256 threads of a block, in
-// thread order; returns the block total through `total`.
+constexpr int SEL_THREADS = 512;          // threads of a top-r selection block
+constexpr int SEL_WAVES = SEL_THREADS / 64;
+constexpr int SEL_UNROLL = 8;             // independent loads in flight per thread
+
+// Exclusive prefix count of `flag` over the threads of a block, in thread
+// order; returns the block total through `total`.
 __device__ inline int block_excl_count(bool flag, int* wsum, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long bal = __ballot(flag);
@@ -16,7 +21,7 @@ __device__ inline int block_excl_count(bool flag, int* wsum, int& total) {
   __syncthreads();
   int before = 0;
   total = 0;
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < SEL_WAVES; ++w) {
     if (w < wave) before += wsum[w];
     total += wsum[w];
   }
@@ -47,27 +52,41 @@ __device__ inline uint32_t desc_key(float s) { return ~float_order(s); }
 
 constexpr int MAX_R = 1024;
 
-__global__ __launch_bounds__(256) void select_top_kernel(
-    const float* __restrict__ S, int64_t n, int r, int32_t* __restrict__ out_id,
-    float* __restrict__ out_s) {
+// One block per query row; rows b >= *active are skipped (active may be
+// null).  Radix selection of the r-th smallest key, 8 bits per pass, with
+// SEL_UNROLL coalesced loads in flight per thread, then the in-order
+// collection of the r keys and a bitonic sort.
+__global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
+    const float* __restrict__ S, int64_t n, int r, const int32_t* __restrict__ active,
+    int32_t* __restrict__ out_id, float* __restrict__ out_s) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh_prefix, sh_need;
-  __shared__ int wsum[4];
+  __shared__ int wsum[SEL_WAVES];
   __shared__ uint64_t keys[MAX_R];
   __shared__ int cnt_less;
   const int b = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
   const float* row = S + (int64_t)b * n;
   const int tid = threadIdx.x;
+  constexpr int64_t STRIDE = (int64_t)SEL_THREADS * SEL_UNROLL;
 
-  // Radix select of the r-th smallest 32-bit key, 8 bits per pass.
   uint32_t prefix = 0, mask = 0, need = (uint32_t)r;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
-    hist[tid] = 0;
+    for (int i = tid; i < 256; i += SEL_THREADS) hist[i] = 0;
     __syncthreads();
-    for (int64_t i = tid; i < n; i += 256) {
-      const uint32_t k = desc_key(row[i]);
-      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    for (int64_t base = 0; base < n; base += STRIDE) {
+      uint32_t kk[SEL_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; ++u) {
+        const int64_t i = base + u * SEL_THREADS + tid;
+        kk[u] = i < n ? desc_key(row[i]) : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; ++u) {
+        const int64_t i = base + u * SEL_THREADS + tid;
+        if (i < n && (kk[u] & mask) == prefix) atomicAdd(&hist[(kk[u] >> shift) & 255u], 1u);
+      }
     }
     __syncthreads();
     if (tid == 0) {
@@ -92,52 +111,79 @@ __global__ __launch_bounds__(256) void select_top_kernel(
   __syncthreads();
   const int n_less = r - (int)need;
   int taken_eq = 0;
-  for (int64_t base = 0; base < n; base += 256) {
-    const int64_t i = base + tid;
-    uint32_t k = 0xffffffffu;
-    if (i < n) k = desc_key(row[i]);
-    const bool less = i < n && k < prefix;
-    const bool eq = i < n && k == prefix;
-    if (less) {
-      const int pos = atomicAdd(&cnt_less, 1);
-      keys[pos] = ((uint64_t)k << 32) | (uint32_t)i;
+  for (int64_t base = 0; base < n; base += STRIDE) {
+    uint32_t kk[SEL_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SEL_UNROLL; ++u) {
+      const int64_t i = base + u * SEL_THREADS + tid;
+      kk[u] = i < n ? desc_key(row[i]) : 0xffffffffu;
     }
-    int tot;
-    const int pos = block_excl_count(eq, wsum, tot);
-    if (eq && taken_eq + pos < (int)need)
-      keys[n_less + taken_eq + pos] = ((uint64_t)k << 32) | (uint32_t)i;
-    taken_eq += tot;
+#pragma unroll
+    for (int u = 0; u < SEL_UNROLL; ++u) {
+      const int64_t i = base + u * SEL_THREADS + tid;
+      const bool less = i < n && kk[u] < prefix;
+      const bool eq = i < n && kk[u] == prefix;
+      if (less) {
+        const int pos = atomicAdd(&cnt_less, 1);
+        keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+      }
+      if (taken_eq < (int)need) {  // block-uniform
+        int tot;
+        const int pos = block_excl_count(eq, wsum, tot);
+        if (eq && taken_eq + pos < (int)need)
+          keys[n_less + taken_eq + pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+        taken_eq += tot;
+      }
+    }
   }
   __syncthreads();
   int np2 = 1;
   while (np2 < r) np2 <<= 1;
-  for (int i = r + tid; i < np2; i += 256) keys[i] = ~0ull;
+  for (int i = r + tid; i < np2; i += SEL_THREADS) keys[i] = ~0ull;
   __syncthreads();
   bitonic_sort_u64(keys, np2);
-  for (int i = tid; i < r; i += 256) {
+  for (int i = tid; i < r; i += SEL_THREADS) {
     const uint64_t k = keys[i];
     out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
     out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
   }
 }
 
-void launch_select_top(const float* S, int64_t n, int n_queries, int r,
+void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
                        int32_t* out_id, float* out_s, hipStream_t st) {
   if (n_queries <= 0) return;
-  hipLaunchKernelGGL(select_top_kernel, dim3(n_queries), dim3(256), 0, st, S,
-                     n, r, out_id, out_s);
+  hipLaunchKernelGGL(select_top_kernel, dim3(n_queries), dim3(SEL_THREADS), 0, st, S,
+                     n, r, active, out_id, out_s);
 }
 
 // ------------------------------------------------------------------ rescore
-// One block (two waves) per (query, candidate shape).  Phase 1: the float32
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in
+// float32), |r| <= 2^-16 |x|; four floats at a time, packed two per word.
+__device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
+  uint16_t h[4], l[4];
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float x = __builtin_bit_cast(float, w[t]);
+    h[t] = bf16_rne(x);
+    l[t] = bf16_rne(x - __builtin_bit_cast(float, (uint32_t)h[t] << 16));
+  }
+  hi = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+  lo = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+}
+
+// One block (two waves) per (query, candidate shape).  Phase 1: approximate
 // dot products of the candidate's views (rows, 64) with up to 64 query views
 // (columns) on MFMA, 32 x 32 blocks: wave w owns query views 32w..32w+31 and
-// both row blocks.  Each 32-value K-tile is accumulated into a fresh
-// register block and then added into a running total, which bounds the
-// accumulation depth by 2*16 + dim/32 roundings (dot_err).  The lane that
-// holds query view i holds 32 of its row values, so the maximum over the
-// candidate's valid views and the mask of views within 2 * dot_err of it
-// need one cross-half shuffle.  Phase 2: every masked pair is re-evaluated
+// both row blocks.  Each float32 value is split as hi + lo + r (hi, lo
+// bfloat16, |r| <= 2^-16 |x|) and the dot is hi.hi' + hi.lo' + lo.hi' on
+// BF16 MFMA (products exact in float32), missing at most about
+// 3 * 2^-16 sum |x y|.  Each 32-value K-tile is accumulated into a fresh
+// register block and added into a running total, which bounds the float32
+// accumulation depth; dot_err bounds both.  The lane that holds query view
+// i holds 32 of its row values, so the maximum over the candidate's valid
+// views and the mask of views within 2 * dot_err of it need one cross-half
+// shuffle.  Phase 2: every masked pair is re-evaluated
 // with the compensated dot product and the exact maximum kept.  Phase 3:
 // the compensated mean over the query views in ascending order.
 // With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
@@ -148,7 +194,7 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
-    float* __restrict__ s_hi, float* __restrict__ s_lo) {
+    const int32_t* __restrict__ active, float* __restrict__ s_hi, float* __restrict__ s_lo) {
   constexpr int ROWS = 128;  // 64 candidate views + 64 query views
   __shared__ __align__(16) uint8_t lds[ROWS * LROW];
   __shared__ unsigned long long jmask[64];
@@ -158,6 +204,7 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
 
   const int64_t bc = blockIdx.x;
   const int b = (int)(bc / r);
+  if (active != nullptr && b >= *active) return;  // query slot past the batch
   const int64_t shape = cand[bc];
   const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -189,36 +236,62 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int e = 0; e < 16; ++e) tot[bi][e] = 0.f;
-    const uint8_t* arow = lds + l32 * LROW + half * 64;
-    const uint8_t* brow = lds + (64 + wave * 32 + l32) * LROW + half * 64;
-    for (int k0 = 0; k0 < row_bytes; k0 += 128) {
-      uint4 pre[8];
+    // LDS row of a K-tile: 32 high parts (64 bytes) then 32 low parts; lane
+    // half h supplies values [16h, 16h + 16) of the tile in two MFMA steps
+    const uint8_t* arow = lds + l32 * LROW + half * 32;
+    const uint8_t* brow = lds + (64 + wave * 32 + l32) * LROW + half * 32;
+    uint4 pre[8];
+    auto gload = [&](int k0) {
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int off = k0 + ((tid + 128 * p) & 7) * 16;
         pre[p] = src[p] != nullptr ? *reinterpret_cast<const uint4*>(src[p] + off)
                                    : make_uint4(0, 0, 0, 0);
       }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < row_bytes; k0 += 128) {
       __syncthreads();
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int idx = tid + 128 * p;
-        *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[p];
+        uint2 hi, lo;
+        split_bf16x4(pre[p], hi, lo);
+        uint8_t* row = lds + (idx >> 3) * LROW + (idx & 7) * 8;
+        *reinterpret_cast<uint2*>(row) = hi;
+        *reinterpret_cast<uint2*>(row + 64) = lo;
       }
       __syncthreads();
-      uint4 bq[4];
+      if (k0 + 128 < row_bytes) gload(k0 + 128);  // in flight during the MFMAs
+      uint4 bh[2], bl[2];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) bq[s4] = *reinterpret_cast<const uint4*>(brow + s4 * 16);
+      for (int st = 0; st < 2; ++st) {
+        bh[st] = *reinterpret_cast<const uint4*>(brow + st * 16);
+        bl[st] = *reinterpret_cast<const uint4*>(brow + 64 + st * 16);
+      }
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        uint4 a[4];
+        uint4 ah[2], al[2];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          a[s4] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + s4 * 16);
+        for (int st = 0; st < 2; ++st) {
+          ah[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + st * 16);
+          al[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + 64 + st * 16);
+        }
         f32x16 part;
 #pragma unroll
         for (int e = 0; e < 16; ++e) part[e] = 0.f;
-        Mfma<GIFT_F32>::run(a, bq, part);
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[st]),
+                                                         part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bl[st]),
+                                                         part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[st]),
+                                                         part, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) tot[bi][e] += part[e];
       }
@@ -262,7 +335,7 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
     if (half == 0) jmask[i] = i < mi ? bits : 0ull;
     __syncthreads();
     // compensated maximum per query view: one wave per view.  Lane l
-    // takes the float4 pieces l, l + 64, ... of the rows, 8 pieces of each
+    // takes the float4 pieces l, l + 64, ... of the rows, 4 pieces of each
     // row in flight per batch (dim is a multiple of 32, so the piece count
     // is a multiple of 8).
     const int n4 = dim >> 2;
@@ -275,16 +348,16 @@ __global__ __launch_bounds__(128, 2) void rescore_kernel(
         bb &= bb - 1;
         const float4* p4 = reinterpret_cast<const float4*>(pbase + (int64_t)j * dim);
         float s = 0.f, c = 0.f;
-        for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
-          float4 qa[8], pa[8];
+        for (int u0 = lane; u0 < n4; u0 += 64 * 4) {
+          float4 qa[4], pa[4];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
+          for (int k = 0; k < 4; ++k) {
             const int u = u0 + 64 * k;
             qa[k] = u < n4 ? q4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
             pa[k] = u < n4 ? p4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
           }
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
+          for (int k = 0; k < 4; ++k) {
             dot2_step(qa[k].x, pa[k].x, s, c);
             dot2_step(qa[k].y, pa[k].y, s, c);
             dot2_step(qa[k].z, pa[k].z, s, c);
@@ -318,13 +391,13 @@ void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int max_m, const int32_t* cand, int r, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    float* s_hi, float* s_lo, hipStream_t st) {
+                    const int32_t* active, float* s_hi, float* s_lo, hipStream_t st) {
   (void)max_m;
   const int64_t blocks = (int64_t)n_queries * r;
   if (blocks <= 0) return;
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(128), 0, st,
                      master, n_views, dim, qviews, qoff, cand, r, dot_err,
-                     qwords, view_words, ma, s_hi, s_lo);
+                     qwords, view_words, ma, active, s_hi, s_lo);
 }
 
 // ------------------------------------------------------------------ final
@@ -343,9 +416,11 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
     const int32_t* __restrict__ cand, const float* __restrict__ first_s,
     const float* __restrict__ s_hi, const float* __restrict__ s_lo, int r,
     int k, int64_t n_total, float first_err, const int32_t* __restrict__ overflow,
-    int32_t* __restrict__ ids, float* __restrict__ scores, int32_t* __restrict__ flags) {
+    const int32_t* __restrict__ active, int32_t* __restrict__ ids, float* __restrict__ scores,
+    int32_t* __restrict__ flags) {
   __shared__ Cand c[MAX_R];
   const int b = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
   const int64_t base = (int64_t)b * r;
   int np2 = 1;
   while (np2 < r) np2 <<= 1;
@@ -390,12 +465,12 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
                        int r, int k, int64_t n_total, float first_err,
-                       const int32_t* overflow, int32_t* ids, float* scores,
-                       int32_t* flags, hipStream_t st) {
+                       const int32_t* overflow, const int32_t* active, int32_t* ids,
+                       float* scores, int32_t* flags, hipStream_t st) {
   if (n_queries <= 0) return;
   hipLaunchKernelGGL(final_rank_kernel, dim3(n_queries), dim3(256), 0, st,
                      cand, first_s, s_hi, s_lo, r, k, n_total, first_err, overflow,
-                     ids, scores, flags);
+                     active, ids, scores, flags);
 }
 
 }  // namespace gift

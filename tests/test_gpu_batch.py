@@ -106,6 +106,8 @@ def test_plan_replays_with_eager_work_between(L):
         plan.stream.synchronize()
         assert torch.equal(plan.ids, first[0])
         assert torch.equal(plan.scores, first[1])
+    ph = plan.phase_us()
+    assert len(ph) == 9 and all(t >= 0 for t in ph) and ph[7] > 0  # the list scan ran
     plan.close()
 
 
