@@ -124,7 +124,7 @@ def main():
                 L.gift_set_score_tuning(dts[name], bt, bg)
                 tuning[name] = {"tile": bt, "group": bg, "fixed": True}
                 continue
-            bt, bg, ms = L.gift_autotune_score(views[name], Q, [0, 1], [8, 16, 32], reps=2)
+            bt, bg, ms = L.gift_autotune_score(views[name], Q, [0, 1, 2, 3], [8, 16, 32], reps=2)
             tuning[name] = {"tile": bt, "group": bg, "ms_grid": ms.round(2).tolist()}
             log(f"autotuned {name}: tile {bt} group {bg}")
 

@@ -362,8 +362,11 @@ gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
 
 /* ---------------------------------------------------------------------- */
 /* Tuning of the first-pass scorer (host, process-wide, not thread-safe).  */
-/* tile: 0 = 256 database rows x 128 query views per block, 1 = 256 x 256  */
-/* (BF16 / FP8 only; float32 uses 128 x 128); group: number of database    */
+/* tile (BF16 / FP8 storage; float32 always uses 128 x 128 and MX storage */
+/* 256 x 128): bit 0 selects 256 database rows x 256 query views per block */
+/* instead of 256 x 128, bit 1 the pipelined main loop with direct         */
+/* global-to-LDS loads (taken when a stored row is a multiple of 64        */
+/* bytes); the default is 3 with group 32.  group: number of database     */
 /* row tiles that share one sweep over the query tiles in the launch order */
 /* (blocks go to the 8 XCDs round-robin, so multiples of 8 keep each       */
 /* database tile on one XCD).  gift_autotune_score times every (tile,      */

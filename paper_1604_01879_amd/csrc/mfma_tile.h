@@ -353,6 +353,150 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- DMA loop
+// Same tile for BF16 / e4m3 storage with direct global->LDS loads: K in
+// 64-byte sub-tiles, DMA_STAGES LDS stages, loads issued DMA_STAGES - 1
+// sub-tiles ahead, one barrier per sub-tile and no register staging.  A
+// wave's 16-byte load writes 64 consecutive LDS chunks (lane l at chunk l),
+// i.e. 16 rows of 64 bytes; rows are unpadded and the 16-byte chunk c of
+// row r holds the row's chunk c ^ ((r >> 1) & 3), so the 8 rows read
+// together by a lane group hit 8 different bank groups.  row_bytes must be
+// a multiple of 64.  Lane l stages rows wave * WROWS + 16 i + l / 4
+// (i < NI); rowp[i] must point at a readable row (pad rows may point
+// anywhere valid: their results are not used).
+constexpr int DMA_KSUB = 64;
+constexpr int DMA_STAGES = 4;
+
+template <int WM, int WN>
+struct DmaShape {
+  static constexpr int BM = 64 * WM;
+  static constexpr int BN = 64 * WN;
+  static constexpr int ROWS = BM + BN;
+  static constexpr int WROWS = ROWS / 4;  // rows staged by each wave
+  static constexpr int NI = WROWS / 16;   // 16-byte loads per lane per sub-tile
+  static constexpr int STAGE_BYTES = ROWS * DMA_KSUB;
+  static constexpr size_t LDS_BYTES = (size_t)DMA_STAGES * STAGE_BYTES;
+};
+
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// s_waitcnt vmcnt(n) lgkmcnt(0), then a barrier that the compiler may not
+// move memory accesses across (the vmcnt allowance keeps later sub-tiles'
+// loads in flight; a fenced barrier would wait for all of them).
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+  asm volatile("s_barrier" ::: "memory");
+}
+
+template <int DT, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_mainloop_dma(
+    uint8_t* lds, const uint8_t* const (&rowp)[DmaShape<WM, WN>::NI], int row_bytes,
+    f32x16 (&acc)[WM][WN]) {
+  using T = DmaShape<WM, WN>;
+  static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5, l32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int n_kt = row_bytes / DMA_KSUB;
+  lds_u8* l3 = (lds_u8*)lds;
+  int gchunk[T::NI];  // byte offset of the global chunk this lane copies
+#pragma unroll
+  for (int i = 0; i < T::NI; ++i) {
+    const int r = wave * T::WROWS + 16 * i + (lane >> 2);
+    gchunk[i] = ((lane & 3) ^ ((r >> 1) & 3)) * 16;
+  }
+  // The loads are issued from inline asm so that the compiler does not
+  // treat them as pending LDS writes (it would then wait for every one of
+  // them before each LDS read); wait_vm_barrier orders them instead.
+  const uint32_t wave_lds = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (int)(uint32_t)(uintptr_t)(l3 + wave * T::WROWS * DMA_KSUB));
+  auto issue = [&](int kt) {
+    const uint32_t base = wave_lds + (uint32_t)((kt % DMA_STAGES) * T::STAGE_BYTES);
+#pragma unroll
+    for (int i = 0; i < T::NI; ++i) {
+      const uint8_t* g = rowp[i] + kt * DMA_KSUB + gchunk[i];
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                   :
+                   : "v"(g), "s"(base + (uint32_t)(i * 16 * DMA_KSUB))
+                   : "memory", "m0");
+    }
+  };
+#pragma unroll
+  for (int st = 0; st < DMA_STAGES - 1; ++st)
+    if (st < n_kt) issue(st);
+
+  // operand rows all have l32 as their low 5 bits, so one swizzle serves all
+  const int sw = (l32 >> 1) & 3;
+  const int arow = (wr * WM * 32 + l32) * DMA_KSUB;
+  const int brow = (T::BM + wc * WN * 32 + l32) * DMA_KSUB;
+  for (int kt = 0; kt < n_kt; ++kt) {
+    if (kt + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
+    else wait_vm_barrier<0>();
+    // every wave is past sub-tile kt - 1, so its stage can be refilled
+    if (kt + DMA_STAGES - 1 < n_kt) issue(kt + DMA_STAGES - 1);
+    const uint8_t* st = lds + (kt % DMA_STAGES) * T::STAGE_BYTES;
+    if constexpr (DT == GIFT_BF16) {
+      // two 32x32x16 steps; lane half h supplies logical chunk 2 s + h
+      uint4 b[WN][2];
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+          b[j][s2] = *reinterpret_cast<const uint4*>(st + brow + j * 32 * DMA_KSUB +
+                                                     (((2 * s2 + half) ^ sw) * 16));
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        uint4 a[2];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+          a[s2] = *reinterpret_cast<const uint4*>(st + arow + i * 32 * DMA_KSUB +
+                                                  (((2 * s2 + half) ^ sw) * 16));
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, a[s2]), __builtin_bit_cast(bf16x8, b[j][s2]),
+                acc[i][j], 0, 0, 0);
+      }
+    } else {
+      // one 32x32x64 step; lane half h supplies logical chunks 2h, 2h + 1
+      Pair32 b[WN];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const uint8_t* rb = st + brow + j * 32 * DMA_KSUB;
+        b[j].lo = *reinterpret_cast<const uint4*>(rb + (((2 * half) ^ sw) * 16));
+        b[j].hi = *reinterpret_cast<const uint4*>(rb + (((2 * half + 1) ^ sw) * 16));
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const uint8_t* ra = st + arow + i * 32 * DMA_KSUB;
+        Pair32 a;
+        a.lo = *reinterpret_cast<const uint4*>(ra + (((2 * half) ^ sw) * 16));
+        a.hi = *reinterpret_cast<const uint4*>(ra + (((2 * half + 1) ^ sw) * 16));
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b[j]), acc[i][j], 0, 0,
+              0, 127, 0, 127);
+      }
+    }
+  }
+  wait_vm_barrier<0>();  // LDS may be reused by the caller
+}
+
 // Row (within the wave's WM*32 rows) and column of accumulator element e of
 // block (i, j) held by this lane.
 __device__ __forceinline__ int acc_row(int i, int e) {

@@ -42,7 +42,7 @@ void launch_quantize(const float* src, int64_t n, int dim, int dtype,
 // and are masked), so a wave's WM*32 rows hold WM/2 whole shapes and the
 // per-shape max is taken inside the wave: each lane folds its 32 row values,
 // then the two lane halves are combined with one shuffle.
-template <int DT, int WM, int WN>
+template <int DT, int WM, int WN, bool DMA>
 __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
     const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v,
     int64_t n_shapes, int n_views, int row_bytes,
@@ -79,46 +79,68 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   const int64_t shape0 = row_tile * SHAPES_PER_BLOCK;
   const int64_t col0 = col_tile * T::BN;
 
-  const uint8_t* src[T::LOADS];
-#pragma unroll
-  for (int it = 0; it < T::LOADS; ++it) {
-    const int r = staged_row(it);
-    const uint8_t* p = nullptr;
-    if (r < T::BM) {
-      const int64_t shp = shape0 + (r >> 6);
-      const int v = r & 63;
-      if (shp < n_shapes && v < n_views) p = db + (shp * n_views + v) * (int64_t)row_bytes;
-    } else {
-      const int64_t c = col0 + (r - T::BM);
-      if (c < total_q) p = qv + c * (int64_t)row_bytes;
-    }
-    src[it] = p;
-  }
   f32x16 acc[WM][WN];
-  if constexpr (MX) {
-    // E8M0 rows of the row / column this lane supplies in each block
-    const int nblk = (DT == GIFT_MXFP4 ? 2 * row_bytes : row_bytes) / 32;
-    const uint8_t* de8 = static_cast<const uint8_t*>(db_scale_v);
-    const uint8_t* qe8 = static_cast<const uint8_t*>(q_scale_v);
-    const uint8_t* sa_row[WM];
-    const uint8_t* sb_row[WN];
+  if constexpr (DMA) {
+    // staged rows of this lane; pad rows re-read row 0 (their results are
+    // never used)
+    using D = DmaShape<WM, WN>;
+    const uint8_t* rowp[D::NI];
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      const int r = wr * WM * 32 + i * 32 + l32;
-      const int64_t shp = shape0 + (r >> 6);
-      const int v = r & 63;
-      const bool ok = shp < n_shapes && v < n_views;
-      sa_row[i] = de8 + (ok ? (shp * n_views + v) * (int64_t)nblk : 0);
+    for (int i = 0; i < D::NI; ++i) {
+      const int r = wave * D::WROWS + 16 * i + (lane >> 2);
+      const uint8_t* p;
+      if (r < T::BM) {
+        const int64_t shp = shape0 + (r >> 6);
+        const int v = r & 63;
+        p = (shp < n_shapes && v < n_views) ? db + (shp * n_views + v) * (int64_t)row_bytes : db;
+      } else {
+        const int64_t c = col0 + (r - T::BM);
+        p = c < total_q ? qv + c * (int64_t)row_bytes : qv;
+      }
+      rowp[i] = p;
     }
-#pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      const int64_t c = col0 + wc * WN * 32 + j * 32 + l32;
-      sb_row[j] = qe8 + (c < total_q ? c * (int64_t)nblk : 0);
-    }
-    mfma_tile_mainloop_mx<DT == GIFT_MXFP8 ? 0 : 4, WM, WN>(lds, src, row_bytes, sa_row, sb_row,
-                                                            acc);
+    mfma_tile_mainloop_dma<DT, WM, WN>(lds, rowp, row_bytes, acc);
   } else {
-    mfma_tile_mainloop<DT, WM, WN>(lds, src, row_bytes, acc);
+    const uint8_t* src[T::LOADS];
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int r = staged_row(it);
+      const uint8_t* p = nullptr;
+      if (r < T::BM) {
+        const int64_t shp = shape0 + (r >> 6);
+        const int v = r & 63;
+        if (shp < n_shapes && v < n_views) p = db + (shp * n_views + v) * (int64_t)row_bytes;
+      } else {
+        const int64_t c = col0 + (r - T::BM);
+        if (c < total_q) p = qv + c * (int64_t)row_bytes;
+      }
+      src[it] = p;
+    }
+    if constexpr (MX) {
+      // E8M0 rows of the row / column this lane supplies in each block
+      const int nblk = (DT == GIFT_MXFP4 ? 2 * row_bytes : row_bytes) / 32;
+      const uint8_t* de8 = static_cast<const uint8_t*>(db_scale_v);
+      const uint8_t* qe8 = static_cast<const uint8_t*>(q_scale_v);
+      const uint8_t* sa_row[WM];
+      const uint8_t* sb_row[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int r = wr * WM * 32 + i * 32 + l32;
+        const int64_t shp = shape0 + (r >> 6);
+        const int v = r & 63;
+        const bool ok = shp < n_shapes && v < n_views;
+        sa_row[i] = de8 + (ok ? (shp * n_views + v) * (int64_t)nblk : 0);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int64_t c = col0 + wc * WN * 32 + j * 32 + l32;
+        sb_row[j] = qe8 + (c < total_q ? c * (int64_t)nblk : 0);
+      }
+      mfma_tile_mainloop_mx<DT == GIFT_MXFP8 ? 0 : 4, WM, WN>(lds, src, row_bytes, sa_row, sb_row,
+                                                              acc);
+    } else {
+      mfma_tile_mainloop<DT, WM, WN>(lds, src, row_bytes, acc);
+    }
   }
 
   // Epilogue: max over the shape's valid views, the row scale applied
@@ -159,17 +181,19 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   }
 }
 
-// Tuning knobs: tile shape per storage dtype (0: 256 x 128 database rows x
-// query views, 1: 256 x 256; float32 always 128 x 128) and the row-tile
-// group of the launch order.
-static int g_tile[5] = {0, 1, 1, 0, 0};
-static int64_t g_group[5] = {8, 8, 8, 8, 8};
+// Tuning knobs: tile variant per storage dtype and the row-tile group of the
+// launch order.  Variants (BF16 / e4m3 storage): bit 0 selects 256 x 256
+// (database rows x query views) instead of 256 x 128, bit 1 the pipelined
+// direct-to-LDS main loop (used when a row is a multiple of 64 bytes).
+// float32 always uses 128 x 128 and MX storage 256 x 128.
+static int g_tile[5] = {0, 3, 3, 0, 0};
+static int64_t g_group[5] = {8, 32, 32, 8, 8};
 
 gift_status set_score_tuning(int dtype, int tile, int group) {
   GIFT_CHECK(dtype >= 0 && dtype <= 4, GIFT_EINVAL, "bad dtype");
-  GIFT_CHECK(tile == 0 || tile == 1, GIFT_EINVAL, "tile must be 0 or 1");
+  GIFT_CHECK(tile >= 0 && tile <= 3, GIFT_EINVAL, "tile must be in 0..3");
   GIFT_CHECK(tile == 0 || (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3), GIFT_EUNSUPPORTED,
-             "tile 1 is for BF16 / FP8 storage");
+             "tile variants 1..3 are for BF16 / FP8 storage");
   GIFT_CHECK(group >= 1 && group <= 1024, GIFT_EINVAL, "group must be in 1..1024");
   if (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3) g_tile[dtype] = tile;
   g_group[dtype] = group;
@@ -181,7 +205,7 @@ void get_score_tuning(int dtype, int* tile, int* group) {
   *group = (int)g_group[dtype];
 }
 
-template <int DT, int WM, int WN>
+template <int DT, int WM, int WN, bool DMA = false>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
                                 const void* qscale, int64_t total_q,
                                 float* mbuf, int64_t ldm, hipStream_t st) {
@@ -191,8 +215,8 @@ static gift_status launch_tiles(const gift_views* db, const void* qv,
   const int64_t n_col_tiles = (total_q + BN - 1) / BN;
   const int64_t blocks = n_row_tiles * n_col_tiles;
   GIFT_CHECK(blocks < (int64_t)1 << 31, GIFT_ECAPACITY, "score grid too large");
-  const size_t shmem = TileShape<WM, WN>::LDS_BYTES;
-  auto kern = score_tiles_kernel<DT, WM, WN>;
+  const size_t shmem = DMA ? DmaShape<WM, WN>::LDS_BYTES : TileShape<WM, WN>::LDS_BYTES;
+  auto kern = score_tiles_kernel<DT, WM, WN, DMA>;
   {
     const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), shmem);
     if (s != GIFT_OK) return s;
@@ -213,13 +237,20 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
   switch (db->dtype) {
     case GIFT_F32: return launch_tiles<GIFT_F32, 2, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
     case GIFT_BF16:
-      if (g_tile[GIFT_BF16] == 1)
-        return launch_tiles<GIFT_BF16, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);
-      return launch_tiles<GIFT_BF16, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
-    case GIFT_FP8E4M3:
-      if (g_tile[GIFT_FP8E4M3] == 1)
-        return launch_tiles<GIFT_FP8E4M3, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);
-      return launch_tiles<GIFT_FP8E4M3, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
+    case GIFT_FP8E4M3: {
+      int t = g_tile[db->dtype];
+      if (row_bytes_of(db->dtype, db->dim) % DMA_KSUB != 0) t &= 1;
+#define GIFT_TILE_CASES(DTV)                                                                   \
+  switch (t) {                                                                                 \
+    case 0: return launch_tiles<DTV, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);            \
+    case 1: return launch_tiles<DTV, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);            \
+    case 2: return launch_tiles<DTV, 4, 2, true>(db, qv, qscale, total_q, mbuf, ldm, st);      \
+    default: return launch_tiles<DTV, 4, 4, true>(db, qv, qscale, total_q, mbuf, ldm, st);     \
+  }
+      if (db->dtype == GIFT_BF16) GIFT_TILE_CASES(GIFT_BF16)
+      GIFT_TILE_CASES(GIFT_FP8E4M3)
+#undef GIFT_TILE_CASES
+    }
     case GIFT_MXFP8:
       return launch_tiles<GIFT_MXFP8, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);
     case GIFT_MXFP4:
