@@ -59,9 +59,11 @@ def main():
                     help="c3: exhaustive precision headline (default); c4: batched F-IF + "
                          "S-IF plan; c5: continuous-batching serving")
     ap.add_argument("--tune", default="",
-                    help="fixed score tuning 'tile,group' for BF16 and FP8 instead of the "
-                         "autotuner (e.g. 1,32), so that profiled launches are all the timed "
-                         "configuration")
+                    help="fixed score tuning 'tile,group' for BF16 and FP8 (default: the "
+                         "library's defaults)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every score tile variant and row-tile group first and use the "
+                         "fastest (the trial launches then show up in a kernel trace)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rates", default="200,500,1000")
     args = ap.parse_args()
@@ -122,7 +124,11 @@ def main():
             if args.tune:
                 bt, bg = (int(x) for x in args.tune.split(","))
                 L.gift_set_score_tuning(dts[name], bt, bg)
-                tuning[name] = {"tile": bt, "group": bg, "fixed": True}
+                tuning[name] = {"tile": bt, "group": bg, "source": "--tune"}
+                continue
+            if not args.autotune:
+                bt, bg = L.gift_get_score_tuning(dts[name])
+                tuning[name] = {"tile": bt, "group": bg, "source": "library default"}
                 continue
             bt, bg, ms = L.gift_autotune_score(views[name], Q, [0, 1, 2, 3], [8, 16, 32], reps=2)
             tuning[name] = {"tile": bt, "group": bg, "ms_grid": ms.round(2).tolist()}
@@ -218,7 +224,8 @@ def main():
         "kernels_ms": main_run["kern"],
         "autotune": tuning,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": _recorded_traffic(args.dtype, tuning.get(args.dtype), w, B * 64),
                      "kernel": "score_tiles",
                      "algorithmic_flops_per_launch": flops},
     }
@@ -316,6 +323,28 @@ def _build_index(w, torch, L, master, V, k1, log_prefix):
     return cb, F, S, {"codebook_iterations": iters, "codebook_train_views": int(len(sample)),
                       "fif_build_seconds": round(t_fif, 2), "sif_build_seconds": round(t_sif, 2),
                       "sif_postings": S.nnz()}
+
+
+_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                             "score_tiles_bf16_12k_hbm_traffic.md")
+
+
+def _recorded_traffic(dtype, tuning, w, query_views):
+    """Calibrated HBM bytes per launch of the score kernel from the committed
+    rocprofv3 counter summary, when it was taken on this exact kernel variant
+    and workload; otherwise None."""
+    if not tuning or not os.path.exists(_TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(_TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            key, val = line[2:].strip().split(": ", 1)
+            rec[key.strip("`")] = val.strip("`")
+    want = {"dtype": dtype, "tile": str(tuning["tile"]), "group": str(tuning["group"]),
+            "n_shapes": str(w.n_shapes), "dim": str(w.dim), "query_views": str(query_views)}
+    if any(rec.get(k) != v for k, v in want.items()):
+        return None
+    return float(rec["calibrated_bytes_per_launch"])
 
 
 _PHASES = ("quantize", "clear", "codeword_dots", "word_select", "word_offsets", "grouping",
