@@ -231,7 +231,7 @@ struct FifWs {
   int32_t* gitems;
   void* bucket;
   void* qcodes;
-  float* qscale;
+  void* qscale;
   uint32_t* mbuf;
   float* S;
   int64_t* tile_off;
@@ -255,7 +255,9 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
   w.bucket = c.take<uint8_t>(bucket_sort_ws(tq, f->K));
   if (db->dtype != GIFT_F32) {
     w.qcodes = c.take<uint8_t>((size_t)tq * row_bytes_of(db->dtype, db->dim));
-    w.qscale = c.take<float>((size_t)tq);
+    // per-view float32 scales, or E8M0 rows of dim / 32 bytes (MX)
+    w.qscale = c.take<uint8_t>(is_mx(db->dtype) ? (size_t)tq * (db->dim / 32)
+                                                : (size_t)tq * sizeof(float));
   }
   w.mbuf = c.take<uint32_t>((size_t)db->n_shapes * tq);
   w.S = c.take<float>((size_t)q->n_queries * db->n_shapes);
@@ -272,8 +274,6 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
 }
 
 static gift_status check_fif(const gift_fif* f, const gift_views* db) {
-  GIFT_CHECK(!is_mx(db->dtype), GIFT_EUNSUPPORTED,
-             "the F-IF scan reads float32, BF16 or FP8 storage (MX is exhaustive-only)");
   GIFT_CHECK(f != nullptr && f->offsets && f->entry_shape && f->entry_view && f->view_words,
              GIFT_EINVAL, "incomplete F-IF index");
   gift_status s = check_codebook(f->codebook, f->K, f->ma, db->dim);
@@ -298,7 +298,7 @@ static gift_status fif_first_pass(const gift_views* db, const gift_fif* f, const
   prof_end(st);
   if (s != GIFT_OK) return s;
   const void* qv = q->views;
-  const float* qs = nullptr;
+  const void* qs = nullptr;
   if (db->dtype != GIFT_F32) {
     prof_begin(P_QUANT, st);
     launch_quantize(q->views, tq, db->dim, db->dtype, w.qcodes, w.qscale, st);

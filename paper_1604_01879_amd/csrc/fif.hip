@@ -9,7 +9,7 @@ namespace gift {
 
 // ------------------------------------------------------------------ GEMM
 // D[r - r0][k] = x_r . b_k in float32 on MFMA (128 x 128 block tiles).
-__device__ void dots_tile(const float* __restrict__ x, int64_t r0, int64_t r1,
+__device__ __forceinline__ void dots_tile(const float* __restrict__ x, int64_t r0, int64_t r1,
                           const float* __restrict__ cb, int K, int dim, float* __restrict__ D,
                           int64_t row_tile, int64_t col_tile, uint8_t* lds) {
   using T = TileShape<2, 2>;
@@ -88,7 +88,7 @@ constexpr size_t SEL_LDS = 4 * SEL_CAP * 12;
 // Rows r0 + 4*blk .. +3 (one wave each) of the chunk [r0, r1); D holds the
 // chunk's dots.  With `counts` set (ma == 1), the chosen word's counter is
 // incremented.
-__device__ void select_rows(const float* __restrict__ x, int64_t r0, int64_t r1,
+__device__ __forceinline__ void select_rows(const float* __restrict__ x, int64_t r0, int64_t r1,
                             const float* __restrict__ cb, int K, int dim, int ma,
                             const float* __restrict__ D, const float* __restrict__ nhi,
                             const float* __restrict__ nlo, float gamma2,
@@ -521,15 +521,20 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 // an atomic max into mbuf[query view][shape] (row stride ldn; 0 = no
 // matching view yet).
 // Tile b of list w (tile_off[w] <= b < tile_off[w + 1]).
+// Scales: per-view float32 (BF16 / e4m3) or E8M0 rows (MX), null for float32.
 template <int DT>
-__device__ void scan_list_tile(
-    const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
+__device__ __forceinline__ void scan_list_tile(
+    const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v, int n_views,
     int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
     const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int w,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
-    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    const uint8_t* __restrict__ qv, const void* __restrict__ q_scale_v,
     uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds) {
   using T = TileShape<2, 2>;
+  constexpr bool MX = DT == GIFT_MXFP8 || DT == GIFT_MXFP4;
+  constexpr bool SCALED = DT == GIFT_BF16 || DT == GIFT_FP8E4M3;
+  const float* db_scale = static_cast<const float*>(db_scale_v);
+  const float* q_scale = static_cast<const float*>(q_scale_v);
   const int64_t g0 = goff[w], g1 = goff[w + 1];
   if (g0 == g1) return;
   const int64_t e0 = loff[w] + (b - tile_off[w]) * T::BM;
@@ -557,7 +562,31 @@ __device__ void scan_list_tile(
       src[it] = p;
     }
     f32x16 acc[2][2];
-    mfma_tile_mainloop<DT, 2, 2>(lds, src, row_bytes, acc);
+    if constexpr (MX) {
+      // E8M0 rows of the entry / query view this lane supplies in each block
+      const int nblk = (DT == GIFT_MXFP4 ? 2 * row_bytes : row_bytes) / 32;
+      const uint8_t* de8 = static_cast<const uint8_t*>(db_scale_v);
+      const uint8_t* qe8 = static_cast<const uint8_t*>(q_scale_v);
+      const int l32 = threadIdx.x & 31;
+      const uint8_t* sa_row[2];
+      const uint8_t* sb_row[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wr * 64 + i * 32 + l32;
+        sa_row[i] = de8;
+        if (r < ne)
+          sa_row[i] = de8 + ((int64_t)ent_shape[e0 + r] * n_views + ent_view[e0 + r]) * nblk;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t c = c0 + wc * 64 + j * 32 + l32;
+        sb_row[j] = c < g1 ? qe8 + (int64_t)gitems[c] * nblk : qe8;
+      }
+      mfma_tile_mainloop_mx<DT == GIFT_MXFP8 ? 0 : 4, 2, 2>(lds, src, row_bytes, sa_row, sb_row,
+                                                            acc);
+    } else {
+      mfma_tile_mainloop<DT, 2, 2>(lds, src, row_bytes, acc);
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -567,7 +596,7 @@ __device__ void scan_list_tile(
           const int r = wr * 64 + acc_row(i, e);
           const int c = wc * 64 + acc_col(j);
           float v = acc[i][j][e];
-          if (DT != GIFT_F32 && r < ne) {
+          if (SCALED && r < ne) {
             const int64_t en = e0 + r;
             v *= db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
           }
@@ -580,7 +609,7 @@ __device__ void scan_list_tile(
       const int64_t cg = c0 + c;
       if (cg < g1) {
         const int qi = gitems[cg];
-        const float cs = DT != GIFT_F32 ? q_scale[qi] : 1.f;
+        const float cs = SCALED ? q_scale[qi] : 1.f;
         const int rbeg = half * 64;
         const int rend = rbeg + 64 < ne ? rbeg + 64 : ne;
         int cur = -1;
@@ -603,12 +632,12 @@ __device__ void scan_list_tile(
 
 // Tile b of the concatenated lists: finds its list, then as scan_list_tile.
 template <int DT>
-__device__ void scan_tile(
-    const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
+__device__ __forceinline__ void scan_tile(
+    const uint8_t* __restrict__ db, const void* __restrict__ db_scale, int n_views,
     int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
     const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
-    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    const uint8_t* __restrict__ qv, const void* __restrict__ q_scale,
     uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds) {
   if (b >= tile_off[K]) return;
   // list w with tile_off[w] <= b < tile_off[w+1]
@@ -623,11 +652,11 @@ __device__ void scan_tile(
 
 template <int DT>
 __global__ __launch_bounds__(256, 2) void fif_scan_kernel(
-    const uint8_t* __restrict__ db, const float* __restrict__ db_scale, int n_views,
+    const uint8_t* __restrict__ db, const void* __restrict__ db_scale, int n_views,
     int row_bytes, const int64_t* __restrict__ loff, const int32_t* __restrict__ ent_shape,
     const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int K,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
-    const uint8_t* __restrict__ qv, const float* __restrict__ q_scale,
+    const uint8_t* __restrict__ qv, const void* __restrict__ q_scale,
     uint32_t* __restrict__ mbuf, int64_t ldn) {
   extern __shared__ __align__(16) uint8_t lds[];
   scan_tile<DT>(db, db_scale, n_views, row_bytes, loff, ent_shape, ent_view, tile_off, K, goff,
@@ -637,7 +666,7 @@ __global__ __launch_bounds__(256, 2) void fif_scan_kernel(
 gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int32_t* ent_shape,
                             const int32_t* ent_view, int64_t n_entries, int K,
                             int64_t* tile_off, int64_t* tcount, const int64_t* goff,
-                            const int32_t* gitems, const void* qv, const float* qscale,
+                            const int32_t* gitems, const void* qv, const void* qscale,
                             uint32_t* mbuf, int64_t ldn, hipStream_t st) {
   hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tcount);
   GIFT_LAUNCHED();
@@ -653,15 +682,16 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
         reinterpret_cast<const void*>(fif_scan_kernel<DTV>), shmem);                           \
     if (s_ != GIFT_OK) return s_;                                                              \
     hipLaunchKernelGGL(fif_scan_kernel<DTV>, dim3((unsigned)bound), dim3(256), shmem, st,      \
-                       static_cast<const uint8_t*>(db->data),                                  \
-                       static_cast<const float*>(db->scale), db->n_views,                       \
+                       static_cast<const uint8_t*>(db->data), db->scale, db->n_views,          \
                        row_bytes, loff, ent_shape, ent_view, tile_off, K, goff, gitems,        \
                        static_cast<const uint8_t*>(qv), qscale, mbuf, ldn);                    \
   } while (0)
   switch (db->dtype) {
     case GIFT_F32: GIFT_SCAN_LAUNCH(GIFT_F32); break;
     case GIFT_BF16: GIFT_SCAN_LAUNCH(GIFT_BF16); break;
-    default: GIFT_SCAN_LAUNCH(GIFT_FP8E4M3); break;
+    case GIFT_FP8E4M3: GIFT_SCAN_LAUNCH(GIFT_FP8E4M3); break;
+    case GIFT_MXFP8: GIFT_SCAN_LAUNCH(GIFT_MXFP8); break;
+    default: GIFT_SCAN_LAUNCH(GIFT_MXFP4); break;
   }
 #undef GIFT_SCAN_LAUNCH
   GIFT_LAUNCHED();
@@ -875,8 +905,13 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
       switch (ph) {
         case BP_Q: {
           const int wave = tid >> 6;
-          for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4)
-            quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, a.qscale);
+          for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4) {
+            if constexpr (DT == GIFT_MXFP8 || DT == GIFT_MXFP4)
+              quantize_view_mx_wave(a.qviews, v, a.dim, DT, a.qcodes,
+                                    static_cast<uint8_t*>(a.qscale));
+            else
+              quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, static_cast<float*>(a.qscale));
+          }
           wrote = true;
           break;
         }
@@ -1014,7 +1049,9 @@ gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_
   switch (dtype) {
     case GIFT_F32: GIFT_BATCH_LAUNCH(GIFT_F32); break;
     case GIFT_BF16: GIFT_BATCH_LAUNCH(GIFT_BF16); break;
-    default: GIFT_BATCH_LAUNCH(GIFT_FP8E4M3); break;
+    case GIFT_FP8E4M3: GIFT_BATCH_LAUNCH(GIFT_FP8E4M3); break;
+    case GIFT_MXFP8: GIFT_BATCH_LAUNCH(GIFT_MXFP8); break;
+    default: GIFT_BATCH_LAUNCH(GIFT_MXFP4); break;
   }
 #undef GIFT_BATCH_LAUNCH
   GIFT_LAUNCHED();

@@ -76,7 +76,7 @@ void launch_count_changes(const int32_t* a, const int32_t* b, int64_t n, int32_t
 gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int32_t* ent_shape,
                             const int32_t* ent_view, int64_t n_entries, int K,
                             int64_t* tile_off, int64_t* tcount, const int64_t* goff,
-                            const int32_t* gitems, const void* qv, const float* qscale,
+                            const int32_t* gitems, const void* qv, const void* qscale,
                             uint32_t* mbuf, int64_t ldn, hipStream_t st);
 // mbuf is [query view][shape] with row stride ldn (F-IF scan and reduce).
 void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, const int32_t* qoff,
@@ -89,7 +89,7 @@ constexpr int64_t BATCH_FILL_WORDS = (int64_t)1 << 18;  // mbuf words cleared pe
 constexpr int64_t BATCH_RED_SHAPES = 1024;            // shapes of one query per RED item
 struct BatchArgs {
   const uint8_t* db;
-  const float* db_scale;
+  const void* db_scale;      // per-view float32, E8M0 rows (MX) or null
   int n_views, row_bytes;
   int64_t n_shapes;
   const float* cb;
@@ -107,7 +107,7 @@ struct BatchArgs {
   int64_t Vmax;
   const int32_t* desc;  // {n_queries, n_views} of the current batch
   uint8_t* qcodes;
-  float* qscale;
+  void* qscale;              // like db_scale, for the batch's query views
   float* D;
   int32_t* qwords;
   int32_t* counts;

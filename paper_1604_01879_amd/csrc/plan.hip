@@ -17,7 +17,7 @@ struct PlanWs {
   int32_t* act_tile;
   int32_t* desc;
   uint8_t* qcodes;
-  float* qscale;
+  void* qscale;
   float* D;
   int32_t* qwords;
   int32_t* counts;
@@ -52,7 +52,9 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.desc = c.take<int32_t>(4);
   if (db->dtype != GIFT_F32) {
     w.qcodes = c.take<uint8_t>((size_t)Vmax * row_bytes_of(db->dtype, db->dim));
-    w.qscale = c.take<float>((size_t)Vmax);
+    // per-view float32 scales, or E8M0 rows of dim / 32 bytes (MX)
+    w.qscale = c.take<uint8_t>(is_mx(db->dtype) ? (size_t)Vmax * (db->dim / 32)
+                                                : (size_t)Vmax * sizeof(float));
   }
   w.D = c.take<float>((size_t)Vmax * f->K);
   w.qwords = c.take<int32_t>((size_t)Vmax);
@@ -145,7 +147,10 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   GIFT_CHECK(db->n_views >= 1 && db->n_views <= 64 && db->dim >= 32 && db->dim % 32 == 0,
              GIFT_EUNSUPPORTED, "n_views must be 1..64 and dim a multiple of 32");
   GIFT_CHECK(db->dtype == GIFT_F32 || db->scale != nullptr, GIFT_EINVAL, "missing scales");
-  GIFT_CHECK(!is_mx(db->dtype), GIFT_EUNSUPPORTED, "plans read float32, BF16 or FP8 storage");
+  GIFT_CHECK(db->dtype != GIFT_MXFP8 || db->dim % 128 == 0, GIFT_EUNSUPPORTED,
+             "MXFP8 storage needs dim a multiple of 128");
+  GIFT_CHECK(db->dtype != GIFT_MXFP4 || db->dim % 256 == 0, GIFT_EUNSUPPORTED,
+             "MXFP4 storage needs dim a multiple of 256");
   GIFT_CHECK(fif->K >= 1 && fif->K <= 16384 && fif->ma >= 1 && fif->ma <= 8, GIFT_EUNSUPPORTED,
              "K must be 1..16384 and ma 1..8");
   GIFT_CHECK(fif->n_entries == (int64_t)fif->ma * db->n_shapes * db->n_views, GIFT_EINVAL,
@@ -213,7 +218,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   BatchArgs& a = p->args;
   memset(&a, 0, sizeof(a));
   a.db = static_cast<const uint8_t*>(db->data);
-  a.db_scale = static_cast<const float*>(db->scale);
+  a.db_scale = db->scale;
   a.n_views = db->n_views;
   a.row_bytes = (int)row_bytes_of(db->dtype, db->dim);
   a.n_shapes = db->n_shapes;

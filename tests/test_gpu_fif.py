@@ -152,6 +152,43 @@ def test_first_pass_fif_scores(L, dtype_name):
     assert np.allclose(S.cpu().numpy(), ref, rtol=REL, atol=1e-6)
 
 
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_first_pass_fif_scores_mx(L, fmt):
+    """MX block-scaled list payloads: the first pass equals Eq. 4 over the
+    dequantised MX views (words decided on the float32 views)."""
+    _say(f"fif first pass {fmt}")
+    dt = L.MXFP8 if fmt == "mxfp8" else L.MXFP4
+    w = _wl(n_shapes=150, dim=256, m_lo=1, m_hi=64)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 12, 2, dt)
+    S, qw = L.gift_score_fif(V, F, Q)
+    torch.cuda.synchronize()
+    qw = qw.cpu().numpy()
+    assert np.array_equal(qw, O.assign(q, cb, 1)[:, 0])
+    qc, qe = O.quantize_views_mx(q, fmt)
+    dc, de = O.quantize_views_mx(db, fmt)
+    ref = O.fif_scores(O.dequantize_mx(qc, qe), qoff, O.dequantize_mx(dc, de), w.n_views, cb,
+                       off, es, ev, qwords=qw)
+    assert np.allclose(S.cpu().numpy(), ref, rtol=REL, atol=1e-6)
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_query_fif_mx_rescored_all(L, fmt):
+    """With every shape rescored from the float32 master, the MX path's
+    ranking is the exact Eq. 4 ranking."""
+    _say(f"query_fif {fmt} full rescore")
+    dt = L.MXFP8 if fmt == "mxfp8" else L.MXFP4
+    w = _wl(n_shapes=240, dim=256, m_lo=4, m_hi=64, n_queries=5)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 16, 2, dt)
+    k = 20
+    ids, sc, flags = L.gift_query_fif(V, F, Q, k, w.n_shapes)
+    torch.cuda.synchronize()
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    for b in range(len(qoff) - 1):
+        assert_ranked_equal(ids[b], sc[b], S[b], k)
+    assert (flags.cpu().numpy() & 1).all()  # every shape was rescored
+
+
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("ma", [1, 3])
 def test_query_fif_ranked_ids(L, dtype_name, ma):
