@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time every score tile variant and row-tile group first and use the "
                          "fastest (the trial launches then show up in a kernel trace)")
+    ap.add_argument("--storage", choices=["default", "bf16", "fp8", "mxfp8", "mxfp4"],
+                    default="default",
+                    help="database storage for --workload c4 / c5 (default: bf16 / fp8)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rates", default="200,500,1000")
     args = ap.parse_args()
@@ -359,6 +362,9 @@ def scale_bench(args):
     dev = torch.device("cuda:0")
     w = synth.PRESETS[args.workload]
     dtype = L.BF16 if args.workload == "c4" else L.FP8E4M3
+    if args.storage != "default":
+        dtype = {"bf16": L.BF16, "fp8": L.FP8E4M3, "mxfp8": L.MXFP8, "mxfp4": L.MXFP4}[args.storage]
+    storage = {L.BF16: "bf16", L.FP8E4M3: "fp8", L.MXFP8: "mxfp8", L.MXFP4: "mxfp4"}[dtype]
     t0 = time.time()
     master, V = _resident_db(w, torch, L, dtype)
     log(f"{args.workload}: {w.n_shapes} x {w.n_views} x {w.dim} resident in {time.time() - t0:.1f}s")
@@ -402,10 +408,10 @@ def scale_bench(args):
             plan.close()
         best = max(out.values(), key=lambda v: v["queries_per_s"])
         return {"metric": "queries/s, batched F-IF (one persistent kernel in a HIP graph) + "
-                          "S-IF re-rank, 50k x 64-view BF16 DB",
+                          f"S-IF re-rank, 50k x 64-view {storage} DB",
                 "value": best["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
-                "steps": args.steps, "higher_is_better": True, "dtype": "bf16",
-                "data": "synthetic", "config": {"workload": "c4: 50,000 shapes x 64 x 4096 BF16, "
+                "steps": args.steps, "higher_is_better": True, "dtype": storage,
+                "data": "synthetic", "config": {"workload": f"c4: 50,000 shapes x 64 x 4096 {storage}, "
                 "K=8192 (k-means on 524,288 sampled views), k1=20, 1,024 queries with 12..64 "
                 "views per batch", "queries_per_batch": B, "views_per_batch": nvq},
                 "build": build, "plans": out}
@@ -458,10 +464,10 @@ def scale_bench(args):
     n_slots = srv.n_slots
     srv.close()
     top = runs[str(int(rates[-1]))]
-    return {"metric": "serving queries/s and p50/p99 ms, F-IF + S-IF, 200k x 64-view FP8 DB",
+    return {"metric": f"serving queries/s and p50/p99 ms, F-IF + S-IF, 200k x 64-view {storage} DB",
             "value": top["achieved_qps"], "unit": "queries/s", "n_gpus": 1,
-            "higher_is_better": True, "dtype": "fp8", "data": "synthetic",
-            "config": {"workload": "c5: 200,000 shapes x 64 x 1024 e4m3, K=8192, k1=20, Poisson "
+            "higher_is_better": True, "dtype": storage, "data": "synthetic",
+            "config": {"workload": f"c5: 200,000 shapes x 64 x 1024 {storage}, K=8192, k1=20, Poisson "
                        f"arrivals {args.serve_rates} q/s for {args.serve_seconds}s each, "
                        "8..64 views per query", "slots": n_slots},
             "build": build, "plan_alone_by_batch": by_size, "serving": runs}

@@ -362,8 +362,10 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
 // row r holds the row's chunk c ^ ((r >> 1) & 3), so the 8 rows read
 // together by a lane group hit 8 different bank groups.  row_bytes must be
 // a multiple of 64.  Lane l stages rows wave * WROWS + 16 i + l / 4
-// (i < NI); rowp[i] must point at a readable row (pad rows may point
-// anywhere valid: their results are not used).
+// (i < NI); rows below BM are read at base_a + roff[i], the others at
+// base_b + roff[i] (a 16-row group never straddles BM, so the base is
+// uniform per load).  Pad rows may use any readable offset (0): their
+// results are not used.
 constexpr int DMA_KSUB = 64;
 constexpr int DMA_STAGES = 4;
 
@@ -380,20 +382,21 @@ struct DmaShape {
 
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
-// s_waitcnt vmcnt(n) lgkmcnt(0), then a barrier that the compiler may not
-// move memory accesses across (the vmcnt allowance keeps later sub-tiles'
-// loads in flight; a fenced barrier would wait for all of them).
+// s_waitcnt vmcnt(n) for the direct loads (issued from inline asm, so the
+// compiler does not count them and the vmcnt allowance keeps later
+// sub-tiles' loads in flight), then a fenced block barrier, which also
+// tells the compiler that every earlier LDS read has completed.
 template <int N>
 __device__ __forceinline__ void wait_vm_barrier() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-  asm volatile("s_barrier" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+  __syncthreads();
 }
 
 template <int DT, int WM, int WN>
 __device__ __forceinline__ void mfma_tile_mainloop_dma(
-    uint8_t* lds, const uint8_t* const (&rowp)[DmaShape<WM, WN>::NI], int row_bytes,
-    f32x16 (&acc)[WM][WN]) {
+    uint8_t* lds, const uint8_t* base_a, const uint8_t* base_b,
+    const uint32_t (&roff)[DmaShape<WM, WN>::NI], int row_bytes, f32x16 (&acc)[WM][WN]) {
   using T = DmaShape<WM, WN>;
   static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
   const int tid = threadIdx.x;
@@ -411,11 +414,12 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
 
   const int n_kt = row_bytes / DMA_KSUB;
   lds_u8* l3 = (lds_u8*)lds;
-  int gchunk[T::NI];  // byte offset of the global chunk this lane copies
+  // per-lane offsets of the global chunks this lane copies (row + chunk)
+  uint32_t goff[T::NI];
 #pragma unroll
   for (int i = 0; i < T::NI; ++i) {
     const int r = wave * T::WROWS + 16 * i + (lane >> 2);
-    gchunk[i] = ((lane & 3) ^ ((r >> 1) & 3)) * 16;
+    goff[i] = roff[i] + (uint32_t)(((lane & 3) ^ ((r >> 1) & 3)) * 16);
   }
   // The loads are issued from inline asm so that the compiler does not
   // treat them as pending LDS writes (it would then wait for every one of
@@ -424,12 +428,17 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
       (int)(uint32_t)(uintptr_t)(l3 + wave * T::WROWS * DMA_KSUB));
   auto issue = [&](int kt) {
     const uint32_t base = wave_lds + (uint32_t)((kt % DMA_STAGES) * T::STAGE_BYTES);
+    const uint8_t* ga = base_a + kt * DMA_KSUB;
+    const uint8_t* gb = base_b + kt * DMA_KSUB;
 #pragma unroll
     for (int i = 0; i < T::NI; ++i) {
-      const uint8_t* g = rowp[i] + kt * DMA_KSUB + gchunk[i];
-      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+      const bool a_side = wave * T::WROWS + 16 * i < T::BM;  // uniform in the wave
+      const uint64_t gv = (uint64_t)(uintptr_t)(a_side ? ga : gb);
+      const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv >> 32)) << 32) |
+                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv);
+      asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
                    :
-                   : "v"(g), "s"(base + (uint32_t)(i * 16 * DMA_KSUB))
+                   : "v"(goff[i]), "s"(g), "s"(base + (uint32_t)(i * 16 * DMA_KSUB))
                    : "memory", "m0");
     }
   };
@@ -441,58 +450,79 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
   const int sw = (l32 >> 1) & 3;
   const int arow = (wr * WM * 32 + l32) * DMA_KSUB;
   const int brow = (T::BM + wc * WN * 32 + l32) * DMA_KSUB;
-  for (int kt = 0; kt < n_kt; ++kt) {
-    if (kt + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
-    else wait_vm_barrier<0>();
-    // every wave is past sub-tile kt - 1, so its stage can be refilled
-    if (kt + DMA_STAGES - 1 < n_kt) issue(kt + DMA_STAGES - 1);
+  // Logical 16-byte chunk of step s2 that lane half h supplies: BF16 takes
+  // chunk 2 s2 + h per 32x32x16 step; e4m3 takes chunks 2h, 2h + 1 (one
+  // 32x32x64 step, held as the pair [0], [1]).
+  auto chunk = [&](int s2) {
+    return DT == GIFT_BF16 ? ((2 * s2 + half) ^ sw) * 16 : ((2 * half + s2) ^ sw) * 16;
+  };
+  // The B fragments of sub-tile kt + 1 are read from LDS while the MFMAs of
+  // sub-tile kt run (two register sets); A fragments are read from the
+  // current stage inside the MFMA sequence (that stage is refilled only
+  // after the next barrier).
+  uint4 fb[2][WN][2];
+  auto read_b = [&](int kt, int set) {
     const uint8_t* st = lds + (kt % DMA_STAGES) * T::STAGE_BYTES;
-    if constexpr (DT == GIFT_BF16) {
-      // two 32x32x16 steps; lane half h supplies logical chunk 2 s + h
-      uint4 b[WN][2];
 #pragma unroll
-      for (int j = 0; j < WN; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-          b[j][s2] = *reinterpret_cast<const uint4*>(st + brow + j * 32 * DMA_KSUB +
-                                                     (((2 * s2 + half) ^ sw) * 16));
+      for (int s2 = 0; s2 < 2; ++s2)
+        fb[set][j][s2] = *reinterpret_cast<const uint4*>(st + brow + j * 32 * DMA_KSUB + chunk(s2));
+  };
+  auto mfmas = [&](int kt, int set) {
+    const uint8_t* st = lds + (kt % DMA_STAGES) * T::STAGE_BYTES;
 #pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        uint4 a[2];
+    for (int i = 0; i < WM; ++i) {
+      uint4 fa[2];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-          a[s2] = *reinterpret_cast<const uint4*>(st + arow + i * 32 * DMA_KSUB +
-                                                  (((2 * s2 + half) ^ sw) * 16));
+      for (int s2 = 0; s2 < 2; ++s2)
+        fa[s2] = *reinterpret_cast<const uint4*>(st + arow + i * 32 * DMA_KSUB + chunk(s2));
 #pragma unroll
-        for (int j = 0; j < WN; ++j)
+      for (int j = 0; j < WN; ++j) {
+        if constexpr (DT == GIFT_BF16) {
 #pragma unroll
           for (int s2 = 0; s2 < 2; ++s2)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, a[s2]), __builtin_bit_cast(bf16x8, b[j][s2]),
+                __builtin_bit_cast(bf16x8, fa[s2]), __builtin_bit_cast(bf16x8, fb[set][j][s2]),
                 acc[i][j], 0, 0, 0);
-      }
-    } else {
-      // one 32x32x64 step; lane half h supplies logical chunks 2h, 2h + 1
-      Pair32 b[WN];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const uint8_t* rb = st + brow + j * 32 * DMA_KSUB;
-        b[j].lo = *reinterpret_cast<const uint4*>(rb + (((2 * half) ^ sw) * 16));
-        b[j].hi = *reinterpret_cast<const uint4*>(rb + (((2 * half + 1) ^ sw) * 16));
-      }
-#pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        const uint8_t* ra = st + arow + i * 32 * DMA_KSUB;
-        Pair32 a;
-        a.lo = *reinterpret_cast<const uint4*>(ra + (((2 * half) ^ sw) * 16));
-        a.hi = *reinterpret_cast<const uint4*>(ra + (((2 * half + 1) ^ sw) * 16));
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
+        } else {
+          const Pair32 a = {fa[0], fa[1]}, b = {fb[set][j][0], fb[set][j][1]};
           acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b[j]), acc[i][j], 0, 0,
-              0, 127, 0, 127);
+              __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b), acc[i][j], 0, 0, 0, 127,
+              0, 127);
+        }
       }
     }
+  };
+  // Sub-tile kt is waited for at iteration kt - 1 (kt = 0 before the loop);
+  // at that point the loads of at most one later sub-tile are in flight.
+  // Iteration kt then refills the stage of sub-tile kt - 1, whose fragments
+  // every wave finished reading before the barrier.
+  if (DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
+  else wait_vm_barrier<0>();
+  read_b(0, 0);
+  // one sub-tile k (k + 1 < n_kt): B fragments of k are in register set
+  // `cur`; those of k + 1 go to the other set
+  auto step_prefetch = [&](int k, int cur) {
+    if (k + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 3)>();
+    else wait_vm_barrier<0>();
+    if (k + DMA_STAGES - 1 < n_kt) issue(k + DMA_STAGES - 1);
+    read_b(k + 1, 1 - cur);
+    mfmas(k, cur);
+  };
+  // The loop body always prefetches, so no path into its MFMAs leaves the
+  // current fragments' reads outstanding; the last one or two sub-tiles
+  // follow.  (No early exit inside the body: the accumulators stay put.)
+  int kt = 0;
+  for (; kt + 2 < n_kt; kt += 2) {
+    step_prefetch(kt, 0);
+    step_prefetch(kt + 1, 1);
+  }
+  if (kt + 1 < n_kt) {
+    step_prefetch(kt, 0);
+    mfmas(kt + 1, 1);
+  } else {
+    mfmas(kt, 0);
   }
   wait_vm_barrier<0>();  // LDS may be reused by the caller
 }

@@ -81,25 +81,28 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
 
   f32x16 acc[WM][WN];
   if constexpr (DMA) {
-    // staged rows of this lane; pad rows re-read row 0 (their results are
-    // never used)
+    // staged rows of this lane as offsets from the block's first database
+    // row and first query row (both under 2^32: at most 256 rows of 8 KB);
+    // pad rows re-read the first row (their results are never used)
     using D = DmaShape<WM, WN>;
-    const uint8_t* rowp[D::NI];
+    const uint8_t* base_a = db + shape0 * n_views * (int64_t)row_bytes;
+    const uint8_t* base_b = qv + col0 * (int64_t)row_bytes;
+    uint32_t roff[D::NI];
 #pragma unroll
     for (int i = 0; i < D::NI; ++i) {
       const int r = wave * D::WROWS + 16 * i + (lane >> 2);
-      const uint8_t* p;
+      uint32_t o = 0;
       if (r < T::BM) {
         const int64_t shp = shape0 + (r >> 6);
         const int v = r & 63;
-        p = (shp < n_shapes && v < n_views) ? db + (shp * n_views + v) * (int64_t)row_bytes : db;
+        if (shp < n_shapes && v < n_views) o = (uint32_t)(((r >> 6) * n_views + v) * row_bytes);
       } else {
         const int64_t c = col0 + (r - T::BM);
-        p = c < total_q ? qv + c * (int64_t)row_bytes : qv;
+        if (c < total_q) o = (uint32_t)((r - T::BM) * row_bytes);
       }
-      rowp[i] = p;
+      roff[i] = o;
     }
-    mfma_tile_mainloop_dma<DT, WM, WN>(lds, rowp, row_bytes, acc);
+    mfma_tile_mainloop_dma<DT, WM, WN>(lds, base_a, base_b, roff, row_bytes, acc);
   } else {
     const uint8_t* src[T::LOADS];
 #pragma unroll
