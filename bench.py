@@ -40,14 +40,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", choices=["bf16", "fp8", "f32"], default="bf16")
+    ap.add_argument("--dtype", choices=["bf16", "fp8", "f32"], default="fp8",
+                    help="database storage of the headline path (e4m3 meets the recall@100 "
+                         "bar, averaged over queries, at the 200-candidate rescore)")
     ap.add_argument("--shapes", type=int, default=12000)
     ap.add_argument("--queries", type=int, default=256)
     ap.add_argument("--top-k", type=int, default=100)
     ap.add_argument("--rescore", type=int, default=200)
     ap.add_argument("--fp32-steps", type=int, default=2,
                     help="steps of the plain float32 path (reference and speedup)")
-    ap.add_argument("--fp8-steps", type=int, default=3)
+    ap.add_argument("--alt-steps", "--fp8-steps", dest="alt_steps", type=int, default=3,
+                    help="steps of the other reduced-precision storage (BF16 when the "
+                         "headline is e4m3, and the reverse)")
     ap.add_argument("--mx-steps", type=int, default=3,
                     help="steps of the MX block-scaled FP8 / FP4 paths (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
@@ -123,7 +127,7 @@ def main():
     k, R = args.top_k, args.rescore
     tuning = {}
     for name in ("bf16", "fp8"):
-        if name == args.dtype or (name == "fp8" and args.fp8_steps):
+        if name == args.dtype or (name != args.dtype and args.alt_steps):
             if args.tune:
                 bt, bg = (int(x) for x in args.tune.split(","))
                 L.gift_set_score_tuning(dts[name], bt, bg)
@@ -172,7 +176,8 @@ def main():
         ref_run = run("f32", args.fp32_steps, 1, prof=True)
     else:
         ref_run = None
-    fp8_run = run("fp8", args.fp8_steps, 1) if args.dtype != "fp8" and args.fp8_steps else None
+    alt = "bf16" if args.dtype == "fp8" else "fp8"
+    alt_run = run(alt, args.alt_steps, 1) if args.dtype != "f32" and args.alt_steps else None
 
     B = w.n_queries
     qps = B * args.steps / main_run["total"]
@@ -219,7 +224,9 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(main_run["lat"], 50)) * 1e3, 3),
                        "p99": round(float(np.percentile(main_run["lat"], 99)) * 1e3, 3),
                        "note": "per-step batch latency; every query of a step completes together"},
-        "recall": {"at100_mean": r100[0], "at100_min": r100[1], "at10_mean": r10[0],
+        "recall": {"meets_bar": bool(r100[0] >= 0.99),
+                   "bar": "recall@100 averaged over the step's queries >= 0.99",
+                   "at100_mean": r100[0], "at100_min": r100[1], "at10_mean": r10[0],
                    "at10_min": r10[1], "max_score_err": err,
                    "reference": "float32 path with certified exact ranking"
                                 + (" (all queries certified complete)" if exact_ok else " (NOT all certified)"),
@@ -243,10 +250,10 @@ def main():
             rr = recall(mr["ids"], exact_ids, min(100, k))
             result[f"{name}_path"] = {"queries_per_s": round(B * args.mx_steps / mr["total"], 2),
                                       "recall_at100_mean": rr[0], "recall_at100_min": rr[1]}
-    if fp8_run is not None:
-        f8 = recall(fp8_run["ids"], exact_ids, min(100, k))
-        result["fp8_path"] = {"queries_per_s": round(B * args.fp8_steps / fp8_run["total"], 2),
-                              "recall_at100_mean": f8[0], "recall_at100_min": f8[1]}
+    if alt_run is not None:
+        ra = recall(alt_run["ids"], exact_ids, min(100, k))
+        result[f"{alt}_path"] = {"queries_per_s": round(B * args.alt_steps / alt_run["total"], 2),
+                                 "recall_at100_mean": ra[0], "recall_at100_min": ra[1]}
 
     if args.fif and ref_run is not None:
         try:
@@ -328,18 +335,20 @@ def _build_index(w, torch, L, master, V, k1, log_prefix):
                       "sif_postings": S.nnz()}
 
 
-_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                             "score_tiles_bf16_12k_hbm_traffic.md")
+def _traffic_file(dtype):
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"score_tiles_{dtype}_12k_hbm_traffic.md")
 
 
 def _recorded_traffic(dtype, tuning, w, query_views):
     """Calibrated HBM bytes per launch of the score kernel from the committed
     rocprofv3 counter summary, when it was taken on this exact kernel variant
     and workload; otherwise None."""
-    if not tuning or not os.path.exists(_TRAFFIC_FILE):
+    path = _traffic_file(dtype)
+    if not tuning or not os.path.exists(path):
         return None
     rec = {}
-    for line in open(_TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("- ") and ": " in line:
             key, val = line[2:].strip().split(": ", 1)
             rec[key.strip("`")] = val.strip("`")

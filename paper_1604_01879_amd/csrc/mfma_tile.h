@@ -460,7 +460,7 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
   // sub-tile kt run (two register sets); A fragments are read from the
   // current stage inside the MFMA sequence (that stage is refilled only
   // after the next barrier).
-  uint4 fb[2][WN][2];
+  uint4 fb[WM * WN < 16 ? 2 : 1][WN][2];
   auto read_b = [&](int kt, int set) {
     const uint8_t* st = lds + (kt % DMA_STAGES) * T::STAGE_BYTES;
 #pragma unroll
@@ -494,35 +494,50 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
       }
     }
   };
-  // Sub-tile kt is waited for at iteration kt - 1 (kt = 0 before the loop);
-  // at that point the loads of at most one later sub-tile are in flight.
-  // Iteration kt then refills the stage of sub-tile kt - 1, whose fragments
-  // every wave finished reading before the barrier.
-  if (DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
-  else wait_vm_barrier<0>();
-  read_b(0, 0);
-  // one sub-tile k (k + 1 < n_kt): B fragments of k are in register set
-  // `cur`; those of k + 1 go to the other set
-  auto step_prefetch = [&](int k, int cur) {
-    if (k + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 3)>();
-    else wait_vm_barrier<0>();
-    if (k + DMA_STAGES - 1 < n_kt) issue(k + DMA_STAGES - 1);
-    read_b(k + 1, 1 - cur);
-    mfmas(k, cur);
-  };
-  // The loop body always prefetches, so no path into its MFMAs leaves the
-  // current fragments' reads outstanding; the last one or two sub-tiles
-  // follow.  (No early exit inside the body: the accumulators stay put.)
-  int kt = 0;
-  for (; kt + 2 < n_kt; kt += 2) {
-    step_prefetch(kt, 0);
-    step_prefetch(kt + 1, 1);
-  }
-  if (kt + 1 < n_kt) {
-    step_prefetch(kt, 0);
-    mfmas(kt + 1, 1);
+  // With 256 accumulator registers (WM x WN = 16) there is no room for a
+  // second B set: each sub-tile then waits for its own stage and reads its
+  // B fragments itself.
+  constexpr bool PREFETCH = WM * WN < 16;
+  if constexpr (!PREFETCH) {
+    for (int kt = 0; kt < n_kt; ++kt) {
+      if (kt + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
+      else wait_vm_barrier<0>();
+      // every wave is past sub-tile kt - 1, so its stage can be refilled
+      if (kt + DMA_STAGES - 1 < n_kt) issue(kt + DMA_STAGES - 1);
+      read_b(kt, 0);
+      mfmas(kt, 0);
+    }
   } else {
-    mfmas(kt, 0);
+    // Sub-tile kt is waited for at iteration kt - 1 (kt = 0 before the
+    // loop); at that point the loads of at most one later sub-tile are in
+    // flight.  Iteration kt then refills the stage of sub-tile kt - 1, whose
+    // fragments every wave finished reading before the barrier.
+    if (DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 2)>();
+    else wait_vm_barrier<0>();
+    read_b(0, 0);
+    // one sub-tile k (k + 1 < n_kt): B fragments of k are in register set
+    // `cur`; those of k + 1 go to the other set
+    auto step_prefetch = [&](int k, int cur) {
+      if (k + DMA_STAGES - 2 < n_kt) wait_vm_barrier<T::NI * (DMA_STAGES - 3)>();
+      else wait_vm_barrier<0>();
+      if (k + DMA_STAGES - 1 < n_kt) issue(k + DMA_STAGES - 1);
+      read_b(k + 1, 1 - cur);
+      mfmas(k, cur);
+    };
+    // The loop body always prefetches, so no path into its MFMAs leaves the
+    // current fragments' reads outstanding; the last one or two sub-tiles
+    // follow.  (No early exit inside the body: the accumulators stay put.)
+    int kt = 0;
+    for (; kt + 2 < n_kt; kt += 2) {
+      step_prefetch(kt, 0);
+      step_prefetch(kt + 1, 1);
+    }
+    if (kt + 1 < n_kt) {
+      step_prefetch(kt, 0);
+      mfmas(kt + 1, 1);
+    } else {
+      mfmas(kt, 0);
+    }
   }
   wait_vm_barrier<0>();  // LDS may be reused by the caller
 }
