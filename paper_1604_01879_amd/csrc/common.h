@@ -81,6 +81,29 @@ __host__ __device__ inline float order_float(uint32_t k) {
 // compensated dot product of Ogita, Rump and Oishi ("Accurate sum and dot
 // product", SIAM J. Sci. Comput. 26(6), 2005), kept as an unevaluated pair
 // hi + lo.  Contraction is disabled so the compiler keeps every rounding.
+// Global-memory pointers.  Loads through them are global (not flat)
+// instructions, which the LDS wait counter does not track.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+// The value of `p` in lane 0 as a global pointer held in scalar registers:
+// loads through it take the scalar-base + 32-bit vector-offset form.
+template <typename T>
+__device__ __forceinline__ gptr<T> uniform_gptr(const T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  return reinterpret_cast<gptr<T>>(((uint64_t)hi << 32) | lo);
+}
+
+// The 16-byte T at byte offset `off` from `base`.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T load_at(gptr<uint8_t> base, uint32_t off) {
+  static_assert(sizeof(T) == 16, "16-byte loads");
+  return __builtin_bit_cast(T, *reinterpret_cast<gptr<u32x4>>(base + off));
+}
+
 struct ff {
   float hi, lo;
 };

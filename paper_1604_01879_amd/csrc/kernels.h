@@ -39,9 +39,10 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r, const in
 // With qwords != nullptr only pairs whose words match take part (Eq. 4).
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
-                    int max_m, const int32_t* cand, int r, float dot_err,
+                    int64_t total_views, const int32_t* cand, int r, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, float* s_hi, float* s_lo, hipStream_t st);
+                    const int32_t* active, unsigned long long* mask, float* s_hi, float* s_lo,
+                    hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
 // id asc) and writes the top k; sets flags bit 0 when provably complete.

@@ -10,6 +10,7 @@ namespace gift {
 constexpr int SEL_THREADS = 512;          // threads of a top-r selection block
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int SEL_UNROLL = 8;             // independent loads in flight per thread
+constexpr int P2_BATCH = 16;              // float4 loads per row per lane in a rescore batch
 
 // Exclusive prefix count of `flag` over the threads of a block, in thread
 // order; returns the block total through `total`.
@@ -159,245 +160,315 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r, const in
 // ------------------------------------------------------------------ rescore
 // x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in
 // float32), |r| <= 2^-16 |x|; four floats at a time, packed two per word.
-__device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
-  uint16_t h[4], l[4];
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float x = __builtin_bit_cast(float, w[t]);
-    h[t] = bf16_rne(x);
-    l[t] = bf16_rne(x - __builtin_bit_cast(float, (uint32_t)h[t] << 16));
-  }
-  hi = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-  lo = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+// Both roundings are the hardware's round-to-nearest-even pair conversion.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
 
-// One block (two waves) per (query, candidate shape).  Phase 1: approximate
-// dot products of the candidate's views (rows, 64) with up to 64 query views
-// (columns) on MFMA, 32 x 32 blocks: wave w owns query views 32w..32w+31 and
-// both row blocks.  Each float32 value is split as hi + lo + r (hi, lo
-// bfloat16, |r| <= 2^-16 |x|) and the dot is hi.hi' + hi.lo' + lo.hi' on
-// BF16 MFMA (products exact in float32), missing at most about
-// 3 * 2^-16 sum |x y|.  Each 32-value K-tile is accumulated into a fresh
-// register block and added into a running total, which bounds the float32
-// accumulation depth; dot_err bounds both.  The lane that holds query view
-// i holds 32 of its row values, so the maximum over the candidate's valid
-// views and the mask of views within 2 * dot_err of it need one cross-half
-// shuffle.  Phase 2: every masked pair is re-evaluated
-// with the compensated dot product and the exact maximum kept.  Phase 3:
-// the compensated mean over the query views in ascending order.
+__device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
+  const float x0 = __builtin_bit_cast(float, v.x), x1 = __builtin_bit_cast(float, v.y);
+  const float x2 = __builtin_bit_cast(float, v.z), x3 = __builtin_bit_cast(float, v.w);
+  const uint32_t h01 = bf16_pair(x0, x1), h23 = bf16_pair(x2, x3);
+  const float r0 = x0 - __builtin_bit_cast(float, h01 << 16);
+  const float r1 = x1 - __builtin_bit_cast(float, h01 & 0xffff0000u);
+  const float r2 = x2 - __builtin_bit_cast(float, h23 << 16);
+  const float r3 = x3 - __builtin_bit_cast(float, h23 & 0xffff0000u);
+  hi = make_uint2(h01, h23);
+  lo = make_uint2(bf16_pair(r0, r1), bf16_pair(r2, r3));
+}
+
+// Pairs handled by block `blk` when the chip runs blocks round-robin over its
+// 8 XCDs: XCD x takes the contiguous pair range [x c, x c + c), c = ceil(n / 8),
+// so the blocks running together on one XCD (and its L2) share a query.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t blk, int64_t n) {
+  const int64_t c = (n + 7) / 8;
+  return (blk & 7) * c + (blk >> 3);
+}
+
+constexpr int RS_CANDS = 4;                         // candidates per rescore block, one wave each
+constexpr int RS_THREADS = 64 * RS_CANDS;
+constexpr int RS_ROWS = 64 * (RS_CANDS + 1);        // staged rows: candidate views, then query views
+constexpr int RS_PIECES = RS_ROWS * 8 / RS_THREADS;  // 16-byte pieces per thread per K-tile
+
+// Candidate rescore, phase 1 (rescore_mask_kernel): one block (four waves)
+// per (query, 4 consecutive candidates), blocks in XCD-contiguous order
+// (xcd_contiguous), so the query's rows are staged once for four candidates
+// and the blocks sharing an XCD share the query.  Approximate dot products
+// of each candidate's views (rows, 64) with up to 64 query views (columns)
+// on MFMA; wave w owns candidate w, as 2 x 2 blocks of 32 x 32.  Each
+// float32 value is split as hi + lo + r (hi, lo bfloat16, |r| <= 2^-16 |x|)
+// and the dot is hi.hi' + hi.lo' + lo.hi' on BF16 MFMA (products exact in
+// float32), missing at most about 3 * 2^-16 sum |x y|.  Each 32-value K-tile
+// is accumulated into a fresh register block and added into a running total,
+// which bounds the float32 accumulation depth; dot_err bounds both.  The
+// lane that holds query view i holds 32 of its row values, so the maximum
+// over the candidate's valid views and the mask of views within 2 dot_err
+// of it (bit j of mask[c][q0 + i] for candidate c of the query whose views
+// start at q0) need one cross-half shuffle.
 // With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
-// word of q_i is one of the `ma` words of p_j, and a query view with no such
-// pair contributes 0.
-__global__ __launch_bounds__(128, 2) void rescore_kernel(
+// word of q_i is one of the `ma` words of p_j; a query view with no such
+// pair gets an empty mask.
+__global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
-    const int32_t* __restrict__ cand, int r, float dot_err,
+    int n_queries, const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
-    const int32_t* __restrict__ active, float* __restrict__ s_hi, float* __restrict__ s_lo) {
-  constexpr int ROWS = 128;  // 64 candidate views + 64 query views
-  __shared__ __align__(16) uint8_t lds[ROWS * LROW];
-  __shared__ unsigned long long jmask[64];
-  __shared__ float mff_hi[64], mff_lo[64];
-  __shared__ int32_t vw[64 * 8];
-  __shared__ float tot_hi, tot_lo;
+    const int32_t* __restrict__ active, unsigned long long* __restrict__ mask, int64_t mask_ld) {
+  __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
+  __shared__ int32_t vw[RS_CANDS][64 * 8];
 
-  const int64_t bc = blockIdx.x;
-  const int b = (int)(bc / r);
-  if (active != nullptr && b >= *active) return;  // query slot past the batch
-  const int64_t shape = cand[bc];
-  const int q0 = qoff[b], m = qoff[b + 1] - q0;
+  const int groups = (r + RS_CANDS - 1) / RS_CANDS;
+  const int64_t n_items = (int64_t)(active != nullptr ? *active : n_queries) * groups;
+  const int64_t item = xcd_contiguous(blockIdx.x, n_items);
+  if (item >= n_items) return;  // past the batch
+  const int b = (int)(item / groups);
+  const int c0 = (int)(item % groups) * RS_CANDS;
+  const int n_cand = min(RS_CANDS, r - c0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
-  const float* pbase = master + shape * (int64_t)n_views * dim;
+  const bool mine = wave < n_cand;  // this wave's candidate exists
+  const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int row_bytes = dim * 4;
+  const int64_t shape_bytes = (int64_t)n_views * row_bytes;
+  const uint8_t* master_b = reinterpret_cast<const uint8_t*>(master);
+
+  // the block's candidate shapes (the last repeated when fewer than 4)
+  int64_t shape[RS_CANDS];
+#pragma unroll
+  for (int k = 0; k < RS_CANDS; ++k) shape[k] = cand[(int64_t)b * r + c0 + min(k, n_cand - 1)];
+  unsigned long long* wmask = mask + (int64_t)(c0 + (mine ? wave : 0)) * mask_ld + q0;
 
   if (qwords != nullptr)
-    for (int x = tid; x < n_views * ma; x += 128) vw[x] = view_words[shape * n_views * ma + x];
-  if (tid == 0) { tot_hi = 0.f; tot_lo = 0.f; }
+#pragma unroll
+    for (int k = 0; k < RS_CANDS; ++k)
+      for (int x = tid; x < n_views * ma; x += RS_THREADS)
+        vw[k][x] = view_words[shape[k] * n_views * ma + x];
+
+  // staging: thread t copies bytes [16 (t & 7), 16 (t & 7) + 16) of each
+  // 128-byte K-tile of staged rows (t >> 3) + 32 p, p < RS_PIECES: rows
+  // 64 k + i of candidate k, then 64 RS_CANDS + i of the query chunk,
+  // addressed as 32-bit offsets from the row group's base
+  uint32_t roff[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    roff[h] = (uint32_t)((tid >> 3) + 32 * h) * (uint32_t)row_bytes + (uint32_t)(tid & 7) * 16u;
+  gptr<uint8_t> gb[RS_CANDS + 1];
+#pragma unroll
+  for (int k = 0; k < RS_CANDS; ++k) gb[k] = uniform_gptr(master_b + shape[k] * shape_bytes);
+
   for (int it = 0; it * 64 < m; ++it) {
     const int mi = min(64, m - it * 64);
     const float* qbase = qviews + (int64_t)(q0 + it * 64) * dim;
-    // staging pointers: 8 pieces per thread per K-tile
-    const uint8_t* src[8];
+    gb[RS_CANDS] = uniform_gptr(reinterpret_cast<const uint8_t*>(qbase));
+    unsigned valid = 0u;  // bit p: piece p lies in a present row
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int row = (tid + 128 * p) >> 3;
-      const uint8_t* ptr = nullptr;
-      if (row < 64) {
-        if (row < n_views) ptr = reinterpret_cast<const uint8_t*>(pbase + (int64_t)row * dim);
-      } else if (row - 64 < mi) {
-        ptr = reinterpret_cast<const uint8_t*>(qbase + (int64_t)(row - 64) * dim);
-      }
-      src[p] = ptr;
+    for (int p = 0; p < RS_PIECES; ++p) {
+      const int g = p >> 1, row = (tid >> 3) + 32 * (p & 1);
+      const bool ok = g < RS_CANDS ? (g < n_cand && row < n_views) : row < mi;
+      valid |= (ok ? 1u : 0u) << p;
     }
-    f32x16 tot[2];
+    f32x16 tot[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) tot[bi][e] = 0.f;
+      for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tot[bi][cj][e] = 0.f;
     // LDS row of a K-tile: 32 high parts (64 bytes) then 32 low parts; lane
     // half h supplies values [16h, 16h + 16) of the tile in two MFMA steps
-    const uint8_t* arow = lds + l32 * LROW + half * 32;
-    const uint8_t* brow = lds + (64 + wave * 32 + l32) * LROW + half * 32;
-    uint4 pre[8];
+    const uint8_t* arow = lds + (64 * wave + l32) * LROW + half * 32;
+    const uint8_t* brow = lds + (64 * RS_CANDS + l32) * LROW + half * 32;
+    uint4 pre[RS_PIECES];
     auto gload = [&](int k0) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        const int off = k0 + ((tid + 128 * p) & 7) * 16;
-        pre[p] = src[p] != nullptr ? *reinterpret_cast<const uint4*>(src[p] + off)
+      for (int p = 0; p < RS_PIECES; ++p)
+        pre[p] = (valid >> p) & 1u ? load_at<uint4>(gb[p >> 1], roff[p & 1] + (uint32_t)k0)
                                    : make_uint4(0, 0, 0, 0);
-      }
     };
     gload(0);
     for (int k0 = 0; k0 < row_bytes; k0 += 128) {
       __syncthreads();
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        const int idx = tid + 128 * p;
+      for (int p = 0; p < RS_PIECES; ++p) {
         uint2 hi, lo;
         split_bf16x4(pre[p], hi, lo);
-        uint8_t* row = lds + (idx >> 3) * LROW + (idx & 7) * 8;
+        uint8_t* row = lds + ((tid >> 3) + 32 * p) * LROW + (tid & 7) * 8;
         *reinterpret_cast<uint2*>(row) = hi;
         *reinterpret_cast<uint2*>(row + 64) = lo;
       }
       __syncthreads();
       if (k0 + 128 < row_bytes) gload(k0 + 128);  // in flight during the MFMAs
-      uint4 bh[2], bl[2];
 #pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        bh[st] = *reinterpret_cast<const uint4*>(brow + st * 16);
-        bl[st] = *reinterpret_cast<const uint4*>(brow + 64 + st * 16);
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        uint4 ah[2], al[2];
+      for (int cj = 0; cj < 2; ++cj) {
+        uint4 bh[2], bl[2];
 #pragma unroll
         for (int st = 0; st < 2; ++st) {
-          ah[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + st * 16);
-          al[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + 64 + st * 16);
-        }
-        f32x16 part;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) part[e] = 0.f;
-#pragma unroll
-        for (int st = 0; st < 2; ++st) {
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
-                                                         __builtin_bit_cast(bf16x8, bh[st]),
-                                                         part, 0, 0, 0);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
-                                                         __builtin_bit_cast(bf16x8, bl[st]),
-                                                         part, 0, 0, 0);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[st]),
-                                                         __builtin_bit_cast(bf16x8, bh[st]),
-                                                         part, 0, 0, 0);
+          bh[st] = *reinterpret_cast<const uint4*>(brow + cj * 32 * LROW + st * 16);
+          bl[st] = *reinterpret_cast<const uint4*>(brow + cj * 32 * LROW + 64 + st * 16);
         }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) tot[bi][e] += part[e];
+        for (int bi = 0; bi < 2; ++bi) {
+          uint4 ah[2], al[2];
+#pragma unroll
+          for (int st = 0; st < 2; ++st) {
+            ah[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + st * 16);
+            al[st] = *reinterpret_cast<const uint4*>(arow + bi * 32 * LROW + 64 + st * 16);
+          }
+          f32x16 part;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) part[e] = 0.f;
+#pragma unroll
+          for (int st = 0; st < 2; ++st) {
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, ah[st]), __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, ah[st]), __builtin_bit_cast(bf16x8, bl[st]), part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, al[st]), __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
+          }
+#pragma unroll
+          for (int e = 0; e < 16; ++e) tot[bi][cj][e] += part[e];
+        }
       }
     }
-    // per query view (this lane's column): maximum over valid views and the
-    // mask of views that may hold the exact maximum
-    const int i = wave * 32 + l32;
-    int wq = -1;
-    if (qwords != nullptr && i < mi) wq = qwords[q0 + it * 64 + i];
-    float mx = -INFINITY;
-    unsigned valid = 0u;  // bit (bi*16 + e)
+    // per query view i (this lane's column in block cj): maximum over the
+    // views that may pair with it, and the mask of views within 2 dot_err
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
-        bool ok = j < n_views;
-        if (ok && qwords != nullptr) {
-          bool hit = false;
-          for (int a2 = 0; a2 < ma; ++a2) hit |= vw[j * ma + a2] == wq;
-          ok = hit;
-        }
-        if (ok) {
-          valid |= 1u << (bi * 16 + e);
-          mx = fmaxf(mx, tot[bi][e]);
+    for (int cj = 0; cj < 2; ++cj) {
+      const int i = cj * 32 + l32;
+      unsigned long long allowed = n_views >= 64 ? ~0ull : (1ull << n_views) - 1ull;
+      if (qwords != nullptr) {
+        allowed = 0ull;
+        if (mine && i < mi) {
+          const int wq = qwords[q0 + it * 64 + i];
+          for (int j = 0; j < n_views; ++j)
+            for (int a2 = 0; a2 < ma; ++a2)
+              if (vw[wave][j * ma + a2] == wq) allowed |= 1ull << j;
         }
       }
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-    unsigned long long bits = 0ull;
+      float mx = -INFINITY;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
-        if (((valid >> (bi * 16 + e)) & 1u) && tot[bi][e] >= mx - 2.f * dot_err)
-          bits |= 1ull << j;
-      }
-    const unsigned lo_b = (unsigned)bits, hi_b = (unsigned)(bits >> 32);
-    bits |= (unsigned long long)__shfl_xor(lo_b, 32, 64) |
-            ((unsigned long long)__shfl_xor(hi_b, 32, 64) << 32);
-    if (half == 0) jmask[i] = i < mi ? bits : 0ull;
-    __syncthreads();
-    // compensated maximum per query view: one wave per view.  Lane l
-    // takes the float4 pieces l, l + 64, ... of the rows, 4 pieces of each
-    // row in flight per batch (dim is a multiple of 32, so the piece count
-    // is a multiple of 8).
-    const int n4 = dim >> 2;
-    for (int iv = wave; iv < mi; iv += 2) {
-      const float4* q4 = reinterpret_cast<const float4*>(qbase + (int64_t)iv * dim);
-      unsigned long long bb = jmask[iv];
+        for (int e = 0; e < 16; ++e) {
+          const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+          if ((allowed >> j) & 1ull) mx = fmaxf(mx, tot[bi][cj][e]);
+        }
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      unsigned long long bits = 0ull;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int j = bi * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+          if (((allowed >> j) & 1ull) && tot[bi][cj][e] >= mx - 2.f * dot_err) bits |= 1ull << j;
+        }
+      const unsigned lo_b = (unsigned)bits, hi_b = (unsigned)(bits >> 32);
+      bits |= (unsigned long long)__shfl_xor(lo_b, 32, 64) |
+              ((unsigned long long)__shfl_xor(hi_b, 32, 64) << 32);
+      if (half == 0 && mine && i < mi) wmask[it * 64 + i] = bits;
+    }
+  }
+}
+
+// Candidate rescore, phases 2 and 3 (rescore_exact_kernel): one block (four
+// waves) per (query, candidate), blocks in XCD-contiguous order.  Every
+// masked pair (q_i, p_j) is re-evaluated with the compensated dot product
+// and the exact maximum kept (wave w takes query views w, w + 4, ...); the
+// block then forms the compensated mean over the query views in ascending
+// order.  A query view with an empty mask contributes 0.  Lane l takes the
+// float4 pieces l, l + 64, ... of both rows; a 4096-value row pair is one
+// batch of 16 + 16 loads in flight per lane, summed in two independent
+// compensated chains.
+__global__ __launch_bounds__(256) void rescore_exact_kernel(
+    const float* __restrict__ master, int n_views, int dim,
+    const float* __restrict__ qviews, const int32_t* __restrict__ qoff, int n_queries,
+    const int32_t* __restrict__ cand, int r, const unsigned long long* __restrict__ mask,
+    int64_t mask_ld, const int32_t* __restrict__ active,
+    float* __restrict__ s_hi, float* __restrict__ s_lo) {
+  __shared__ float mff_hi[64], mff_lo[64];
+  const int64_t n_pairs = (int64_t)(active != nullptr ? *active : n_queries) * r;
+  const int64_t pair = xcd_contiguous(blockIdx.x, n_pairs);
+  if (pair >= n_pairs) return;  // past the batch
+  const int b = (int)(pair / r);
+  const int q0 = qoff[b], m = qoff[b + 1] - q0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* pbase = master + (int64_t)cand[pair] * n_views * dim;
+  const unsigned long long* pmask = mask + (pair - (int64_t)b * r) * mask_ld + q0;
+  const int n4 = dim >> 2;
+  ff acc = {0.f, 0.f};
+  for (int it = 0; it * 64 < m; ++it) {
+    const int mi = min(64, m - it * 64);
+    for (int iv = wave; iv < mi; iv += 4) {
+      const float* qrow = qviews + (int64_t)(q0 + it * 64 + iv) * dim;
+      const gptr<uint8_t> q4 = uniform_gptr(reinterpret_cast<const uint8_t*>(qrow));
+      unsigned long long bb = pmask[it * 64 + iv];
       ff best = {-INFINITY, 0.f};
       while (bb) {
         const int j = __builtin_ctzll(bb);
         bb &= bb - 1;
-        const float4* p4 = reinterpret_cast<const float4*>(pbase + (int64_t)j * dim);
-        float s = 0.f, c = 0.f;
-        for (int u0 = lane; u0 < n4; u0 += 64 * 4) {
-          float4 qa[4], pa[4];
+        const gptr<uint8_t> p4 = uniform_gptr(reinterpret_cast<const uint8_t*>(pbase + (int64_t)j * dim));
+        float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f;
+        for (int u0 = lane; u0 < n4; u0 += 64 * P2_BATCH) {
+          float4 qa[P2_BATCH], pa[P2_BATCH];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int u = u0 + 64 * k;
-            qa[k] = u < n4 ? q4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-            pa[k] = u < n4 ? p4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+          for (int k = 0; k < P2_BATCH; ++k) {
+            const uint32_t u = (uint32_t)(u0 + 64 * k);
+            qa[k] = u < (uint32_t)n4 ? load_at<float4>(q4, u * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
+            pa[k] = u < (uint32_t)n4 ? load_at<float4>(p4, u * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
           }
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            dot2_step(qa[k].x, pa[k].x, s, c);
-            dot2_step(qa[k].y, pa[k].y, s, c);
-            dot2_step(qa[k].z, pa[k].z, s, c);
-            dot2_step(qa[k].w, pa[k].w, s, c);
+          for (int k = 0; k < P2_BATCH; k += 2) {
+            dot2_step(qa[k].x, pa[k].x, s0, c0);
+            dot2_step(qa[k + 1].x, pa[k + 1].x, s1, c1);
+            dot2_step(qa[k].y, pa[k].y, s0, c0);
+            dot2_step(qa[k + 1].y, pa[k + 1].y, s1, c1);
+            dot2_step(qa[k].z, pa[k].z, s0, c0);
+            dot2_step(qa[k + 1].z, pa[k + 1].z, s1, c1);
+            dot2_step(qa[k].w, pa[k].w, s0, c0);
+            dot2_step(qa[k + 1].w, pa[k + 1].w, s1, c1);
           }
         }
-        const ff v = ff_wave_sum(s, c);
+        float s, e;
+        two_sum(s0, s1, s, e);
+        const ff v = ff_wave_sum(s, (c0 + c1) + e);
         if (ff_gt(v, best)) best = v;
       }
       if (best.hi == -INFINITY) best = ff{0.f, 0.f};  // no matching view
       if (lane == 0) { mff_hi[iv] = best.hi; mff_lo[iv] = best.lo; }
     }
     __syncthreads();
-    if (tid == 0) {
-      ff acc = {tot_hi, tot_lo};
+    if (threadIdx.x == 0)
       for (int iv = 0; iv < mi; ++iv) acc = ff_add(acc, ff{mff_hi[iv], mff_lo[iv]});
-      tot_hi = acc.hi;
-      tot_lo = acc.lo;
-    }
     __syncthreads();
   }
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     ff res = {0.f, 0.f};
-    if (m > 0) res = ff_div_int(ff{tot_hi, tot_lo}, m);
-    s_hi[bc] = res.hi;
-    s_lo[bc] = res.lo;
+    if (m > 0) res = ff_div_int(acc, m);
+    s_hi[pair] = res.hi;
+    s_lo[pair] = res.lo;
   }
 }
 
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
-                    int max_m, const int32_t* cand, int r, float dot_err,
+                    int64_t total_views, const int32_t* cand, int r, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, float* s_hi, float* s_lo, hipStream_t st) {
-  (void)max_m;
-  const int64_t blocks = (int64_t)n_queries * r;
-  if (blocks <= 0) return;
-  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)blocks), dim3(128), 0, st,
-                     master, n_views, dim, qviews, qoff, cand, r, dot_err,
-                     qwords, view_words, ma, active, s_hi, s_lo);
+                    const int32_t* active, unsigned long long* mask, float* s_hi, float* s_lo,
+                    hipStream_t st) {
+  const int64_t items = (int64_t)n_queries * ((r + RS_CANDS - 1) / RS_CANDS);
+  if (items <= 0) return;
+  // grids cover every slot of the XCD-contiguous order
+  hipLaunchKernelGGL(rescore_mask_kernel, dim3((unsigned)((items + 7) / 8 * 8)), dim3(RS_THREADS),
+                     0, st, master, n_views, dim, qviews, qoff, n_queries, cand, r,
+                     dot_err, qwords, view_words, ma, active, mask, total_views);
+  const int64_t pairs = (int64_t)n_queries * r;
+  hipLaunchKernelGGL(rescore_exact_kernel, dim3((unsigned)((pairs + 7) / 8 * 8)), dim3(256), 0, st,
+                     master, n_views, dim, qviews, qoff, n_queries, cand, r, mask, total_views,
+                     active, s_hi, s_lo);
 }
 
 // ------------------------------------------------------------------ final
