@@ -516,10 +516,10 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 }
 
 // One block per list tile of 128 entries and the batch's query views whose
-// word is that list: MFMA dots (entries x query views), the per-shape
-// maximum over the tile's entries (entries of a shape are contiguous), and
-// an atomic max into mbuf[query view][shape] (row stride ldn; 0 = no
-// matching view yet).
+// word is that list: MFMA dots (entries x query views, 128 x 128 tiles, or
+// one 128 x 32 tile for up to 32 query views), the per-shape maximum over
+// the tile's entries (entries of a shape are contiguous), and an atomic max
+// into mbuf[query view][shape] (row stride ldn; 0 = no matching view yet).
 // Tile b of list w (tile_off[w] <= b < tile_off[w + 1]).
 // Scales: per-view float32 (BF16 / e4m3) or E8M0 rows (MX), null for float32.
 template <int DT>
@@ -543,6 +543,68 @@ __device__ __forceinline__ void scan_list_tile(
   float* C = reinterpret_cast<float*>(lds);  // [128][129] after the main loop
   const int wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
+
+  // Per-shape maximum over this tile's entries for column c (rows [rbeg,
+  // rend) of C, row stride ld), folded into mbuf for query view qi.
+  auto fold = [&](int c, int ld, int rbeg, int rend, int qi) {
+    const float cs = SCALED ? q_scale[qi] : 1.f;
+    int cur = -1;
+    float m = -INFINITY;
+    for (int r = rbeg; r < rend; ++r) {
+      const int shp = ent_shape[e0 + r];
+      if (shp != cur) {
+        if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
+        cur = shp;
+        m = -INFINITY;
+      }
+      m = fmaxf(m, C[r * ld + c]);
+    }
+    if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
+  };
+
+  if constexpr (!MX) {
+    // up to 32 query views: one 128 x 32 tile instead of 128 x 128 mostly padding
+    if (g1 - g0 <= NarrowShape::BN) {
+      using N = NarrowShape;
+      const uint8_t* src[N::LOADS];
+#pragma unroll
+      for (int it = 0; it < N::LOADS; ++it) {
+        const int r = staged_row(it);
+        const uint8_t* p = nullptr;
+        if (r < N::BM) {
+          if (r < ne) {
+            const int64_t e = e0 + r;
+            p = db + ((int64_t)ent_shape[e] * n_views + ent_view[e]) * (int64_t)row_bytes;
+          }
+        } else if (g0 + (r - N::BM) < g1) {
+          p = qv + (int64_t)gitems[g0 + (r - N::BM)] * row_bytes;
+        }
+        src[it] = p;
+      }
+      f32x16 acc;
+      mfma_tile_mainloop_narrow<DT>(lds, src, row_bytes, acc);
+      constexpr int LD = N::BN + 1;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = wave * 32 + acc_row(0, e);
+        float v = acc[e];
+        if (SCALED && r < ne) {
+          const int64_t en = e0 + r;
+          v *= db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
+        }
+        C[r * LD + acc_col(0)] = v;
+      }
+      __syncthreads();
+      // 32 columns x 8 segments of 16 rows
+      const int c = threadIdx.x & 31, seg = threadIdx.x >> 5;
+      if (g0 + c < g1) {
+        const int rbeg = seg * 16, rend = rbeg + 16 < ne ? rbeg + 16 : ne;
+        fold(c, LD, rbeg, rend, gitems[g0 + c]);
+      }
+      __syncthreads();
+      return;
+    }
+  }
 
   for (int64_t c0 = g0; c0 < g1; c0 += T::BN) {
     const uint8_t* src[T::LOADS];
@@ -606,24 +668,9 @@ __device__ __forceinline__ void scan_list_tile(
     {
       const int c = threadIdx.x & 127;
       const int half = threadIdx.x >> 7;
-      const int64_t cg = c0 + c;
-      if (cg < g1) {
-        const int qi = gitems[cg];
-        const float cs = SCALED ? q_scale[qi] : 1.f;
-        const int rbeg = half * 64;
-        const int rend = rbeg + 64 < ne ? rbeg + 64 : ne;
-        int cur = -1;
-        float m = -INFINITY;
-        for (int r = rbeg; r < rend; ++r) {
-          const int shp = ent_shape[e0 + r];
-          if (shp != cur) {
-            if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
-            cur = shp;
-            m = -INFINITY;
-          }
-          m = fmaxf(m, C[r * 129 + c]);
-        }
-        if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
+      if (c0 + c < g1) {
+        const int rbeg = half * 64, rend = rbeg + 64 < ne ? rbeg + 64 : ne;
+        fold(c, 129, rbeg, rend, gitems[c0 + c]);
       }
     }
     __syncthreads();

@@ -144,6 +144,62 @@ __device__ __forceinline__ void mfma_tile_mainloop(
   __syncthreads();  // LDS may be reused by the caller's epilogue
 }
 
+// Narrow tile for small query-view groups: 128 rows x 32 columns, wave w
+// owning rows 32w..32w+31 (one 32 x 32 block); staged rows 0..127 are the A
+// side, 128..159 the B side, loaded as in mfma_tile_mainloop.
+struct NarrowShape {
+  static constexpr int BM = 128;
+  static constexpr int BN = 32;
+  static constexpr int ROWS = BM + BN;
+  static constexpr int LOADS = ROWS * 8 / 256;
+  static constexpr size_t LDS_BYTES = (size_t)ROWS * LROW;
+};
+
+template <int DT>
+__device__ __forceinline__ void mfma_tile_mainloop_narrow(
+    uint8_t* lds, const uint8_t* const (&src)[NarrowShape::LOADS], int row_bytes, f32x16& acc) {
+  using T = NarrowShape;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  const int n_kt = (row_bytes + 127) / 128;
+  uint4 pre[T::LOADS];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
+      if (src[it] != nullptr && off < row_bytes)
+        pre[it] = *reinterpret_cast<const uint4*>(src[it] + off);
+      else
+        pre[it] = make_uint4(0, 0, 0, 0);
+    }
+  };
+  gload(0);
+  const uint8_t* arow = lds + (wave * 32 + l32) * LROW + half * 64;
+  const uint8_t* brow = lds + (T::BM + l32) * LROW + half * 64;
+  for (int kt = 0; kt < n_kt; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int idx = tid + 256 * it;
+      *reinterpret_cast<uint4*>(lds + (idx >> 3) * LROW + (idx & 7) * 16) = pre[it];
+    }
+    __syncthreads();
+    if (kt + 1 < n_kt) gload(kt + 1);
+    uint4 a[4], b[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      b[s2] = *reinterpret_cast<const uint4*>(brow + s2 * 16);
+      a[s2] = *reinterpret_cast<const uint4*>(arow + s2 * 16);
+    }
+    Mfma<DT>::run(a, b, acc);
+  }
+  __syncthreads();  // LDS may be reused by the caller's epilogue
+}
+
 // Same tile with two LDS stages and global loads issued two K-tiles ahead
 // (two register sets), so one barrier per K-tile and about two K-tiles of
 // MFMA work to hide each load.  Needs 2 * LDS_BYTES of shared memory.
