@@ -8,7 +8,8 @@
 namespace gift {
 
 // ------------------------------------------------------------------ GEMM
-// D[r - r0][k] = x_r . b_k in float32 on MFMA (128 x 128 block tiles).
+// D[r - r0][k] ~ x_r . b_k in split-BF16 on MFMA (128 x 128 block tiles),
+// within (3.02 * 2^-16 + 1.02 gamma(6 * 17 + dim / 32 + 2)) ||x_r|| ||b_k||.
 __device__ __forceinline__ void dots_tile(const float* __restrict__ x, int64_t r0, int64_t r1,
                           const float* __restrict__ cb, int K, int dim, float* __restrict__ D,
                           int64_t row_tile, int64_t col_tile, uint8_t* lds) {
@@ -30,7 +31,7 @@ __device__ __forceinline__ void dots_tile(const float* __restrict__ x, int64_t r
     src[it] = p;
   }
   f32x16 acc[2][2];
-  mfma_tile_mainloop<GIFT_F32, 2, 2>(lds, src, row_bytes, acc);
+  mfma_tile_mainloop_split<2, 2>(lds, src, row_bytes, acc);
   const int wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 #pragma unroll
@@ -284,9 +285,7 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
     const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(dots_kernel), T::LDS_BYTES);
     if (s != GIFT_OK) return s;
   }
-  // accumulation depth of the MFMA dot: dim/2 steps, charged 2 roundings each
-  const double u = 5.9604644775390625e-08, nn = 2.0 * dim + 4;
-  const float gamma2 = (float)(2.0 * (nn * u / (1 - nn * u)) * 1.001);
+  const float gamma2 = assign_gamma2(dim);
   const int64_t n_col_tiles = (K + T::BN - 1) / T::BN;
   for (int64_t r0 = 0; r0 < n; r0 += chunk_rows) {
     const int64_t r1 = r0 + chunk_rows < n ? r0 + chunk_rows : n;
@@ -1125,9 +1124,11 @@ gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64
   return GIFT_OK;
 }
 
+// Twice (d^_k carries -2 x.b_k) the split-BF16 dot bound of dots_tile,
+// per unit of ||x|| ||b_k||.
 float assign_gamma2(int dim) {
-  const double u = 5.9604644775390625e-08, nn = 2.0 * dim + 4;
-  return (float)(2.0 * (nn * u / (1 - nn * u)) * 1.001);
+  const double u = 5.9604644775390625e-08, nn = 6.0 * 17 + dim / 32 + 2;
+  return (float)(2.0 * (3.02 / 65536.0 + 1.02 * (nn * u / (1 - nn * u))) * 1.001);
 }
 
 }  // namespace gift

@@ -144,6 +144,115 @@ __device__ __forceinline__ void mfma_tile_mainloop(
   __syncthreads();  // LDS may be reused by the caller's epilogue
 }
 
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in
+// float32), |r| <= 2^-16 |x|; four floats at a time, packed two per word.
+// Both roundings are the hardware's round-to-nearest-even pair conversion.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+__device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
+  const float x0 = __builtin_bit_cast(float, v.x), x1 = __builtin_bit_cast(float, v.y);
+  const float x2 = __builtin_bit_cast(float, v.z), x3 = __builtin_bit_cast(float, v.w);
+  const uint32_t h01 = bf16_pair(x0, x1), h23 = bf16_pair(x2, x3);
+  const float r0 = x0 - __builtin_bit_cast(float, h01 << 16);
+  const float r1 = x1 - __builtin_bit_cast(float, h01 & 0xffff0000u);
+  const float r2 = x2 - __builtin_bit_cast(float, h23 << 16);
+  const float r3 = x3 - __builtin_bit_cast(float, h23 & 0xffff0000u);
+  hi = make_uint2(h01, h23);
+  lo = make_uint2(bf16_pair(r0, r1), bf16_pair(r2, r3));
+}
+
+// Float32 tile product in split-BF16: each value x = hi + lo + r (above),
+// the dot taken as hi.hi' + hi.lo' + lo.hi' on BF16 MFMA.  Same tiles and
+// staging as mfma_tile_mainloop<GIFT_F32> (32 values = 128 bytes per row
+// per K-tile), but each staged piece is split on its way to LDS (32 high
+// parts, then 32 low parts per row) and each K-tile's 6 MFMAs per block go
+// into a fresh register block added into the running total, which bounds
+// the float32 accumulation depth: the result is within (3.02 * 2^-16 +
+// 1.02 gamma(6 * 17 + K-tiles + 2)) sum |x y| of the exact dot.
+template <int WM, int WN>
+__device__ __forceinline__ void mfma_tile_mainloop_split(
+    uint8_t* lds, const uint8_t* const (&src)[TileShape<WM, WN>::LOADS], int row_bytes,
+    f32x16 (&acc)[WM][WN]) {
+  using T = TileShape<WM, WN>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5, l32 = lane & 31;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  const int n_kt = row_bytes / 128;  // rows of 32k float32 values
+  uint4 pre[T::LOADS];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
+      pre[it] = src[it] != nullptr ? *reinterpret_cast<const uint4*>(src[it] + off)
+                                   : make_uint4(0, 0, 0, 0);
+    }
+  };
+  gload(0);
+  // lane half h supplies values [16h, 16h + 16) of the K-tile in two steps
+  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 32;
+  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + half * 32;
+  for (int kt = 0; kt < n_kt; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < T::LOADS; ++it) {
+      const int idx = tid + 256 * it;
+      uint2 hi, lo;
+      split_bf16x4(pre[it], hi, lo);
+      uint8_t* row = lds + (idx >> 3) * LROW + (idx & 7) * 8;
+      *reinterpret_cast<uint2*>(row) = hi;
+      *reinterpret_cast<uint2*>(row + 64) = lo;
+    }
+    __syncthreads();
+    if (kt + 1 < n_kt) gload(kt + 1);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      uint4 bh[2], bl[2];
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        bh[st] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + st * 16);
+        bl[st] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + 64 + st * 16);
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        uint4 ah[2], al[2];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          ah[st] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + st * 16);
+          al[st] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + 64 + st * 16);
+        }
+        f32x16 part;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[e] = 0.f;
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bl[st]), part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][j][e] += part[e];
+      }
+    }
+  }
+  __syncthreads();  // LDS may be reused by the caller's epilogue
+}
+
 // Narrow tile for small query-view groups: 128 rows x 32 columns, wave w
 // owning rows 32w..32w+31 (one 32 x 32 block); staged rows 0..127 are the A
 // side, 128..159 the B side, loaded as in mfma_tile_mainloop.

@@ -158,28 +158,6 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r, const in
 }
 
 // ------------------------------------------------------------------ rescore
-// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in
-// float32), |r| <= 2^-16 |x|; four floats at a time, packed two per word.
-// Both roundings are the hardware's round-to-nearest-even pair conversion.
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
-}
-
-__device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
-  const float x0 = __builtin_bit_cast(float, v.x), x1 = __builtin_bit_cast(float, v.y);
-  const float x2 = __builtin_bit_cast(float, v.z), x3 = __builtin_bit_cast(float, v.w);
-  const uint32_t h01 = bf16_pair(x0, x1), h23 = bf16_pair(x2, x3);
-  const float r0 = x0 - __builtin_bit_cast(float, h01 << 16);
-  const float r1 = x1 - __builtin_bit_cast(float, h01 & 0xffff0000u);
-  const float r2 = x2 - __builtin_bit_cast(float, h23 << 16);
-  const float r3 = x3 - __builtin_bit_cast(float, h23 & 0xffff0000u);
-  hi = make_uint2(h01, h23);
-  lo = make_uint2(bf16_pair(r0, r1), bf16_pair(r2, r3));
-}
-
 // Pairs handled by block `blk` when the chip runs blocks round-robin over its
 // 8 XCDs: XCD x takes the contiguous pair range [x c, x c + c), c = ceil(n / 8),
 // so the blocks running together on one XCD (and its L2) share a query.
