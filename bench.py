@@ -59,7 +59,8 @@ def main():
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
     ap.add_argument("--fif-steps", type=int, default=5)
     ap.add_argument("--kmeans-iters", type=int, default=10)
-    ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy", "sweep"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy", "peaks", "sweep"],
+                    default="c3",
                     help="c3: exhaustive precision headline (default); c4: batched F-IF + "
                          "S-IF plan; c5: continuous-batching serving")
     ap.add_argument("--tune", default="",
@@ -98,6 +99,9 @@ def main():
         dt = time.perf_counter() - t0
         print(json.dumps({"workload": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
                           "copies": args.steps + 1, "GBps": round(8 * n / dt / 1e9, 1)}))
+        return
+    if args.workload == "peaks":
+        print(json.dumps(peaks_bench(args)))
         return
     if args.workload in ("c4", "c5"):
         print(json.dumps(scale_bench(args)))
@@ -281,6 +285,66 @@ def main():
         result["recall"]["fp32_path_ids_equal_fp64_oracle_sample"] = bool(
             np.array_equal(exact_ids[:ns], ids64))
     print(json.dumps(result))
+
+
+# Vendor dense peaks of MI355X (TFLOP/s) and the probe's flop per MFMA.
+_VENDOR_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+_PROBE_FLOP = {"f32": 4096, "bf16": 32768, "fp8": 131072}
+
+
+def peaks_bench(args):
+    """Measured ceilings beside the vendor figures: a 4 GiB device copy
+    (HBM) and the MFMA rate probe per dtype (all CUs, 2 blocks of 4 waves
+    each, 8 independent 32 x 32 MFMA chains per wave), with the shader and
+    wall clock counters read around the probe loop."""
+    import torch
+    from paper_1604_01879_amd import _lib as L
+    dev = torch.device("cuda:0")
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 8.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    out = {"workload": "peaks", "hbm_copy_GBps": round(copy_gbps, 1), "hbm_vendor_GBps": 8000.0,
+           "mfma": {}}
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 2 * n_cu
+    dts = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}
+    for name, dt in dts.items():
+        iters = 2000
+        for _ in range(3):  # grow iters until one launch takes >= 50 ms
+            L.gift_probe_mfma(dt, blocks, iters)
+            e0.record()
+            sink, clocks, wall_khz = L.gift_probe_mfma(dt, blocks, iters)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            if ms >= 50.0:
+                break
+            iters = int(iters * 60.0 / max(ms, 0.01)) + 1
+        flop = blocks * 4.0 * iters * 8 * _PROBE_FLOP[name]
+        tf = flop / (ms * 1e-3) / 1e12
+        ck = clocks.cpu().numpy()
+        out["mfma"][name] = {
+            "TFLOPs": round(tf, 1), "vendor_TFLOPs": _VENDOR_TFLOPS[name],
+            "frac_of_vendor": round(tf / _VENDOR_TFLOPS[name], 4), "ms": round(ms, 3),
+            "iters": iters, "blocks": blocks,
+            "shader_clock_MHz": round(float(np.median(ck[:, 0] / ck[:, 1])) * wall_khz / 1e3, 1),
+            "wall_clock_MHz": wall_khz / 1e3,
+            "checksum": float(sink.double().sum().item())}
+        log(f"probe {name}: {tf:.1f} TFLOP/s ({tf / _VENDOR_TFLOPS[name]:.3f} of vendor)")
+    out["note"] = ("shader_clock_MHz: median over blocks of the clock64 / wall_clock64 "
+                   "deltas around the probe loop times the wall clock rate")
+    return out
 
 
 def _resident_db(w, torch, L, dtype):

@@ -401,6 +401,23 @@ gift_status gift_profile_reset(void);
 gift_status gift_profile_read(int32_t tag, double* total_ms, int32_t* count);
 const char* gift_profile_tag_name(int32_t tag);
 
+/* ---------------------------------------------------------------------- */
+/* Measurement probe (not part of the search path): the sustained rate of */
+/* one 32 x 32 MFMA kind.  Launches `blocks` blocks of 4 waves; each wave */
+/* issues `iters` rounds of 8 independent MFMAs of dtype GIFT_F32         */
+/* (32x32x2, 4096 flop each), GIFT_BF16 (32x32x16, 32768 flop) or         */
+/* GIFT_FP8E4M3 (32x32x64 e4m3, 131072 flop), on `stream`.  Writes each   */
+/* thread's accumulator sum to sink (device, blocks * 256 floats) and, per */
+/* block, the clock64() and wall_clock64() deltas of its first wave to    */
+/* clocks (device, 2 * blocks), and the wall clock's rate in kHz to       */
+/* *wall_khz (host), so delta[0] / delta[1] * wall_khz is the shader      */
+/* clock in kHz over that block's loop.  Time the launch with events on   */
+/* the same stream.  GIFT_EINVAL for another dtype, a non-positive count  */
+/* or a null pointer.                                                     */
+/* ---------------------------------------------------------------------- */
+gift_status gift_probe_mfma(int32_t dtype, int32_t blocks, int32_t iters, float* sink,
+                            uint64_t* clocks, int32_t* wall_khz, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

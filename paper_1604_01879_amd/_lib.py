@@ -106,6 +106,8 @@ _sig = {
     "gift_profile_reset": (C.c_int32, []),
     "gift_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "gift_profile_tag_name": (C.c_char_p, [C.c_int32]),
+    "gift_probe_mfma": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, _P, _P,
+                                    C.POINTER(C.c_int32), _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -228,6 +230,19 @@ def gift_profile_enable(capacity: int):
 
 def gift_profile_reset():
     _check(_lib.gift_profile_reset())
+
+
+def gift_probe_mfma(dtype: int, blocks: int, iters: int, stream=None):
+    """Launches the MFMA rate probe; returns (sink, clocks, wall_khz): device
+    tensors (clocks: [blocks, 2] int64 of clock64 and wall_clock64 deltas)
+    and the wall clock's rate in kHz."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    clocks = torch.empty((blocks, 2), dtype=torch.int64, device=dev)
+    khz = C.c_int32(0)
+    _check(_lib.gift_probe_mfma(dtype, blocks, iters, _ptr(sink), _ptr(clocks), C.byref(khz),
+                                _stream(stream)))
+    return sink, clocks, khz.value
 
 
 def gift_profile_read(tag: str):

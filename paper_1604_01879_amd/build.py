@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgift.so")
-SOURCES = ["api.hip", "score.hip", "rank.hip", "fif.hip", "sif.hip", "plan.hip"]
+SOURCES = ["api.hip", "score.hip", "rank.hip", "fif.hip", "sif.hip", "plan.hip", "probe.hip"]
 
 
 def hipcc() -> str:
