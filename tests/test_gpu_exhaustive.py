@@ -112,7 +112,7 @@ def test_first_pass_scores(L, dtype_name):
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
-@pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views"])
+@pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views", "many-query-views"])
 def test_query_exhaustive_ranked_ids(L, dtype_name, case):
     _say(f"query_exhaustive {dtype_name} {case}")
     if case == "c1-like":
@@ -121,9 +121,14 @@ def test_query_exhaustive_ranked_ids(L, dtype_name, case):
     elif case == "ragged":
         w, db, q, qoff = _data(N=257, dim=160, B=7, m=(1, 64), seed=3)
         k, R = 20, 257  # R = N: every shape rescored
-    else:
+    elif case == "few-views":
         w, db, q, qoff = _data(N=90, dim=64, B=3, m=(5, 40), nv=7, seed=5)
         k, R = 15, 40
+    else:
+        # queries of 65..150 views (rescored in chunks of 64), 33 views per
+        # shape, a candidate count that leaves a partial group of candidates
+        w, db, q, qoff = _data(N=120, dim=96, B=4, m=(65, 150), nv=33, seed=9)
+        k, R = 12, 23
     dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
     V, _, _ = _views(L, db, w.n_views, dt)
     Q = _queries(L, q, qoff)

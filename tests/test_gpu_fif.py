@@ -152,6 +152,29 @@ def test_first_pass_fif_scores(L, dtype_name):
     assert np.allclose(S.cpu().numpy(), ref, rtol=REL, atol=1e-6)
 
 
+@pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
+@pytest.mark.parametrize("n_group", [31, 32, 33, 130])
+def test_scan_group_sizes_around_narrow_tile(L, dtype_name, n_group):
+    """One word (K = 1) puts every query view of the batch in one group: up
+    to 32 views take the 128 x 32 scan tile, more the 128 x 128 tiles (130
+    views: two column passes, the second of 2 views)."""
+    _say(f"fif group of {n_group} {dtype_name}")
+    dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]
+    w = _wl(n_shapes=70, dim=96, n_queries=1, m_lo=n_group, m_hi=n_group, n_views=19)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 1, 1, dt)
+    S, qw = L.gift_score_fif(V, F, Q)
+    torch.cuda.synchronize()
+    assert int(qoff[-1]) == n_group and (qw.cpu().numpy() == 0).all()
+    if dtype_name == "f32":
+        ref = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    else:
+        qc, qs = O.quantize_views(q, dtype_name)
+        dc, ds = O.quantize_views(db, dtype_name)
+        ref = O.fif_scores(O.dequantize(qc, qs), qoff, O.dequantize(dc, ds), w.n_views, cb,
+                           off, es, ev, qwords=qw.cpu().numpy())
+    assert np.allclose(S.cpu().numpy(), ref, rtol=REL, atol=1e-6)
+
+
 @pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
 def test_first_pass_fif_scores_mx(L, fmt):
     """MX block-scaled list payloads: the first pass equals Eq. 4 over the
