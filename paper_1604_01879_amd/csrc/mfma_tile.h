@@ -534,13 +534,16 @@ __device__ __forceinline__ void mfma_tile_mainloop_mx(
 constexpr int DMA_KSUB = 64;
 constexpr int DMA_STAGES = 4;
 
-template <int WM, int WN>
+// 2 x WC waves per block: wave w owns rows (w / WC) * WM * 32 .. + WM * 32
+// and columns (w % WC) * WN * 32 .. + WN * 32.
+template <int WM, int WN, int WC = 2>
 struct DmaShape {
+  static constexpr int WAVES = 2 * WC;
   static constexpr int BM = 64 * WM;
-  static constexpr int BN = 64 * WN;
+  static constexpr int BN = 32 * WC * WN;
   static constexpr int ROWS = BM + BN;
-  static constexpr int WROWS = ROWS / 4;  // rows staged by each wave
-  static constexpr int NI = WROWS / 16;   // 16-byte loads per lane per sub-tile
+  static constexpr int WROWS = ROWS / WAVES;  // rows staged by each wave
+  static constexpr int NI = WROWS / 16;       // 16-byte loads per lane per sub-tile
   static constexpr int STAGE_BYTES = ROWS * DMA_KSUB;
   static constexpr size_t LDS_BYTES = (size_t)DMA_STAGES * STAGE_BYTES;
 };
@@ -558,16 +561,16 @@ __device__ __forceinline__ void wait_vm_barrier() {
   __syncthreads();
 }
 
-template <int DT, int WM, int WN>
+template <int DT, int WM, int WN, int WC = 2>
 __device__ __forceinline__ void mfma_tile_mainloop_dma(
     uint8_t* lds, const uint8_t* base_a, const uint8_t* base_b,
-    const uint32_t (&roff)[DmaShape<WM, WN>::NI], int row_bytes, f32x16 (&acc)[WM][WN]) {
-  using T = DmaShape<WM, WN>;
+    const uint32_t (&roff)[DmaShape<WM, WN, WC>::NI], int row_bytes, f32x16 (&acc)[WM][WN]) {
+  using T = DmaShape<WM, WN, WC>;
   static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int half = lane >> 5, l32 = lane & 31;
 
 #pragma unroll
@@ -702,6 +705,132 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma(
       mfmas(kt + 1, 1);
     } else {
       mfmas(kt, 0);
+    }
+  }
+  wait_vm_barrier<0>();  // LDS may be reused by the caller
+}
+
+// ---------------------------------------------------------- DMA loop, K128
+// The same direct global->LDS tile with 128-byte sub-tiles (a whole L2 line
+// of each row per sub-tile, so each line is requested once instead of once
+// per 64-byte half) and two LDS stages: sub-tile kt + 1 is loaded while the
+// MFMAs of kt run, one barrier per 128 bytes of K.  A wave's 16-byte load
+// writes 64 consecutive LDS chunks, i.e. 8 rows of 128 bytes; chunk slot s
+// of row r holds the row's chunk s ^ dma2_swizzle(r), so any 8 or 16
+// consecutive rows read at one logical chunk fall in distinct 16-byte bank
+// groups.  row_bytes must be a multiple of 128.  Lane l stages rows
+// wave * WROWS + 8 i + l / 8 (i < NI), at base_a + roff[i] below BM and
+// base_b + roff[i] above (an 8-row group never straddles BM).
+constexpr int DMA2_KSUB = 128;
+
+__device__ __forceinline__ int dma2_swizzle(int r) { return (r & 7) ^ ((r >> 3) & 3); }
+
+template <int WM, int WN, int WC = 2>
+struct Dma2Shape {
+  static constexpr int WAVES = 2 * WC;
+  static constexpr int BM = 64 * WM;
+  static constexpr int BN = 32 * WC * WN;
+  static constexpr int ROWS = BM + BN;
+  static constexpr int WROWS = ROWS / WAVES;  // rows staged by each wave
+  static constexpr int NI = WROWS / 8;        // 16-byte loads per lane per sub-tile
+  static constexpr int STAGE_BYTES = ROWS * DMA2_KSUB;
+  static constexpr size_t LDS_BYTES = 2 * (size_t)STAGE_BYTES;
+};
+
+template <int DT, int WM, int WN, int WC = 2>
+__device__ __forceinline__ void mfma_tile_mainloop_dma128(
+    uint8_t* lds, const uint8_t* base_a, const uint8_t* base_b,
+    const uint32_t (&roff)[Dma2Shape<WM, WN, WC>::NI], int row_bytes, f32x16 (&acc)[WM][WN]) {
+  using T = Dma2Shape<WM, WN, WC>;
+  static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int half = lane >> 5, l32 = lane & 31;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int n_kt = row_bytes / DMA2_KSUB;
+  lds_u8* l3 = (lds_u8*)lds;
+  uint32_t goff[T::NI];
+#pragma unroll
+  for (int i = 0; i < T::NI; ++i) {
+    const int r = wave * T::WROWS + 8 * i + (lane >> 3);
+    goff[i] = roff[i] + (uint32_t)(((lane & 7) ^ dma2_swizzle(r)) * 16);
+  }
+  const uint32_t wave_lds = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (int)(uint32_t)(uintptr_t)(l3 + wave * T::WROWS * DMA2_KSUB));
+  auto issue = [&](int kt) {
+    const uint32_t base = wave_lds + (uint32_t)((kt & 1) * T::STAGE_BYTES);
+    const uint8_t* ga = base_a + kt * DMA2_KSUB;
+    const uint8_t* gb = base_b + kt * DMA2_KSUB;
+#pragma unroll
+    for (int i = 0; i < T::NI; ++i) {
+      const bool a_side = wave * T::WROWS + 8 * i < T::BM;  // uniform in the wave
+      const uint64_t gv = (uint64_t)(uintptr_t)(a_side ? ga : gb);
+      const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv >> 32)) << 32) |
+                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv);
+      asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                   :
+                   : "v"(goff[i]), "s"(g), "s"(base + (uint32_t)(i * 8 * DMA2_KSUB))
+                   : "memory", "m0");
+    }
+  };
+  // operand rows all have l32 as their low 5 bits, so one swizzle serves all
+  const int sw = dma2_swizzle(l32);
+  const int arow = (wr * WM * 32 + l32) * DMA2_KSUB;
+  const int brow = (T::BM + wc * WN * 32 + l32) * DMA2_KSUB;
+  // MFMA steps per sub-tile and 16-byte pieces per lane per step: BF16 takes
+  // logical chunk 2 s + h at 32x32x16 step s; e4m3 takes chunks 4 s + 2 h
+  // and 4 s + 2 h + 1 at 32x32x64 step s.
+  constexpr int NSTEP = DT == GIFT_BF16 ? 4 : 2;
+  constexpr int FR = DT == GIFT_BF16 ? 1 : 2;
+  auto chunk = [&](int st, int f) {
+    return DT == GIFT_BF16 ? ((2 * st + half) ^ sw) * 16 : ((4 * st + 2 * half + f) ^ sw) * 16;
+  };
+  issue(0);
+  for (int kt = 0; kt < n_kt; ++kt) {
+    // sub-tile kt has landed and every wave is past sub-tile kt - 1, whose
+    // stage sub-tile kt + 1 refills
+    wait_vm_barrier<0>();
+    if (kt + 1 < n_kt) issue(kt + 1);
+    const uint8_t* stg = lds + (kt & 1) * T::STAGE_BYTES;
+    uint4 fb[WN][NSTEP][FR];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int st = 0; st < NSTEP; ++st)
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+          fb[j][st][f] = *reinterpret_cast<const uint4*>(stg + brow + j * 32 * DMA2_KSUB + chunk(st, f));
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      uint4 fa[NSTEP][FR];
+#pragma unroll
+      for (int st = 0; st < NSTEP; ++st)
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+          fa[st][f] = *reinterpret_cast<const uint4*>(stg + arow + i * 32 * DMA2_KSUB + chunk(st, f));
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int st = 0; st < NSTEP; ++st) {
+          if constexpr (DT == GIFT_BF16) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, fa[st][0]), __builtin_bit_cast(bf16x8, fb[j][st][0]),
+                acc[i][j], 0, 0, 0);
+          } else {
+            const Pair32 a = {fa[st][0], fa[st][FR - 1]}, b = {fb[j][st][0], fb[j][st][FR - 1]};
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b), acc[i][j], 0, 0, 0,
+                127, 0, 127);
+          }
+        }
     }
   }
   wait_vm_barrier<0>();  // LDS may be reused by the caller

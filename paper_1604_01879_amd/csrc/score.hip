@@ -3,6 +3,7 @@
 // per-view reduced-precision quantizer and the per-query mean.
 #include "kernels.h"
 #include "mfma_tile.h"
+#include <type_traits>
 #include "quant.h"
 
 namespace gift {
@@ -42,8 +43,8 @@ void launch_quantize(const float* src, int64_t n, int dim, int dtype,
 // and are masked), so a wave's WM*32 rows hold WM/2 whole shapes and the
 // per-shape max is taken inside the wave: each lane folds its 32 row values,
 // then the two lane halves are combined with one shuffle.
-template <int DT, int WM, int WN, bool DMA>
-__global__ __launch_bounds__(256, 1) void score_tiles_kernel(
+template <int DT, int WM, int WN, bool DMA, int WC = 2, bool K128 = false>
+__global__ __launch_bounds__(128 * WC, 1) void score_tiles_kernel(
     const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v,
     int64_t n_shapes, int n_views, int row_bytes,
     const uint8_t* __restrict__ qv, const void* __restrict__ q_scale_v,
@@ -54,8 +55,10 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   const float* db_scale = static_cast<const float*>(db_scale_v);
   const float* q_scale = static_cast<const float*>(q_scale_v);
   using T = TileShape<WM, WN>;
+  constexpr int BN = 32 * WC * WN;  // query views per block
   constexpr int SHAPES_PER_BLOCK = T::BM / 64;
   static_assert(WM % 2 == 0, "a wave must hold whole shapes");
+  static_assert(WC == 2 || DMA, "4-wave-column tiles use the direct-to-LDS loop");
   extern __shared__ __align__(16) uint8_t lds[];
 
   // Tile order: GROUP consecutive row tiles share each column sweep.  Blocks
@@ -74,23 +77,24 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int half = lane >> 5, l32 = lane & 31;
   const int64_t shape0 = row_tile * SHAPES_PER_BLOCK;
-  const int64_t col0 = col_tile * T::BN;
+  const int64_t col0 = col_tile * BN;
 
   f32x16 acc[WM][WN];
   if constexpr (DMA) {
     // staged rows of this lane as offsets from the block's first database
     // row and first query row (both under 2^32: at most 256 rows of 8 KB);
     // pad rows re-read the first row (their results are never used)
-    using D = DmaShape<WM, WN>;
+    using D = std::conditional_t<K128, Dma2Shape<WM, WN, WC>, DmaShape<WM, WN, WC>>;
+    constexpr int RPI = K128 ? 8 : 16;  // rows per 16-byte load of a wave
     const uint8_t* base_a = db + shape0 * n_views * (int64_t)row_bytes;
     const uint8_t* base_b = qv + col0 * (int64_t)row_bytes;
     uint32_t roff[D::NI];
 #pragma unroll
     for (int i = 0; i < D::NI; ++i) {
-      const int r = wave * D::WROWS + 16 * i + (lane >> 2);
+      const int r = wave * D::WROWS + RPI * i + lane / (64 / RPI);
       uint32_t o = 0;
       if (r < T::BM) {
         const int64_t shp = shape0 + (r >> 6);
@@ -102,7 +106,10 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
       }
       roff[i] = o;
     }
-    mfma_tile_mainloop_dma<DT, WM, WN>(lds, base_a, base_b, roff, row_bytes, acc);
+    if constexpr (K128)
+      mfma_tile_mainloop_dma128<DT, WM, WN, WC>(lds, base_a, base_b, roff, row_bytes, acc);
+    else
+      mfma_tile_mainloop_dma<DT, WM, WN, WC>(lds, base_a, base_b, roff, row_bytes, acc);
   } else {
     const uint8_t* src[T::LOADS];
 #pragma unroll
@@ -185,18 +192,23 @@ __global__ __launch_bounds__(256, 1) void score_tiles_kernel(
 }
 
 // Tuning knobs: tile variant per storage dtype and the row-tile group of the
-// launch order.  Variants (BF16 / e4m3 storage): bit 0 selects 256 x 256
-// (database rows x query views) instead of 256 x 128, bit 1 the pipelined
-// direct-to-LDS main loop (used when a row is a multiple of 64 bytes).
-// float32 always uses 128 x 128 and MX storage 256 x 128.
-static int g_tile[5] = {0, 3, 3, 0, 0};
+// launch order.  Variants (BF16 / e4m3 storage): for 0..3, bit 0 selects
+// 256 x 256 (database rows x query views) instead of 256 x 128 and bit 1 the
+// pipelined direct-to-LDS main loop, with 4 waves; 4 is the 256 x 256
+// direct-to-LDS tile with 8 waves of 128 x 64 (two per SIMD); 5 and 6 are
+// 3 and 4 with 128-byte sub-tiles in two stages (6, the default, is the
+// fastest measured).  The direct loops need rows of whole sub-tiles: 5 and
+// 6 fall back to 3 and 4 for rows of 64-byte sub-tiles, and 2..4 to 0, 1,
+// 1 otherwise.  float32 always uses 128 x 128 and MX storage
+// 256 x 128.
+static int g_tile[5] = {0, 6, 6, 0, 0};
 static int64_t g_group[5] = {8, 32, 32, 8, 8};
 
 gift_status set_score_tuning(int dtype, int tile, int group) {
   GIFT_CHECK(dtype >= 0 && dtype <= 4, GIFT_EINVAL, "bad dtype");
-  GIFT_CHECK(tile >= 0 && tile <= 3, GIFT_EINVAL, "tile must be in 0..3");
+  GIFT_CHECK(tile >= 0 && tile <= 6, GIFT_EINVAL, "tile must be in 0..6");
   GIFT_CHECK(tile == 0 || (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3), GIFT_EUNSUPPORTED,
-             "tile variants 1..3 are for BF16 / FP8 storage");
+             "tile variants 1..6 are for BF16 / FP8 storage");
   GIFT_CHECK(group >= 1 && group <= 1024, GIFT_EINVAL, "group must be in 1..1024");
   if (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3) g_tile[dtype] = tile;
   g_group[dtype] = group;
@@ -208,23 +220,25 @@ void get_score_tuning(int dtype, int* tile, int* group) {
   *group = (int)g_group[dtype];
 }
 
-template <int DT, int WM, int WN, bool DMA = false>
+template <int DT, int WM, int WN, bool DMA = false, int WC = 2, bool K128 = false>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
                                 const void* qscale, int64_t total_q,
                                 float* mbuf, int64_t ldm, hipStream_t st) {
-  constexpr int BM = TileShape<WM, WN>::BM, BN = TileShape<WM, WN>::BN;
+  constexpr int BM = TileShape<WM, WN>::BM, BN = 32 * WC * WN;
   const int row_bytes = (int)row_bytes_of(DT, db->dim);
   const int64_t n_row_tiles = (db->n_shapes + BM / 64 - 1) / (BM / 64);
   const int64_t n_col_tiles = (total_q + BN - 1) / BN;
   const int64_t blocks = n_row_tiles * n_col_tiles;
   GIFT_CHECK(blocks < (int64_t)1 << 31, GIFT_ECAPACITY, "score grid too large");
-  const size_t shmem = DMA ? DmaShape<WM, WN>::LDS_BYTES : TileShape<WM, WN>::LDS_BYTES;
-  auto kern = score_tiles_kernel<DT, WM, WN, DMA>;
+  const size_t shmem = !DMA ? TileShape<WM, WN>::LDS_BYTES
+                       : K128 ? Dma2Shape<WM, WN, WC>::LDS_BYTES
+                              : DmaShape<WM, WN, WC>::LDS_BYTES;
+  auto kern = score_tiles_kernel<DT, WM, WN, DMA, WC, K128>;
   {
     const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), shmem);
     if (s != GIFT_OK) return s;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), shmem, st,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(128 * WC), shmem, st,
                      static_cast<const uint8_t*>(db->data), db->scale,
                      db->n_shapes, db->n_views, row_bytes,
                      static_cast<const uint8_t*>(qv), qscale, total_q, mbuf,
@@ -242,13 +256,20 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
     case GIFT_BF16:
     case GIFT_FP8E4M3: {
       int t = g_tile[db->dtype];
-      if (row_bytes_of(db->dtype, db->dim) % DMA_KSUB != 0) t &= 1;
+      const int rb = row_bytes_of(db->dtype, db->dim);
+      if (t >= 5 && rb % DMA2_KSUB != 0) t -= 2;  // 128-byte sub-tiles -> 64-byte ones
+      if (rb % DMA_KSUB != 0) t = t == 4 ? 1 : (t & 1);
 #define GIFT_TILE_CASES(DTV)                                                                   \
   switch (t) {                                                                                 \
     case 0: return launch_tiles<DTV, 4, 2>(db, qv, qscale, total_q, mbuf, ldm, st);            \
     case 1: return launch_tiles<DTV, 4, 4>(db, qv, qscale, total_q, mbuf, ldm, st);            \
     case 2: return launch_tiles<DTV, 4, 2, true>(db, qv, qscale, total_q, mbuf, ldm, st);      \
-    default: return launch_tiles<DTV, 4, 4, true>(db, qv, qscale, total_q, mbuf, ldm, st);     \
+    case 3: return launch_tiles<DTV, 4, 4, true>(db, qv, qscale, total_q, mbuf, ldm, st);      \
+    case 4: return launch_tiles<DTV, 4, 2, true, 4>(db, qv, qscale, total_q, mbuf, ldm, st);   \
+    case 5: return launch_tiles<DTV, 4, 4, true, 2, true>(db, qv, qscale, total_q, mbuf, ldm,  \
+                                                          st);                                 \
+    default: return launch_tiles<DTV, 4, 2, true, 4, true>(db, qv, qscale, total_q, mbuf, ldm, \
+                                                           st);                                \
   }
       if (db->dtype == GIFT_BF16) GIFT_TILE_CASES(GIFT_BF16)
       GIFT_TILE_CASES(GIFT_FP8E4M3)

@@ -111,6 +111,32 @@ def test_first_pass_scores(L, dtype_name):
     assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
 
 
+@pytest.mark.parametrize("dtype_name", ["bf16", "fp8"])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("dim", [256, 96])
+def test_first_pass_tile_variants(L, dtype_name, tile, dim):
+    """Every score tile variant against the oracle: several row and column
+    tiles with ragged edges (301 shapes, 1..100 views per query).  At
+    dim 96 an e4m3 row (96 bytes) holds no whole number of 64- or 128-byte
+    sub-tiles and a BF16 row (192 bytes) no whole number of 128-byte ones,
+    so those direct-to-LDS variants fall back to register-staged tiles."""
+    _say(f"first pass {dtype_name} tile {tile} dim {dim}")
+    w, db, q, qoff = _data(N=301, dim=dim, B=7, m=(1, 100), seed=4)
+    dt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
+    V, _, _ = _views(L, db, w.n_views, dt)
+    Q = _queries(L, q, qoff)
+    saved = L.gift_get_score_tuning(dt)
+    try:
+        L.gift_set_score_tuning(dt, tile, 8)
+        S = L.gift_score_exhaustive(V, Q).cpu().numpy()
+    finally:
+        L.gift_set_score_tuning(dt, *saved)
+    qc, qs = O.quantize_views(q, dtype_name)
+    dc, ds = O.quantize_views(db, dtype_name)
+    ref = O.lowprec_exhaustive_scores(qc, qs, qoff, dc, ds, w.n_views)
+    assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
+
+
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views", "many-query-views"])
 def test_query_exhaustive_ranked_ids(L, dtype_name, case):
