@@ -725,7 +725,11 @@ constexpr int DMA2_KSUB = 128;
 
 __device__ __forceinline__ int dma2_swizzle(int r) { return (r & 7) ^ ((r >> 3) & 3); }
 
-template <int WM, int WN, int WC = 2>
+// BST: LDS stages of the B side (query rows); the A side always has two.
+// With BST = 3 the B rows, which stream through L2 (all query tiles per
+// database tile group) and so miss it more often, are loaded two sub-tiles
+// ahead.  The A stages come first in LDS, then the B stages.
+template <int WM, int WN, int WC = 2, int BST = 2>
 struct Dma2Shape {
   static constexpr int WAVES = 2 * WC;
   static constexpr int BM = 64 * WM;
@@ -733,16 +737,19 @@ struct Dma2Shape {
   static constexpr int ROWS = BM + BN;
   static constexpr int WROWS = ROWS / WAVES;  // rows staged by each wave
   static constexpr int NI = WROWS / 8;        // 16-byte loads per lane per sub-tile
-  static constexpr int STAGE_BYTES = ROWS * DMA2_KSUB;
-  static constexpr size_t LDS_BYTES = 2 * (size_t)STAGE_BYTES;
+  static constexpr int A_STAGE = BM * DMA2_KSUB;
+  static constexpr int B_STAGE = BN * DMA2_KSUB;
+  static constexpr size_t LDS_BYTES = 2 * (size_t)A_STAGE + (size_t)BST * B_STAGE;
 };
 
-template <int DT, int WM, int WN, int WC = 2>
+template <int DT, int WM, int WN, int WC = 2, int BST = 2>
 __device__ __forceinline__ void mfma_tile_mainloop_dma128(
     uint8_t* lds, const uint8_t* base_a, const uint8_t* base_b,
-    const uint32_t (&roff)[Dma2Shape<WM, WN, WC>::NI], int row_bytes, f32x16 (&acc)[WM][WN]) {
-  using T = Dma2Shape<WM, WN, WC>;
+    const uint32_t (&roff)[Dma2Shape<WM, WN, WC, BST>::NI], int row_bytes,
+    f32x16 (&acc)[WM][WN]) {
+  using T = Dma2Shape<WM, WN, WC, BST>;
   static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
+  static_assert(T::BM % T::WROWS == 0, "a wave stages rows of one side only");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -757,34 +764,42 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
 
   const int n_kt = row_bytes / DMA2_KSUB;
   lds_u8* l3 = (lds_u8*)lds;
+  // row r of a side sits at LDS row r of that side's stage; its chunk slot
+  // s holds the row's chunk s ^ dma2_swizzle(r)
   uint32_t goff[T::NI];
 #pragma unroll
   for (int i = 0; i < T::NI; ++i) {
     const int r = wave * T::WROWS + 8 * i + (lane >> 3);
-    goff[i] = roff[i] + (uint32_t)(((lane & 7) ^ dma2_swizzle(r)) * 16);
+    const int rs = r < T::BM ? r : r - T::BM;
+    goff[i] = roff[i] + (uint32_t)(((lane & 7) ^ dma2_swizzle(rs)) * 16);
   }
-  const uint32_t wave_lds = (uint32_t)__builtin_amdgcn_readfirstlane(
-      (int)(uint32_t)(uintptr_t)(l3 + wave * T::WROWS * DMA2_KSUB));
+  // this wave stages rows of one side: A (database) rows or B (query) rows
+  const bool a_wave = wave * T::WROWS < T::BM;  // uniform in the wave
+  const int srow = a_wave ? wave * T::WROWS : wave * T::WROWS - T::BM;  // first row in its side
+  const uint32_t side_lds = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)(
+      l3 + (a_wave ? 0 : 2 * T::A_STAGE) + srow * DMA2_KSUB));
+  const uint64_t gv0 = (uint64_t)(uintptr_t)(a_wave ? base_a : base_b);
+  const uint64_t gside = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv0 >> 32)) << 32) |
+                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv0);
   auto issue = [&](int kt) {
-    const uint32_t base = wave_lds + (uint32_t)((kt & 1) * T::STAGE_BYTES);
-    const uint8_t* ga = base_a + kt * DMA2_KSUB;
-    const uint8_t* gb = base_b + kt * DMA2_KSUB;
+    // wave-uniform values the compiler cannot prove uniform (they depend on
+    // the wave's side): taken from lane 0 into scalar registers
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(
+        side_lds + (uint32_t)(a_wave ? (kt & 1) * T::A_STAGE : (kt % BST) * T::B_STAGE)));
+    const uint64_t gk = gside + (uint64_t)(kt * DMA2_KSUB);
+    const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gk >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gk);
 #pragma unroll
-    for (int i = 0; i < T::NI; ++i) {
-      const bool a_side = wave * T::WROWS + 8 * i < T::BM;  // uniform in the wave
-      const uint64_t gv = (uint64_t)(uintptr_t)(a_side ? ga : gb);
-      const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv >> 32)) << 32) |
-                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv);
+    for (int i = 0; i < T::NI; ++i)
       asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
                    :
                    : "v"(goff[i]), "s"(g), "s"(base + (uint32_t)(i * 8 * DMA2_KSUB))
                    : "memory", "m0");
-    }
   };
   // operand rows all have l32 as their low 5 bits, so one swizzle serves all
   const int sw = dma2_swizzle(l32);
   const int arow = (wr * WM * 32 + l32) * DMA2_KSUB;
-  const int brow = (T::BM + wc * WN * 32 + l32) * DMA2_KSUB;
+  const int brow = (wc * WN * 32 + l32) * DMA2_KSUB;
   // MFMA steps per sub-tile and 16-byte pieces per lane per step: BF16 takes
   // logical chunk 2 s + h at 32x32x16 step s; e4m3 takes chunks 4 s + 2 h
   // and 4 s + 2 h + 1 at 32x32x64 step s.
@@ -793,13 +808,19 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
   auto chunk = [&](int st, int f) {
     return DT == GIFT_BF16 ? ((2 * st + half) ^ sw) * 16 : ((4 * st + 2 * half + f) ^ sw) * 16;
   };
+  // A waves keep one sub-tile in flight, B waves BST - 1
   issue(0);
+  if (BST == 3 && !a_wave && 1 < n_kt) issue(1);
   for (int kt = 0; kt < n_kt; ++kt) {
-    // sub-tile kt has landed and every wave is past sub-tile kt - 1, whose
-    // stage sub-tile kt + 1 refills
-    wait_vm_barrier<0>();
-    if (kt + 1 < n_kt) issue(kt + 1);
-    const uint8_t* stg = lds + (kt & 1) * T::STAGE_BYTES;
+    // this wave's rows of sub-tile kt have landed (a B wave may still have
+    // sub-tile kt + 1 in flight); after the barrier every wave is past
+    // sub-tile kt - 1, whose stages the next loads refill
+    if (BST == 3 && !a_wave && kt + 1 < n_kt) wait_vm_barrier<T::NI>();
+    else wait_vm_barrier<0>();
+    const int ahead = (BST == 3 && !a_wave) ? 2 : 1;
+    if (kt + ahead < n_kt) issue(kt + ahead);
+    const uint8_t* sta = lds + (kt & 1) * T::A_STAGE;
+    const uint8_t* stb = lds + 2 * T::A_STAGE + (kt % BST) * T::B_STAGE;
     uint4 fb[WN][NSTEP][FR];
 #pragma unroll
     for (int j = 0; j < WN; ++j)
@@ -807,7 +828,7 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
       for (int st = 0; st < NSTEP; ++st)
 #pragma unroll
         for (int f = 0; f < FR; ++f)
-          fb[j][st][f] = *reinterpret_cast<const uint4*>(stg + brow + j * 32 * DMA2_KSUB + chunk(st, f));
+          fb[j][st][f] = *reinterpret_cast<const uint4*>(stb + brow + j * 32 * DMA2_KSUB + chunk(st, f));
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
       uint4 fa[NSTEP][FR];
@@ -815,7 +836,7 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
       for (int st = 0; st < NSTEP; ++st)
 #pragma unroll
         for (int f = 0; f < FR; ++f)
-          fa[st][f] = *reinterpret_cast<const uint4*>(stg + arow + i * 32 * DMA2_KSUB + chunk(st, f));
+          fa[st][f] = *reinterpret_cast<const uint4*>(sta + arow + i * 32 * DMA2_KSUB + chunk(st, f));
 #pragma unroll
       for (int j = 0; j < WN; ++j)
 #pragma unroll

@@ -43,7 +43,7 @@ void launch_quantize(const float* src, int64_t n, int dim, int dtype,
 // and are masked), so a wave's WM*32 rows hold WM/2 whole shapes and the
 // per-shape max is taken inside the wave: each lane folds its 32 row values,
 // then the two lane halves are combined with one shuffle.
-template <int DT, int WM, int WN, bool DMA, int WC = 2, bool K128 = false>
+template <int DT, int WM, int WN, bool DMA, int WC = 2, bool K128 = false, int BST = 2>
 __global__ __launch_bounds__(128 * WC, 1) void score_tiles_kernel(
     const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v,
     int64_t n_shapes, int n_views, int row_bytes,
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(128 * WC, 1) void score_tiles_kernel(
     // staged rows of this lane as offsets from the block's first database
     // row and first query row (both under 2^32: at most 256 rows of 8 KB);
     // pad rows re-read the first row (their results are never used)
-    using D = std::conditional_t<K128, Dma2Shape<WM, WN, WC>, DmaShape<WM, WN, WC>>;
+    using D = std::conditional_t<K128, Dma2Shape<WM, WN, WC, BST>, DmaShape<WM, WN, WC>>;
     constexpr int RPI = K128 ? 8 : 16;  // rows per 16-byte load of a wave
     const uint8_t* base_a = db + shape0 * n_views * (int64_t)row_bytes;
     const uint8_t* base_b = qv + col0 * (int64_t)row_bytes;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(128 * WC, 1) void score_tiles_kernel(
       roff[i] = o;
     }
     if constexpr (K128)
-      mfma_tile_mainloop_dma128<DT, WM, WN, WC>(lds, base_a, base_b, roff, row_bytes, acc);
+      mfma_tile_mainloop_dma128<DT, WM, WN, WC, BST>(lds, base_a, base_b, roff, row_bytes, acc);
     else
       mfma_tile_mainloop_dma<DT, WM, WN, WC>(lds, base_a, base_b, roff, row_bytes, acc);
   } else {
@@ -206,9 +206,9 @@ static int64_t g_group[5] = {8, 32, 32, 8, 8};
 
 gift_status set_score_tuning(int dtype, int tile, int group) {
   GIFT_CHECK(dtype >= 0 && dtype <= 4, GIFT_EINVAL, "bad dtype");
-  GIFT_CHECK(tile >= 0 && tile <= 6, GIFT_EINVAL, "tile must be in 0..6");
+  GIFT_CHECK(tile >= 0 && tile <= 7, GIFT_EINVAL, "tile must be in 0..7");
   GIFT_CHECK(tile == 0 || (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3), GIFT_EUNSUPPORTED,
-             "tile variants 1..6 are for BF16 / FP8 storage");
+             "tile variants 1..7 are for BF16 / FP8 storage");
   GIFT_CHECK(group >= 1 && group <= 1024, GIFT_EINVAL, "group must be in 1..1024");
   if (dtype == GIFT_BF16 || dtype == GIFT_FP8E4M3) g_tile[dtype] = tile;
   g_group[dtype] = group;
@@ -220,7 +220,7 @@ void get_score_tuning(int dtype, int* tile, int* group) {
   *group = (int)g_group[dtype];
 }
 
-template <int DT, int WM, int WN, bool DMA = false, int WC = 2, bool K128 = false>
+template <int DT, int WM, int WN, bool DMA = false, int WC = 2, bool K128 = false, int BST = 2>
 static gift_status launch_tiles(const gift_views* db, const void* qv,
                                 const void* qscale, int64_t total_q,
                                 float* mbuf, int64_t ldm, hipStream_t st) {
@@ -231,9 +231,9 @@ static gift_status launch_tiles(const gift_views* db, const void* qv,
   const int64_t blocks = n_row_tiles * n_col_tiles;
   GIFT_CHECK(blocks < (int64_t)1 << 31, GIFT_ECAPACITY, "score grid too large");
   const size_t shmem = !DMA ? TileShape<WM, WN>::LDS_BYTES
-                       : K128 ? Dma2Shape<WM, WN, WC>::LDS_BYTES
+                       : K128 ? Dma2Shape<WM, WN, WC, BST>::LDS_BYTES
                               : DmaShape<WM, WN, WC>::LDS_BYTES;
-  auto kern = score_tiles_kernel<DT, WM, WN, DMA, WC, K128>;
+  auto kern = score_tiles_kernel<DT, WM, WN, DMA, WC, K128, BST>;
   {
     const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), shmem);
     if (s != GIFT_OK) return s;
@@ -257,7 +257,7 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
     case GIFT_FP8E4M3: {
       int t = g_tile[db->dtype];
       const int rb = row_bytes_of(db->dtype, db->dim);
-      if (t >= 5 && rb % DMA2_KSUB != 0) t -= 2;  // 128-byte sub-tiles -> 64-byte ones
+      if (t >= 5 && rb % DMA2_KSUB != 0) t = t == 5 ? 3 : 4;  // 128-byte sub-tiles -> 64-byte ones
       if (rb % DMA_KSUB != 0) t = t == 4 ? 1 : (t & 1);
 #define GIFT_TILE_CASES(DTV)                                                                   \
   switch (t) {                                                                                 \
@@ -268,8 +268,10 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
     case 4: return launch_tiles<DTV, 4, 2, true, 4>(db, qv, qscale, total_q, mbuf, ldm, st);   \
     case 5: return launch_tiles<DTV, 4, 4, true, 2, true>(db, qv, qscale, total_q, mbuf, ldm,  \
                                                           st);                                 \
-    default: return launch_tiles<DTV, 4, 2, true, 4, true>(db, qv, qscale, total_q, mbuf, ldm, \
-                                                           st);                                \
+    case 6: return launch_tiles<DTV, 4, 2, true, 4, true>(db, qv, qscale, total_q, mbuf, ldm,  \
+                                                          st);                                 \
+    default: return launch_tiles<DTV, 4, 2, true, 4, true, 3>(db, qv, qscale, total_q, mbuf,   \
+                                                              ldm, st);                        \
   }
       if (db->dtype == GIFT_BF16) GIFT_TILE_CASES(GIFT_BF16)
       GIFT_TILE_CASES(GIFT_FP8E4M3)

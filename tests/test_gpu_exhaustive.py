@@ -112,7 +112,7 @@ def test_first_pass_scores(L, dtype_name):
 
 
 @pytest.mark.parametrize("dtype_name", ["bf16", "fp8"])
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("dim", [256, 96])
 def test_first_pass_tile_variants(L, dtype_name, tile, dim):
     """Every score tile variant against the oracle: several row and column
