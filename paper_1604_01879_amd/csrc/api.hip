@@ -140,7 +140,7 @@ struct ExhaustiveWs {
   float* cand_s;
   float* s_hi;
   float* s_lo;
-  unsigned long long* rmask;  // rescore masks, [r][total_views]
+  RescoreScratch rs;  // rescore masks, approximate scores, top-k marks
   size_t bytes;
 };
 
@@ -161,7 +161,9 @@ static ExhaustiveWs carve_exhaustive(void* base, const gift_views* db,
     w.cand_s = c.take<float>((size_t)q->n_queries * r);
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
-    w.rmask = c.take<unsigned long long>((size_t)r * q->total_views);
+    w.rs.mask = c.take<unsigned long long>((size_t)r * q->total_views);
+    w.rs.s1 = c.take<float>((size_t)q->n_queries * r);
+    w.rs.mark = c.take<uint8_t>((size_t)q->n_queries * r);
   }
   w.bytes = c.bytes();
   return w;
@@ -242,7 +244,7 @@ struct FifWs {
   float* cand_s;
   float* s_hi;
   float* s_lo;
-  unsigned long long* rmask;  // rescore masks, [r][total_views]
+  RescoreScratch rs;  // rescore masks, approximate scores, top-k marks
   size_t bytes;
 };
 
@@ -271,7 +273,9 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
     w.cand_s = c.take<float>((size_t)q->n_queries * r);
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
-    w.rmask = c.take<unsigned long long>((size_t)r * q->total_views);
+    w.rs.mask = c.take<unsigned long long>((size_t)r * q->total_views);
+    w.rs.s1 = c.take<float>((size_t)q->n_queries * r);
+    w.rs.mark = c.take<uint8_t>((size_t)q->n_queries * r);
   }
   w.bytes = c.bytes();
   return w;
@@ -443,8 +447,8 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
-                 q->total_views, w.cand, rescore_r, rescore_dot_err(db->dim), nullptr, nullptr, 0,
-                 nullptr, w.rmask, w.s_hi, w.s_lo, st);
+                 q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), nullptr,
+                 nullptr, 0, nullptr, w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
@@ -649,8 +653,8 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
-                 q->total_views, w.cand, rescore_r, rescore_dot_err(db->dim), w.qwords,
-                 fif->view_words, fif->ma, nullptr, w.rmask, w.s_hi, w.s_lo, st);
+                 q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), w.qwords,
+                 fif->view_words, fif->ma, nullptr, w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);

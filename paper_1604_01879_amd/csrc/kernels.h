@@ -33,15 +33,24 @@ void launch_reduce_queries(const float* mbuf, int64_t ldm, int64_t n_shapes,
 void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
                        int32_t* out_id, float* out_s, hipStream_t st);
 
-// Exact rescore of candidates: float32 dot products with a known error
-// bound, then a compensated re-evaluation of every view pair that float32
-// rounding could make the maximum.  Writes the float-float score.
+// Exact rescore of candidates: split-BF16 dot products with a known error
+// bound give each view's candidate maxima and an approximate score; the
+// candidates that can still reach the top_k get a compensated
+// re-evaluation of every view pair that the bound cannot exclude as the
+// maximum, and their float-float score; the others score -inf.
 // With qwords != nullptr only pairs whose words match take part (Eq. 4).
+// Scratch: view masks [r][total views], approximate scores and top-k marks
+// [queries][r].
+struct RescoreScratch {
+  unsigned long long* mask;
+  float* s1;
+  uint8_t* mark;
+};
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
-                    int64_t total_views, const int32_t* cand, int r, float dot_err,
+                    int64_t total_views, const int32_t* cand, int r, int top_k, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, unsigned long long* mask, float* s_hi, float* s_lo,
+                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
                     hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,

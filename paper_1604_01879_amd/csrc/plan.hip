@@ -33,7 +33,7 @@ struct PlanWs {
   float* cand_s;
   float* s_hi;
   float* s_lo;
-  unsigned long long* rmask;  // rescore masks, [r][Vmax]
+  RescoreScratch rs;  // rescore masks [r][Vmax], approximate scores, top-k marks
   size_t bytes;
 };
 
@@ -72,7 +72,9 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.cand_s = c.take<float>((size_t)Bmax * r);
   w.s_hi = c.take<float>((size_t)Bmax * r);
   w.s_lo = c.take<float>((size_t)Bmax * r);
-  w.rmask = c.take<unsigned long long>((size_t)r * Vmax);
+  w.rs.mask = c.take<unsigned long long>((size_t)r * Vmax);
+  w.rs.s1 = c.take<float>((size_t)Bmax * r);
+  w.rs.mark = c.take<uint8_t>((size_t)Bmax * r);
   w.bytes = c.bytes();
   return w;
 }
@@ -111,8 +113,8 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
                     st);
   GIFT_LAUNCHED();
   launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->Vmax,
-                 p->ws.cand, p->r, rescore_dot_error(p->db.dim), p->ws.qwords, p->view_words,
-                 p->ma, active, p->ws.rmask, p->ws.s_hi, p->ws.s_lo, st);
+                 p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim), p->ws.qwords,
+                 p->view_words, p->ma, active, p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
                     p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim, p->max_m),

@@ -194,7 +194,8 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     int n_queries, const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
-    const int32_t* __restrict__ active, unsigned long long* __restrict__ mask, int64_t mask_ld) {
+    const int32_t* __restrict__ active, unsigned long long* __restrict__ mask, int64_t mask_ld,
+    float* __restrict__ s1) {
   __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
   __shared__ int32_t vw[RS_CANDS][64 * 8];
 
@@ -218,6 +219,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
 #pragma unroll
   for (int k = 0; k < RS_CANDS; ++k) shape[k] = cand[(int64_t)b * r + c0 + min(k, n_cand - 1)];
   unsigned long long* wmask = mask + (int64_t)(c0 + (mine ? wave : 0)) * mask_ld + q0;
+  float s1_acc = 0.f;  // sum of this wave's approximate row maxima
 
   if (qwords != nullptr)
 #pragma unroll
@@ -348,8 +350,52 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
       bits |= (unsigned long long)__shfl_xor(lo_b, 32, 64) |
               ((unsigned long long)__shfl_xor(hi_b, 32, 64) << 32);
       if (half == 0 && mine && i < mi) wmask[it * 64 + i] = bits;
+      // approximate maximum of view i (0 without a matching view, as the
+      // exact score takes it), summed over the wave's half 0
+      float v = (half == 0 && i < mi && mx != -INFINITY) ? mx : 0.f;
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      s1_acc += v;
     }
   }
+  if (mine && lane == 0) s1[(int64_t)b * r + c0 + wave] = m > 0 ? s1_acc / (float)m : 0.f;
+}
+
+// Which candidates can still reach the top k (rescore_mark_kernel, one block
+// per query).  s1, the mean of the approximate maxima, is within
+// delta = dot_err + (m + 2) 2^-24 1.01 of the exact score (each maximum is
+// within dot_err, plus the rounding of the float sum of values below 1 +
+// dot_err).  With T the k-th largest s1 - delta, at least k candidates score
+// T or more, so one with s1 + delta < T cannot be in the top k; the others
+// are marked for the exact evaluation.
+__global__ __launch_bounds__(256) void rescore_mark_kernel(
+    const float* __restrict__ s1, const int32_t* __restrict__ qoff, int r, int k, float dot_err,
+    const int32_t* __restrict__ active, uint8_t* __restrict__ mark) {
+  __shared__ float lb[MAX_R];
+  const int b = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
+  const int m = qoff[b + 1] - qoff[b];
+  const float delta = dot_err + (float)(m + 2) * 5.96046448e-08f * 1.01f;
+  const int64_t base = (int64_t)b * r;
+  int np2 = 1;
+  while (np2 < r) np2 <<= 1;
+  for (int i = threadIdx.x; i < np2; i += 256) lb[i] = i < r ? s1[base + i] - delta : -INFINITY;
+  __syncthreads();
+  // bitonic sort, descending
+  for (int kk = 2; kk <= np2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np2; i += 256) {
+        const int ix = i ^ j;
+        if (ix > i) {
+          const bool down = (i & kk) == 0;
+          const float a = lb[i], d = lb[ix];
+          if ((d > a) == down) { lb[i] = d; lb[ix] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const float T = lb[k - 1];
+  for (int i = threadIdx.x; i < r; i += 256) mark[base + i] = s1[base + i] + delta >= T ? 1 : 0;
 }
 
 // Candidate rescore, phases 2 and 3 (rescore_exact_kernel): one block (four
@@ -365,12 +411,16 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff, int n_queries,
     const int32_t* __restrict__ cand, int r, const unsigned long long* __restrict__ mask,
-    int64_t mask_ld, const int32_t* __restrict__ active,
+    int64_t mask_ld, const uint8_t* __restrict__ mark, const int32_t* __restrict__ active,
     float* __restrict__ s_hi, float* __restrict__ s_lo) {
   __shared__ float mff_hi[64], mff_lo[64];
   const int64_t n_pairs = (int64_t)(active != nullptr ? *active : n_queries) * r;
   const int64_t pair = xcd_contiguous(blockIdx.x, n_pairs);
   if (pair >= n_pairs) return;  // past the batch
+  if (!mark[pair]) {  // cannot reach the top k: ranked last, never returned
+    if (threadIdx.x == 0) { s_hi[pair] = -INFINITY; s_lo[pair] = 0.f; }
+    return;
+  }
   const int b = (int)(pair / r);
   const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -433,20 +483,22 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
 
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
-                    int64_t total_views, const int32_t* cand, int r, float dot_err,
+                    int64_t total_views, const int32_t* cand, int r, int top_k, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, unsigned long long* mask, float* s_hi, float* s_lo,
+                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
                     hipStream_t st) {
   const int64_t items = (int64_t)n_queries * ((r + RS_CANDS - 1) / RS_CANDS);
   if (items <= 0) return;
   // grids cover every slot of the XCD-contiguous order
   hipLaunchKernelGGL(rescore_mask_kernel, dim3((unsigned)((items + 7) / 8 * 8)), dim3(RS_THREADS),
                      0, st, master, n_views, dim, qviews, qoff, n_queries, cand, r,
-                     dot_err, qwords, view_words, ma, active, mask, total_views);
+                     dot_err, qwords, view_words, ma, active, sc.mask, total_views, sc.s1);
+  hipLaunchKernelGGL(rescore_mark_kernel, dim3((unsigned)n_queries), dim3(256), 0, st, sc.s1,
+                     qoff, r, top_k, dot_err, active, sc.mark);
   const int64_t pairs = (int64_t)n_queries * r;
   hipLaunchKernelGGL(rescore_exact_kernel, dim3((unsigned)((pairs + 7) / 8 * 8)), dim3(256), 0, st,
-                     master, n_views, dim, qviews, qoff, n_queries, cand, r, mask, total_views,
-                     active, s_hi, s_lo);
+                     master, n_views, dim, qviews, qoff, n_queries, cand, r, sc.mask, total_views,
+                     sc.mark, active, s_hi, s_lo);
 }
 
 // ------------------------------------------------------------------ final
