@@ -138,7 +138,8 @@ def test_first_pass_tile_variants(L, dtype_name, tile, dim):
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
-@pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views", "many-query-views"])
+@pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views", "many-query-views",
+                                  "shared-candidates"])
 def test_query_exhaustive_ranked_ids(L, dtype_name, case):
     _say(f"query_exhaustive {dtype_name} {case}")
     if case == "c1-like":
@@ -150,11 +151,16 @@ def test_query_exhaustive_ranked_ids(L, dtype_name, case):
     elif case == "few-views":
         w, db, q, qoff = _data(N=90, dim=64, B=3, m=(5, 40), nv=7, seed=5)
         k, R = 15, 40
-    else:
+    elif case == "many-query-views":
         # queries of 65..150 views (rescored in chunks of 64), 33 views per
         # shape, a candidate count that leaves a partial group of candidates
         w, db, q, qoff = _data(N=120, dim=96, B=4, m=(65, 150), nv=33, seed=9)
         k, R = 12, 23
+    else:
+        # every query rescores every shape (each candidate shared by all
+        # queries), queries of 20..150 views
+        w, db, q, qoff = _data(N=41, dim=128, B=6, m=(20, 150), nv=64, seed=12)
+        k, R = 17, 41
     dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
     V, _, _ = _views(L, db, w.n_views, dt)
     Q = _queries(L, q, qoff)

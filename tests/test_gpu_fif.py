@@ -229,6 +229,23 @@ def test_query_fif_ranked_ids(L, dtype_name, ma):
     assert (flags == 1).all()
 
 
+@pytest.mark.parametrize("ma", [1, 2])
+def test_query_fif_shared_candidates(L, ma):
+    """Eq. 4 ranking when every query rescores every shape (each candidate
+    shared by all queries, word-matched view pairs), queries of 10..140
+    views."""
+    _say(f"fif shared candidates ma={ma}")
+    w = _wl(n_shapes=37, dim=96, m_lo=10, m_hi=140, n_queries=5)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 9, ma, L.F32)
+    k, R = 14, 37
+    ids, sc, flags = L.gift_query_fif(V, F, Q, k, R)
+    torch.cuda.synchronize()
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    for b in range(len(qoff) - 1):
+        assert_ranked_equal(ids[b], sc[b], S[b], k)
+
+
 def test_fif_one_word_and_full_ma_equal_exhaustive(L):
     """K = 1 and MA = K both make Eq. 4 identical to Eq. 3."""
     _say("fif reduces to exhaustive")
