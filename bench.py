@@ -141,7 +141,7 @@ def main():
                 bt, bg = L.gift_get_score_tuning(dts[name])
                 tuning[name] = {"tile": bt, "group": bg, "source": "library default"}
                 continue
-            bt, bg, ms = L.gift_autotune_score(views[name], Q, list(range(7)), [8, 16, 32], reps=2)
+            bt, bg, ms = L.gift_autotune_score(views[name], Q, list(range(9)), [8, 16, 32], reps=2)
             tuning[name] = {"tile": bt, "group": bg, "ms_grid": ms.round(2).tolist()}
             log(f"autotuned {name}: tile {bt} group {bg}")
 

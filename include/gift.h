@@ -363,13 +363,16 @@ gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
 /* ---------------------------------------------------------------------- */
 /* Tuning of the first-pass scorer (host, process-wide, not thread-safe).  */
 /* tile (BF16 / FP8 storage; float32 always uses 128 x 128 and MX storage */
-/* 256 x 128), 0..6: for 0..3, bit 0 selects 256 database rows x 256 query */
+/* 256 x 128), 0..8: for 0..3, bit 0 selects 256 database rows x 256 query */
 /* views per block instead of 256 x 128 and bit 1 the pipelined main loop */
 /* with direct global-to-LDS loads in 64-byte sub-tiles (4 waves); 4 is   */
 /* the 256 x 256 direct-load tile with 8 waves (two per SIMD); 5 and 6 are */
-/* 3 and 4 with 128-byte sub-tiles.  A stored row that is no whole number */
-/* of sub-tiles falls back to a tile it holds (6 -> 4 -> 1, 5 -> 3 -> 1). */
-/* The default is 6 with group 32.  group: number of database             */
+/* 3 and 4 with 128-byte sub-tiles; 7 is 6 with three LDS stages of query */
+/* rows; 8 is 6 as a persistent kernel (one block per CU walking the      */
+/* tiles, the next tile's first sub-tile loading during the epilogue).    */
+/* A stored row that is no whole number of sub-tiles falls back to a tile */
+/* it holds (6, 7, 8 -> 4 -> 1; 5 -> 3 -> 1).                             */
+/* The default is 8 with group 32.  group: number of database             */
 /* row tiles that share one sweep over the query tiles in the launch order */
 /* (blocks go to the 8 XCDs round-robin, so multiples of 8 keep each       */
 /* database tile on one XCD).  gift_autotune_score times every (tile,      */

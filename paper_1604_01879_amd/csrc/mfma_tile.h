@@ -742,6 +742,79 @@ struct Dma2Shape {
   static constexpr size_t LDS_BYTES = 2 * (size_t)A_STAGE + (size_t)BST * B_STAGE;
 };
 
+// Direct-to-LDS load of one 128-byte sub-tile of a wave's rows: NI 16-byte
+// loads per lane, load i reading g + goff[i] and writing the 8 LDS rows
+// that start at byte base + 1024 i.  base and g are wave-uniform values the
+// compiler cannot always prove uniform (they depend on the wave's side), so
+// they are taken from lane 0 into scalar registers.
+template <int NI>
+__device__ __forceinline__ void dma128_issue(uint32_t base, uint64_t g, const uint32_t (&goff)[NI]) {
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+  const uint64_t gu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(g >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g);
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(goff[i]), "s"(gu), "s"(b + (uint32_t)(i * 8 * DMA2_KSUB))
+                 : "memory", "m0");
+}
+
+// MFMAs of one staged 128-byte sub-tile: the wave multiplies its WM x WN
+// blocks of 32 x 32 (rows wr * WM * 32 + 32 i, columns wc * WN * 32 + 32 j of
+// the A stage sta and the B stage stb).  Operand rows all have l32 as their
+// low 5 bits, so one swizzle serves all.  BF16 takes logical chunk 2 s + h
+// at 32x32x16 step s; e4m3 takes chunks 4 s + 2 h and 4 s + 2 h + 1 at
+// 32x32x64 step s.
+template <int DT, int WM, int WN, int WC>
+__device__ __forceinline__ void dma128_subtile_mfma(const uint8_t* sta, const uint8_t* stb,
+                                                    f32x16 (&acc)[WM][WN]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int sw = dma2_swizzle(l32);
+  const int arow = (wr * WM * 32 + l32) * DMA2_KSUB;
+  const int brow = (wc * WN * 32 + l32) * DMA2_KSUB;
+  constexpr int NSTEP = DT == GIFT_BF16 ? 4 : 2;  // MFMA steps per sub-tile
+  constexpr int FR = DT == GIFT_BF16 ? 1 : 2;     // 16-byte pieces per lane per step
+  auto chunk = [&](int st, int f) {
+    return DT == GIFT_BF16 ? ((2 * st + half) ^ sw) * 16 : ((4 * st + 2 * half + f) ^ sw) * 16;
+  };
+  uint4 fb[WN][NSTEP][FR];
+#pragma unroll
+  for (int j = 0; j < WN; ++j)
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st)
+#pragma unroll
+      for (int f = 0; f < FR; ++f)
+        fb[j][st][f] = *reinterpret_cast<const uint4*>(stb + brow + j * 32 * DMA2_KSUB + chunk(st, f));
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    uint4 fa[NSTEP][FR];
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st)
+#pragma unroll
+      for (int f = 0; f < FR; ++f)
+        fa[st][f] = *reinterpret_cast<const uint4*>(sta + arow + i * 32 * DMA2_KSUB + chunk(st, f));
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int st = 0; st < NSTEP; ++st) {
+        if constexpr (DT == GIFT_BF16) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              __builtin_bit_cast(bf16x8, fa[st][0]), __builtin_bit_cast(bf16x8, fb[j][st][0]),
+              acc[i][j], 0, 0, 0);
+        } else {
+          const Pair32 a = {fa[st][0], fa[st][FR - 1]}, b = {fb[j][st][0], fb[j][st][FR - 1]};
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b), acc[i][j], 0, 0, 0,
+              127, 0, 127);
+        }
+      }
+  }
+}
+
 template <int DT, int WM, int WN, int WC = 2, int BST = 2>
 __device__ __forceinline__ void mfma_tile_mainloop_dma128(
     uint8_t* lds, const uint8_t* base_a, const uint8_t* base_b,
@@ -753,8 +826,6 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave / WC, wc = wave % WC;
-  const int half = lane >> 5, l32 = lane & 31;
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -782,31 +853,8 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
   const uint64_t gside = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv0 >> 32)) << 32) |
                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv0);
   auto issue = [&](int kt) {
-    // wave-uniform values the compiler cannot prove uniform (they depend on
-    // the wave's side): taken from lane 0 into scalar registers
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(
-        side_lds + (uint32_t)(a_wave ? (kt & 1) * T::A_STAGE : (kt % BST) * T::B_STAGE)));
-    const uint64_t gk = gside + (uint64_t)(kt * DMA2_KSUB);
-    const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gk >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gk);
-#pragma unroll
-    for (int i = 0; i < T::NI; ++i)
-      asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
-                   :
-                   : "v"(goff[i]), "s"(g), "s"(base + (uint32_t)(i * 8 * DMA2_KSUB))
-                   : "memory", "m0");
-  };
-  // operand rows all have l32 as their low 5 bits, so one swizzle serves all
-  const int sw = dma2_swizzle(l32);
-  const int arow = (wr * WM * 32 + l32) * DMA2_KSUB;
-  const int brow = (wc * WN * 32 + l32) * DMA2_KSUB;
-  // MFMA steps per sub-tile and 16-byte pieces per lane per step: BF16 takes
-  // logical chunk 2 s + h at 32x32x16 step s; e4m3 takes chunks 4 s + 2 h
-  // and 4 s + 2 h + 1 at 32x32x64 step s.
-  constexpr int NSTEP = DT == GIFT_BF16 ? 4 : 2;
-  constexpr int FR = DT == GIFT_BF16 ? 1 : 2;
-  auto chunk = [&](int st, int f) {
-    return DT == GIFT_BF16 ? ((2 * st + half) ^ sw) * 16 : ((4 * st + 2 * half + f) ^ sw) * 16;
+    dma128_issue<T::NI>(side_lds + (uint32_t)(a_wave ? (kt & 1) * T::A_STAGE : (kt % BST) * T::B_STAGE),
+                        gside + (uint64_t)(kt * DMA2_KSUB), goff);
   };
   // A waves keep one sub-tile in flight, B waves BST - 1
   issue(0);
@@ -819,40 +867,8 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
     else wait_vm_barrier<0>();
     const int ahead = (BST == 3 && !a_wave) ? 2 : 1;
     if (kt + ahead < n_kt) issue(kt + ahead);
-    const uint8_t* sta = lds + (kt & 1) * T::A_STAGE;
-    const uint8_t* stb = lds + 2 * T::A_STAGE + (kt % BST) * T::B_STAGE;
-    uint4 fb[WN][NSTEP][FR];
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int st = 0; st < NSTEP; ++st)
-#pragma unroll
-        for (int f = 0; f < FR; ++f)
-          fb[j][st][f] = *reinterpret_cast<const uint4*>(stb + brow + j * 32 * DMA2_KSUB + chunk(st, f));
-#pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      uint4 fa[NSTEP][FR];
-#pragma unroll
-      for (int st = 0; st < NSTEP; ++st)
-#pragma unroll
-        for (int f = 0; f < FR; ++f)
-          fa[st][f] = *reinterpret_cast<const uint4*>(sta + arow + i * 32 * DMA2_KSUB + chunk(st, f));
-#pragma unroll
-      for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int st = 0; st < NSTEP; ++st) {
-          if constexpr (DT == GIFT_BF16) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, fa[st][0]), __builtin_bit_cast(bf16x8, fb[j][st][0]),
-                acc[i][j], 0, 0, 0);
-          } else {
-            const Pair32 a = {fa[st][0], fa[st][FR - 1]}, b = {fb[j][st][0], fb[j][st][FR - 1]};
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                __builtin_bit_cast(i32x8, a), __builtin_bit_cast(i32x8, b), acc[i][j], 0, 0, 0,
-                127, 0, 127);
-          }
-        }
-    }
+    dma128_subtile_mfma<DT, WM, WN, WC>(lds + (kt & 1) * T::A_STAGE,
+                                         lds + 2 * T::A_STAGE + (kt % BST) * T::B_STAGE, acc);
   }
   wait_vm_barrier<0>();  // LDS may be reused by the caller
 }

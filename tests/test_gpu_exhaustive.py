@@ -112,7 +112,7 @@ def test_first_pass_scores(L, dtype_name):
 
 
 @pytest.mark.parametrize("dtype_name", ["bf16", "fp8"])
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("dim", [256, 96])
 def test_first_pass_tile_variants(L, dtype_name, tile, dim):
     """Every score tile variant against the oracle: several row and column
@@ -135,6 +135,37 @@ def test_first_pass_tile_variants(L, dtype_name, tile, dim):
     dc, ds = O.quantize_views(db, dtype_name)
     ref = O.lowprec_exhaustive_scores(qc, qs, qoff, dc, ds, w.n_views)
     assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
+
+
+@pytest.mark.parametrize("dtype_name", ["bf16", "fp8"])
+@pytest.mark.parametrize("dim", [128, 384])
+@pytest.mark.parametrize("group", [8, 32])
+def test_first_pass_persistent_many_tiles(L, dtype_name, dim, group):
+    """The persistent tile (variant 8) with several tiles per block: 1,203
+    shapes of 21 views (pad views in every shape, a ragged last row tile)
+    against about 350 query views (a ragged second column tile), 602 tiles
+    for a grid of one block per CU.  Rows of 1, 2, 3 and 6 sub-tiles of 128
+    bytes make the stage parity alternate between tiles or not, and group 32
+    leaves a partial last row-tile group."""
+    _say(f"first pass persistent {dtype_name} dim {dim} group {group}")
+    w, db, q, qoff = _data(N=1203, dim=dim, B=5, m=(40, 100), nv=21, seed=12)
+    dt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
+    V, _, _ = _views(L, db, w.n_views, dt)
+    Q = _queries(L, q, qoff)
+    saved = L.gift_get_score_tuning(dt)
+    try:
+        L.gift_set_score_tuning(dt, 8, group)
+        S = L.gift_score_exhaustive(V, Q).cpu().numpy()
+        L.gift_set_score_tuning(dt, 6, group)
+        S6 = L.gift_score_exhaustive(V, Q).cpu().numpy()
+    finally:
+        L.gift_set_score_tuning(dt, *saved)
+    qc, qs = O.quantize_views(q, dtype_name)
+    dc, ds = O.quantize_views(db, dtype_name)
+    ref = O.lowprec_exhaustive_scores(qc, qs, qoff, dc, ds, w.n_views)
+    assert np.allclose(S, ref, rtol=REL, atol=1e-6), np.abs(S - ref).max()
+    # same MFMA order as the one-tile-per-block kernel: identical scores
+    assert np.array_equal(S, S6)
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
