@@ -516,7 +516,8 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 
 // One block per list tile of 128 entries and the batch's query views whose
 // word is that list: MFMA dots (entries x query views, 128 x 128 tiles, or
-// one 128 x 32 tile for up to 32 query views), the per-shape maximum over
+// one 128 x 32 tile for up to 32 query views, 128 x 16 for up to 16 with
+// float32 rows), the per-shape maximum over
 // the tile's entries (entries of a shape are contiguous), and an atomic max
 // into mbuf[query view][shape] (row stride ldn; 0 = no matching view yet).
 // Tile b of list w (tile_off[w] <= b < tile_off[w + 1]).
@@ -565,23 +566,63 @@ __device__ __forceinline__ void scan_list_tile(
     // up to 32 query views: one 128 x 32 tile instead of 128 x 128 mostly padding
     if (g1 - g0 <= NarrowShape::BN) {
       using N = NarrowShape;
-      const uint8_t* src[N::LOADS];
-#pragma unroll
-      for (int it = 0; it < N::LOADS; ++it) {
-        const int r = staged_row(it);
-        const uint8_t* p = nullptr;
-        if (r < N::BM) {
-          if (r < ne) {
-            const int64_t e = e0 + r;
-            p = db + ((int64_t)ent_shape[e] * n_views + ent_view[e]) * (int64_t)row_bytes;
-          }
-        } else if (g0 + (r - N::BM) < g1) {
-          p = qv + (int64_t)gitems[g0 + (r - N::BM)] * row_bytes;
-        }
-        src[it] = p;
-      }
       f32x16 acc;
-      mfma_tile_mainloop_narrow<DT>(lds, src, row_bytes, acc);
+      if (row_bytes % DMA2_KSUB == 0) {
+        // direct-to-LDS gather, two 128-byte sub-tiles in flight; pad rows
+        // read the tile's first entry or query view
+        const uint8_t* src[NARROW_NI];
+#pragma unroll
+        for (int i = 0; i < NARROW_NI; ++i) {
+          const int r = narrow_dma_row(i);
+          if (r < N::BM) {
+            const int64_t e = e0 + (r < ne ? r : 0);
+            src[i] = db + ((int64_t)ent_shape[e] * n_views + ent_view[e]) * (int64_t)row_bytes;
+          } else {
+            const int64_t c = g0 + (r - N::BM);
+            src[i] = qv + (int64_t)gitems[c < g1 ? c : g0] * row_bytes;
+          }
+        }
+        if constexpr (DT == GIFT_F32) {
+          if (g1 - g0 <= 16) {
+            // up to 16 query views: 128 x 16 on 16x16x4 MFMA, 8 rows per segment
+            f32x4 acc16[2];
+            mfma_tile_mainloop_narrow16_dma_f32(lds, src, row_bytes, acc16);
+            constexpr int LD16 = 17;
+#pragma unroll
+            for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                C[(wave * 32 + bk * 16 + 4 * ((threadIdx.x & 63) >> 4) + t) * LD16 + (threadIdx.x & 15)] =
+                    acc16[bk][t];
+            __syncthreads();
+            const int c = threadIdx.x & 15, seg = threadIdx.x >> 4;
+            if (g0 + c < g1) {
+              const int rbeg = seg * 8, rend = rbeg + 8 < ne ? rbeg + 8 : ne;
+              fold(c, LD16, rbeg, rend, gitems[g0 + c]);
+            }
+            __syncthreads();
+            return;
+          }
+        }
+        mfma_tile_mainloop_narrow_dma<DT>(lds, src, row_bytes, acc);
+      } else {
+        const uint8_t* src[N::LOADS];
+#pragma unroll
+        for (int it = 0; it < N::LOADS; ++it) {
+          const int r = staged_row(it);
+          const uint8_t* p = nullptr;
+          if (r < N::BM) {
+            if (r < ne) {
+              const int64_t e = e0 + r;
+              p = db + ((int64_t)ent_shape[e] * n_views + ent_view[e]) * (int64_t)row_bytes;
+            }
+          } else if (g0 + (r - N::BM) < g1) {
+            p = qv + (int64_t)gitems[g0 + (r - N::BM)] * row_bytes;
+          }
+          src[it] = p;
+        }
+        mfma_tile_mainloop_narrow<DT>(lds, src, row_bytes, acc);
+      }
       constexpr int LD = N::BN + 1;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -720,6 +761,7 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
   GIFT_LAUNCHED();
   const int64_t bound = n_entries / 128 + K + 1;
   GIFT_CHECK(bound < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many list tiles");
+  static_assert(NARROW_DMA_LDS_BYTES <= 128 * 129 * 4, "the narrow pipeline fits the C tile's LDS");
   const size_t shmem = 128 * 129 * 4;
   const int row_bytes = (int)row_bytes_of(db->dtype, db->dim);
 #define GIFT_SCAN_LAUNCH(DTV)                                                                  \

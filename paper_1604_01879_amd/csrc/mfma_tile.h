@@ -873,6 +873,135 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
   wait_vm_barrier<0>();  // LDS may be reused by the caller
 }
 
+// ------------------------------------------------- narrow tile, DMA loop
+// The 128 x 32 narrow tile with direct global->LDS loads of 128-byte
+// sub-tiles in NARROW_STAGES stages (two sub-tiles in flight while one is
+// multiplied).  Each lane gathers its own rows, so list entries need no
+// common base: wave w stages rows 40 w + 8 i + lane / 8 (i < 5) of the 160
+// (128 entries, then 32 query views), and chunk slot s of LDS row r holds
+// the row's chunk s ^ dma2_swizzle(r).  row_bytes must be a multiple of
+// 128, and every src row readable for row_bytes bytes (pad rows point at a
+// real row; their results are never used).
+constexpr int NARROW_STAGES = 3;
+static_assert(NARROW_STAGES >= 2 && NARROW_STAGES <= 4, "the loop waits for up to 2 later sub-tiles");
+constexpr int NARROW_NI = NarrowShape::ROWS / 32;  // 16-byte loads per lane per sub-tile
+constexpr int NARROW_STAGE_BYTES = NarrowShape::ROWS * DMA2_KSUB;
+constexpr size_t NARROW_DMA_LDS_BYTES = (size_t)NARROW_STAGES * NARROW_STAGE_BYTES;
+
+__device__ __forceinline__ int narrow_dma_row(int i) {
+  return (int)(threadIdx.x >> 6) * (NarrowShape::ROWS / 4) + 8 * i + (int)((threadIdx.x & 63) >> 3);
+}
+
+// The staging pipeline: calls step(stage) once per sub-tile, in order, with
+// that sub-tile's 160 rows in LDS (LDS row r at stage + 128 r).
+template <typename Step>
+__device__ __forceinline__ void narrow_dma_pipeline(uint8_t* lds, const uint8_t* const (&src)[NARROW_NI],
+                                                    int row_bytes, Step&& step) {
+  static_assert(NarrowShape::ROWS == 4 * 8 * NARROW_NI, "4 waves of 8-row loads");
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n_kt = row_bytes / DMA2_KSUB;
+  uint64_t gp[NARROW_NI];
+#pragma unroll
+  for (int i = 0; i < NARROW_NI; ++i)
+    gp[i] = (uint64_t)(uintptr_t)src[i] +
+            (uint64_t)(((lane & 7) ^ dma2_swizzle(narrow_dma_row(i))) * 16);
+  const uint32_t wave_lds = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (int)(uint32_t)(uintptr_t)((lds_u8*)lds + wave * (NarrowShape::ROWS / 4) * DMA2_KSUB));
+  auto issue = [&](int kt) {
+    const uint32_t base = wave_lds + (uint32_t)((kt % NARROW_STAGES) * NARROW_STAGE_BYTES);
+#pragma unroll
+    for (int i = 0; i < NARROW_NI; ++i)
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                   :
+                   : "v"(gp[i] + (uint64_t)(kt * DMA2_KSUB)), "s"(base + (uint32_t)(i * 8 * DMA2_KSUB))
+                   : "memory", "m0");
+  };
+#pragma unroll
+  for (int p = 0; p + 1 < NARROW_STAGES; ++p)
+    if (p < n_kt) issue(p);
+  for (int kt = 0; kt < n_kt; ++kt) {
+    // this wave's rows of sub-tile kt have landed (later ones may still be
+    // in flight); after the barrier every wave is past sub-tile kt - 1,
+    // whose stage the next load refills
+    const int later = min(NARROW_STAGES - 2, n_kt - 1 - kt);  // sub-tiles issued after kt
+    if (later >= 2) wait_vm_barrier<2 * NARROW_NI>();
+    else if (later == 1) wait_vm_barrier<NARROW_NI>();
+    else wait_vm_barrier<0>();
+    if (kt + NARROW_STAGES - 1 < n_kt) issue(kt + NARROW_STAGES - 1);
+    step(lds + (kt % NARROW_STAGES) * NARROW_STAGE_BYTES);
+  }
+  __syncthreads();  // LDS may be reused by the caller's epilogue
+}
+
+// 128 x 32 products: wave w holds rows 32 w .. 32 w + 31 (32x32 accumulator
+// layout), with the K-tile MFMAs of Mfma<DT>.
+template <int DT>
+__device__ __forceinline__ void mfma_tile_mainloop_narrow_dma(
+    uint8_t* lds, const uint8_t* const (&src)[NARROW_NI], int row_bytes, f32x16& acc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  const int sw = dma2_swizzle(l32);
+  narrow_dma_pipeline(lds, src, row_bytes, [&](const uint8_t* st) {
+    uint4 a[4], b[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int ch = ((4 * half + s2) ^ sw) * 16;
+      b[s2] = *reinterpret_cast<const uint4*>(st + (NarrowShape::BM + l32) * DMA2_KSUB + ch);
+      a[s2] = *reinterpret_cast<const uint4*>(st + (wave * 32 + l32) * DMA2_KSUB + ch);
+    }
+    Mfma<DT>::run(a, b, acc);
+  });
+}
+
+// float32 products of the 128 entries with the first 16 staged query views
+// on 16x16x4 MFMA, half the matrix work of the 32-column tile.  Lane l
+// supplies row (or column) l % 16 and, in step c of a sub-tile, the value
+// at float 8 (l / 16) + c; so lane group g covers floats [8 g, 8 g + 8)
+// and the 8 steps together all 32 floats of the sub-tile.  acc[b][t] is
+// row 32 w + 16 b + 4 (l / 16) + t, column l % 16.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void mfma_tile_mainloop_narrow16_dma_f32(
+    uint8_t* lds, const uint8_t* const (&src)[NARROW_NI], int row_bytes, f32x4 (&acc)[2]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[bk][t] = 0.f;
+  // LDS rows 32 w + 16 b + l16 (entries) and 128 + l16 (query views)
+  const int swa0 = dma2_swizzle(l16), swa1 = dma2_swizzle(16 + l16), swb = dma2_swizzle(l16);
+  narrow_dma_pipeline(lds, src, row_bytes, [&](const uint8_t* st) {
+    uint4 bq[2], aq[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bq[h] = *reinterpret_cast<const uint4*>(st + (NarrowShape::BM + l16) * DMA2_KSUB +
+                                              ((2 * g + h) ^ swb) * 16);
+      aq[0][h] = *reinterpret_cast<const uint4*>(st + (wave * 32 + l16) * DMA2_KSUB +
+                                                 ((2 * g + h) ^ swa0) * 16);
+      aq[1][h] = *reinterpret_cast<const uint4*>(st + (wave * 32 + 16 + l16) * DMA2_KSUB +
+                                                 ((2 * g + h) ^ swa1) * 16);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float bv[4] = {__builtin_bit_cast(float, bq[h].x), __builtin_bit_cast(float, bq[h].y),
+                           __builtin_bit_cast(float, bq[h].z), __builtin_bit_cast(float, bq[h].w)};
+#pragma unroll
+      for (int bk = 0; bk < 2; ++bk) {
+        const float av[4] = {__builtin_bit_cast(float, aq[bk][h].x), __builtin_bit_cast(float, aq[bk][h].y),
+                             __builtin_bit_cast(float, aq[bk][h].z), __builtin_bit_cast(float, aq[bk][h].w)};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], acc[bk], 0, 0, 0);
+      }
+    }
+  });
+}
+
 // Row (within the wave's WM*32 rows) and column of accumulator element e of
 // block (i, j) held by this lane.
 __device__ __forceinline__ int acc_row(int i, int e) {

@@ -153,14 +153,18 @@ def test_first_pass_fif_scores(L, dtype_name):
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
-@pytest.mark.parametrize("n_group", [31, 32, 33, 130])
-def test_scan_group_sizes_around_narrow_tile(L, dtype_name, n_group):
+@pytest.mark.parametrize("n_group", [1, 15, 16, 17, 31, 32, 33, 130])
+@pytest.mark.parametrize("dim", [96, 256])
+def test_scan_group_sizes_around_narrow_tile(L, dtype_name, n_group, dim):
     """One word (K = 1) puts every query view of the batch in one group: up
-    to 32 views take the 128 x 32 scan tile, more the 128 x 128 tiles (130
-    views: two column passes, the second of 2 views)."""
-    _say(f"fif group of {n_group} {dtype_name}")
+    to 16 views take the 128 x 16 scan tile (float32 rows of whole 128-byte
+    sub-tiles), up to 32 the 128 x 32 tile, more the 128 x 128 tiles (130
+    views: two column passes, the second of 2 views).  float32 rows of 384
+    and 1,024 bytes take the direct-to-LDS narrow loop (3 and 8 sub-tiles),
+    e4m3 rows of 96 bytes the register-staged one."""
+    _say(f"fif group of {n_group} {dtype_name} dim {dim}")
     dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]
-    w = _wl(n_shapes=70, dim=96, n_queries=1, m_lo=n_group, m_hi=n_group, n_views=19)
+    w = _wl(n_shapes=70, dim=dim, n_queries=1, m_lo=n_group, m_hi=n_group, n_views=19)
     db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 1, 1, dt)
     S, qw = L.gift_score_fif(V, F, Q)
     torch.cuda.synchronize()
