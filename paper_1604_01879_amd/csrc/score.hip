@@ -514,7 +514,9 @@ gift_status launch_score_tiles(const gift_views* db, const void* qv,
 // S[b][p] = (sum over the query's views, ascending) / m.  One block per
 // (256 shapes, query): the query's columns of the 256 mbuf rows are staged
 // through LDS 64 at a time with one wave reading one 256-byte row segment
-// (coalesced), then each thread sums its shape's values in view order.
+// (coalesced), then each thread sums its shape's values in view order.  A
+// wave keeps 16 row loads in flight; rows past the last shape and columns
+// past the query's last view re-read an in-range element, never summed.
 __global__ __launch_bounds__(256) void reduce_queries_kernel(
     const float* __restrict__ mbuf, int64_t ldm, int64_t n_shapes,
     const int32_t* __restrict__ qoff, float* __restrict__ S) {
@@ -526,10 +528,18 @@ __global__ __launch_bounds__(256) void reduce_queries_kernel(
   float acc = 0.f;
   for (int c0 = lo; c0 < hi; c0 += 64) {
     const int w = hi - c0 < 64 ? hi - c0 : 64;
+    const float* src = mbuf + c0 + (lane < w ? lane : w - 1);
     __syncthreads();
-    for (int r = wave; r < 256; r += 4) {
-      const int64_t p = p0 + r;
-      if (p < n_shapes && lane < w) tile[r * 65 + lane] = mbuf[p * ldm + c0 + lane];
+#pragma unroll
+    for (int r0 = 0; r0 < 256; r0 += 64) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int64_t p = p0 + r0 + wave + 4 * u;
+        v[u] = src[(p < n_shapes ? p : n_shapes - 1) * ldm];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) tile[(r0 + wave + 4 * u) * 65 + lane] = v[u];
     }
     __syncthreads();
     for (int i = 0; i < w; ++i) acc += tile[tid * 65 + i];
