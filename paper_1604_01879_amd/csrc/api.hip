@@ -199,6 +199,8 @@ struct AssignWs {
   float* nhi;
   float* nlo;
   int32_t* overflow;
+  uint8_t* xs;   // BF16-split rows of a chunk
+  uint8_t* cbs;  // BF16-split codebook
   int64_t chunk;
 };
 
@@ -208,13 +210,15 @@ static int64_t assign_chunk(int64_t n, int K) {
   return n < c ? (n > 0 ? n : 1) : c;
 }
 
-static AssignWs carve_assign(Carver& c, int64_t n, int K) {
+static AssignWs carve_assign(Carver& c, int64_t n, int K, int dim) {
   AssignWs w{};
   w.chunk = assign_chunk(n, K);
   w.D = c.take<float>((size_t)w.chunk * K);
   w.nhi = c.take<float>((size_t)K);
   w.nlo = c.take<float>((size_t)K);
   w.overflow = c.take<int32_t>(1);
+  w.xs = c.take<uint8_t>((size_t)w.chunk * dim * 4);
+  w.cbs = c.take<uint8_t>((size_t)K * dim * 4);
   return w;
 }
 
@@ -254,7 +258,7 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
   FifWs w{};
   const int64_t tq = q->total_views;
   w.qwords = c.take<int32_t>((size_t)tq);
-  w.as = carve_assign(c, tq, f->K);
+  w.as = carve_assign(c, tq, f->K, db->dim);
   w.goff = c.take<int64_t>((size_t)f->K + 1);
   w.gitems = c.take<int32_t>((size_t)tq);
   w.bucket = c.take<uint8_t>(bucket_sort_ws(tq, f->K));
@@ -298,7 +302,8 @@ static gift_status fif_first_pass(const gift_views* db, const gift_fif* f, const
   launch_fill_i32(w.as.overflow, 1, 0, st);
   prof_begin(P_ASSIGN, st);
   gift_status s = launch_assign(q->views, tq, db->dim, f->codebook, f->K, 1, w.qwords, w.as.D,
-                                w.as.chunk, w.as.nhi, w.as.nlo, w.as.overflow, st);
+                                w.as.chunk, w.as.nhi, w.as.nlo, w.as.overflow, w.as.xs, w.as.cbs,
+                                st);
   prof_end(st);
   if (s != GIFT_OK) return s;
   prof_begin(P_GROUP, st);
@@ -462,10 +467,9 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
 
 /* ------------------------------------------------------------ quantizer */
 size_t gift_assign_workspace(int64_t n, int32_t dim, int32_t K, int32_t ma) {
-  (void)dim;
   (void)ma;
   Carver c(nullptr);
-  carve_assign(c, n, K);
+  carve_assign(c, n, K, dim);
   return c.bytes();
 }
 
@@ -478,14 +482,15 @@ gift_status gift_assign(const float* x, int64_t n, int32_t dim, const float* cod
   GIFT_CHECK(aligned(x, 16), GIFT_EINVAL, "input rows must be 16-byte aligned");
   const hipStream_t st = (hipStream_t)stream;
   Carver c(ws);
-  AssignWs w = carve_assign(c, n, K);
+  AssignWs w = carve_assign(c, n, K, dim);
   GIFT_CHECK(ws != nullptr && ws_bytes >= c.bytes(), GIFT_EWORKSPACE,
              "workspace needs %zu bytes, got %zu", c.bytes(), ws_bytes);
   int32_t* ovf = n_uncertified ? n_uncertified : w.overflow;
   launch_fill_i32(ovf, 1, 0, st);
   GIFT_LAUNCHED();
   prof_begin(P_ASSIGN, st);
-  s = launch_assign(x, n, dim, codebook, K, ma, words, w.D, w.chunk, w.nhi, w.nlo, ovf, st);
+  s = launch_assign(x, n, dim, codebook, K, ma, words, w.D, w.chunk, w.nhi, w.nlo, ovf, w.xs,
+                    w.cbs, st);
   prof_end(st);
   return s;
 }
@@ -513,7 +518,7 @@ static KmWs carve_km(void* base, int64_t n, int dim, int K) {
   w.changes = c.take<int32_t>(1);
   w.idx = c.take<int64_t>((size_t)K);
   w.bucket = c.take<uint8_t>(bucket_sort_ws(n, K));
-  w.as = carve_assign(c, n, K);
+  w.as = carve_assign(c, n, K, dim);
   w.bytes = c.bytes();
   return w;
 }
@@ -542,7 +547,7 @@ gift_status gift_build_codebook(const float* train, int64_t n, int32_t dim, int3
   GIFT_LAUNCHED();
   launch_fill_i32(w.as.overflow, 1, 0, st);
   s = launch_assign(train, n, dim, codebook, K, 1, assign, w.as.D, w.as.chunk, w.as.nhi,
-                    w.as.nlo, w.as.overflow, st);
+                    w.as.nlo, w.as.overflow, w.as.xs, w.as.cbs, st);
   if (s != GIFT_OK) return s;
   float* cur = codebook;
   float* nxt = w.cb2;
@@ -555,7 +560,7 @@ gift_status gift_build_codebook(const float* train, int64_t n, int32_t dim, int3
     launch_centroids(train, dim, K, w.moff, w.members, cur, nxt, st);
     GIFT_LAUNCHED();
     s = launch_assign(train, n, dim, nxt, K, 1, a_nxt, w.as.D, w.as.chunk, w.as.nhi, w.as.nlo,
-                      w.as.overflow, st);
+                      w.as.overflow, w.as.xs, w.as.cbs, st);
     if (s != GIFT_OK) return s;
     launch_fill_i32(w.changes, 1, 0, st);
     launch_count_changes(a_cur, a_nxt, n, w.changes, st);
@@ -585,7 +590,7 @@ size_t gift_build_fif_workspace(const gift_views* db, int32_t K, int32_t ma) {
   if (check_views(db) != GIFT_OK) return 0;
   const int64_t nv = db->n_shapes * db->n_views;
   Carver c(nullptr);
-  carve_assign(c, nv, K);
+  carve_assign(c, nv, K, db->dim);
   c.take<uint8_t>(bucket_sort_ws(nv * ma, K));
   return c.bytes();
 }
@@ -602,14 +607,14 @@ gift_status gift_build_fif(const gift_views* db, const float* codebook, int32_t 
   GIFT_CHECK(nv * ma < ((int64_t)1 << 31), GIFT_ECAPACITY, "too many entries");
   const hipStream_t st = (hipStream_t)stream;
   Carver c(ws);
-  AssignWs w = carve_assign(c, nv, K);
+  AssignWs w = carve_assign(c, nv, K, db->dim);
   void* bucket = c.take<uint8_t>(bucket_sort_ws(nv * ma, K));
   GIFT_CHECK(ws != nullptr && ws_bytes >= c.bytes(), GIFT_EWORKSPACE,
              "workspace needs %zu bytes, got %zu", c.bytes(), ws_bytes);
   launch_fill_i32(w.overflow, 1, 0, st);
   GIFT_LAUNCHED();
   s = launch_assign(db->master, nv, db->dim, codebook, K, ma, view_words, w.D, w.chunk, w.nhi,
-                    w.nlo, w.overflow, st);
+                    w.nlo, w.overflow, w.xs, w.cbs, st);
   if (s != GIFT_OK) return s;
   s = launch_bucket_sort(view_words, nv * ma, K, offsets, 1, ma, db->n_views, entry_shape,
                          entry_view, bucket, st);

@@ -54,6 +54,87 @@ __global__ __launch_bounds__(256, 2) void dots_kernel(
   dots_tile(x, r0, r1, cb, K, dim, D, row_tile, blockIdx.x - row_tile * n_col_tiles, lds);
 }
 
+// ------------------------------------------------------- split-row GEMM
+// The same dots from rows split once into BF16 parts (split_bf16x4: hi =
+// bf16(x), lo = bf16(x - hi)).  A split row holds, per 32 values, their 32
+// high parts (64 bytes) then their 32 low parts, so its 128-byte chunk c is
+// sub-tile c of the direct-to-LDS loop (values 32 c .. 32 c + 31).  Rows
+// must be a whole number of 32 values.
+__global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ src,
+                                                         int64_t n_rows, int dim,
+                                                         uint8_t* __restrict__ dst) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;  // 4 values per thread
+  const int per_row = dim / 4;
+  if (q >= n_rows * per_row) return;
+  const int64_t r = q / per_row;
+  const int t = (int)(q - r * per_row) * 4;  // first value
+  uint2 hi, lo;
+  split_bf16x4(*reinterpret_cast<const uint4*>(src + r * dim + t), hi, lo);
+  uint8_t* row = dst + r * (int64_t)dim * 4 + (t / 32) * 128 + (t % 32) * 2;
+  *reinterpret_cast<uint2*>(row) = hi;
+  *reinterpret_cast<uint2*>(row + 64) = lo;
+}
+
+// 256 x 256 tile of D from split rows on the score kernel's direct-to-LDS
+// loop (8 waves of 128 x-rows x 64 codewords, two 64 KB stages of 128-byte
+// sub-tiles).  Each sub-tile's 6 MFMAs per 32 x 32 block go into a fresh
+// part added into the total: the products, order and bound of dots_tile,
+// so D is bit-identical to it.  Tiles in the score kernel's order, GROUP
+// row tiles sharing each column sweep.  xs holds the split rows r0 .. r1 - 1
+// (row r at index r - r0).
+constexpr int SPLIT_TILE = 256;
+
+__global__ __launch_bounds__(512, 1) void dots_split_kernel(
+    const uint8_t* __restrict__ xs, int64_t r0, int64_t r1, const uint8_t* __restrict__ cbs, int K,
+    int dim, float* __restrict__ D, int64_t n_row_tiles, int64_t n_col_tiles) {
+  constexpr int WM = 4, WN = 2, WC = 4;
+  using S = Dma2Shape<WM, WN, WC, 2>;
+  static_assert(S::BM == SPLIT_TILE && S::BN == SPLIT_TILE, "256 x 256 tiles");
+  extern __shared__ __align__(16) uint8_t lds[];
+  constexpr int64_t GROUP = 8;
+  const int64_t id = blockIdx.x;
+  const int64_t per_group = GROUP * n_col_tiles;
+  const int64_t gi = id / per_group;
+  const int64_t rem = id - gi * per_group;
+  const int64_t rows_in_group = n_row_tiles - gi * GROUP < GROUP ? n_row_tiles - gi * GROUP : GROUP;
+  const int64_t row_tile = gi * GROUP + rem % rows_in_group;
+  const int64_t col_tile = rem / rows_in_group;
+  const int64_t rb = r0 + row_tile * SPLIT_TILE;  // first x row of the tile
+  const int64_t cb0 = col_tile * SPLIT_TILE;      // first codeword
+  const int row_bytes = dim * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  // staged rows as offsets from the tile's first x row and first codeword
+  // (under 2^32: 256 rows of at most 16 MB); pad rows re-read the first
+  uint32_t roff[S::NI];
+#pragma unroll
+  for (int i = 0; i < S::NI; ++i) {
+    const int r = wave * S::WROWS + 8 * i + lane / 8;
+    uint32_t o = 0;
+    if (r < S::BM) {
+      if (rb + r < r1) o = (uint32_t)(r * row_bytes);
+    } else if (cb0 + (r - S::BM) < K) {
+      o = (uint32_t)((r - S::BM) * row_bytes);
+    }
+    roff[i] = o;
+  }
+  f32x16 acc[WM][WN];
+  mfma_tile_mainloop_dma128<DMA_SPLIT_BF16, WM, WN, WC>(
+      lds, xs + (rb - r0) * (int64_t)row_bytes, cbs + cb0 * (int64_t)row_bytes, roff, row_bytes,
+      acc);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t r = rb + wr * WM * 32 + acc_row(i, e);
+        const int64_t k = cb0 + wc * WN * 32 + acc_col(j);
+        if (r < r1 && k < K) D[(r - r0) * K + k] = acc[i][j][e];
+      }
+}
+
 // ------------------------------------------------------------------ norms
 // ||b_k||^2 as a compensated sum, one wave per codeword.
 __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb, int K, int dim,
@@ -276,22 +357,43 @@ __global__ __launch_bounds__(256) void assign_select_kernel(
 
 gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, int K, int ma,
                           int32_t* words, float* D, int64_t chunk_rows, float* nhi, float* nlo,
-                          int32_t* overflow, hipStream_t st) {
+                          int32_t* overflow, uint8_t* xs, uint8_t* cbs, hipStream_t st) {
   if (n <= 0) return GIFT_OK;
   hipLaunchKernelGGL(norms_kernel, dim3((K + 3) / 4), dim3(256), 0, st, cb, K, dim, nhi, nlo);
   GIFT_LAUNCHED();
   using T = TileShape<2, 2>;
+  // the pipelined GEMM on split rows when their buffers are given
+  const bool split = xs != nullptr && cbs != nullptr;
+  const size_t split_lds = Dma2Shape<4, 2, 4, 2>::LDS_BYTES;
   {
-    const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(dots_kernel), T::LDS_BYTES);
+    const gift_status s =
+        split ? ensure_dynamic_lds(reinterpret_cast<const void*>(dots_split_kernel), split_lds)
+              : ensure_dynamic_lds(reinterpret_cast<const void*>(dots_kernel), T::LDS_BYTES);
     if (s != GIFT_OK) return s;
+  }
+  if (split) {
+    const int64_t q = (int64_t)K * (dim / 4);
+    hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, cb,
+                       (int64_t)K, dim, cbs);
+    GIFT_LAUNCHED();
   }
   const float gamma2 = assign_gamma2(dim);
   const int64_t n_col_tiles = (K + T::BN - 1) / T::BN;
   for (int64_t r0 = 0; r0 < n; r0 += chunk_rows) {
     const int64_t r1 = r0 + chunk_rows < n ? r0 + chunk_rows : n;
     const int64_t n_row_tiles = (r1 - r0 + T::BM - 1) / T::BM;
-    hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(n_row_tiles * n_col_tiles)), dim3(256),
-                       T::LDS_BYTES, st, x, r0, r1, cb, K, dim, D, n_col_tiles);
+    if (split) {
+      const int64_t q = (r1 - r0) * (dim / 4);
+      hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st,
+                         x + r0 * dim, r1 - r0, dim, xs);
+      GIFT_LAUNCHED();
+      const int64_t nr = (r1 - r0 + SPLIT_TILE - 1) / SPLIT_TILE, nc = (K + SPLIT_TILE - 1) / SPLIT_TILE;
+      hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st,
+                         xs, r0, r1, cbs, K, dim, D, nr, nc);
+    } else {
+      hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(n_row_tiles * n_col_tiles)), dim3(256),
+                         T::LDS_BYTES, st, x, r0, r1, cb, K, dim, D, n_col_tiles);
+    }
     GIFT_LAUNCHED();
     hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)((r1 - r0 + 3) / 4)), dim3(256), 0, st,
                        x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow);

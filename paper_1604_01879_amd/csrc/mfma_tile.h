@@ -760,6 +760,11 @@ __device__ __forceinline__ void dma128_issue(uint32_t base, uint64_t g, const ui
                  : "memory", "m0");
 }
 
+// Pseudo storage type of the K128 loop for float32 rows split once into
+// BF16 parts: each 128-byte sub-tile holds 32 values as 32 high parts
+// (bf16(x)) then 32 low parts (bf16(x - hi)).
+constexpr int DMA_SPLIT_BF16 = 16;
+
 // MFMAs of one staged 128-byte sub-tile: the wave multiplies its WM x WN
 // blocks of 32 x 32 (rows wr * WM * 32 + 32 i, columns wc * WN * 32 + 32 j of
 // the A stage sta and the B stage stb).  Operand rows all have l32 as their
@@ -776,6 +781,49 @@ __device__ __forceinline__ void dma128_subtile_mfma(const uint8_t* sta, const ui
   const int sw = dma2_swizzle(l32);
   const int arow = (wr * WM * 32 + l32) * DMA2_KSUB;
   const int brow = (wc * WN * 32 + l32) * DMA2_KSUB;
+  if constexpr (DT == DMA_SPLIT_BF16) {
+    // 32 values: chunks 0..3 hold their high parts, 4..7 their low parts;
+    // lane half h supplies values 16 h + 8 st .. + 8 at step st.  Per block,
+    // hi.hi', hi.lo', lo.hi' of both steps go into a fresh part added into
+    // the total (the split loop's products, order and bound).
+    uint4 bh[WN][2], bl[WN][2];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const int c = 2 * half + st;
+        bh[j][st] = *reinterpret_cast<const uint4*>(stb + brow + j * 32 * DMA2_KSUB + (c ^ sw) * 16);
+        bl[j][st] = *reinterpret_cast<const uint4*>(stb + brow + j * 32 * DMA2_KSUB + ((4 + c) ^ sw) * 16);
+      }
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      uint4 ah[2], al[2];
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const int c = 2 * half + st;
+        ah[st] = *reinterpret_cast<const uint4*>(sta + arow + i * 32 * DMA2_KSUB + (c ^ sw) * 16);
+        al[st] = *reinterpret_cast<const uint4*>(sta + arow + i * 32 * DMA2_KSUB + ((4 + c) ^ sw) * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        f32x16 part;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[e] = 0.f;
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[j][st]), part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
+                                                         __builtin_bit_cast(bf16x8, bl[j][st]), part, 0, 0, 0);
+          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[st]),
+                                                         __builtin_bit_cast(bf16x8, bh[j][st]), part, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][j][e] += part[e];
+      }
+    }
+    return;
+  }
   constexpr int NSTEP = DT == GIFT_BF16 ? 4 : 2;  // MFMA steps per sub-tile
   constexpr int FR = DT == GIFT_BF16 ? 1 : 2;     // 16-byte pieces per lane per step
   auto chunk = [&](int st, int f) {
@@ -821,7 +869,8 @@ __device__ __forceinline__ void mfma_tile_mainloop_dma128(
     const uint32_t (&roff)[Dma2Shape<WM, WN, WC, BST>::NI], int row_bytes,
     f32x16 (&acc)[WM][WN]) {
   using T = Dma2Shape<WM, WN, WC, BST>;
-  static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3, "BF16 / e4m3 storage only");
+  static_assert(DT == GIFT_BF16 || DT == GIFT_FP8E4M3 || DT == DMA_SPLIT_BF16,
+                "BF16 / e4m3 storage or split float32 rows only");
   static_assert(T::BM % T::WROWS == 0, "a wave stages rows of one side only");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
