@@ -56,13 +56,13 @@ def test_assign_matches_oracle(L, ma):
     _assert_words(words.cpu().numpy(), x, cb, ma)
 
 
-@pytest.mark.parametrize("dim", [64, 96, 192, 256])
+@pytest.mark.parametrize("dim", [32, 64, 96, 192, 256])
 @pytest.mark.parametrize("ma", [1, 3])
 def test_assign_row_lengths(L, dim, ma):
     """The quantizer (pipelined GEMM on BF16-split rows) against the oracle
-    for rows of 2, 3, 6 and 8 sub-tiles of 32 values, so the two LDS stages
-    end on either parity, with ragged 256 x 256 tiles (1,000 rows, 300
-    codewords)."""
+    for rows of 1, 2, 3, 6 and 8 sub-tiles of 32 values, so the two LDS
+    stages end on either parity, with ragged 256 x 256 tiles (1,000 rows,
+    300 codewords)."""
     _say(f"assign dim={dim} ma={ma}")
     w = _wl(n_shapes=40, dim=dim, n_views=25)
     db, _, _ = synth.make_db(w)
