@@ -423,7 +423,7 @@ def _recorded_traffic(dtype, tuning, w, query_views):
     return float(rec["calibrated_bytes_per_launch"])
 
 
-_PHASES = ("quantize", "clear", "codeword_dots", "word_select", "word_offsets", "grouping",
+_PHASES = ("quantize", "codeword_dots", "clear", "word_select", "word_offsets", "grouping",
            "active_tiles", "list_scan", "query_mean")
 
 

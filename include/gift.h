@@ -318,10 +318,11 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* before each run; q_offsets[0] = 0), and the outputs ids / scores        */
 /* [max_queries][top_k] and flags [max_queries] (NULL allowed).  The first */
 /* pass runs as ONE persistent kernel whose blocks take work items         */
-/* (quantize, clear, dot tiles, word selection, grouping, list tiles,      */
-/* per-query means) in order from a device queue; it is followed by the    */
-/* selection, rescore and final-ranking kernels, and the whole sequence is */
-/* captured once into a HIP graph.  gift_fif_plan_run(n_queries, n_views)  */
+/* (split and quantize, dot tiles, clear, word selection, grouping, list   */
+/* tiles, per-query means) in order from a device queue; it is followed by */
+/* the selection, rescore and final-ranking kernels, and the whole         */
+/* sequence is captured once into a HIP graph.                              */
+/* gift_fif_plan_run(n_queries, n_views)                                   */
 /* launches that graph for a batch occupying the first n_queries slots and  */
 /* n_views rows; outputs of unused slots are unspecified.  Results equal   */
 /* those of gift_query_fif on the same batch.  blocks_per_cu (1 or 2) sets */
@@ -333,8 +334,8 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* gift_fif_plan_phase_us (SYNCHRONISES) writes, for the last run, the     */
 /* block-microseconds spent in each phase of the persistent kernel (sum    */
 /* over blocks of the wall time from taking an item to finishing it):      */
-/* out[9] = quantize, clear, codeword dots, word selection, word offsets,  */
-/* grouping, active-tile listing, list scan, per-query mean.               */
+/* out[9] = split and quantize, codeword dots, clear, word selection,     */
+/* word offsets, grouping, active-tile listing, list scan, per-query mean. */
 /* ---------------------------------------------------------------------- */
 typedef struct gift_fif_plan gift_fif_plan;
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,

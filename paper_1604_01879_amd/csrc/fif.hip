@@ -135,6 +135,69 @@ __global__ __launch_bounds__(512, 1) void dots_split_kernel(
       }
 }
 
+void launch_split_rows(const float* src, int64_t n, int dim, uint8_t* dst, hipStream_t st) {
+  const int64_t q = n * (dim / 4);
+  if (q <= 0) return;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, src, n,
+                     dim, dst);
+}
+
+// One wave splits row v of x into dst (the split_rows_kernel layout).
+__device__ __forceinline__ void split_row_wave(const float* __restrict__ x, int64_t v, int dim,
+                                               uint8_t* __restrict__ dst) {
+  const int lane = threadIdx.x & 63;
+  const float* src = x + v * dim;
+  uint8_t* row = dst + v * (int64_t)dim * 4;
+  for (int t = lane * 4; t < dim; t += 256) {
+    uint2 hi, lo;
+    split_bf16x4(*reinterpret_cast<const uint4*>(src + t), hi, lo);
+    uint8_t* o = row + (t / 32) * 128 + (t % 32) * 2;
+    *reinterpret_cast<uint2*>(o) = hi;
+    *reinterpret_cast<uint2*>(o + 64) = lo;
+  }
+}
+
+// 128 x 128 tile of D (rows of xs, codewords of cbs, both split) for a
+// 4-wave block with 64 KB of LDS: the direct-to-LDS loop with 64 x 64 per
+// wave.  Same products, order and bound as dots_tile.
+__device__ __forceinline__ void dots_split_tile(const uint8_t* __restrict__ xs, int64_t n_rows,
+                                                const uint8_t* __restrict__ cbs, int K, int dim,
+                                                float* __restrict__ D, int64_t row_tile,
+                                                int64_t col_tile, uint8_t* lds) {
+  constexpr int WM = 2, WN = 2, WC = 2;
+  using S = Dma2Shape<WM, WN, WC, 2>;
+  const int64_t rb = row_tile * S::BM, cb0 = col_tile * S::BN;
+  const int row_bytes = dim * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  uint32_t roff[S::NI];
+#pragma unroll
+  for (int i = 0; i < S::NI; ++i) {
+    const int r = wave * S::WROWS + 8 * i + lane / 8;
+    uint32_t o = 0;
+    if (r < S::BM) {
+      if (rb + r < n_rows) o = (uint32_t)(r * row_bytes);
+    } else if (cb0 + (r - S::BM) < K) {
+      o = (uint32_t)((r - S::BM) * row_bytes);
+    }
+    roff[i] = o;
+  }
+  f32x16 acc[WM][WN];
+  mfma_tile_mainloop_dma128<DMA_SPLIT_BF16, WM, WN, WC>(
+      lds, xs + rb * (int64_t)row_bytes, cbs + cb0 * (int64_t)row_bytes, roff, row_bytes, acc);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t r = rb + wr * WM * 32 + acc_row(i, e);
+        const int64_t k = cb0 + wc * WN * 32 + acc_col(j);
+        if (r < n_rows && k < K) D[r * K + k] = acc[i][j][e];
+      }
+}
+
 // ------------------------------------------------------------------ norms
 // ||b_k||^2 as a compensated sum, one wave per codeword.
 __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb, int K, int dim,
@@ -974,7 +1037,7 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   // counters, word counts, and the offsets of unused query slots
   const int n_q = a.desc[0];
-  for (int i = threadIdx.x; i < 4; i += 256) a.ctrl[i] = 0ull;
+  for (int i = threadIdx.x; i < BATCH_CTRL_WORDS; i += 256) a.ctrl[i] = 0ull;
   for (int i = threadIdx.x; i < BP_END; i += 256) a.phase_ticks[i] = 0ull;
   for (int k = threadIdx.x; k < a.K; k += 256) a.counts[k] = 0;
   if (threadIdx.x == 0) *a.overflow = 0;
@@ -1020,15 +1083,16 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   unsigned long long* done = a.ctrl + 1;
   unsigned long long* err = a.ctrl + 2;
   unsigned long long* n_active_w = a.ctrl + 3;  // active list tiles, written by PRE
+  unsigned long long* q_done = a.ctrl + 4;      // finished Q items
   const int n_q = a.desc[0];
   const int64_t n_v = a.desc[1];
   // first items of Q..TILE and of SCAN, from the batch's view count
   int64_t first[BP_SCAN + 1];
   {
     const int64_t n_items[BP_SCAN] = {
-        DT == GIFT_F32 ? 0 : (n_v + 63) / 64,                                   // Q
-        (n_v * a.n_shapes + BATCH_FILL_WORDS - 1) / BATCH_FILL_WORDS,           // FILL
+        (n_v + 63) / 64,                                                        // Q
         ((n_v + 127) / 128) * a.gemm_col_tiles,                                 // GEMM
+        (n_v * a.n_shapes + BATCH_FILL_WORDS - 1) / BATCH_FILL_WORDS,           // FILL
         (n_v + 3) / 4,                                                          // SEL
         1,                                                                      // PRE
         (n_v + 255) / 256,                                                      // SCAT
@@ -1087,13 +1151,18 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
         break;
       }
     }
-    const bool needs_wait = ph == BP_SEL || ph == BP_PRE || ph == BP_SCAT || ph == BP_TILE ||
-                            ph == BP_RED;
+    // GEMM reads the views Q split; later phases read what all earlier
+    // phases wrote
+    const bool needs_wait = ph == BP_GEMM || ph == BP_SEL || ph == BP_PRE || ph == BP_SCAT ||
+                            ph == BP_TILE || ph == BP_RED;
     if (tid == 0) {
       int e = (int)__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // phases only grow within a block: one wait and one acquire per phase
       if (needs_wait && ph > acquired && e == 0) {
-        e = wait_done(done, err, (unsigned long long)need, a.wait_ticks);
+        // GEMM waits for the Q items alone: they precede it in the queue but
+        // may finish after FILL items, which wait for nothing
+        e = ph == BP_GEMM ? wait_done(q_done, err, (unsigned long long)first[BP_GEMM], a.wait_ticks)
+                          : wait_done(done, err, (unsigned long long)need, a.wait_ticks);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         acquired = ph;
       }
@@ -1105,12 +1174,15 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     if (!sh_err) {
       switch (ph) {
         case BP_Q: {
+          // split the views for the codeword GEMM; code them in the storage
+          // type for the list scan
           const int wave = tid >> 6;
           for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4) {
+            split_row_wave(a.qviews, v, a.dim, a.qsplit);
             if constexpr (DT == GIFT_MXFP8 || DT == GIFT_MXFP4)
               quantize_view_mx_wave(a.qviews, v, a.dim, DT, a.qcodes,
                                     static_cast<uint8_t*>(a.qscale));
-            else
+            else if constexpr (DT != GIFT_F32)
               quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, static_cast<float*>(a.qscale));
           }
           wrote = true;
@@ -1131,7 +1203,8 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
         }
         case BP_GEMM: {
           const int64_t rt = j / a.gemm_col_tiles;
-          dots_tile(a.qviews, 0, n_v, a.cb, a.K, a.dim, a.D, rt, j - rt * a.gemm_col_tiles, lds);
+          dots_split_tile(a.qsplit, n_v, a.cbsplit, a.K, a.dim, a.D, rt,
+                          j - rt * a.gemm_col_tiles, lds);
           wrote = true;
           break;
         }
@@ -1229,6 +1302,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
+      if (ph == BP_Q) __hip_atomic_fetch_add(q_done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&a.phase_ticks[ph], (unsigned long long)(wall_clock64() - t_item),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -96,7 +96,8 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
                        int n_queries, float* S, hipStream_t st);
 
 // ---- persistent batch of the F-IF first pass
-enum BatchPhase { BP_Q = 0, BP_FILL, BP_GEMM, BP_SEL, BP_PRE, BP_SCAT, BP_TILE, BP_SCAN, BP_RED,
+constexpr int BATCH_CTRL_WORDS = 8;
+enum BatchPhase { BP_Q = 0, BP_GEMM, BP_FILL, BP_SEL, BP_PRE, BP_SCAT, BP_TILE, BP_SCAN, BP_RED,
                   BP_END };
 constexpr int64_t BATCH_FILL_WORDS = (int64_t)1 << 18;  // mbuf words cleared per FILL item
 constexpr int64_t BATCH_RED_SHAPES = 1024;            // shapes of one query per RED item
@@ -115,6 +116,8 @@ struct BatchArgs {
   const int64_t* tile_off;
   const int32_t* tile_word;  // list of each tile of the concatenated lists
   const float* qviews;
+  uint8_t* qsplit;           // the batch's query views split into BF16 parts
+  const uint8_t* cbsplit;    // the codebook split into BF16 parts
   int32_t* qoff;
   int Bmax;
   int64_t Vmax;
@@ -132,7 +135,7 @@ struct BatchArgs {
   uint32_t* mbuf;
   float* S;
   int32_t* overflow;
-  unsigned long long* ctrl;  // head, done, error, spare
+  unsigned long long* ctrl;  // [BATCH_CTRL_WORDS]: head, done, error, active tiles, Q done
   unsigned long long* phase_ticks;  // [BP_END] wall-clock ticks per phase
   float gamma2;
   int64_t wait_ticks;        // wall-clock ticks a phase wait may take
@@ -141,6 +144,9 @@ struct BatchArgs {
 void launch_batch_reset(const BatchArgs& a, hipStream_t st);
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st);
 gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo, hipStream_t st);
+// n rows of dim float32 values split into BF16 parts, dim x 4 bytes per row:
+// per 32 values, 32 high parts then 32 low parts (split_rows_kernel).
+void launch_split_rows(const float* src, int64_t n, int dim, uint8_t* dst, hipStream_t st);
 gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64_t* tile_off,
                               hipStream_t st);
 void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStream_t st);

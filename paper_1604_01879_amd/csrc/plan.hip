@@ -18,6 +18,8 @@ struct PlanWs {
   int32_t* desc;
   uint8_t* qcodes;
   void* qscale;
+  uint8_t* qsplit;   // query views split into BF16 parts (codeword GEMM)
+  uint8_t* cbsplit;  // codebook split into BF16 parts
   float* D;
   int32_t* qwords;
   int32_t* counts;
@@ -57,6 +59,8 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
     w.qscale = c.take<uint8_t>(is_mx(db->dtype) ? (size_t)Vmax * (db->dim / 32)
                                                 : (size_t)Vmax * sizeof(float));
   }
+  w.qsplit = c.take<uint8_t>((size_t)Vmax * db->dim * 4);
+  w.cbsplit = c.take<uint8_t>((size_t)f->K * db->dim * 4);
   w.D = c.take<float>((size_t)Vmax * f->K);
   w.qwords = c.take<int32_t>((size_t)Vmax);
   w.counts = c.take<int32_t>((size_t)f->K);
@@ -66,7 +70,7 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.mbuf = c.take<uint32_t>((size_t)db->n_shapes * Vmax);
   w.S = c.take<float>((size_t)Bmax * db->n_shapes);
   w.overflow = c.take<int32_t>(1);
-  w.ctrl = c.take<unsigned long long>(4);
+  w.ctrl = c.take<unsigned long long>(BATCH_CTRL_WORDS);
   w.phase_ticks = c.take<unsigned long long>(BP_END);
   w.cand = c.take<int32_t>((size_t)Bmax * r);
   w.cand_s = c.take<float>((size_t)Bmax * r);
@@ -207,8 +211,12 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
     return fail(GIFT_EHIP, "cannot query the wall-clock rate");
   }
 
-  // once per plan: codebook norms and list-tile offsets
+  // once per plan: codebook norms, split codebook and list-tile offsets
   gift_status s = launch_norms(fif->codebook, fif->K, db->dim, w.nhi, w.nlo, st);
+  if (s == GIFT_OK) {
+    launch_split_rows(fif->codebook, fif->K, db->dim, w.cbsplit, st);
+    if (hipGetLastError() != hipSuccess) s = fail(GIFT_EHIP, "codebook split launch failed");
+  }
   if (s == GIFT_OK) s = launch_list_tiles(fif->offsets, fif->K, w.tcount, w.tile_off, st);
   if (s == GIFT_OK) {
     launch_tile_word(w.tile_off, fif->K, w.tile_word, st);
@@ -237,6 +245,8 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.tile_off = w.tile_off;
   a.tile_word = w.tile_word;
   a.qviews = q_views;
+  a.qsplit = w.qsplit;
+  a.cbsplit = w.cbsplit;
   a.qoff = q_offsets;
   a.Bmax = max_queries;
   a.Vmax = max_views;
