@@ -8,55 +8,10 @@
 namespace gift {
 
 // ------------------------------------------------------------------ GEMM
-// D[r - r0][k] ~ x_r . b_k in split-BF16 on MFMA (128 x 128 block tiles),
-// within (3.02 * 2^-16 + 1.02 gamma(6 * 17 + dim / 32 + 2)) ||x_r|| ||b_k||.
-__device__ __forceinline__ void dots_tile(const float* __restrict__ x, int64_t r0, int64_t r1,
-                          const float* __restrict__ cb, int K, int dim, float* __restrict__ D,
-                          int64_t row_tile, int64_t col_tile, uint8_t* lds) {
-  using T = TileShape<2, 2>;
-  const int64_t rb = r0 + row_tile * T::BM;
-  const int64_t cb0 = col_tile * T::BN;
-  const int row_bytes = dim * 4;
-  const uint8_t* src[T::LOADS];
-#pragma unroll
-  for (int it = 0; it < T::LOADS; ++it) {
-    const int r = staged_row(it);
-    const uint8_t* p = nullptr;
-    if (r < T::BM) {
-      if (rb + r < r1) p = reinterpret_cast<const uint8_t*>(x + (rb + r) * dim);
-    } else {
-      const int64_t k = cb0 + (r - T::BM);
-      if (k < K) p = reinterpret_cast<const uint8_t*>(cb + k * dim);
-    }
-    src[it] = p;
-  }
-  f32x16 acc[2][2];
-  mfma_tile_mainloop_split<2, 2>(lds, src, row_bytes, acc);
-  const int wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t r = rb + wr * 64 + acc_row(i, e);
-        const int64_t k = cb0 + wc * 64 + acc_col(j);
-        if (r < r1 && k < K) D[(r - r0) * K + k] = acc[i][j][e];
-      }
-}
-
-__global__ __launch_bounds__(256, 2) void dots_kernel(
-    const float* __restrict__ x, int64_t r0, int64_t r1, const float* __restrict__ cb,
-    int K, int dim, float* __restrict__ D, int64_t n_col_tiles) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  const int64_t row_tile = blockIdx.x / n_col_tiles;
-  dots_tile(x, r0, r1, cb, K, dim, D, row_tile, blockIdx.x - row_tile * n_col_tiles, lds);
-}
-
-// ------------------------------------------------------- split-row GEMM
-// The same dots from rows split once into BF16 parts (split_bf16x4: hi =
-// bf16(x), lo = bf16(x - hi)).  A split row holds, per 32 values, their 32
+// D[r - r0][k] ~ x_r . b_k in split-BF16 on MFMA, within (3.02 * 2^-16 +
+// 1.02 gamma(6 * 17 + dim / 32 + 2)) ||x_r|| ||b_k|| (DMA_SPLIT_BF16), from
+// rows split once into BF16 parts (split_bf16x4: hi = bf16(x), lo =
+// bf16(x - hi)).  A split row holds, per 32 values, their 32
 // high parts (64 bytes) then their 32 low parts, so its 128-byte chunk c is
 // sub-tile c of the direct-to-LDS loop (values 32 c .. 32 c + 31).  Rows
 // must be a whole number of 32 values.
@@ -77,9 +32,7 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
 
 // 256 x 256 tile of D from split rows on the score kernel's direct-to-LDS
 // loop (8 waves of 128 x-rows x 64 codewords, two 64 KB stages of 128-byte
-// sub-tiles).  Each sub-tile's 6 MFMAs per 32 x 32 block go into a fresh
-// part added into the total: the products, order and bound of dots_tile,
-// so D is bit-identical to it.  Tiles in the score kernel's order, GROUP
+// sub-tiles).  Tiles in the score kernel's order, GROUP
 // row tiles sharing each column sweep.  xs holds the split rows r0 .. r1 - 1
 // (row r at index r - r0).
 constexpr int SPLIT_TILE = 256;
@@ -159,7 +112,8 @@ __device__ __forceinline__ void split_row_wave(const float* __restrict__ x, int6
 
 // 128 x 128 tile of D (rows of xs, codewords of cbs, both split) for a
 // 4-wave block with 64 KB of LDS: the direct-to-LDS loop with 64 x 64 per
-// wave.  Same products, order and bound as dots_tile.
+// wave.  Same products, order and bound as dots_split_kernel, so the same
+// D.
 __device__ __forceinline__ void dots_split_tile(const uint8_t* __restrict__ xs, int64_t n_rows,
                                                 const uint8_t* __restrict__ cbs, int K, int dim,
                                                 float* __restrict__ D, int64_t row_tile,
@@ -422,41 +376,25 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
                           int32_t* words, float* D, int64_t chunk_rows, float* nhi, float* nlo,
                           int32_t* overflow, uint8_t* xs, uint8_t* cbs, hipStream_t st) {
   if (n <= 0) return GIFT_OK;
+  GIFT_CHECK(xs != nullptr && cbs != nullptr, GIFT_EINVAL, "split-row buffers missing");
   hipLaunchKernelGGL(norms_kernel, dim3((K + 3) / 4), dim3(256), 0, st, cb, K, dim, nhi, nlo);
   GIFT_LAUNCHED();
-  using T = TileShape<2, 2>;
-  // the pipelined GEMM on split rows when their buffers are given
-  const bool split = xs != nullptr && cbs != nullptr;
   const size_t split_lds = Dma2Shape<4, 2, 4, 2>::LDS_BYTES;
   {
-    const gift_status s =
-        split ? ensure_dynamic_lds(reinterpret_cast<const void*>(dots_split_kernel), split_lds)
-              : ensure_dynamic_lds(reinterpret_cast<const void*>(dots_kernel), T::LDS_BYTES);
+    const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(dots_split_kernel), split_lds);
     if (s != GIFT_OK) return s;
   }
-  if (split) {
-    const int64_t q = (int64_t)K * (dim / 4);
-    hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, cb,
-                       (int64_t)K, dim, cbs);
-    GIFT_LAUNCHED();
-  }
+  launch_split_rows(cb, K, dim, cbs, st);
+  GIFT_LAUNCHED();
   const float gamma2 = assign_gamma2(dim);
-  const int64_t n_col_tiles = (K + T::BN - 1) / T::BN;
+  const int64_t nc = (K + SPLIT_TILE - 1) / SPLIT_TILE;
   for (int64_t r0 = 0; r0 < n; r0 += chunk_rows) {
     const int64_t r1 = r0 + chunk_rows < n ? r0 + chunk_rows : n;
-    const int64_t n_row_tiles = (r1 - r0 + T::BM - 1) / T::BM;
-    if (split) {
-      const int64_t q = (r1 - r0) * (dim / 4);
-      hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st,
-                         x + r0 * dim, r1 - r0, dim, xs);
-      GIFT_LAUNCHED();
-      const int64_t nr = (r1 - r0 + SPLIT_TILE - 1) / SPLIT_TILE, nc = (K + SPLIT_TILE - 1) / SPLIT_TILE;
-      hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st,
-                         xs, r0, r1, cbs, K, dim, D, nr, nc);
-    } else {
-      hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(n_row_tiles * n_col_tiles)), dim3(256),
-                         T::LDS_BYTES, st, x, r0, r1, cb, K, dim, D, n_col_tiles);
-    }
+    launch_split_rows(x + r0 * dim, r1 - r0, dim, xs, st);
+    GIFT_LAUNCHED();
+    const int64_t nr = (r1 - r0 + SPLIT_TILE - 1) / SPLIT_TILE;
+    hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st, xs,
+                       r0, r1, cbs, K, dim, D, nr, nc);
     GIFT_LAUNCHED();
     hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)((r1 - r0 + 3) / 4)), dim3(256), 0, st,
                        x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow);
@@ -1355,7 +1293,7 @@ gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64
   return GIFT_OK;
 }
 
-// Twice (d^_k carries -2 x.b_k) the split-BF16 dot bound of dots_tile,
+// Twice (d^_k carries -2 x.b_k) the split-BF16 dot bound of the GEMM,
 // per unit of ||x|| ||b_k||.
 float assign_gamma2(int dim) {
   const double u = 5.9604644775390625e-08, nn = 6.0 * 17 + dim / 32 + 2;

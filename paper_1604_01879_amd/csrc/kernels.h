@@ -68,8 +68,7 @@ void launch_final_rank(const int32_t* cand, const float* first_s,
 // lower index).  D holds chunk_rows x K floats; nhi/nlo K floats each;
 // *overflow is incremented when a row has more than 256 candidates.
 // xs (chunk_rows x dim x 4 bytes) and cbs (K x dim x 4 bytes): buffers for
-// the BF16-split rows of the pipelined GEMM (null: the register-staged
-// GEMM).
+// the BF16-split rows of the GEMM.
 gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, int K, int ma,
                           int32_t* words, float* D, int64_t chunk_rows, float* nhi, float* nlo,
                           int32_t* overflow, uint8_t* xs, uint8_t* cbs, hipStream_t st);

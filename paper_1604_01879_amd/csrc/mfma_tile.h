@@ -166,93 +166,6 @@ __device__ __forceinline__ void split_bf16x4(uint4 v, uint2& hi, uint2& lo) {
   lo = make_uint2(bf16_pair(r0, r1), bf16_pair(r2, r3));
 }
 
-// Float32 tile product in split-BF16: each value x = hi + lo + r (above),
-// the dot taken as hi.hi' + hi.lo' + lo.hi' on BF16 MFMA.  Same tiles and
-// staging as mfma_tile_mainloop<GIFT_F32> (32 values = 128 bytes per row
-// per K-tile), but each staged piece is split on its way to LDS (32 high
-// parts, then 32 low parts per row) and each K-tile's 6 MFMAs per block go
-// into a fresh register block added into the running total, which bounds
-// the float32 accumulation depth: the result is within (3.02 * 2^-16 +
-// 1.02 gamma(6 * 17 + K-tiles + 2)) sum |x y| of the exact dot.
-template <int WM, int WN>
-__device__ __forceinline__ void mfma_tile_mainloop_split(
-    uint8_t* lds, const uint8_t* const (&src)[TileShape<WM, WN>::LOADS], int row_bytes,
-    f32x16 (&acc)[WM][WN]) {
-  using T = TileShape<WM, WN>;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int half = lane >> 5, l32 = lane & 31;
-#pragma unroll
-  for (int i = 0; i < WM; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-  const int n_kt = row_bytes / 128;  // rows of 32k float32 values
-  uint4 pre[T::LOADS];
-  auto gload = [&](int kt) {
-#pragma unroll
-    for (int it = 0; it < T::LOADS; ++it) {
-      const int off = kt * 128 + ((tid + 256 * it) & 7) * 16;
-      pre[it] = src[it] != nullptr ? *reinterpret_cast<const uint4*>(src[it] + off)
-                                   : make_uint4(0, 0, 0, 0);
-    }
-  };
-  gload(0);
-  // lane half h supplies values [16h, 16h + 16) of the K-tile in two steps
-  const uint8_t* arow = lds + (wr * WM * 32 + l32) * LROW + half * 32;
-  const uint8_t* brow = lds + (T::BM + wc * WN * 32 + l32) * LROW + half * 32;
-  for (int kt = 0; kt < n_kt; ++kt) {
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < T::LOADS; ++it) {
-      const int idx = tid + 256 * it;
-      uint2 hi, lo;
-      split_bf16x4(pre[it], hi, lo);
-      uint8_t* row = lds + (idx >> 3) * LROW + (idx & 7) * 8;
-      *reinterpret_cast<uint2*>(row) = hi;
-      *reinterpret_cast<uint2*>(row + 64) = lo;
-    }
-    __syncthreads();
-    if (kt + 1 < n_kt) gload(kt + 1);
-#pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      uint4 bh[2], bl[2];
-#pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        bh[st] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + st * 16);
-        bl[st] = *reinterpret_cast<const uint4*>(brow + j * 32 * LROW + 64 + st * 16);
-      }
-#pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        uint4 ah[2], al[2];
-#pragma unroll
-        for (int st = 0; st < 2; ++st) {
-          ah[st] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + st * 16);
-          al[st] = *reinterpret_cast<const uint4*>(arow + i * 32 * LROW + 64 + st * 16);
-        }
-        f32x16 part;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) part[e] = 0.f;
-#pragma unroll
-        for (int st = 0; st < 2; ++st) {
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
-                                                         __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[st]),
-                                                         __builtin_bit_cast(bf16x8, bl[st]), part, 0, 0, 0);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[st]),
-                                                         __builtin_bit_cast(bf16x8, bh[st]), part, 0, 0, 0);
-        }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[i][j][e] += part[e];
-      }
-    }
-  }
-  __syncthreads();  // LDS may be reused by the caller's epilogue
-}
-
 // Narrow tile for small query-view groups: 128 rows x 32 columns, wave w
 // owning rows 32w..32w+31 (one 32 x 32 block); staged rows 0..127 are the A
 // side, 128..159 the B side, loaded as in mfma_tile_mainloop.
@@ -761,8 +674,13 @@ __device__ __forceinline__ void dma128_issue(uint32_t base, uint64_t g, const ui
 }
 
 // Pseudo storage type of the K128 loop for float32 rows split once into
-// BF16 parts: each 128-byte sub-tile holds 32 values as 32 high parts
-// (bf16(x)) then 32 low parts (bf16(x - hi)).
+// BF16 parts (split_bf16x4: x = hi + lo + r, |r| <= 2^-16 |x|): each
+// 128-byte sub-tile holds 32 values as 32 high parts then 32 low parts.
+// The dot is taken as hi.hi' + hi.lo' + lo.hi' on BF16 MFMA, and each
+// sub-tile's 6 MFMAs per 32 x 32 block go into a fresh part added into the
+// running total, which bounds the float32 accumulation depth: the result is
+// within (3.02 * 2^-16 + 1.02 gamma(6 * 17 + sub-tiles + 2)) sum |x y| of
+// the exact dot.
 constexpr int DMA_SPLIT_BF16 = 16;
 
 // MFMAs of one staged 128-byte sub-tile: the wave multiplies its WM x WN
