@@ -400,13 +400,15 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
 
 // Candidate rescore, phases 2 and 3 (rescore_exact_kernel): one block (four
 // waves) per (query, candidate), blocks in XCD-contiguous order.  Every
-// masked pair (q_i, p_j) is re-evaluated with the compensated dot product
-// and the exact maximum kept (wave w takes query views w, w + 4, ...); the
-// block then forms the compensated mean over the query views in ascending
-// order.  A query view with an empty mask contributes 0.  Lane l takes the
-// float4 pieces l, l + 64, ... of both rows; a 4096-value row pair is one
-// batch of 16 + 16 loads in flight per lane, summed in two independent
-// compensated chains.
+// masked pair (q_i, p_j) is re-evaluated in float64 (float32 products are
+// exact there; the sum is within gamma_dim of float64 of sum |x y|) and
+// kept as a float pair, and the exact maximum kept (wave w takes query
+// views w, w + 4, ...); the block then forms the compensated mean over the
+// query views in ascending order.  A query view with an empty mask
+// contributes 0.  Lane l takes the float4 pieces l, l + 64, ... of both
+// rows; a 4096-value row pair is one batch of 16 + 16 loads in flight per
+// lane, summed in four float64 FMA chains and then across the wave in a
+// fixed order.
 __global__ __launch_bounds__(256) void rescore_exact_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff, int n_queries,
@@ -439,7 +441,8 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
         const int j = __builtin_ctzll(bb);
         bb &= bb - 1;
         const gptr<uint8_t> p4 = uniform_gptr(reinterpret_cast<const uint8_t*>(pbase + (int64_t)j * dim));
-        float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f;
+        // float32 products are exact in float64; four float64 FMA chains
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
         for (int u0 = lane; u0 < n4; u0 += 64 * P2_BATCH) {
           float4 qa[P2_BATCH], pa[P2_BATCH];
 #pragma unroll
@@ -449,20 +452,17 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
             pa[k] = u < (uint32_t)n4 ? load_at<float4>(p4, u * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
           }
 #pragma unroll
-          for (int k = 0; k < P2_BATCH; k += 2) {
-            dot2_step(qa[k].x, pa[k].x, s0, c0);
-            dot2_step(qa[k + 1].x, pa[k + 1].x, s1, c1);
-            dot2_step(qa[k].y, pa[k].y, s0, c0);
-            dot2_step(qa[k + 1].y, pa[k + 1].y, s1, c1);
-            dot2_step(qa[k].z, pa[k].z, s0, c0);
-            dot2_step(qa[k + 1].z, pa[k + 1].z, s1, c1);
-            dot2_step(qa[k].w, pa[k].w, s0, c0);
-            dot2_step(qa[k + 1].w, pa[k + 1].w, s1, c1);
+          for (int k = 0; k < P2_BATCH; ++k) {
+            d[k & 3] = __builtin_fma((double)qa[k].x, (double)pa[k].x, d[k & 3]);
+            d[k & 3] = __builtin_fma((double)qa[k].y, (double)pa[k].y, d[k & 3]);
+            d[k & 3] = __builtin_fma((double)qa[k].z, (double)pa[k].z, d[k & 3]);
+            d[k & 3] = __builtin_fma((double)qa[k].w, (double)pa[k].w, d[k & 3]);
           }
         }
-        float s, e;
-        two_sum(s0, s1, s, e);
-        const ff v = ff_wave_sum(s, (c0 + c1) + e);
+        double t = (d[0] + d[1]) + (d[2] + d[3]);
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        const float th = (float)t;
+        const ff v = ff_norm(th, (float)(t - (double)th));
         if (ff_gt(v, best)) best = v;
       }
       if (best.hi == -INFINITY) best = ff{0.f, 0.f};  // no matching view
