@@ -406,8 +406,8 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
 // ------------------------------------------------------------------ bucket sort
 // Stable counting sort of items 0..n-1 by key in [0, K): per-block key
 // histograms, a scan over blocks per key, a scan over keys, and an in-order
-// scatter by one thread per block.  Items of one key end up in ascending
-// item order.  K <= 16384.
+// scatter by one wave per block.  Items of one key end up in ascending item
+// order.  K <= 16384.
 constexpr int BK_ITEMS = 4096;
 
 __global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* __restrict__ keys,
@@ -468,7 +468,11 @@ __global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int64_t* __r
   if (threadIdx.x == 1023) off[K] = part[1023];
 }
 
-// In-order scatter; `mode` selects what is written per item:
+// In-order scatter by one wave per block, 64 items at a time: a lane's
+// item goes after the block's earlier items of its key and after the
+// earlier lanes of its chunk with that key (counted with shuffles), and the
+// last such lane advances the key's position.  `mode` selects what is
+// written per item:
 //   0: out_a[pos] = item
 //   1: F-IF entries, item e = v * ma + a: out_a = v / n_views (shape),
 //      out_b = v % n_views (view)
@@ -477,22 +481,36 @@ __global__ __launch_bounds__(64) void bucket_scatter_kernel(
     const int64_t* __restrict__ off, int mode, int ma, int n_views,
     int32_t* __restrict__ out_a, int32_t* __restrict__ out_b) {
   extern __shared__ int32_t pos[];
-  for (int k = threadIdx.x; k < K; k += 64) pos[k] = (int32_t)(off[k] + hist[(int64_t)k * nb + blockIdx.x]);
+  const int lane = threadIdx.x;
+  for (int k = lane; k < K; k += 64) pos[k] = (int32_t)(off[k] + hist[(int64_t)k * nb + blockIdx.x]);
   __syncthreads();
-  if (threadIdx.x != 0) return;
   const int64_t i0 = (int64_t)blockIdx.x * BK_ITEMS;
   const int64_t i1 = i0 + BK_ITEMS < n ? i0 + BK_ITEMS : n;
-  for (int64_t i = i0; i < i1; ++i) {
-    const int k = keys[i];
-    if (k < 0 || k >= K) continue;
-    const int64_t p = pos[k]++;  // < n < 2^31
-    if (mode == 0) {
-      out_a[p] = (int32_t)i;
-    } else {
-      const int64_t v = i / ma;
-      out_a[p] = (int32_t)(v / n_views);
-      out_b[p] = (int32_t)(v % n_views);
+  for (int64_t c0 = i0; c0 < i1; c0 += 64) {
+    const int64_t i = c0 + lane;
+    const int k = i < i1 ? keys[i] : -1;
+    const bool ok = k >= 0 && k < K;  // out-of-range keys are dropped
+    int rank = 0, last = 1;
+    for (int j = 0; j < 64; ++j) {
+      const int kj = __shfl(k, j, 64);
+      if (kj == k) {
+        if (j < lane) ++rank;
+        if (j > lane) last = 0;
+      }
     }
+    const int64_t p = ok ? (int64_t)pos[k] + rank : 0;  // < n < 2^31
+    __syncthreads();  // every lane has read its key's position
+    if (ok) {
+      if (mode == 0) {
+        out_a[p] = (int32_t)i;
+      } else {
+        const int64_t v = i / ma;
+        out_a[p] = (int32_t)(v / n_views);
+        out_b[p] = (int32_t)(v % n_views);
+      }
+      if (last) pos[k] = (int32_t)p + 1;
+    }
+    __syncthreads();  // positions advanced before the next chunk reads them
   }
 }
 
