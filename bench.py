@@ -77,8 +77,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
-                          "supported (the path shards by shape, see the design notes)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus above 1 is not supported. "
+                          "The path would shard by shape: each GPU scores its share of the "
+                          "database and returns a local top-k, merged after one all-gather"}))
         sys.exit(2)
 
     import torch

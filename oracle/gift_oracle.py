@@ -10,8 +10,8 @@ float64, so the only rounding left is the float64 summation (relative error
 around 1e-13 at d = 4096).  Library matmuls are used as the dot-product step;
 there is no other blocking, fusion or reordering.
 
-Readings of points the paper leaves open are marked READING and listed, with
-their reasons, in the design notes of the repository.
+Readings of points the paper leaves open are marked READING where they are
+applied, each with the choice it makes.
 """
 from __future__ import annotations
 
