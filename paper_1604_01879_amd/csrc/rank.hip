@@ -55,13 +55,19 @@ constexpr int MAX_R = 1024;
 
 // One block per query row; rows b >= *active are skipped (active may be
 // null).  Radix selection of the r-th smallest key, 8 bits per pass, with
-// SEL_UNROLL coalesced loads in flight per thread, then the in-order
-// collection of the r keys and a bitonic sort.
+// SEL_UNROLL coalesced loads in flight per thread, then the collection of
+// the r keys and a bitonic sort.  Scores share their high bits, so the
+// digit histogram has SEL_HCOPIES copies (lane l counts into copy l %
+// SEL_HCOPIES, rows padded against bank conflicts): at most 64 /
+// SEL_HCOPIES lanes of a wave add to one counter at once.
+constexpr int SEL_HCOPIES = 16;
+constexpr int SEL_HLD = 257;  // counters per copy: 256 digits + 1 pad
+
 __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
     const float* __restrict__ S, int64_t n, int r, const int32_t* __restrict__ active,
     int32_t* __restrict__ out_id, float* __restrict__ out_s) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t sh_prefix, sh_need;
+  __shared__ uint32_t hist[SEL_HCOPIES * SEL_HLD];
+  __shared__ uint32_t sh_prefix, sh_need, sh_eq;
   __shared__ int wsum[SEL_WAVES];
   __shared__ uint64_t keys[MAX_R];
   __shared__ int cnt_less;
@@ -69,12 +75,13 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
   if (active != nullptr && b >= *active) return;
   const float* row = S + (int64_t)b * n;
   const int tid = threadIdx.x;
+  uint32_t* my_hist = hist + (tid % SEL_HCOPIES) * SEL_HLD;
   constexpr int64_t STRIDE = (int64_t)SEL_THREADS * SEL_UNROLL;
 
   uint32_t prefix = 0, mask = 0, need = (uint32_t)r;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
-    for (int i = tid; i < 256; i += SEL_THREADS) hist[i] = 0;
+    for (int i = tid; i < SEL_HCOPIES * SEL_HLD; i += SEL_THREADS) hist[i] = 0;
     __syncthreads();
     for (int64_t base = 0; base < n; base += STRIDE) {
       uint32_t kk[SEL_UNROLL];
@@ -86,8 +93,15 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
 #pragma unroll
       for (int u = 0; u < SEL_UNROLL; ++u) {
         const int64_t i = base + u * SEL_THREADS + tid;
-        if (i < n && (kk[u] & mask) == prefix) atomicAdd(&hist[(kk[u] >> shift) & 255u], 1u);
+        if (i < n && (kk[u] & mask) == prefix) atomicAdd(&my_hist[(kk[u] >> shift) & 255u], 1u);
       }
+    }
+    __syncthreads();
+    // fold the copies into copy 0
+    for (int d = tid; d < 256; d += SEL_THREADS) {
+      uint32_t t = 0;
+      for (int c = 0; c < SEL_HCOPIES; ++c) t += hist[c * SEL_HLD + d];
+      hist[d] = t;
     }
     __syncthreads();
     if (tid == 0) {
@@ -99,6 +113,7 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
       }
       sh_need = need - cum;
       sh_prefix = prefix | ((uint32_t)d << shift);
+      sh_eq = hist[d];  // after the last pass: the keys equal to the r-th
     }
     __syncthreads();
     need = sh_need;
@@ -111,6 +126,40 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
   if (tid == 0) cnt_less = 0;
   __syncthreads();
   const int n_less = r - (int)need;
+  const int n_eq = (int)sh_eq;
+  if (n_less + n_eq <= MAX_R) {
+    // few ties: gather every key up to the r-th in any order; the sort by
+    // (key, id) puts the lowest ids of the tied keys first
+    for (int64_t base = 0; base < n; base += STRIDE) {
+      uint32_t kk[SEL_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; ++u) {
+        const int64_t i = base + u * SEL_THREADS + tid;
+        kk[u] = i < n ? desc_key(row[i]) : 0xffffffffu;
+      }
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; ++u) {
+        const int64_t i = base + u * SEL_THREADS + tid;
+        if (i < n && kk[u] <= prefix) {
+          const int pos = atomicAdd(&cnt_less, 1);
+          keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+        }
+      }
+    }
+    __syncthreads();
+    const int cnt = n_less + n_eq;
+    int np2 = 1;
+    while (np2 < cnt) np2 <<= 1;
+    for (int i = cnt + tid; i < np2; i += SEL_THREADS) keys[i] = ~0ull;
+    __syncthreads();
+    bitonic_sort_u64(keys, np2);
+    for (int i = tid; i < r; i += SEL_THREADS) {
+      const uint64_t k = keys[i];
+      out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
+      out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
+    }
+    return;
+  }
   int taken_eq = 0;
   for (int64_t base = 0; base < n; base += STRIDE) {
     uint32_t kk[SEL_UNROLL];
