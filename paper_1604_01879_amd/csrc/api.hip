@@ -138,6 +138,7 @@ struct ExhaustiveWs {
   float* S;
   int32_t* cand;
   float* cand_s;
+  void* sel_tmp;  // chunk winners of the top-r selection
   float* s_hi;
   float* s_lo;
   RescoreScratch rs;  // rescore masks, approximate scores, top-k marks
@@ -159,6 +160,7 @@ static ExhaustiveWs carve_exhaustive(void* base, const gift_views* db,
   if (r > 0) {
     w.cand = c.take<int32_t>((size_t)q->n_queries * r);
     w.cand_s = c.take<float>((size_t)q->n_queries * r);
+    w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, q->n_queries, r));
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
     w.rs.mask = c.take<unsigned long long>((size_t)r * q->total_views);
@@ -246,6 +248,7 @@ struct FifWs {
   int64_t* tcount;
   int32_t* cand;
   float* cand_s;
+  void* sel_tmp;  // chunk winners of the top-r selection
   float* s_hi;
   float* s_lo;
   RescoreScratch rs;  // rescore masks, approximate scores, top-k marks
@@ -275,6 +278,7 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
   if (r > 0) {
     w.cand = c.take<int32_t>((size_t)q->n_queries * r);
     w.cand_s = c.take<float>((size_t)q->n_queries * r);
+    w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, q->n_queries, r));
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
     w.rs.mask = c.take<unsigned long long>((size_t)r * q->total_views);
@@ -447,7 +451,8 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
   if ((s = first_pass(db, q, w, st)) != GIFT_OK) return s;
   prof_begin(P_SELECT, st);
-  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s, st);
+  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s,
+                    w.sel_tmp, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
@@ -653,7 +658,8 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
   if ((s = fif_first_pass(db, fif, q, w, st)) != GIFT_OK) return s;
   prof_begin(P_SELECT, st);
-  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s, st);
+  launch_select_top(w.S, db->n_shapes, q->n_queries, rescore_r, nullptr, w.cand, w.cand_s,
+                    w.sel_tmp, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);

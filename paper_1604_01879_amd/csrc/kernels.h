@@ -30,8 +30,11 @@ void launch_reduce_queries(const float* mbuf, int64_t ldm, int64_t n_shapes,
 // Top-r of each row of S [B][N] by (score desc, id asc), sorted.  In this
 // and the next two launchers, rows (queries) b >= *active are skipped when
 // `active` is not null (batch plans sized for more queries than a batch).
+// tmp (select_top_ws bytes, may be 0) holds the chunk winners of long rows
+// (null: one block per row).
+size_t select_top_ws(int64_t n, int n_queries, int r);
 void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
-                       int32_t* out_id, float* out_s, hipStream_t st);
+                       int32_t* out_id, float* out_s, void* tmp, hipStream_t st);
 
 // Exact rescore of candidates: split-BF16 dot products with a known error
 // bound give each view's candidate maxima and an approximate score; the

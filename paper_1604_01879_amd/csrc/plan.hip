@@ -33,6 +33,7 @@ struct PlanWs {
   unsigned long long* phase_ticks;
   int32_t* cand;
   float* cand_s;
+  void* sel_tmp;  // chunk winners of the top-r selection
   float* s_hi;
   float* s_lo;
   RescoreScratch rs;  // rescore masks [r][Vmax], approximate scores, top-k marks
@@ -74,6 +75,7 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.phase_ticks = c.take<unsigned long long>(BP_END);
   w.cand = c.take<int32_t>((size_t)Bmax * r);
   w.cand_s = c.take<float>((size_t)Bmax * r);
+  w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, Bmax, r));
   w.s_hi = c.take<float>((size_t)Bmax * r);
   w.s_lo = c.take<float>((size_t)Bmax * r);
   w.rs.mask = c.take<unsigned long long>((size_t)r * Vmax);
@@ -114,7 +116,7 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   // query slots past the batch (desc[0]) are skipped by every ranking kernel
   const int32_t* active = p->ws.desc;
   launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, active, p->ws.cand, p->ws.cand_s,
-                    st);
+                    p->ws.sel_tmp, st);
   GIFT_LAUNCHED();
   launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->Vmax,
                  p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim), p->ws.qwords,

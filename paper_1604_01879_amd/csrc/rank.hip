@@ -63,25 +63,42 @@ constexpr int MAX_R = 1024;
 constexpr int SEL_HCOPIES = 16;
 constexpr int SEL_HLD = 257;  // counters per copy: 256 digits + 1 pad
 
-__global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
-    const float* __restrict__ S, int64_t n, int r, const int32_t* __restrict__ active,
-    int32_t* __restrict__ out_id, float* __restrict__ out_s) {
-  __shared__ uint32_t hist[SEL_HCOPIES * SEL_HLD];
-  __shared__ uint32_t sh_prefix, sh_need, sh_eq;
-  __shared__ int wsum[SEL_WAVES];
-  __shared__ uint64_t keys[MAX_R];
-  __shared__ int cnt_less;
-  const int b = blockIdx.x;
-  if (active != nullptr && b >= *active) return;
-  const float* row = S + (int64_t)b * n;
+// Shared memory of a selection block.
+struct SelShared {
+  uint32_t hist[SEL_HCOPIES * SEL_HLD];
+  uint32_t prefix, need, eq;
+  int wsum[SEL_WAVES];
+  int cnt_less;
+  uint64_t keys[MAX_R];
+};
+
+// The r smallest (key, id) of row[0, n), id = id0 + index, sorted into
+// sh.keys[0, r) (padded with ~0 when n < r).  Block-wide: every thread of
+// the block calls it.
+__device__ void select_block(const float* __restrict__ row, int64_t n, int64_t id0, int r,
+                             SelShared& sh) {
   const int tid = threadIdx.x;
-  uint32_t* my_hist = hist + (tid % SEL_HCOPIES) * SEL_HLD;
+  uint32_t* my_hist = sh.hist + (tid % SEL_HCOPIES) * SEL_HLD;
   constexpr int64_t STRIDE = (int64_t)SEL_THREADS * SEL_UNROLL;
+  auto finish = [&](int cnt) {  // sort the cnt gathered keys
+    int np2 = 1;
+    while (np2 < cnt || np2 < r) np2 <<= 1;
+    for (int i = cnt + tid; i < np2; i += SEL_THREADS) sh.keys[i] = ~0ull;
+    __syncthreads();
+    bitonic_sort_u64(sh.keys, np2);
+  };
+  if (n <= r) {  // every element
+    for (int64_t i = tid; i < n; i += SEL_THREADS)
+      sh.keys[i] = ((uint64_t)desc_key(row[i]) << 32) | (uint32_t)(id0 + i);
+    __syncthreads();
+    finish((int)n);
+    return;
+  }
 
   uint32_t prefix = 0, mask = 0, need = (uint32_t)r;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
-    for (int i = tid; i < SEL_HCOPIES * SEL_HLD; i += SEL_THREADS) hist[i] = 0;
+    for (int i = tid; i < SEL_HCOPIES * SEL_HLD; i += SEL_THREADS) sh.hist[i] = 0;
     __syncthreads();
     for (int64_t base = 0; base < n; base += STRIDE) {
       uint32_t kk[SEL_UNROLL];
@@ -100,33 +117,33 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
     // fold the copies into copy 0
     for (int d = tid; d < 256; d += SEL_THREADS) {
       uint32_t t = 0;
-      for (int c = 0; c < SEL_HCOPIES; ++c) t += hist[c * SEL_HLD + d];
-      hist[d] = t;
+      for (int c = 0; c < SEL_HCOPIES; ++c) t += sh.hist[c * SEL_HLD + d];
+      sh.hist[d] = t;
     }
     __syncthreads();
     if (tid == 0) {
       uint32_t cum = 0;
       int d = 0;
       for (; d < 255; ++d) {
-        if (cum + hist[d] >= need) break;
-        cum += hist[d];
+        if (cum + sh.hist[d] >= need) break;
+        cum += sh.hist[d];
       }
-      sh_need = need - cum;
-      sh_prefix = prefix | ((uint32_t)d << shift);
-      sh_eq = hist[d];  // after the last pass: the keys equal to the r-th
+      sh.need = need - cum;
+      sh.prefix = prefix | ((uint32_t)d << shift);
+      sh.eq = sh.hist[d];  // after the last pass: the keys equal to the r-th
     }
     __syncthreads();
-    need = sh_need;
-    prefix = sh_prefix;
+    need = sh.need;
+    prefix = sh.prefix;
     mask |= 255u << shift;
     __syncthreads();
   }
   // `prefix` is the r-th smallest key; take every smaller key and the
   // `need` lowest ids among the keys equal to it.
-  if (tid == 0) cnt_less = 0;
+  if (tid == 0) sh.cnt_less = 0;
   __syncthreads();
   const int n_less = r - (int)need;
-  const int n_eq = (int)sh_eq;
+  const int n_eq = (int)sh.eq;
   if (n_less + n_eq <= MAX_R) {
     // few ties: gather every key up to the r-th in any order; the sort by
     // (key, id) puts the lowest ids of the tied keys first
@@ -141,25 +158,16 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
       for (int u = 0; u < SEL_UNROLL; ++u) {
         const int64_t i = base + u * SEL_THREADS + tid;
         if (i < n && kk[u] <= prefix) {
-          const int pos = atomicAdd(&cnt_less, 1);
-          keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+          const int pos = atomicAdd(&sh.cnt_less, 1);
+          sh.keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)(id0 + i);
         }
       }
     }
     __syncthreads();
-    const int cnt = n_less + n_eq;
-    int np2 = 1;
-    while (np2 < cnt) np2 <<= 1;
-    for (int i = cnt + tid; i < np2; i += SEL_THREADS) keys[i] = ~0ull;
-    __syncthreads();
-    bitonic_sort_u64(keys, np2);
-    for (int i = tid; i < r; i += SEL_THREADS) {
-      const uint64_t k = keys[i];
-      out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
-      out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
-    }
+    finish(n_less + n_eq);
     return;
   }
+  // many ties: the smaller keys, then the tied keys in index order
   int taken_eq = 0;
   for (int64_t base = 0; base < n; base += STRIDE) {
     uint32_t kk[SEL_UNROLL];
@@ -174,36 +182,106 @@ __global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
       const bool less = i < n && kk[u] < prefix;
       const bool eq = i < n && kk[u] == prefix;
       if (less) {
-        const int pos = atomicAdd(&cnt_less, 1);
-        keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+        const int pos = atomicAdd(&sh.cnt_less, 1);
+        sh.keys[pos] = ((uint64_t)kk[u] << 32) | (uint32_t)(id0 + i);
       }
       if (taken_eq < (int)need) {  // block-uniform
         int tot;
-        const int pos = block_excl_count(eq, wsum, tot);
+        const int pos = block_excl_count(eq, sh.wsum, tot);
         if (eq && taken_eq + pos < (int)need)
-          keys[n_less + taken_eq + pos] = ((uint64_t)kk[u] << 32) | (uint32_t)i;
+          sh.keys[n_less + taken_eq + pos] = ((uint64_t)kk[u] << 32) | (uint32_t)(id0 + i);
         taken_eq += tot;
       }
     }
   }
   __syncthreads();
+  finish(r);
+}
+
+__device__ __forceinline__ void write_top(const SelShared& sh, int64_t b, int r,
+                                          int32_t* __restrict__ out_id, float* __restrict__ out_s) {
+  for (int i = threadIdx.x; i < r; i += SEL_THREADS) {
+    const uint64_t k = sh.keys[i];
+    out_id[b * r + i] = (int32_t)(k & 0xffffffffu);
+    out_s[b * r + i] = order_float(~(uint32_t)(k >> 32));
+  }
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void select_top_kernel(
+    const float* __restrict__ S, int64_t n, int r, const int32_t* __restrict__ active,
+    int32_t* __restrict__ out_id, float* __restrict__ out_s) {
+  __shared__ SelShared sh;
+  const int b = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
+  select_block(S + (int64_t)b * n, n, 0, r, sh);
+  write_top(sh, b, r, out_id, out_s);
+}
+
+// Long rows: chunk c of row b (grid chunks x queries) keeps its r smallest
+// (key, id) in tmp[b][c][0, r); every key of the row's top r is among its
+// chunk's top r, so the merge below is exact.
+__global__ __launch_bounds__(SEL_THREADS) void select_chunk_kernel(
+    const float* __restrict__ S, int64_t n, int64_t chunk, int r, const int32_t* __restrict__ active,
+    uint64_t* __restrict__ tmp) {
+  __shared__ SelShared sh;
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
+  const int64_t c0 = (int64_t)c * chunk;
+  const int64_t len = n - c0 < chunk ? n - c0 : chunk;
+  select_block(S + (int64_t)b * n + c0, len, c0, r, sh);
+  uint64_t* dst = tmp + ((int64_t)b * gridDim.x + c) * r;
+  for (int i = threadIdx.x; i < r; i += SEL_THREADS) dst[i] = sh.keys[i];
+}
+
+// The r smallest of row b's n_keys chunk winners (at most SEL_MERGE_CAP).
+constexpr int SEL_MERGE_CAP = 4096;
+__global__ __launch_bounds__(SEL_THREADS) void select_merge_kernel(
+    const uint64_t* __restrict__ tmp, int n_keys, int r, const int32_t* __restrict__ active,
+    int32_t* __restrict__ out_id, float* __restrict__ out_s) {
+  __shared__ uint64_t keys[SEL_MERGE_CAP];
+  const int b = blockIdx.x;
+  if (active != nullptr && b >= *active) return;
   int np2 = 1;
-  while (np2 < r) np2 <<= 1;
-  for (int i = r + tid; i < np2; i += SEL_THREADS) keys[i] = ~0ull;
+  while (np2 < n_keys) np2 <<= 1;
+  const uint64_t* src = tmp + (int64_t)b * n_keys;
+  for (int i = threadIdx.x; i < np2; i += SEL_THREADS) keys[i] = i < n_keys ? src[i] : ~0ull;
   __syncthreads();
   bitonic_sort_u64(keys, np2);
-  for (int i = tid; i < r; i += SEL_THREADS) {
+  for (int i = threadIdx.x; i < r; i += SEL_THREADS) {
     const uint64_t k = keys[i];
     out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
     out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
   }
 }
 
+// Rows longer than two chunks of 16,384 scores (doubled until the chunk
+// winners fit the merge) go through the chunked path.
+static int64_t select_chunk_len(int64_t n, int r) {
+  int64_t chunk = 16384;
+  while (((n + chunk - 1) / chunk) * r > SEL_MERGE_CAP) chunk *= 2;
+  return n > 2 * chunk ? chunk : 0;
+}
+
+size_t select_top_ws(int64_t n, int n_queries, int r) {
+  const int64_t chunk = select_chunk_len(n, r);
+  if (chunk == 0 || n_queries <= 0) return 0;
+  return (size_t)n_queries * ((n + chunk - 1) / chunk) * r * sizeof(uint64_t);
+}
+
 void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
-                       int32_t* out_id, float* out_s, hipStream_t st) {
+                       int32_t* out_id, float* out_s, void* tmp, hipStream_t st) {
   if (n_queries <= 0) return;
-  hipLaunchKernelGGL(select_top_kernel, dim3(n_queries), dim3(SEL_THREADS), 0, st, S,
-                     n, r, active, out_id, out_s);
+  const int64_t chunk = select_chunk_len(n, r);
+  if (chunk == 0 || tmp == nullptr) {
+    hipLaunchKernelGGL(select_top_kernel, dim3(n_queries), dim3(SEL_THREADS), 0, st, S, n, r,
+                       active, out_id, out_s);
+    return;
+  }
+  const int n_chunks = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(select_chunk_kernel, dim3(n_chunks, n_queries), dim3(SEL_THREADS), 0, st, S,
+                     n, chunk, r, active, static_cast<uint64_t*>(tmp));
+  hipLaunchKernelGGL(select_merge_kernel, dim3(n_queries), dim3(SEL_THREADS), 0, st,
+                     static_cast<const uint64_t*>(tmp), n_chunks * r, r, active, out_id, out_s);
 }
 
 // ------------------------------------------------------------------ rescore

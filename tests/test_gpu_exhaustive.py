@@ -168,6 +168,21 @@ def test_first_pass_persistent_many_tiles(L, dtype_name, dim, group):
     assert np.array_equal(S, S6)
 
 
+def test_query_exhaustive_long_rows(L):
+    """Rows of 40,000 shapes: the top-r selection splits each row into
+    chunks of 16,384 and merges the chunk winners."""
+    _say("query_exhaustive long rows")
+    w, db, q, qoff = _data(N=40000, dim=32, B=3, m=(1, 4), nv=2, seed=21)
+    V, _, _ = _views(L, db, w.n_views, L.F32)
+    Q = _queries(L, q, qoff)
+    k, R = 20, 64
+    ids, sc, flags = L.gift_query_exhaustive(V, Q, k, R)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    S = O.exhaustive_scores(q, qoff, db, w.n_views)
+    for b in range(len(qoff) - 1):
+        assert_ranked_equal(ids[b], sc[b], S[b], k)
+
+
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("case", ["c1-like", "ragged", "few-views", "many-query-views",
                                   "shared-candidates"])

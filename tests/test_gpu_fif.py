@@ -251,6 +251,27 @@ def test_query_fif_ranked_ids(L, dtype_name, ma):
     assert (flags == 1).all()
 
 
+def test_query_fif_long_rows_zero_ties(L):
+    """Rows of 40,000 shapes with a large vocabulary, so each query matches
+    a few hundred shapes and the rest score 0: the chunked top-r selection
+    resolves the tie at 0 by id in every chunk and in the merge, and the
+    returned tail is the lowest-id zero-score shapes."""
+    _say("fif long rows")
+    w = _wl(n_shapes=40000, dim=32, n_views=1, m_lo=2, m_hi=4, n_queries=3)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 1000, 1, L.F32)
+    k, R = 250, 256
+    ids, sc, flags = L.gift_query_fif(V, F, Q, k, R)
+    torch.cuda.synchronize()
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    for b in range(len(qoff) - 1):
+        assert (S[b] > 0).sum() < k  # the tail is zero-score shapes
+        assert_ranked_equal(ids[b], sc[b], S[b], k)
+        ref_ids, _ = O.rank_topk(S[b][None], k)
+        zero = S[b][ref_ids[0]] == 0
+        assert np.array_equal(ids[b][zero], ref_ids[0][zero])  # zero ties in id order
+
+
 @pytest.mark.parametrize("ma", [1, 2])
 def test_query_fif_shared_candidates(L, ma):
     """Eq. 4 ranking when every query rescores every shape (each candidate
