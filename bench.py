@@ -477,7 +477,9 @@ def scale_bench(args):
                                            "queries_per_s": round(B / dt, 1),
                                            "eager_first_pass_ms": round(t_eager * 1e3, 3),
                                            "rerank_ms": rr_ms / max(rr_n, 1), "queue_error": err,
-                                           "phase_block_ms": phases}
+                                           "phase_block_ms": phases,
+                                           "phase_end_us": dict(zip(_PHASES, (
+                                               round(x, 1) for x in plan.phase_end_us())))}
             log(f"c4 plan bpc={bpc}: {dt * 1e3:.2f} ms per batch of {B}")
             plan.close()
         best = max(out.values(), key=lambda v: v["queries_per_s"])
@@ -513,7 +515,9 @@ def scale_bench(args):
         plan.stream.synchronize()
         by_size[str(nb)] = {"views": nv, "ms_per_batch": round(ev0.elapsed_time(ev1) / 5, 3),
                             "phase_block_ms": dict(zip(_PHASES, (round(x / 1e3, 3)
-                                                                 for x in plan.phase_us())))}
+                                                                 for x in plan.phase_us()))),
+                            "phase_end_us": dict(zip(_PHASES, (round(x, 1)
+                                                               for x in plan.phase_end_us())))}
         log(f"c5 plan alone: {nb} queries in {by_size[str(nb)]['ms_per_batch']} ms")
     plan.close()
     rates = [float(r) for r in args.serve_rates.split(",")]

@@ -333,9 +333,13 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* last run hit its time limit (results invalid), else 0.                  */
 /* gift_fif_plan_phase_us (SYNCHRONISES) writes, for the last run, the     */
 /* block-microseconds spent in each phase of the persistent kernel (sum    */
-/* over blocks of the wall time from taking an item to finishing it):      */
-/* out[9] = split and quantize, codeword dots, clear, word selection,     */
-/* word offsets, grouping, active-tile listing, list scan, per-query mean. */
+/* over blocks of the wall time from the end of an item's wait for its     */
+/* inputs to the end of the item): out[9] = split and quantize, codeword   */
+/* dots, clear, word selection, word offsets, grouping, active-tile        */
+/* listing, list scan, per-query mean.                                     */
+/* gift_fif_plan_phase_end_us (SYNCHRONISES) writes, for the last run and  */
+/* the same nine phases, the microseconds from the start of the run's      */
+/* queue reset to the end of the phase's last item (0: no item).           */
 /* ---------------------------------------------------------------------- */
 typedef struct gift_fif_plan gift_fif_plan;
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,
@@ -359,6 +363,8 @@ gift_status gift_fif_plan_error(gift_fif_plan* plan, int32_t* err,
                                 void* stream);
 gift_status gift_fif_plan_phase_us(gift_fif_plan* plan, double* out /* host [9] */,
                                    void* stream);
+gift_status gift_fif_plan_phase_end_us(gift_fif_plan* plan, double* out /* host [9] */,
+                                       void* stream);
 gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
 
 /* ---------------------------------------------------------------------- */

@@ -101,6 +101,7 @@ _sig = {
     "gift_fif_plan_run_eager": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
     "gift_fif_plan_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), _P]),
     "gift_fif_plan_phase_us": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), _P]),
+    "gift_fif_plan_phase_end_us": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), _P]),
     "gift_fif_plan_destroy": (C.c_int32, [C.c_void_p]),
     "gift_profile_enable": (C.c_int32, [C.c_int32]),
     "gift_profile_reset": (C.c_int32, []),
@@ -444,11 +445,19 @@ class FifPlan:
         _check(f(self.handle, n_queries, n_views, _stream(stream or self.stream)))
 
     def phase_us(self, stream=None):
-        """Block-microseconds per phase of the last run (quantize, clear,
-        codeword dots, word selection, word offsets, grouping, active-tile
-        listing, list scan, per-query mean)."""
+        """Block-microseconds per phase of the last run, waits for inputs
+        excluded (split and quantize, codeword dots, clear, word selection,
+        word offsets, grouping, active-tile listing, list scan, per-query
+        mean)."""
         out = (C.c_double * 9)()
         _check(_lib.gift_fif_plan_phase_us(self.handle, out, _stream(stream or self.stream)))
+        return list(out)
+
+    def phase_end_us(self, stream=None):
+        """Microseconds from the start of the last run to the end of each
+        phase's last item, in the order of phase_us."""
+        out = (C.c_double * 9)()
+        _check(_lib.gift_fif_plan_phase_end_us(self.handle, out, _stream(stream or self.stream)))
         return list(out)
 
     def error(self, stream=None):

@@ -961,9 +961,10 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // One persistent kernel runs the whole first pass of a ragged query batch
 // (assign + group + scan + reduce) from a device work queue.  Items are
 // numbered phase by phase:
-//   Q    quantize query views to the storage format (BF16/FP8 only)
-//   FILL clear rows [0, n_v) of mbuf
+//   Q    split 64 query views for the dot tiles and code them in the
+//        storage format
 //   GEMM query view x codeword dot tiles (MFMA)
+//   FILL clear rows [0, n_v) of mbuf
 //   SEL  certified nearest word of 4 query views; count views per word
 //   PRE  word offsets of the groups and of the active list tiles (one item)
 //   SCAT place every query view in its word's group
@@ -976,10 +977,12 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // touch, not what the plan could hold.  Blocks take items in increasing
 // order from an atomic counter.  An item of phase p first waits until every
 // item numbered below the first item of p has finished (one `done`
-// counter); an item at or past the first SCAN item first waits for all of
-// Q..TILE, and then knows the SCAN and RED ranges.  The items waited for
-// were all taken before by blocks that are running, and the earliest
-// unfinished item never waits, so the queue always drains.  A wait that
+// counter), except that GEMM waits for the Q items alone (a second
+// counter) and FILL waits for nothing; an item at or past the first SCAN
+// item first waits for all of Q..TILE, and then knows the SCAN and RED
+// ranges.  The items waited for were all taken before by blocks that are
+// running, and the earliest unfinished item never waits, so the queue
+// always drains.  A wait that
 // exceeds its wall-clock limit sets the error word; from then on every wait
 // and every item is skipped, so every block exits.
 //
@@ -994,7 +997,8 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BatchArgs a) {
   // counters, word counts, and the offsets of unused query slots
   const int n_q = a.desc[0];
   for (int i = threadIdx.x; i < BATCH_CTRL_WORDS; i += 256) a.ctrl[i] = 0ull;
-  for (int i = threadIdx.x; i < BP_END; i += 256) a.phase_ticks[i] = 0ull;
+  for (int i = threadIdx.x; i < 2 * BP_END; i += 256) a.phase_ticks[i] = 0ull;
+  if (threadIdx.x == 0) a.phase_ticks[2 * BP_END] = (unsigned long long)wall_clock64();
   for (int k = threadIdx.x; k < a.K; k += 256) a.counts[k] = 0;
   if (threadIdx.x == 0) *a.overflow = 0;
   const int32_t last = a.qoff[n_q];
@@ -1065,12 +1069,9 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   const int64_t n_red = (int64_t)n_q * red_chunks;
   int64_t n_active = -1;  // active list tiles, once this block has waited for PRE
   int acquired = -1;      // thread 0: last phase whose inputs this block acquired
-  long long t_item = 0;   // thread 0: wall clock when the item was taken
+  long long t_item = 0;   // thread 0: wall clock once the item's inputs are ready
   for (;;) {
-    if (tid == 0) {
-      sh_item = (int64_t)atomicAdd(head, 1ull);
-      t_item = wall_clock64();
-    }
+    if (tid == 0) sh_item = (int64_t)atomicAdd(head, 1ull);
     __syncthreads();
     const int64_t item = sh_item;
     __syncthreads();
@@ -1123,6 +1124,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
         acquired = ph;
       }
       sh_err = e;
+      t_item = wall_clock64();
     }
     __syncthreads();
     // whether the item stored data that later items read with plain loads
@@ -1260,7 +1262,10 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     if (tid == 0) {
       if (ph == BP_Q) __hip_atomic_fetch_add(q_done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&a.phase_ticks[ph], (unsigned long long)(wall_clock64() - t_item),
+      const long long t_end = wall_clock64();
+      __hip_atomic_fetch_add(&a.phase_ticks[ph], (unsigned long long)(t_end - t_item),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&a.phase_ticks[BP_END + ph], (unsigned long long)t_end,
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }

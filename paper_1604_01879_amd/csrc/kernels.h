@@ -138,7 +138,9 @@ struct BatchArgs {
   float* S;
   int32_t* overflow;
   unsigned long long* ctrl;  // [BATCH_CTRL_WORDS]: head, done, error, active tiles, Q done
-  unsigned long long* phase_ticks;  // [BP_END] wall-clock ticks per phase
+  // [2 * BP_END + 1] wall-clock ticks: busy ticks per phase (waits
+  // excluded), the last item end per phase, and the reset's start
+  unsigned long long* phase_ticks;
   float gamma2;
   int64_t wait_ticks;        // wall-clock ticks a phase wait may take
   int64_t gemm_col_tiles;

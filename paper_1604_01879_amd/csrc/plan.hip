@@ -72,7 +72,7 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.S = c.take<float>((size_t)Bmax * db->n_shapes);
   w.overflow = c.take<int32_t>(1);
   w.ctrl = c.take<unsigned long long>(BATCH_CTRL_WORDS);
-  w.phase_ticks = c.take<unsigned long long>(BP_END);
+  w.phase_ticks = c.take<unsigned long long>(2 * BP_END + 1);
   w.cand = c.take<int32_t>((size_t)Bmax * r);
   w.cand_s = c.take<float>((size_t)Bmax * r);
   w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, Bmax, r));
@@ -359,6 +359,20 @@ gift_status gift_fif_plan_phase_us(gift_fif_plan* p, double* out, void* stream) 
                           (hipStream_t)stream));
   GIFT_HIP(hipStreamSynchronize((hipStream_t)stream));
   for (int i = 0; i < BP_END; ++i) out[i] = (double)t[i] * 1000.0 / (double)p->clock_khz;
+  return GIFT_OK;
+}
+
+gift_status gift_fif_plan_phase_end_us(gift_fif_plan* p, double* out, void* stream) {
+  GIFT_CHECK(p != nullptr && out != nullptr, GIFT_EINVAL, "null argument");
+  unsigned long long t[2 * BP_END + 1];
+  GIFT_HIP(hipMemcpyAsync(t, p->ws.phase_ticks, sizeof(t), hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+  GIFT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  const unsigned long long t0 = t[2 * BP_END];
+  for (int i = 0; i < BP_END; ++i) {
+    const unsigned long long e = t[BP_END + i];
+    out[i] = e > t0 ? (double)(e - t0) * 1000.0 / (double)p->clock_khz : 0.0;
+  }
   return GIFT_OK;
 }
 

@@ -120,6 +120,7 @@ void launch_build_sif(const int32_t* ids, const float* vals, int64_t N, int k1, 
 // compensated arithmetic, and the shapes are ranked by (S' desc, id asc);
 // shapes sharing no coordinate score 0 and fill the list in id order.
 constexpr int SIF_CAP = 4096;  // expanded postings per query
+constexpr int SIF_THREADS = 1024;  // one block per query; its LDS leaves room for one per CU
 
 struct SCand {
   float hi, lo;
@@ -145,16 +146,19 @@ __device__ inline ff ff_div(ff a, ff b) {
   return ff_norm(q1, q2);
 }
 
-__global__ __launch_bounds__(256) void rerank_sif_kernel(
+__global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     const float* __restrict__ l1, const int64_t* __restrict__ post_off,
     const int32_t* __restrict__ post_id, const float* __restrict__ post_val, int64_t N,
     const int32_t* __restrict__ q_id, const float* __restrict__ q_val,
     const float* __restrict__ q_self, int k1, int k, int32_t* __restrict__ out_id,
     float* __restrict__ out_s, int32_t* __restrict__ flags) {
   __shared__ int64_t pre[257];
+  __shared__ int64_t cnt_r[256];  // postings taken from coordinate r
+  __shared__ float val_r[256];    // membership at coordinate r
+  __shared__ uint8_t in_r[256];   // coordinate r names a shape in range
   __shared__ float Ahi, Alo;
   __shared__ int overflow;
-  __shared__ int wsum[4];
+  __shared__ int wsum[SIF_THREADS / 64];
   extern __shared__ __align__(16) uint8_t sm[];
   uint64_t* key = reinterpret_cast<uint64_t*>(sm);                // (shape << 32) | slot
   float* pv = reinterpret_cast<float*>(sm + 8 * SIF_CAP);           // min value per slot
@@ -164,16 +168,24 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   const int32_t* qi = q_id + (int64_t)b * k1;
   const float* qv = q_val + (int64_t)b * k1;
 
+  // the coordinates' posting counts, loaded in parallel; then the prefix
+  // and ||F_q||_1 in coordinate order
+  for (int r = tid; r < k1; r += SIF_THREADS) {
+    const int32_t i = qi[r];
+    const bool ok = i >= 0 && i < N;
+    const float v = qv[r];
+    cnt_r[r] = ok && v > 0.f ? post_off[i + 1] - post_off[i] : 0;
+    val_r[r] = v;
+    in_r[r] = ok;
+  }
+  __syncthreads();
   if (tid == 0) {
     ff A = {q_self != nullptr ? q_self[b] : 0.f, 0.f};
     int64_t run = 0;
     for (int r = 0; r < k1; ++r) {
       pre[r] = run;
-      const int32_t i = qi[r];
-      if (i >= 0 && i < N) {
-        A = ff_add(A, ff{qv[r], 0.f});
-        if (qv[r] > 0.f) run += post_off[i + 1] - post_off[i];
-      }
+      if (in_r[r]) A = ff_add(A, ff{val_r[r], 0.f});
+      run += cnt_r[r];
     }
     pre[k1] = run;
     overflow = run > SIF_CAP;
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   }
   __syncthreads();
   const int L = (int)(pre[k1] < SIF_CAP ? pre[k1] : SIF_CAP);
-  for (int s = tid; s < L; s += 256) {
+  for (int s = tid; s < L; s += SIF_THREADS) {
     int lo = 0, hi = k1;  // r with pre[r] <= s < pre[r+1]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -194,11 +206,11 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   }
   int np2 = 1;
   while (np2 < L) np2 <<= 1;
-  for (int s = L + tid; s < np2; s += 256) key[s] = ~0ull;
+  for (int s = L + tid; s < np2; s += SIF_THREADS) key[s] = ~0ull;
   __syncthreads();
   for (int kk = 2; kk <= np2; kk <<= 1) {
     for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < np2; i += 256) {
+      for (int i = tid; i < np2; i += SIF_THREADS) {
         const int ix = i ^ j;
         if (ix > i) {
           const bool up = (i & kk) == 0;
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   }
   // one candidate per distinct shape, in ascending shape order
   int base_u = 0;
-  for (int s0 = 0; s0 < L; s0 += 256) {
+  for (int s0 = 0; s0 < L; s0 += SIF_THREADS) {
     const int s = s0 + tid;
     const bool start = s < L && (s == 0 || (key[s] >> 32) != (key[s - 1] >> 32));
     const int lane = tid & 63, wave = tid >> 6;
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
     if (lane == 0) wsum[wave] = __popcll(bal);
     __syncthreads();
     int before = 0, tot = 0;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < SIF_THREADS / 64; ++w) {
       if (w < wave) before += wsum[w];
       tot += wsum[w];
     }
@@ -241,14 +253,14 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
   const int U = base_u;
   // candidate ids are ascending here; remember them for the zero padding
   // by sorting a copy of the ids into `key` (already ascending by shape)
-  for (int i = tid; i < U; i += 256) key[i] = (uint64_t)(uint32_t)cand[i].id;
+  for (int i = tid; i < U; i += SIF_THREADS) key[i] = (uint64_t)(uint32_t)cand[i].id;
   int np2u = 1;
   while (np2u < U) np2u <<= 1;
-  for (int i = U + tid; i < np2u; i += 256) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
+  for (int i = U + tid; i < np2u; i += SIF_THREADS) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
   __syncthreads();
   for (int kk = 2; kk <= np2u; kk <<= 1) {
     for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < np2u; i += 256) {
+      for (int i = tid; i < np2u; i += SIF_THREADS) {
         const int ix = i ^ j;
         if (ix > i) {
           const bool up = (i & kk) == 0;
@@ -260,7 +272,7 @@ __global__ __launch_bounds__(256) void rerank_sif_kernel(
     }
   }
   const int kp = k < U ? k : U;
-  for (int i = tid; i < kp; i += 256) {
+  for (int i = tid; i < kp; i += SIF_THREADS) {
     out_id[(int64_t)b * k + i] = cand[i].id;
     out_s[(int64_t)b * k + i] = cand[i].hi;
   }
@@ -453,7 +465,7 @@ void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* 
   if (B <= 0) return;
   const size_t shmem = (size_t)SIF_CAP * (8 + 4 + sizeof(SCand));
   (void)ensure_dynamic_lds(reinterpret_cast<const void*>(rerank_sif_kernel), shmem);
-  hipLaunchKernelGGL(rerank_sif_kernel, dim3(B), dim3(256), shmem, st, l1, post_off, post_id,
+  hipLaunchKernelGGL(rerank_sif_kernel, dim3(B), dim3(SIF_THREADS), shmem, st, l1, post_off, post_id,
                      post_val, N, q_id, q_val, q_self, k1, k, out_id, out_s, flags);
 }
 
