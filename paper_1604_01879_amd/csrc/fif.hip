@@ -1172,41 +1172,64 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           wrote = true;
           break;
         case BP_PRE: {
-          // group offsets (goff) and active-tile offsets (act_off) over words
-          int64_t* part = reinterpret_cast<int64_t*>(lds);
-          int64_t* tpart = part + 256;
+          // group offsets (goff) and active-tile offsets (act_off) over
+          // words: each thread sums a contiguous range of words (8 words'
+          // loads in flight), then an exclusive scan over the 256 sums
+          int64_t* wsum = reinterpret_cast<int64_t*>(lds);  // [4] + [4]
           const int per = (a.K + 255) / 256;
-          const int k0 = tid * per;
+          const int k0 = tid * per, k1 = k0 + per < a.K ? k0 + per : a.K;
           int64_t sum = 0, tsum = 0;
-          for (int k = k0; k < k0 + per && k < a.K; ++k) {
-            const int c = a.counts[k];
-            sum += c;
-            if (c > 0) tsum += a.tile_off[k + 1] - a.tile_off[k];
-          }
-          part[tid] = sum;
-          tpart[tid] = tsum;
-          __syncthreads();
-          if (tid == 0) {
-            int64_t run = 0, trun = 0;
-            for (int t = 0; t < 256; ++t) {
-              const int64_t v = part[t], tv = tpart[t];
-              part[t] = run;
-              tpart[t] = trun;
-              run += v;
-              trun += tv;
+          for (int k = k0; k < k1; k += 8) {
+            int c[8];
+            int64_t tl[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              c[q] = kk < k1 ? a.counts[kk] : 0;
+              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
             }
-            a.goff[a.K] = run;
-            *n_active_w = (unsigned long long)trun;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              sum += c[q];
+              if (c[q] > 0) tsum += tl[q];
+            }
           }
+          // inclusive scan within the wave, then across the 4 waves
+          const int lane = tid & 63, wave = tid >> 6;
+          int64_t is = sum, it = tsum;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int64_t ps = __shfl_up(is, o, 64), pt = __shfl_up(it, o, 64);
+            if (lane >= o) { is += ps; it += pt; }
+          }
+          if (lane == 63) { wsum[wave] = is; wsum[4 + wave] = it; }
           __syncthreads();
-          int64_t run = part[tid], trun = tpart[tid];
-          for (int k = k0; k < k0 + per && k < a.K; ++k) {
-            const int c = a.counts[k];
-            a.goff[k] = run;
-            a.act_off[k] = (int32_t)trun;
-            run += c;
-            if (c > 0) trun += a.tile_off[k + 1] - a.tile_off[k];
-            a.fillc[k] = 0;
+          int64_t run = is - sum, trun = it - tsum;
+          for (int w = 0; w < wave; ++w) { run += wsum[w]; trun += wsum[4 + w]; }
+          if (tid == 255) {
+            a.goff[a.K] = run + sum;
+            *n_active_w = (unsigned long long)(trun + tsum);
+          }
+          for (int k = k0; k < k1; k += 8) {
+            int c[8];
+            int64_t tl[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              c[q] = kk < k1 ? a.counts[kk] : 0;
+              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              if (kk < k1) {
+                a.goff[kk] = run;
+                a.act_off[kk] = (int32_t)trun;
+                a.fillc[kk] = 0;
+              }
+              run += c[q];
+              if (c[q] > 0) trun += tl[q];
+            }
           }
           wrote = true;
           break;
