@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb
 // arithmetic and the ma smallest (distance, index) are written.
 constexpr int SEL_CAP = 256;   // candidates kept per row
 constexpr int MAX_MA = 8;
-constexpr int SEL_UNROLL = 8;  // codewords per lane with loads in flight together
+constexpr int SEL_UNROLL = 16;  // codewords per lane with loads in flight together
 
 __device__ inline bool dk_less(float ah, float al, int ak, float bh, float bl, int bk) {
   if (ah != bh) return ah < bh;
