@@ -53,12 +53,15 @@ def _load(plan, q, qoff):
     return n_q, int(qoff[-1])
 
 
-@pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8", "mxfp8", "mxfp4"])
+# "bf16_263": a shape count that is not a multiple of 4 (the per-query mean
+# then reads one shape per load instead of four)
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8", "mxfp8", "mxfp4", "bf16_263"])
 def test_plan_equals_query_fif(L, dtype_name):
     _say(f"plan vs query_fif {dtype_name}")
+    name, _, ns = dtype_name.partition("_")
     dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3, "mxfp8": L.MXFP8,
-          "mxfp4": L.MXFP4}[dtype_name]
-    w, db, q, qoff, cb, V, F = _setup(L, dt)
+          "mxfp4": L.MXFP4}[name]
+    w, db, q, qoff, cb, V, F = _setup(L, dt, n_shapes=int(ns) if ns else 260)
     torch.cuda.synchronize()
     _say("index built")
     k, R = 15, 60
