@@ -941,20 +941,20 @@ __device__ __forceinline__ float fif_mean(const uint32_t* __restrict__ mbuf, int
 }
 
 // fif_mean of the 4 consecutive shapes p..p+3 (p and ldn multiples of 4,
-// mbuf 16-byte aligned): one 16-byte load per view, 8 views in flight.
+// mbuf 16-byte aligned): one 16-byte load per view, 16 views in flight.
 // Each shape's sum is taken in ascending view order, as in fif_mean, so the
 // results are the same bits.
 __device__ __forceinline__ float4 fif_mean4(const uint32_t* __restrict__ mbuf, int64_t ldn,
                                             int64_t p, int lo, int hi) {
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int i = lo; i < hi; i += 8) {
-    uint4 u[8];
+  for (int i = lo; i < hi; i += 16) {
+    uint4 u[16];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < 16; ++t)
       u[t] = i + t < hi ? *reinterpret_cast<const uint4*>(mbuf + (int64_t)(i + t) * ldn + p)
                         : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < 16; ++t) {
       if (u[t].x != 0u) acc[0] += order_float(u[t].x);
       if (u[t].y != 0u) acc[1] += order_float(u[t].y);
       if (u[t].z != 0u) acc[2] += order_float(u[t].z);
@@ -1064,6 +1064,9 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   __shared__ int64_t sh_item;
   __shared__ int64_t sh_nact;
   __shared__ int sh_err;
+  // thread 0's per-phase busy ticks and last item end, added to the plan's
+  // counters once when the block leaves the queue
+  __shared__ unsigned long long sh_busy[BP_END], sh_end[BP_END];
   const int tid = threadIdx.x;
   unsigned long long* head = a.ctrl;
   unsigned long long* done = a.ctrl + 1;
@@ -1093,6 +1096,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   }
   const int64_t red_chunks = (a.n_shapes + BATCH_RED_SHAPES - 1) / BATCH_RED_SHAPES;
   const int64_t n_red = (int64_t)n_q * red_chunks;
+  if (tid < BP_END) { sh_busy[tid] = 0ull; sh_end[tid] = 0ull; }
   int64_t n_active = -1;  // active list tiles, once this block has waited for PRE
   int acquired = -1;      // thread 0: last phase whose inputs this block acquired
   long long t_item = 0;   // thread 0: wall clock once the item's inputs are ready
@@ -1321,12 +1325,20 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     __syncthreads();
     if (tid == 0) {
       if (ph == BP_Q) __hip_atomic_fetch_add(q_done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const long long t_end = wall_clock64();
-      __hip_atomic_fetch_add(&a.phase_ticks[ph], (unsigned long long)(t_end - t_item),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_max(&a.phase_ticks[BP_END + ph], (unsigned long long)t_end,
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // no item waits for RED items, so they skip the shared counter
+      if (ph != BP_RED) __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long t_end = (unsigned long long)wall_clock64();
+      sh_busy[ph] += t_end - (unsigned long long)t_item;
+      if (t_end > sh_end[ph]) sh_end[ph] = t_end;
+    }
+  }
+  if (tid == 0) {
+    for (int i = 0; i < BP_END; ++i) {
+      if (sh_end[i] == 0ull) continue;
+      __hip_atomic_fetch_add(&a.phase_ticks[i], sh_busy[i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&a.phase_ticks[BP_END + i], sh_end[i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
