@@ -1319,9 +1319,13 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
       }
     }
     // Release what later items read with plain loads.  The list scan writes
-    // only through device-scope atomics (as the queue counters do) and the
-    // per-query means are read only after the kernel.
+    // only through device-scope atomics, which are performed where every
+    // XCD sees them (as the queue counters are); each wave waits until its
+    // own have been performed (vmcnt 0), so thread 0's counter increment
+    // after the barrier cannot overtake them.  The per-query means are read
+    // only after the kernel.
     if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else if (ph == BP_SCAN) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (tid == 0) {
       if (ph == BP_Q) __hip_atomic_fetch_add(q_done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
