@@ -324,8 +324,10 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* sequence is captured once into a HIP graph.                              */
 /* gift_fif_plan_run(n_queries, n_views)                                   */
 /* launches that graph for a batch occupying the first n_queries slots and  */
-/* n_views rows; outputs of unused slots are unspecified.  Results equal   */
-/* those of gift_query_fif on the same batch.  blocks_per_cu (1 or 2) sets */
+/* n_views rows; outputs of unused slots are unspecified.  Ids and scores */
+/* equal those of gift_query_fif on the same batch; its float32 first pass */
+/* sums in another order (last-bit differences), so a flag can differ when */
+/* its margin is below that.  blocks_per_cu (1 or 2) sets                 */
 /* the persistent grid.  Create SYNCHRONISES `stream` (which must be a     */
 /* non-default stream not being captured); run is asynchronous.  A plan is */
 /* not thread-safe and its runs on different streams must not overlap.     */
