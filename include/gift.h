@@ -122,7 +122,9 @@ gift_status gift_quantize_views(const float* src, int64_t n, int32_t dim,
 /*   flags  [n_queries] int32 or NULL: bit 0 set when the returned list is  */
 /*          provably the exact top_k over all N shapes (no shape outside   */
 /*          the rescored set can belong to it, given the error bound of    */
-/*          the first-pass dtype).                                         */
+/*          the first-pass dtype for this query's own view count, so a     */
+/*          query's flag does not depend on the rest of its batch).  A set */
+/*          bit is sound; a clear bit claims nothing.                      */
 /* Requires top_k <= rescore_r <= min(1024, N).                             */
 /* ---------------------------------------------------------------------- */
 size_t gift_query_exhaustive_workspace(const gift_views* db,
@@ -298,8 +300,12 @@ gift_status gift_fuse_activations(int32_t n_rows, const int32_t* ids1,
 /* enters ||F_q||_1; pass 0, or q_self = NULL, for a database shape whose   */
 /* own id is in q_ids).  Returns the top_k shapes by (S' desc, id asc);    */
 /* shapes sharing no coordinate score 0 and fill the list in id order.     */
-/* S' is formed in compensated arithmetic.  flags[b] = 1, or 2 when the     */
-/* query touched more than 4096 postings and only the first were used.    */
+/* S' is formed in compensated arithmetic.  The result is exact for any    */
+/* number of postings: a query whose coordinates hold more than 4096       */
+/* postings is processed in several ranges of shape ids, each of at most   */
+/* 4096 postings.  flags [n_queries] (or NULL): bit 0 always set (exact),  */
+/* bit 1 set when the query took more than one range.                     */
+/* Requires 1 <= top_k <= min(n_shapes, 1024), 1 <= k1 <= 256.             */
 /* ---------------------------------------------------------------------- */
 gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
                             const int64_t* post_off, const int32_t* post_id,
@@ -312,7 +318,9 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* ---------------------------------------------------------------------- */
 /* Batch plans for the F-IF path (Eq. 4, then the exact rescore and        */
 /* ranking of gift_query_fif).  A plan fixes the database, the index and   */
-/* capacities (max_queries, max_views in total, max_views_per_query) and   */
+/* capacities (max_queries, max_views in total, max_views_per_query, the   */
+/* last checked at creation only: certificates use each query's own view   */
+/* count) and                                                              */
 /* binds caller-owned device buffers: q_views [max_views][dim] float32 and */
 /* q_offsets [max_queries + 1] (the batch input, written by the caller     */
 /* before each run; q_offsets[0] = 0), and the outputs ids / scores        */

@@ -75,22 +75,23 @@ static float rescore_dot_err(int dim) {
   return (float)((split + 1.02 * gamma_n(6.0 * 17 + dim / 32 + 2)) * 1.0001 + 1e-25);
 }
 
-// Bound on |first-pass score - exact Eq. 3 score| for unit-norm views.
-// Storage rounding: each stored value is within u_s of the scaled value
-// (u_s = 2^-8 for BF16, 2^-4 for e4m3), so a product is within
-// 2 u_s + u_s^2 relative; the MFMA accumulation is charged 2*dim roundings;
-// the mean over at most max_m views adds gamma_(max_m + 1).
-static float first_pass_err(int dtype, int dim, int max_m) {
+// Bound on |first-pass score - exact Eq. 3 score| for unit-norm views,
+// without the mean's term.  Storage rounding: each stored value is within
+// u_s of the scaled value (u_s = 2^-8 for BF16, 2^-4 for e4m3), so a product
+// is within 2 u_s + u_s^2 relative; the MFMA accumulation is charged 2*dim
+// roundings.  The final ranking adds the mean over the query's own m views,
+// gamma_(m + 2), per query (so a query's certificate does not depend on the
+// other queries of its batch), and a 1.001 safety factor.
+static double first_pass_err(int dtype, int dim) {
   // MX element errors are relative to the block maximum, not the element
   // (saturation can cost an eighth of it): no useful bound, so never certify
-  if (dtype == GIFT_MXFP8 || dtype == GIFT_MXFP4) return 4.f;
+  if (dtype == GIFT_MXFP8 || dtype == GIFT_MXFP4) return 4.0;
   double us = dtype == GIFT_BF16 ? 1.0 / 256 : dtype == GIFT_FP8E4M3 ? 1.0 / 16 : 0.0;
-  double e = (2 * us + us * us) + gamma_n(2.0 * dim + 4) + gamma_n(max_m + 2.0);
-  return (float)(e * 1.001);
+  return (2 * us + us * us) + gamma_n(2.0 * dim + 4);
 }
 
 float rescore_dot_error(int dim) { return rescore_dot_err(dim); }
-float first_pass_error(int dtype, int dim, int max_m) { return first_pass_err(dtype, dim, max_m); }
+double first_pass_error(int dtype, int dim) { return first_pass_err(dtype, dim); }
 
 // Rows are read with 16-byte vector loads and scales with 4-byte loads.
 static bool aligned(const void* p, uintptr_t a) {
@@ -463,7 +464,7 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
-                    db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views), nullptr,
+                    db->n_shapes, first_pass_err(db->dtype, db->dim), q->offsets, nullptr,
                     nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
@@ -670,7 +671,7 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
-                    db->n_shapes, first_pass_err(db->dtype, db->dim, q->max_views),
+                    db->n_shapes, first_pass_err(db->dtype, db->dim), q->offsets,
                     w.as.overflow, nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
@@ -847,7 +848,8 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1, const int64_t* po
                             int32_t* flags, void* stream) {
   GIFT_CHECK(n_shapes >= 1 && n_shapes < ((int64_t)1 << 31), GIFT_EINVAL, "n_shapes out of range");
   GIFT_CHECK(k1 >= 1 && k1 <= 256, GIFT_EINVAL, "k1 must be in 1..256");
-  GIFT_CHECK(top_k >= 1 && top_k <= n_shapes, GIFT_EINVAL, "need 1 <= top_k <= n_shapes");
+  GIFT_CHECK(top_k >= 1 && top_k <= n_shapes && top_k <= 1024, GIFT_EINVAL,
+             "need 1 <= top_k <= min(n_shapes, 1024)");
   GIFT_CHECK(n_queries >= 0, GIFT_EINVAL, "n_queries < 0");
   GIFT_CHECK(l1 && post_off && post_id && post_val && q_ids && q_scores && ids && scores,
              GIFT_EINVAL, "null pointer");

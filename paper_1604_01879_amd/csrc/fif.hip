@@ -1238,7 +1238,10 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           for (int w = 0; w < wave; ++w) { run += wsum[w]; trun += wsum[4 + w]; }
           if (tid == 255) {
             a.goff[a.K] = run + sum;
-            *n_active_w = (unsigned long long)(trun + tsum);
+            // read with an atomic load by every block entering the scan
+            // range: published the same way as the queue counters
+            __hip_atomic_store(n_active_w, (unsigned long long)(trun + tsum), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
           }
           for (int k = k0; k < k1; k += 8) {
             int c[8];

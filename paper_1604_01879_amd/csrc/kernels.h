@@ -57,13 +57,15 @@ void launch_rescore(const float* master, int n_views, int dim,
                     hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
-// id asc) and writes the top k; sets flags bit 0 when provably complete.
+// id asc) and writes the top k; sets flags bit 0 when provably complete:
+// the first-pass error bound of query b is first_err + gamma_(m_b + 2)
+// (times 1.001), m_b = qoff[b + 1] - qoff[b] its view count.
 // flags bit 1 is set when *overflow != 0 (a quantizer decision could not
 // be certified); bit 0 then stays clear.
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
-                       int r, int k, int64_t n_total, float first_err,
-                       const int32_t* overflow, const int32_t* active, int32_t* ids,
+                       int r, int k, int64_t n_total, double first_err,
+                       const int32_t* qoff, const int32_t* overflow, const int32_t* active, int32_t* ids,
                        float* scores, int32_t* flags, hipStream_t st);
 
 // ---- first inverted file
@@ -157,7 +159,7 @@ void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStr
 float assign_gamma2(int dim);
 // error bounds of the rescore dot product and of the first pass (api.hip)
 float rescore_dot_error(int dim);
-float first_pass_error(int dtype, int dim, int max_m);
+double first_pass_error(int dtype, int dim);
 
 // ---- second inverted file
 // l1 [N][2] (compensated ||F_p||_1), post_off [N+1], post_id / post_val

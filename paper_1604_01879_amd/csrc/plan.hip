@@ -123,7 +123,7 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
                  p->view_words, p->ma, active, p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
-                    p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim, p->max_m),
+                    p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim), p->qoff,
                     p->ws.overflow, active, p->ids, p->scores, p->flags, st);
   GIFT_LAUNCHED();
   return GIFT_OK;

@@ -643,7 +643,8 @@ __device__ inline bool cand_before(const Cand& a, const Cand& b) {
 __global__ __launch_bounds__(256) void final_rank_kernel(
     const int32_t* __restrict__ cand, const float* __restrict__ first_s,
     const float* __restrict__ s_hi, const float* __restrict__ s_lo, int r,
-    int k, int64_t n_total, float first_err, const int32_t* __restrict__ overflow,
+    int k, int64_t n_total, double first_err, const int32_t* __restrict__ qoff,
+    const int32_t* __restrict__ overflow,
     const int32_t* __restrict__ active, int32_t* __restrict__ ids, float* __restrict__ scores,
     int32_t* __restrict__ flags) {
   __shared__ Cand c[MAX_R];
@@ -681,8 +682,11 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
     // the k-th exact score.
     bool complete = (int64_t)r >= n_total;
     if (!complete) {
+      // the mean over this query's own views adds gamma_(m + 2)
+      const double u = 5.9604644775390625e-08, nm = (double)(qoff[b + 1] - qoff[b]) + 2.0;
+      const float err = (float)((first_err + nm * u / (1.0 - nm * u)) * 1.001);
       const float kth = c[k - 1].hi;
-      const float bound = first_s[base + r - 1] + first_err;
+      const float bound = first_s[base + r - 1] + err;
       complete = bound < kth - fabsf(kth) * 2.4e-7f;
     }
     const bool ovf = overflow != nullptr && *overflow != 0;
@@ -692,12 +696,12 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
 
 void launch_final_rank(const int32_t* cand, const float* first_s,
                        const float* s_hi, const float* s_lo, int n_queries,
-                       int r, int k, int64_t n_total, float first_err,
-                       const int32_t* overflow, const int32_t* active, int32_t* ids,
-                       float* scores, int32_t* flags, hipStream_t st) {
+                       int r, int k, int64_t n_total, double first_err,
+                       const int32_t* qoff, const int32_t* overflow, const int32_t* active,
+                       int32_t* ids, float* scores, int32_t* flags, hipStream_t st) {
   if (n_queries <= 0) return;
   hipLaunchKernelGGL(final_rank_kernel, dim3(n_queries), dim3(256), 0, st,
-                     cand, first_s, s_hi, s_lo, r, k, n_total, first_err, overflow,
+                     cand, first_s, s_hi, s_lo, r, k, n_total, first_err, qoff, overflow,
                      active, ids, scores, flags);
 }
 

@@ -119,8 +119,19 @@ void launch_build_sif(const int32_t* ids, const float* vals, int64_t N, int k1, 
 // score S' = num / (||F_q||_1 + ||F_p||_1 - num) (Eq. 14) is formed in
 // compensated arithmetic, and the shapes are ranked by (S' desc, id asc);
 // shapes sharing no coordinate score 0 and fill the list in id order.
-constexpr int SIF_CAP = 4096;  // expanded postings per query
+//
+// Every posting list is sorted by shape, so the postings of the shapes
+// below a bound p_hi form a prefix of each list.  When a query's postings
+// exceed SIF_CAP, the block walks the shape axis in passes: each pass takes
+// the largest p_hi whose prefixes fit SIF_CAP (a shape has at most k1 <=
+// 256 postings, so every pass advances), scores those shapes exactly as a
+// single pass would (a shape's postings all fall in one pass, in the same
+// order), and merges its best shapes into the running top k.  The result is
+// the same for any posting count.
+constexpr int SIF_CAP = 4096;      // expanded postings per pass
+constexpr int SIF_KMAX = 1024;     // largest top_k
 constexpr int SIF_THREADS = 1024;  // one block per query; its LDS leaves room for one per CU
+constexpr int SIF_WAVES = SIF_THREADS / 64;
 
 struct SCand {
   float hi, lo;
@@ -146,6 +157,32 @@ __device__ inline ff ff_div(ff a, ff b) {
   return ff_norm(q1, q2);
 }
 
+// Sum (op 0) or minimum (op 1) of v over the block; every thread gets it.
+__device__ inline int64_t sif_block_reduce(int64_t v, int op, int64_t* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t w = __shfl_xor(v, o, 64);
+    v = op == 0 ? v + w : (w < v ? w : v);
+  }
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  int64_t t = red[0];
+  for (int w = 1; w < SIF_WAVES; ++w) t = op == 0 ? t + red[w] : (red[w] < t ? red[w] : t);
+  __syncthreads();
+  return t;
+}
+
+// First position in [lo, hi) of the ascending ids whose id is >= x.
+__device__ inline int64_t sif_lower_bound(const int32_t* __restrict__ ids, int64_t lo, int64_t hi,
+                                          int64_t x) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)ids[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     const float* __restrict__ l1, const int64_t* __restrict__ post_off,
     const int32_t* __restrict__ post_id, const float* __restrict__ post_val, int64_t N,
@@ -153,141 +190,228 @@ __global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     const float* __restrict__ q_self, int k1, int k, int32_t* __restrict__ out_id,
     float* __restrict__ out_s, int32_t* __restrict__ flags) {
   __shared__ int64_t pre[257];
-  __shared__ int64_t cnt_r[256];  // postings taken from coordinate r
-  __shared__ float val_r[256];    // membership at coordinate r
-  __shared__ uint8_t in_r[256];   // coordinate r names a shape in range
+  __shared__ int64_t cur_r[256];   // next unused posting of coordinate r
+  __shared__ int64_t end_r[256];   // end of coordinate r's postings
+  __shared__ int64_t take_r[256];  // postings of coordinate r in this pass
+  __shared__ float val_r[256];     // membership at coordinate r
+  __shared__ uint8_t in_r[256];    // coordinate r names a shape in range
+  __shared__ int64_t red[SIF_WAVES];
   __shared__ float Ahi, Alo;
-  __shared__ int overflow;
-  __shared__ int wsum[SIF_THREADS / 64];
+  __shared__ int wsum[SIF_WAVES];
+  __shared__ int n_best;
   extern __shared__ __align__(16) uint8_t sm[];
   uint64_t* key = reinterpret_cast<uint64_t*>(sm);                // (shape << 32) | slot
   float* pv = reinterpret_cast<float*>(sm + 8 * SIF_CAP);           // min value per slot
-  SCand* cand = reinterpret_cast<SCand*>(sm + 12 * SIF_CAP);
+  SCand* cand = reinterpret_cast<SCand*>(sm + 12 * SIF_CAP);        // this pass's shapes
+  SCand* best = cand + SIF_CAP;                                     // running top k
+  SCand* best2 = best + SIF_KMAX;                                   // merge output
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int32_t* qi = q_id + (int64_t)b * k1;
   const float* qv = q_val + (int64_t)b * k1;
 
-  // the coordinates' posting counts, loaded in parallel; then the prefix
-  // and ||F_q||_1 in coordinate order
+  // the coordinates' posting ranges, loaded in parallel; then ||F_q||_1 in
+  // coordinate order
   for (int r = tid; r < k1; r += SIF_THREADS) {
     const int32_t i = qi[r];
     const bool ok = i >= 0 && i < N;
     const float v = qv[r];
-    cnt_r[r] = ok && v > 0.f ? post_off[i + 1] - post_off[i] : 0;
+    const bool use = ok && v > 0.f;
+    cur_r[r] = use ? post_off[i] : 0;
+    end_r[r] = use ? post_off[i + 1] : 0;
     val_r[r] = v;
     in_r[r] = ok;
   }
   __syncthreads();
   if (tid == 0) {
     ff A = {q_self != nullptr ? q_self[b] : 0.f, 0.f};
-    int64_t run = 0;
-    for (int r = 0; r < k1; ++r) {
-      pre[r] = run;
+    for (int r = 0; r < k1; ++r)
       if (in_r[r]) A = ff_add(A, ff{val_r[r], 0.f});
-      run += cnt_r[r];
-    }
-    pre[k1] = run;
-    overflow = run > SIF_CAP;
     Ahi = A.hi;
     Alo = A.lo;
+    n_best = 0;
   }
   __syncthreads();
-  const int L = (int)(pre[k1] < SIF_CAP ? pre[k1] : SIF_CAP);
-  for (int s = tid; s < L; s += SIF_THREADS) {
-    int lo = 0, hi = k1;  // r with pre[r] <= s < pre[r+1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pre[mid] <= s) lo = mid; else hi = mid;
-    }
-    const int64_t e = post_off[qi[lo]] + (s - pre[lo]);
-    key[s] = ((uint64_t)(uint32_t)post_id[e] << 32) | (uint32_t)s;
-    pv[s] = fminf(qv[lo], post_val[e]);
-  }
-  int np2 = 1;
-  while (np2 < L) np2 <<= 1;
-  for (int s = L + tid; s < np2; s += SIF_THREADS) key[s] = ~0ull;
-  __syncthreads();
-  for (int kk = 2; kk <= np2; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < np2; i += SIF_THREADS) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const bool up = (i & kk) == 0;
-          const uint64_t x = key[i], y = key[ix];
-          if ((x > y) == up) { key[i] = y; key[ix] = x; }
-        }
+  int passes = 0;
+  for (;;) {
+    // postings left, over the coordinates
+    const int64_t left =
+        sif_block_reduce(tid < k1 ? end_r[tid] - cur_r[tid] : 0, 0, red);
+    if (left == 0) break;
+    ++passes;
+    if (left <= SIF_CAP) {
+      if (tid < k1) take_r[tid] = end_r[tid] - cur_r[tid];
+    } else {
+      // largest p_hi with at most SIF_CAP postings of shapes below it:
+      // count(lo) <= SIF_CAP < count(hi), lo starting just past the smallest
+      // shape left (at most k1 postings) and hi above every int32 id (all
+      // postings); each pass takes at least the smallest shape's postings
+      const int64_t pmin = sif_block_reduce(
+          tid < k1 && cur_r[tid] < end_r[tid] ? (int64_t)post_id[cur_r[tid]] : ((int64_t)1 << 31),
+          1, red);
+      int64_t lo = pmin + 1, hi = (int64_t)1 << 31;
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int64_t c = sif_block_reduce(
+            tid < k1 ? sif_lower_bound(post_id, cur_r[tid], end_r[tid], mid) - cur_r[tid] : 0, 0,
+            red);
+        if (c <= SIF_CAP) lo = mid; else hi = mid;
       }
+      if (tid < k1) take_r[tid] = sif_lower_bound(post_id, cur_r[tid], end_r[tid], lo) - cur_r[tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int64_t run = 0;
+      for (int r = 0; r < k1; ++r) {
+        pre[r] = run;
+        run += take_r[r];
+      }
+      pre[k1] = run;
+    }
+    __syncthreads();
+    const int L = (int)pre[k1];  // <= SIF_CAP
+    for (int s = tid; s < L; s += SIF_THREADS) {
+      int lo = 0, hi = k1;  // r with pre[r] <= s < pre[r+1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= s) lo = mid; else hi = mid;
+      }
+      const int64_t e = cur_r[lo] + (s - pre[lo]);
+      key[s] = ((uint64_t)(uint32_t)post_id[e] << 32) | (uint32_t)s;
+      pv[s] = fminf(val_r[lo], post_val[e]);
+    }
+    int np2 = 1;
+    while (np2 < L) np2 <<= 1;
+    for (int s = L + tid; s < np2; s += SIF_THREADS) key[s] = ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= np2; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < np2; i += SIF_THREADS) {
+          const int ix = i ^ j;
+          if (ix > i) {
+            const bool up = (i & kk) == 0;
+            const uint64_t x = key[i], y = key[ix];
+            if ((x > y) == up) { key[i] = y; key[ix] = x; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // one candidate per distinct shape, in ascending shape order
+    int base_u = 0;
+    for (int s0 = 0; s0 < L; s0 += SIF_THREADS) {
+      const int s = s0 + tid;
+      const bool start = s < L && (s == 0 || (key[s] >> 32) != (key[s - 1] >> 32));
+      const int lane = tid & 63, wave = tid >> 6;
+      const unsigned long long bal = __ballot(start);
+      if (lane == 0) wsum[wave] = __popcll(bal);
+      __syncthreads();
+      int before = 0, tot = 0;
+      for (int w = 0; w < SIF_WAVES; ++w) {
+        if (w < wave) before += wsum[w];
+        tot += wsum[w];
+      }
+      const int u = base_u + before + __popcll(bal & ((1ull << lane) - 1ull));
+      if (start) {
+        const int32_t p = (int32_t)(key[s] >> 32);
+        ff num = {0.f, 0.f};
+        for (int t = s; t < L && (key[t] >> 32) == (uint64_t)(uint32_t)p; ++t)
+          num = ff_add(num, ff{pv[(uint32_t)key[t]], 0.f});
+        // denominator ||F_q||_1 + ||F_p||_1 - num (Eq. 14)
+        ff den = ff_add(ff{Ahi, Alo}, ff{l1[2 * (int64_t)p], l1[2 * (int64_t)p + 1]});
+        den = ff_add(den, ff{-num.hi, -num.lo});
+        const ff sc = ff_div(num, den);
+        cand[u] = SCand{sc.hi, sc.lo, p};
+      }
+      base_u += tot;
       __syncthreads();
     }
-  }
-  // one candidate per distinct shape, in ascending shape order
-  int base_u = 0;
-  for (int s0 = 0; s0 < L; s0 += SIF_THREADS) {
-    const int s = s0 + tid;
-    const bool start = s < L && (s == 0 || (key[s] >> 32) != (key[s - 1] >> 32));
-    const int lane = tid & 63, wave = tid >> 6;
-    const unsigned long long bal = __ballot(start);
-    if (lane == 0) wsum[wave] = __popcll(bal);
+    const int U = base_u;
+    int np2u = 1;
+    while (np2u < U) np2u <<= 1;
+    for (int i = U + tid; i < np2u; i += SIF_THREADS) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
     __syncthreads();
-    int before = 0, tot = 0;
-    for (int w = 0; w < SIF_THREADS / 64; ++w) {
-      if (w < wave) before += wsum[w];
-      tot += wsum[w];
-    }
-    const int u = base_u + before + __popcll(bal & ((1ull << lane) - 1ull));
-    if (start) {
-      const int32_t p = (int32_t)(key[s] >> 32);
-      ff num = {0.f, 0.f};
-      for (int t = s; t < L && (key[t] >> 32) == (uint64_t)(uint32_t)p; ++t)
-        num = ff_add(num, ff{pv[(uint32_t)key[t]], 0.f});
-      // denominator ||F_q||_1 + ||F_p||_1 - num (Eq. 14)
-      ff den = ff_add(ff{Ahi, Alo}, ff{l1[2 * (int64_t)p], l1[2 * (int64_t)p + 1]});
-      den = ff_add(den, ff{-num.hi, -num.lo});
-      const ff sc = ff_div(num, den);
-      cand[u] = SCand{sc.hi, sc.lo, p};
-    }
-    base_u += tot;
-    __syncthreads();
-  }
-  const int U = base_u;
-  // candidate ids are ascending here; remember them for the zero padding
-  // by sorting a copy of the ids into `key` (already ascending by shape)
-  for (int i = tid; i < U; i += SIF_THREADS) key[i] = (uint64_t)(uint32_t)cand[i].id;
-  int np2u = 1;
-  while (np2u < U) np2u <<= 1;
-  for (int i = U + tid; i < np2u; i += SIF_THREADS) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
-  __syncthreads();
-  for (int kk = 2; kk <= np2u; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < np2u; i += SIF_THREADS) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const bool up = (i & kk) == 0;
-          const SCand x = cand[i], y = cand[ix];
-          if (scand_before(y, x) == up) { cand[i] = y; cand[ix] = x; }
+    for (int kk = 2; kk <= np2u; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < np2u; i += SIF_THREADS) {
+          const int ix = i ^ j;
+          if (ix > i) {
+            const bool up = (i & kk) == 0;
+            const SCand x = cand[i], y = cand[ix];
+            if (scand_before(y, x) == up) { cand[i] = y; cand[ix] = x; }
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    // merge the pass's best min(U, k) into the running top k: an element's
+    // output rank is its rank in its own list plus the number of elements of
+    // the other list ordered before it (shapes of different passes differ)
+    const int nA = U < k ? U : k, nB = n_best;
+    for (int i = tid; i < nA; i += SIF_THREADS) {
+      const SCand x = cand[i];
+      int lo = 0, hi = nB;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (scand_before(best[mid], x)) lo = mid + 1; else hi = mid;
+      }
+      if (i + lo < k) best2[i + lo] = x;
+    }
+    for (int j = tid; j < nB; j += SIF_THREADS) {
+      const SCand y = best[j];
+      int lo = 0, hi = nA;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (scand_before(cand[mid], y)) lo = mid + 1; else hi = mid;
+      }
+      if (j + lo < k) best2[j + lo] = y;
+    }
+    __syncthreads();
+    const int nn = nA + nB < k ? nA + nB : k;
+    for (int i = tid; i < nn; i += SIF_THREADS) best[i] = best2[i];
+    if (tid < k1) cur_r[tid] += take_r[tid];
+    if (tid == 0) n_best = nn;
+    __syncthreads();
   }
-  const int kp = k < U ? k : U;
+  const int kp = n_best;
   for (int i = tid; i < kp; i += SIF_THREADS) {
-    out_id[(int64_t)b * k + i] = cand[i].id;
-    out_s[(int64_t)b * k + i] = cand[i].hi;
+    out_id[(int64_t)b * k + i] = best[i].id;
+    out_s[(int64_t)b * k + i] = best[i].hi;
   }
-  if (tid == 0) {
-    // zero-score shapes in id order, skipping the candidates
-    int pos = kp, c = 0;
-    for (int64_t id = 0; pos < k && id < N; ++id) {
-      while (c < U && (int64_t)key[c] < id) ++c;
-      if (c < U && (int64_t)key[c] == id) continue;
-      out_id[(int64_t)b * k + pos] = (int32_t)id;
-      out_s[(int64_t)b * k + pos] = 0.f;
-      ++pos;
+  if (kp < k) {
+    // every shape with a shared coordinate is in `best`: sort its ids to
+    // skip them in the zero-score padding
+    int np2k = 1;
+    while (np2k < kp) np2k <<= 1;
+    for (int i = tid; i < np2k; i += SIF_THREADS)
+      key[i] = i < kp ? (uint64_t)(uint32_t)best[i].id : ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= np2k; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < np2k; i += SIF_THREADS) {
+          const int ix = i ^ j;
+          if (ix > i) {
+            const bool up = (i & kk) == 0;
+            const uint64_t x = key[i], y = key[ix];
+            if ((x > y) == up) { key[i] = y; key[ix] = x; }
+          }
+        }
+        __syncthreads();
+      }
     }
-    if (flags != nullptr) flags[b] = overflow ? 2 : 1;
+    if (tid == 0) {
+      // zero-score shapes in id order, skipping the candidates
+      int pos = kp, c = 0;
+      for (int64_t id = 0; pos < k && id < N; ++id) {
+        while (c < kp && (int64_t)key[c] < id) ++c;
+        if (c < kp && (int64_t)key[c] == id) continue;
+        out_id[(int64_t)b * k + pos] = (int32_t)id;
+        out_s[(int64_t)b * k + pos] = 0.f;
+        ++pos;
+      }
+    }
   }
+  if (tid == 0 && flags != nullptr) flags[b] = passes > 1 ? 3 : 1;
 }
 
 // ------------------------------------------------------------------ augment
@@ -463,7 +587,7 @@ void launch_rerank_sif(const float* l1, const int64_t* post_off, const int32_t* 
                        const float* q_self, int B, int k1, int k, int32_t* out_id, float* out_s,
                        int32_t* flags, hipStream_t st) {
   if (B <= 0) return;
-  const size_t shmem = (size_t)SIF_CAP * (8 + 4 + sizeof(SCand));
+  const size_t shmem = (size_t)SIF_CAP * (8 + 4 + sizeof(SCand)) + 2 * (size_t)SIF_KMAX * sizeof(SCand);
   (void)ensure_dynamic_lds(reinterpret_cast<const void*>(rerank_sif_kernel), shmem);
   hipLaunchKernelGGL(rerank_sif_kernel, dim3(B), dim3(SIF_THREADS), shmem, st, l1, post_off, post_id,
                      post_val, N, q_id, q_val, q_self, k1, k, out_id, out_s, flags);

@@ -88,7 +88,16 @@ def test_plan_equals_query_fif(L, dtype_name):
             sc = plan.scores[:n_q].cpu().numpy()
             assert np.array_equal(ids, ref_ids.cpu().numpy())
             assert np.array_equal(sc, ref_sc.cpu().numpy())
-            assert np.array_equal(plan.flags[:n_q].cpu().numpy(), ref_fl.cpu().numpy())
+            fl = plan.flags[:n_q].cpu().numpy()
+            if dt != L.F32:
+                # same first-pass arithmetic and the same per-query bound
+                assert np.array_equal(fl, ref_fl.cpu().numpy())
+            # float32: the plan's first pass sums in another order, so a
+            # flag may differ where its margin is below one ulp; a set flag
+            # must still be sound (checked below: the ids are the exact top k)
+            for b in range(n_q):
+                if fl[b] & 1:
+                    assert_ranked_equal(ids[b], sc[b], S[b], k)
             for b in range(n_q):
                 if dt in (L.MXFP8, L.MXFP4):
                     # MX first passes are never certified complete: check that
@@ -145,6 +154,7 @@ def test_plan_alone_and_in_the_mix(L):
     plan.run(n_q, n_v)
     plan.stream.synchronize()
     mix_ids, mix_sc = plan.ids[:n_q].cpu().numpy(), plan.scores[:n_q].cpu().numpy()
+    mix_fl = plan.flags[:n_q].cpu().numpy()
     for b in (0, 5, 7):
         lo, hi = qoff[b], qoff[b + 1]
         _load(plan, q[lo:hi], np.array([0, hi - lo], np.int32))
@@ -152,6 +162,8 @@ def test_plan_alone_and_in_the_mix(L):
         plan.stream.synchronize()
         assert np.array_equal(plan.ids[0].cpu().numpy(), mix_ids[b])
         assert np.array_equal(plan.scores[0].cpu().numpy(), mix_sc[b])
+        # the certificate uses the query's own view count, not the batch's
+        assert int(plan.flags[0].item()) == int(mix_fl[b])
     plan.close()
 
 

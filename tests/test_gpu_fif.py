@@ -8,7 +8,8 @@ import torch
 
 import oracle as O
 import synth
-from test_gpu_exhaustive import assert_ranked_equal, REL
+from test_gpu_exhaustive import (REL, assert_flags_as_predicted, assert_ranked_equal,
+                                 assert_returned_exact)
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -236,19 +237,39 @@ def test_query_fif_mx_rescored_all(L, fmt):
 
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("ma", [1, 3])
-def test_query_fif_ranked_ids(L, dtype_name, ma):
-    _say(f"query_fif {dtype_name} ma={ma}")
+@pytest.mark.parametrize("R", [300, 120, 60])
+def test_query_fif_ranked_ids(L, dtype_name, ma, R):
+    """Eq. 4 ranking with every shape rescored (R = N) and with the top 120 or
+    60 of 300: returned scores are the exact Eq. 4 scores of their ids in
+    (score desc, id asc) order on every row; a certified row is the exact
+    top k; the certificate holds where the oracle's first pass leaves it
+    room (e4m3 at R = 60: only where its margin is positive)."""
+    _say(f"query_fif {dtype_name} ma={ma} R={R}")
     dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
     w = _wl(n_shapes=300, dim=128, m_lo=4, m_hi=64, n_queries=6)
     db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 16, ma, dt)
-    k, R = 20, 300
+    k = 20
     ids, sc, flags = L.gift_query_fif(V, F, Q, k, R)
     torch.cuda.synchronize()
     S = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
     ids, sc, flags = ids.cpu().numpy(), sc.cpu().numpy(), flags.cpu().numpy()
+    if dtype_name == "f32":
+        S1 = S
+    else:
+        qc, qs = O.quantize_views(q, dtype_name)
+        dc, ds = O.quantize_views(db, dtype_name)
+        S1 = O.fif_scores(O.dequantize(qc, qs), qoff, O.dequantize(dc, ds), w.n_views, cb,
+                          off, es, ev, qwords=O.assign(q, cb, 1)[:, 0])
     for b in range(len(qoff) - 1):
-        assert_ranked_equal(ids[b], sc[b], S[b], k)
-    assert (flags == 1).all()
+        assert_returned_exact(ids[b], sc[b], S[b], k)
+        if dtype_name == "f32" or R == w.n_shapes or flags[b] & 1:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
+    need = assert_flags_as_predicted(flags, S1, S, qoff, R, k, dtype_name, w.dim)
+    assert (flags >> 1 == 0).all()  # every query word certified
+    if R == w.n_shapes:
+        assert (flags == 1).all()
+    if not (dtype_name == "fp8" and R == 60 and ma == 3):
+        assert need >= 1
 
 
 def test_query_fif_long_rows_zero_ties(L):

@@ -231,3 +231,81 @@ def test_fusion_and_co_augmentation_match_oracle(L):
             valid = fi[p] >= 0
             got[fi[p][valid]] = fs[p][valid]
             assert np.allclose(got, ref[p], rtol=2e-6, atol=1e-7)
+
+
+def _hub_lists(rng, N, k1, hubs, n_fans, p_hub):
+    """Neighbour lists where most entries point at a few hub shapes: shapes
+    below n_fans list only hubs after themselves, the others take each entry
+    from the hubs with probability p_hub."""
+    ids = np.empty((N, k1), np.int32)
+    sc = np.empty((N, k1), np.float32)
+    for p in range(N):
+        pool_h = hubs[hubs != p]
+        if p < n_fans:
+            nb = rng.choice(pool_h, size=k1 - 1, replace=False)
+        else:
+            nh = min(int(rng.binomial(k1 - 1, p_hub)), len(pool_h))
+            nb = rng.choice(pool_h, size=nh, replace=False).tolist()
+            while len(nb) < k1 - 1:
+                c = int(rng.integers(0, N))
+                if c != p and c not in nb:
+                    nb.append(c)
+            nb = np.array(nb)
+        ids[p] = [p] + list(nb)
+        sc[p] = [1.0] + sorted(rng.random(k1 - 1).astype(np.float32).tolist(), reverse=True)
+    return ids, sc
+
+
+@pytest.mark.parametrize("case", ["mixed-k100", "mixed-k1000", "fans-k1000"])
+def test_rerank_hub_queries_many_passes(L, case):
+    """Queries whose coordinates hold more than 4,096 postings (hub shapes
+    that appear in thousands of neighbour lists) are re-ranked in several
+    ranges of shape ids and still equal the oracle's Eq. 8 ranking.  "mixed":
+    ordinary shapes list hubs with probability 0.6, so hub queries touch 4-8
+    ranges of about 6,000 shapes.  "fans": only 700 shapes list hubs, so a hub
+    query's ~6,000 postings fall on fewer shapes than k = 1,000 and the
+    zero-score padding follows a multi-range result.  Flag bit 1 marks the
+    queries that took more than one range."""
+    _say(f"rerank hubs {case}")
+    rng = np.random.default_rng(11)
+    kind, _, kk = case.partition("-k")
+    k = int(kk)
+    hubs = np.arange(1000, 1040, dtype=np.int32)
+    k1 = 20
+    if kind == "mixed":
+        N = 6000
+        ids, sc = _hub_lists(rng, N, k1, hubs, n_fans=300, p_hub=0.6)
+        plain = rng.choice(np.setdiff1d(np.arange(N), hubs), size=19, replace=False)
+        q_ids = [ids[1000], ids[1017], np.concatenate([hubs[:19], [-1]]), ids[5],
+                 np.concatenate([plain, [-1]])]
+        q_sc = [sc[1000], sc[1017], np.concatenate([np.linspace(0.9, 0.3, 19), [0.0]]), sc[5],
+                np.concatenate([np.linspace(0.8, 0.2, 19), [0.0]])]
+        q_self = np.array([0, 0, 1, 0, 1], np.float32)
+    else:
+        N = 3000
+        ids, sc = _hub_lists(rng, N, k1, hubs, n_fans=700, p_hub=0.0)
+        q_ids = [np.concatenate([hubs[:19], [-1]]), ids[5], ids[2500]]
+        q_sc = [np.concatenate([np.linspace(0.9, 0.3, 19), [0.0]]), sc[5], sc[2500]]
+        q_self = np.array([1, 0, 0], np.float32)
+    S = L.gift_build_sif(_t(ids), _t(sc))
+    l1, po, pid, pv = O.build_sif(ids, sc.astype(np.float64), N)
+    counts = np.diff(po)
+    q_ids = np.stack(q_ids).astype(np.int32)
+    q_sc = np.stack(q_sc).astype(np.float32)
+    n_post = np.array([sum(int(counts[i]) for i, v in zip(r, s) if 0 <= i < N and v > 0)
+                       for r, s in zip(q_ids, q_sc)])
+    if kind == "mixed":
+        assert n_post[:4].min() > 4 * 4096 and n_post[4] < 4096, n_post
+    else:
+        assert n_post[:2].min() > 4096 and n_post[2] < 4096, n_post
+    gi, gs, fl = L.gift_rerank_sif(S, _t(q_ids), _t(q_sc), _t(q_self), k)
+    torch.cuda.synchronize()
+    gi, gs, fl = gi.cpu().numpy(), gs.cpu().numpy(), fl.cpu().numpy()
+    for b in range(len(q_ids)):
+        _, _, Sref = O.rerank_sif(l1, po, pid, pv, q_ids[b], q_sc[b].astype(np.float64),
+                                  float(q_self[b]), k)
+        if kind == "fans" and b == 0:
+            assert (Sref > 0).sum() < k  # the list ends in zero-score padding
+        assert_ranked_equal(gi[b], gs[b], Sref, k)
+        assert fl[b] & 1
+        assert bool(fl[b] & 2) == bool(n_post[b] > 4096), (b, n_post[b], fl[b])
