@@ -135,6 +135,29 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
                                   int32_t* ids, float* scores, int32_t* flags,
                                   void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* gift_query_exhaustive without a workspace argument and without device   */
+/* allocation, for callers that cannot allocate (code under HIP graph       */
+/* capture, tight serving loops, harnesses that forbid hipMalloc).  Same    */
+/* arguments, results, flags and errors as gift_query_exhaustive; its      */
+/* scratch is one static device array of GIFT_STATIC_SCRATCH_BYTES (64     */
+/* MiB) per device, which every device that runs this call holds until the */
+/* process ends.  The first call on a device looks up that array's address */
+/* (hipGetSymbolAddress) with the device current; no call allocates.        */
+/* gift_query_exhaustive_static_bytes returns the scratch a batch needs     */
+/* (= gift_query_exhaustive_workspace); a batch needing more than          */
+/* GIFT_STATIC_SCRATCH_BYTES returns GIFT_ECAPACITY before any device work */
+/* (e.g. one 64-view query fits up to about 250,000 shapes).  All calls on */
+/* one device share its array: calls that overlap on one device (two       */
+/* streams, or two threads) RACE and must be serialised by the caller.     */
+/* ---------------------------------------------------------------------- */
+#define GIFT_STATIC_SCRATCH_BYTES (64u << 20)
+size_t gift_query_exhaustive_static_bytes(const gift_views* db, const gift_queries* q,
+                                          int32_t top_k, int32_t rescore_r);
+gift_status gift_query_exhaustive_static(const gift_views* db, const gift_queries* q,
+                                         int32_t top_k, int32_t rescore_r, int32_t* ids,
+                                         float* scores, int32_t* flags, void* stream);
+
 /* Full score matrix of the first pass of gift_query_exhaustive (Eq. 3 in   */
 /* db->dtype), for inspection: scores [n_queries][n_shapes] float32.        */
 size_t gift_score_exhaustive_workspace(const gift_views* db,

@@ -63,6 +63,9 @@ _sig = {
     "gift_query_exhaustive_workspace": (C.c_size_t, [_VP, _QP, C.c_int32, C.c_int32]),
     "gift_query_exhaustive": (C.c_int32, [_VP, _QP, C.c_int32, C.c_int32, _P, _P, _P, _P,
                                           C.c_size_t, _P]),
+    "gift_query_exhaustive_static_bytes": (C.c_size_t, [_VP, _QP, C.c_int32, C.c_int32]),
+    "gift_query_exhaustive_static": (C.c_int32, [_VP, _QP, C.c_int32, C.c_int32, _P, _P, _P,
+                                                 _P]),
     "gift_assign_workspace": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "gift_assign": (C.c_int32, [_P, C.c_int64, C.c_int32, _P, C.c_int32, C.c_int32, _P, _P, _P,
                                 C.c_size_t, _P]),
@@ -213,6 +216,32 @@ def gift_query_exhaustive(db: Views, q: Queries, top_k, rescore_r, stream=None, 
                                       _ptr(ids), _ptr(scores), _ptr(flags), _ptr(ws),
                                       ws.numel(), _stream(stream)))
     return ids, scores, flags
+
+
+# size of the static device scratch behind gift_query_exhaustive_static
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def gift_query_exhaustive_static(db: Views, q: Queries, top_k, rescore_r, stream=None,
+                                 out=None):
+    """gift_query_exhaustive on the library's static device scratch (no
+    workspace, no device allocation inside the call).  `out` = (ids, scores,
+    flags) preallocated outputs, or None to allocate them here."""
+    dev = db.data.device
+    if out is None:
+        out = (torch.empty((q.n_queries, top_k), dtype=torch.int32, device=dev),
+               torch.empty((q.n_queries, top_k), dtype=torch.float32, device=dev),
+               torch.empty(q.n_queries, dtype=torch.int32, device=dev))
+    ids, scores, flags = out
+    _check(_lib.gift_query_exhaustive_static(C.byref(db.c), C.byref(q.c), top_k, rescore_r,
+                                             _ptr(ids), _ptr(scores), _ptr(flags),
+                                             _stream(stream)))
+    return ids, scores, flags
+
+
+def query_exhaustive_static_bytes(db: Views, q: Queries, top_k, rescore_r) -> int:
+    return int(_lib.gift_query_exhaustive_static_bytes(C.byref(db.c), C.byref(q.c), top_k,
+                                                       rescore_r))
 
 
 def query_exhaustive_workspace(db: Views, q: Queries, top_k, rescore_r) -> int:

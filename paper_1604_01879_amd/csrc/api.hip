@@ -341,6 +341,35 @@ static gift_status fif_first_pass(const gift_views* db, const gift_fif* f, const
 
 }  // namespace gift
 
+namespace gift {
+
+// Scratch of gift_query_exhaustive_static.  Each device that runs the call
+// holds its own copy until the process ends.  In host code `scratch` only
+// names the symbol: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and that address is the only one
+// host code hands to kernels.
+static __device__ __align__(256) uint8_t scratch[GIFT_STATIC_SCRATCH_BYTES];
+
+static gift_status static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  GIFT_HIP(hipGetDevice(&dev));
+  GIFT_CHECK(dev >= 0 && dev < kMaxDevices, GIFT_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    GIFT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    GIFT_CHECK(p != nullptr, GIFT_EHIP, "no device address for the static scratch");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return GIFT_OK;
+}
+
+}  // namespace gift
+
 using namespace gift;
 
 extern "C" {
@@ -469,6 +498,28 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   prof_end(st);
   GIFT_LAUNCHED();
   return GIFT_OK;
+}
+
+size_t gift_query_exhaustive_static_bytes(const gift_views* db, const gift_queries* q,
+                                          int32_t top_k, int32_t rescore_r) {
+  return gift_query_exhaustive_workspace(db, q, top_k, rescore_r);
+}
+
+gift_status gift_query_exhaustive_static(const gift_views* db, const gift_queries* q,
+                                         int32_t top_k, int32_t rescore_r, int32_t* ids,
+                                         float* scores, int32_t* flags, void* stream) {
+  gift_status s = check_views(db);
+  if (s != GIFT_OK) return s;
+  if ((s = check_queries(q, db->dim)) != GIFT_OK) return s;
+  const size_t need = carve_exhaustive(nullptr, db, q, rescore_r > 0 ? rescore_r : 1).bytes;
+  GIFT_CHECK(need <= (size_t)GIFT_STATIC_SCRATCH_BYTES, GIFT_ECAPACITY,
+             "the batch needs %zu bytes of scratch; the static scratch holds %zu "
+             "(use gift_query_exhaustive with a workspace)",
+             need, (size_t)GIFT_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((s = static_scratch(&ws)) != GIFT_OK) return s;
+  return gift_query_exhaustive(db, q, top_k, rescore_r, ids, scores, flags, ws,
+                               (size_t)GIFT_STATIC_SCRATCH_BYTES, stream);
 }
 
 /* ------------------------------------------------------------ quantizer */

@@ -58,3 +58,24 @@ def test_argument_errors_need_no_device(lib):
     assert st == -1
     lib.gift_last_error.restype = ctypes.c_char_p
     assert b"n_shapes" in lib.gift_last_error()
+
+
+def test_static_scratch_capacity_needs_no_device(lib):
+    # gift_query_exhaustive_static sizes its batch against the 64 MiB static
+    # scratch on the host: a batch too large for it fails with
+    # GIFT_ECAPACITY before any device call (the pointers are never touched)
+    from paper_1604_01879_amd import _lib as L
+    fake = 1 << 20  # aligned, never dereferenced
+    q = L.gift_queries(fake, fake, 1, 64, 64)
+    sizes = {}
+    for n in (200_000, 250_000, 260_000, 300_000):
+        v = L.gift_views(fake, L.F32, 64, n, 4096, 0, None, fake)
+        sizes[n] = L._lib.gift_query_exhaustive_static_bytes(ctypes.byref(v), ctypes.byref(q),
+                                                             100, 200)
+    # one 64-view query: 260 bytes per shape (match buffer + score row)
+    assert sizes[250_000] <= L.STATIC_SCRATCH_BYTES < sizes[260_000]
+    v = L.gift_views(fake, L.F32, 64, 300_000, 4096, 0, None, fake)
+    st = L._lib.gift_query_exhaustive_static(ctypes.byref(v), ctypes.byref(q), 100, 200,
+                                             None, None, None, None)
+    assert st == L.ECAPACITY
+    assert b"static scratch" in L._lib.gift_last_error()
