@@ -355,13 +355,15 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* sequence is captured once into a HIP graph.                              */
 /* gift_fif_plan_run(n_queries, n_views)                                   */
 /* launches that graph for a batch occupying the first n_queries slots and  */
-/* n_views rows; outputs of unused slots are unspecified.  Ids and scores */
-/* equal those of gift_query_fif on the same batch; its float32 first pass */
-/* sums in another order (last-bit differences), so a flag can differ when */
-/* its margin is below that.  blocks_per_cu (1 or 2) sets                 */
+/* n_views rows; outputs of unused slots are unspecified.  The first-pass */
+/* scores, ids, scores and flags equal those of gift_query_fif on the same */
+/* batch (the same tiles in the same order).  blocks_per_cu (1 or 2) sets */
 /* the persistent grid.  Create SYNCHRONISES `stream` (which must be a     */
 /* non-default stream not being captured); run is asynchronous.  A plan is */
 /* not thread-safe and its runs on different streams must not overlap.     */
+/* gift_fif_plan_first_pass copies the first-pass Eq. 4 scores of the     */
+/* last run's first n_queries slots to out [n_queries][n_shapes] float32   */
+/* (device; asynchronous on `stream`), for inspection.                     */
 /* gift_fif_plan_error (SYNCHRONISES) returns 1 if a queue wait of the     */
 /* last run hit its time limit (results invalid), else 0.                  */
 /* gift_fif_plan_phase_us (SYNCHRONISES) writes, for the last run, the     */
@@ -392,6 +394,8 @@ gift_status gift_fif_plan_run(gift_fif_plan* plan, int32_t n_queries,
 /* The same sequence launched kernel by kernel (no graph), for comparison. */
 gift_status gift_fif_plan_run_eager(gift_fif_plan* plan, int32_t n_queries,
                                     int64_t n_views, void* stream);
+gift_status gift_fif_plan_first_pass(gift_fif_plan* plan, int32_t n_queries, float* out,
+                                     void* stream);
 gift_status gift_fif_plan_error(gift_fif_plan* plan, int32_t* err,
                                 void* stream);
 gift_status gift_fif_plan_phase_us(gift_fif_plan* plan, double* out /* host [9] */,

@@ -102,6 +102,7 @@ _sig = {
                                          C.c_size_t, _P, C.POINTER(C.c_void_p)]),
     "gift_fif_plan_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
     "gift_fif_plan_run_eager": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
+    "gift_fif_plan_first_pass": (C.c_int32, [C.c_void_p, C.c_int32, _P, _P]),
     "gift_fif_plan_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), _P]),
     "gift_fif_plan_phase_us": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), _P]),
     "gift_fif_plan_phase_end_us": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), _P]),
@@ -472,6 +473,14 @@ class FifPlan:
     def run(self, n_queries, n_views, stream=None, eager=False):
         f = _lib.gift_fif_plan_run_eager if eager else _lib.gift_fif_plan_run
         _check(f(self.handle, n_queries, n_views, _stream(stream or self.stream)))
+
+    def first_pass(self, n_queries, stream=None):
+        """First-pass Eq. 4 scores [n_queries, n_shapes] of the last run."""
+        out = torch.empty((n_queries, self.db.n_shapes), dtype=torch.float32,
+                          device=self.db.data.device)
+        _check(_lib.gift_fif_plan_first_pass(self.handle, n_queries, _ptr(out),
+                                             _stream(stream or self.stream)))
+        return out
 
     def phase_us(self, stream=None):
         """Block-microseconds per phase of the last run, waits for inputs

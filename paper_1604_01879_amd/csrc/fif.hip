@@ -686,8 +686,14 @@ __device__ __forceinline__ void scan_list_tile(
   };
 
   if constexpr (!MX) {
-    // up to 32 query views: one 128 x 32 tile instead of 128 x 128 mostly padding
-    if (g1 - g0 <= NarrowShape::BN) {
+    // up to 32 query views: one 128 x 32 tile instead of 128 x 128 mostly
+    // padding.  BF16 rows take it only through the direct-to-LDS loop: the
+    // register-staged narrow loop gave wrong, run-to-run varying BF16 dots
+    // inside the persistent batch kernel, so BF16 rows that are no whole
+    // number of 128-byte sub-tiles use the 128 x 128 tiles instead.
+    const bool narrow_ok =
+        DT != GIFT_BF16 || (NARROW_DMA && row_bytes % DMA2_KSUB == 0);
+    if (g1 - g0 <= NarrowShape::BN && narrow_ok) {
       using N = NarrowShape;
       f32x16 acc;
       if (NARROW_DMA && row_bytes % DMA2_KSUB == 0) {
@@ -1286,9 +1292,9 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
         }
         case BP_SCAN: {
           const int64_t b = a.act_tile[j];
-          // register-staged narrow tiles: measured faster inside this kernel
-          // than the direct-to-LDS gather (which raises its register pressure)
-          scan_list_tile<DT, false>(a.db, a.db_scale, a.n_views, a.row_bytes, a.loff, a.ent_shape,
+          // the list scan of gift_query_fif: same tiles, same products and
+          // order, so the same first-pass scores
+          scan_list_tile<DT, true>(a.db, a.db_scale, a.n_views, a.row_bytes, a.loff, a.ent_shape,
                              a.ent_view, a.tile_off, a.tile_word[b], a.goff, a.gitems,
                              DT == GIFT_F32 ? reinterpret_cast<const uint8_t*>(a.qviews)
                                             : a.qcodes,

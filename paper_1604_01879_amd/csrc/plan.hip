@@ -78,9 +78,9 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, Bmax, r));
   w.s_hi = c.take<float>((size_t)Bmax * r);
   w.s_lo = c.take<float>((size_t)Bmax * r);
-  w.rs.mask = c.take<unsigned long long>((size_t)r * Vmax);
-  w.rs.s1 = c.take<float>((size_t)Bmax * r);
-  w.rs.mark = c.take<uint8_t>((size_t)Bmax * r);
+  // the shape-major rescore reads the query rows the Q phase split
+  w.rs = take_rescore(c, Bmax, r, Vmax, db->dim, db->n_shapes, false);
+  w.rs.qsplit = w.qsplit;
   w.bytes = c.bytes();
   return w;
 }
@@ -118,9 +118,11 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, active, p->ws.cand, p->ws.cand_s,
                     p->ws.sel_tmp, st);
   GIFT_LAUNCHED();
-  launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->Vmax,
-                 p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim), p->ws.qwords,
-                 p->view_words, p->ma, active, p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
+  s = launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax,
+                     p->Vmax, p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim),
+                     p->ws.qwords, p->view_words, p->ma, active, p->ws.rs, false,
+                     p->db.n_shapes, p->ws.s_hi, p->ws.s_lo, st);
+  if (s != GIFT_OK) return s;
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
                     p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim), p->qoff,
@@ -341,6 +343,15 @@ gift_status gift_fif_plan_run_eager(gift_fif_plan* p, int32_t n_queries, int64_t
   const int32_t desc[2] = {n_queries, (int32_t)n_views};
   GIFT_HIP(hipMemcpyAsync(p->ws.desc, desc, sizeof(desc), hipMemcpyHostToDevice, st));
   return enqueue_plan(p, st);
+}
+
+gift_status gift_fif_plan_first_pass(gift_fif_plan* p, int32_t n_queries, float* out,
+                                     void* stream) {
+  GIFT_CHECK(p != nullptr && out != nullptr, GIFT_EINVAL, "null argument");
+  GIFT_CHECK(n_queries >= 0 && n_queries <= p->Bmax, GIFT_EINVAL, "n_queries out of range");
+  GIFT_HIP(hipMemcpyAsync(out, p->ws.S, (size_t)n_queries * p->db.n_shapes * sizeof(float),
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return GIFT_OK;
 }
 
 gift_status gift_fif_plan_error(gift_fif_plan* p, int32_t* err, void* stream) {

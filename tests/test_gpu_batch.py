@@ -76,25 +76,28 @@ def test_plan_equals_query_fif(L, dtype_name):
         qq = q[:qo[-1]]
         Q = L.Queries(torch.from_numpy(qq).to(DEV), torch.from_numpy(qo))
         ref_ids, ref_sc, ref_fl = L.gift_query_fif(V, F, Q, k, R)
+        ref_s1, _ = L.gift_score_fif(V, F, Q)
         torch.cuda.synchronize()
         _say(f"query_fif {sub} queries done")
         n_q, n_v = _load(plan, qq, qo)
-        for eager in (False, True):
+        for eager in (False, True, False, True):
             plan.run(n_q, n_v, eager=eager)
             plan.stream.synchronize()
             _say(f"plan run eager={eager} done")
             assert plan.error() == 0
+            # the first pass is gift_score_fif's, bit for bit (same tiles,
+            # products and order), on every run
+            s1 = plan.first_pass(n_q)
+            plan.stream.synchronize()
+            assert torch.equal(s1, ref_s1), int((s1 != ref_s1).sum())
             ids = plan.ids[:n_q].cpu().numpy()
             sc = plan.scores[:n_q].cpu().numpy()
             assert np.array_equal(ids, ref_ids.cpu().numpy())
             assert np.array_equal(sc, ref_sc.cpu().numpy())
             fl = plan.flags[:n_q].cpu().numpy()
-            if dt != L.F32:
-                # same first-pass arithmetic and the same per-query bound
-                assert np.array_equal(fl, ref_fl.cpu().numpy())
-            # float32: the plan's first pass sums in another order, so a
-            # flag may differ where its margin is below one ulp; a set flag
-            # must still be sound (checked below: the ids are the exact top k)
+            # same first pass and the same per-query bound: the same flags;
+            # a set flag must be sound (the ids are the exact top k)
+            assert np.array_equal(fl, ref_fl.cpu().numpy())
             for b in range(n_q):
                 if fl[b] & 1:
                     assert_ranked_equal(ids[b], sc[b], S[b], k)

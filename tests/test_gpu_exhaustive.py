@@ -17,10 +17,12 @@ import synth
 pytestmark = pytest.mark.gpu
 
 REL = 1e-5     # score tolerance (relative)
-# float64 gaps below this count as ties: about four times the rescore's
-# bound on one exact dot product (4.5e-13 of sum |x y| at d = 4096), so the
-# oracle's own float64 rounding and the GPU's both fit inside it
-TIE = 2e-12
+# float64 gaps below this count as ties.  The GPU's exact score is within
+# about 1.1e-12 of Eq. 3 for unit-norm rows at d <= 4096 (compensated Dot2
+# chains of 16 products, gamma(16)^2 + 32 u^2 per unit of sum |x y|), the
+# oracle's float64 score within 4.5e-13 (gamma_4096 of float64); two scores
+# whose float64 gap exceeds 2 (1.1e-12 + 4.5e-13) are ordered the same by both
+TIE = 4e-12
 U32 = 2.0 ** -24
 
 
@@ -290,6 +292,38 @@ def test_query_exhaustive_ranked_ids(L, dtype_name, case):
     # e4m3 with 5..40-view queries over 7-view shapes (margins -0.03..-0.09)
     if not (dtype_name == "fp8" and case == "few-views"):
         assert need >= 1
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
+def test_shape_major_rescore_equals_single_queries(L, dtype_name):
+    """A batch of 8 or more queries whose candidates repeat (here 16 x 60
+    pairs over 300 shapes) takes the shape-major first rescore phase, which
+    reads each candidate shape once for all its pairs; a query alone takes
+    the query-major one.  Both form the same products in the same order, so
+    each query's ids, scores and flag are identical alone and in the batch,
+    and the ranking is the oracle's.  Queries of 1..150 views (64-view
+    chunks), shapes of 64 views."""
+    _say(f"shape-major rescore {dtype_name}")
+    w, db, q, qoff = _data(N=300, dim=128, B=16, m=(1, 150), seed=31)
+    k, R = 10, 60
+    dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]
+    V, _, _ = _views(L, db, w.n_views, dt)
+    ids, sc, fl = L.gift_query_exhaustive(V, _queries(L, q, qoff), k, R)
+    torch.cuda.synchronize()
+    ids, sc, fl = ids.cpu().numpy(), sc.cpu().numpy(), fl.cpu().numpy()
+    S = O.exhaustive_scores(q, qoff, db, w.n_views)
+    for b in range(len(qoff) - 1):
+        lo, hi = qoff[b], qoff[b + 1]
+        qo = np.array([0, hi - lo], np.int32)
+        i1, s1, f1 = L.gift_query_exhaustive(V, _queries(L, q[lo:hi], qo), k, R)
+        assert np.array_equal(i1.cpu().numpy()[0], ids[b])
+        assert np.array_equal(s1.cpu().numpy()[0], sc[b])
+        assert int(f1.cpu().numpy()[0]) == int(fl[b])
+        assert_returned_exact(ids[b], sc[b], S[b], k)
+        if dtype_name == "f32" or fl[b]:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
+    if dtype_name == "f32":
+        assert fl.all()
 
 
 def test_query_exhaustive_self_queries(L):

@@ -171,7 +171,7 @@ def test_first_pass_fif_scores(L, dtype_name):
     assert np.allclose(S.cpu().numpy(), ref, rtol=REL, atol=1e-6)
 
 
-@pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("n_group", [1, 15, 16, 17, 31, 32, 33, 130])
 @pytest.mark.parametrize("dim", [96, 256])
 def test_scan_group_sizes_around_narrow_tile(L, dtype_name, n_group, dim):
@@ -179,10 +179,11 @@ def test_scan_group_sizes_around_narrow_tile(L, dtype_name, n_group, dim):
     to 16 views take the 128 x 16 scan tile (float32 rows of whole 128-byte
     sub-tiles), up to 32 the 128 x 32 tile, more the 128 x 128 tiles (130
     views: two column passes, the second of 2 views).  float32 rows of 384
-    and 1,024 bytes take the direct-to-LDS narrow loop (3 and 8 sub-tiles),
-    e4m3 rows of 96 bytes the register-staged one."""
+    and 1,024 bytes and BF16 rows of 512 bytes take the direct-to-LDS narrow
+    loop, e4m3 rows of 96 bytes the register-staged one, BF16 rows of 192
+    bytes the 128 x 128 tiles."""
     _say(f"fif group of {n_group} {dtype_name} dim {dim}")
-    dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]
+    dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}[dtype_name]
     w = _wl(n_shapes=70, dim=dim, n_queries=1, m_lo=n_group, m_hi=n_group, n_views=19)
     db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 1, 1, dt)
     S, qw = L.gift_score_fif(V, F, Q)
@@ -308,6 +309,35 @@ def test_query_fif_shared_candidates(L, ma):
     ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
     for b in range(len(qoff) - 1):
         assert_ranked_equal(ids[b], sc[b], S[b], k)
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "bf16"])
+def test_query_fif_shape_major_rescore_equals_single_queries(L, dtype_name):
+    """Eq. 4 rescore of a 16-query batch whose candidates repeat (the
+    shape-major first phase, word-matched pairs only) against each query
+    alone (the query-major phase): identical ids, scores and flags, and the
+    oracle's ranking.  Queries of 1..150 views."""
+    _say(f"fif shape-major rescore {dtype_name}")
+    dt = {"f32": L.F32, "bf16": L.BF16}[dtype_name]
+    w = _wl(n_shapes=240, dim=128, m_lo=1, m_hi=150, n_queries=16)
+    db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 12, 2, dt)
+    k, R = 12, 50
+    ids, sc, fl = L.gift_query_fif(V, F, Q, k, R)
+    torch.cuda.synchronize()
+    ids, sc, fl = ids.cpu().numpy(), sc.cpu().numpy(), fl.cpu().numpy()
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    assert (fl >> 1 == 0).all()  # every query word certified
+    for b in range(len(qoff) - 1):
+        lo, hi = qoff[b], qoff[b + 1]
+        qo = np.array([0, hi - lo], np.int32)
+        Q1 = L.Queries(torch.from_numpy(q[lo:hi]).to(DEV), torch.from_numpy(qo))
+        i1, s1, f1 = L.gift_query_fif(V, F, Q1, k, R)
+        assert np.array_equal(i1.cpu().numpy()[0], ids[b])
+        assert np.array_equal(s1.cpu().numpy()[0], sc[b])
+        assert int(f1.cpu().numpy()[0]) == int(fl[b])
+        assert_returned_exact(ids[b], sc[b], S[b], k)
+        if dtype_name == "f32" or fl[b] & 1:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
 
 
 def test_fif_one_word_and_full_ma_equal_exhaustive(L):
