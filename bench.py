@@ -30,6 +30,46 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+FP64_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                            "c3_fp64_top100.npz")
+
+
+def load_fp64_fixture(w, q_np, db_np):
+    """The float64 Eq. 3 top-100 of the 256 precision-workload queries
+    (written by tests/golden/make_c3_fp64_topk.py), or None when the file is
+    missing or its input digests do not match this run's inputs."""
+    import hashlib
+    if not os.path.exists(FP64_FIXTURE) or w.n_queries != 256 or w.n_shapes != 12000:
+        return None
+    f = np.load(FP64_FIXTURE)
+    qd = hashlib.sha256(np.ascontiguousarray(q_np).tobytes()).hexdigest()
+    dd = hashlib.sha256(np.ascontiguousarray(db_np[::1000]).tobytes()).hexdigest()
+    if str(f["q_sha256"]) != qd or str(f["db_probe_sha256"]) != dd:
+        return None
+    return {"ids": f["ids"], "scores": f["scores"], "next": f["next"]}
+
+
+def fp64_compare(ids, scores, fx, k):
+    """Recall@10 / @k (mean, min over queries) of a ranked list against the
+    float64 top-k, and the largest rank-wise |score - float64 score|."""
+    r_k = recall(ids, fx["ids"], k)
+    r10 = recall(ids, fx["ids"], min(10, k))
+    err = float(np.max(np.abs(np.asarray(scores, np.float64)[:, :k] - fx["scores"][:, :k])))
+    return {"at100_mean": r_k[0], "at100_min": r_k[1], "at10_mean": r10[0], "at10_min": r10[1],
+            "max_abs_score_err": err}
+
+
+def first_pass_topk(S, k):
+    """Top-k of first-pass scores [B, N] by (score desc, id asc)."""
+    S = np.asarray(S)
+    out_i = np.empty((S.shape[0], k), np.int64)
+    out_s = np.empty((S.shape[0], k), np.float32)
+    for b in range(S.shape[0]):
+        order = np.lexsort((np.arange(S.shape[1]), -S[b]))[:k]
+        out_i[b], out_s[b] = order, S[b][order]
+    return out_i, out_s
+
+
 def recall(ids, ref, k):
     r = [len(set(a[:k].tolist()) & set(b[:k].tolist())) / k for a, b in zip(ids, ref)]
     return float(np.mean(r)), float(np.min(r))
@@ -199,6 +239,26 @@ def main():
             if i in ref:
                 err = max(err, abs(s - ref[i]))
 
+    # recall and score error against the float64 Eq. 3 top-100 of every query,
+    # before (first-pass ranking) and after the float32 rescore, per storage
+    fx = load_fp64_fixture(w, q_np, db_np) if k == 100 else None
+    fp64 = None
+    if fx is not None:
+        fp64 = {"reference": "float64 Eq. 3 top-100 of all 256 queries "
+                             "(tests/golden/c3_fp64_top100.npz, written by the oracle)",
+                "per_storage": {}}
+
+        def fp64_entry(name, run_out):
+            S1 = L.gift_score_exhaustive(views[name], Q).cpu().numpy()
+            bi, bs = first_pass_topk(S1, k)
+            return {"after_rescore": fp64_compare(run_out["ids"], run_out["scores"], fx, k),
+                    "first_pass_only": fp64_compare(bi, bs, fx, k)}
+        fp64["per_storage"][args.dtype] = fp64_entry(args.dtype, main_run)
+        if ref_run is not None and ref_run is not main_run:
+            fp64["per_storage"]["f32"] = fp64_entry("f32", ref_run)
+        if alt_run is not None:
+            fp64["per_storage"][alt] = fp64_entry(alt, alt_run)
+
     # roofline of the dominant kernel: algorithmic flops of one launch
     flops = 2.0 * w.n_queries * w.n_views * (w.n_shapes * w.n_views) * w.dim
     score_ms = main_run["kern"]["score_tiles"]["avg_ms"]
@@ -229,13 +289,22 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(main_run["lat"], 50)) * 1e3, 3),
                        "p99": round(float(np.percentile(main_run["lat"], 99)) * 1e3, 3),
                        "note": "per-step batch latency; every query of a step completes together"},
-        "recall": {"meets_bar": bool(r100[0] >= 0.99),
-                   "bar": "recall@100 averaged over the step's queries >= 0.99",
-                   "at100_mean": r100[0], "at100_min": r100[1], "at10_mean": r10[0],
-                   "at10_min": r10[1], "max_score_err": err,
-                   "reference": "float32 path with certified exact ranking"
-                                + (" (all queries certified complete)" if exact_ok else " (NOT all certified)"),
-                   "complete_flags": int(main_run["flags"].sum())},
+        "recall": ({"meets_bar": bool(fp64["per_storage"][args.dtype]["after_rescore"]
+                                      ["at100_mean"] >= 0.99),
+                    "bar": "recall@100 against float64 exhaustive, averaged over the 256 "
+                           "queries, >= 0.99",
+                    **fp64["per_storage"][args.dtype]["after_rescore"],
+                    "reference": fp64["reference"],
+                    "complete_flags": int(main_run["flags"].sum())} if fp64 is not None else
+                   {"meets_bar": bool(r100[0] >= 0.99),
+                    "bar": "recall@100 averaged over the step's queries >= 0.99",
+                    "at100_mean": r100[0], "at100_min": r100[1], "at10_mean": r10[0],
+                    "at10_min": r10[1], "max_score_err": err,
+                    "reference": "float32 path with certified exact ranking"
+                                 + (" (all queries certified complete)" if exact_ok
+                                    else " (NOT all certified)"),
+                    "complete_flags": int(main_run["flags"].sum())}),
+        "recall_fp64": fp64,
         "kernels_ms": main_run["kern"],
         "autotune": tuning,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
@@ -255,6 +324,8 @@ def main():
             rr = recall(mr["ids"], exact_ids, min(100, k))
             result[f"{name}_path"] = {"queries_per_s": round(B * args.mx_steps / mr["total"], 2),
                                       "recall_at100_mean": rr[0], "recall_at100_min": rr[1]}
+            if fp64 is not None:
+                fp64["per_storage"][name] = fp64_entry(name, mr)
     if alt_run is not None:
         ra = recall(alt_run["ids"], exact_ids, min(100, k))
         result[f"{alt}_path"] = {"queries_per_s": round(B * args.alt_steps / alt_run["total"], 2),

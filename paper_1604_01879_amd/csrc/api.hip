@@ -164,7 +164,7 @@ static ExhaustiveWs carve_exhaustive(void* base, const gift_views* db,
     w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, q->n_queries, r));
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
-    w.rs = take_rescore(c, q->n_queries, r, q->total_views, db->dim, db->n_shapes, true);
+    w.rs = take_rescore(c, q->n_queries, r, q->total_views);
   }
   w.bytes = c.bytes();
   return w;
@@ -280,7 +280,7 @@ static FifWs carve_fif(void* base, const gift_views* db, const gift_fif* f,
     w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, q->n_queries, r));
     w.s_hi = c.take<float>((size_t)q->n_queries * r);
     w.s_lo = c.take<float>((size_t)q->n_queries * r);
-    w.rs = take_rescore(c, q->n_queries, r, q->total_views, db->dim, db->n_shapes, true);
+    w.rs = take_rescore(c, q->n_queries, r, q->total_views);
   }
   w.bytes = c.bytes();
   return w;
@@ -482,11 +482,10 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
-  s = launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
-                     q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), nullptr,
-                     nullptr, 0, nullptr, w.rs, true, db->n_shapes, w.s_hi, w.s_lo, st);
+  launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
+                 q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), nullptr,
+                 nullptr, 0, nullptr, w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
-  if (s != GIFT_OK) return s;
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
@@ -712,12 +711,10 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_RESCORE, st);
-  s = launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
-                     q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim),
-                     w.qwords, fif->view_words, fif->ma, nullptr, w.rs, true, db->n_shapes,
-                     w.s_hi, w.s_lo, st);
+  launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
+                 q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), w.qwords,
+                 fif->view_words, fif->ma, nullptr, w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
-  if (s != GIFT_OK) return s;
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,

@@ -42,71 +42,28 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r, const in
 // re-evaluation of every view pair that the bound cannot exclude as the
 // maximum, and their float-float score; the others score -inf.
 // With qwords != nullptr only pairs whose words match take part (Eq. 4).
-// Grouping of the (query, candidate) pairs by candidate shape for the
-// shape-major first phase: units (a pair and one 64-view chunk of its
-// query) listed shape by shape, shapes ranked by their first pair.
-constexpr int RSS_UNITS = 8;      // units per shape-major block, one wave each
-constexpr int RS_CTL_WORDS = 16;
-enum { RS_CTL_DISTINCT = 0, RS_CTL_SHAPE_MAJOR = 1, RS_CTL_ITEMS = 2, RS_CTL_XCD = 8 };
-struct RsSort {
-  int32_t* first_pair;  // [n_shapes] lowest pair index with this candidate
-  int32_t* shape_rank;  // [n_shapes] rank of a candidate shape
-  int32_t* rank_shape;  // [queries * r]
-  int32_t* ucnt;        // [queries * r] units per rank
-  int32_t* ufill;       // [queries * r]
-  int32_t* unit_off;    // [queries * r + 1]
-  int32_t* item_off;    // [queries * r + 1]
-  int32_t* item_rank;   // [max units]
-  int64_t* units;       // [max units] (pair << 32) | chunk; NULL: query-major only
-  int32_t* ctl;         // [RS_CTL_WORDS] distinct shapes, path, items, XCD counters
-};
 struct RescoreScratch {
   unsigned long long* mask;  // [r][ld] view masks (candidate slot, query view)
   float* s1;                 // [r][ld] per-chunk sums of approximate maxima
   uint8_t* mark;             // [queries][r] candidates that can reach the top k
-  uint8_t* qsplit;           // [ld][dim * 4] query rows split into BF16 parts
-  RsSort sort;
 };
 
-// Rescore scratch from a workspace carver.  ld = rows of query views the
-// masks are indexed by (total or maximum views).  The shape-major phase is
-// set up for batches of at least 8 query slots; own_qsplit: the query rows
-// are split here (else the caller provides split rows in qsplit).
-inline RescoreScratch take_rescore(Carver& c, int n_queries, int r, int64_t ld, int dim,
-                                   int64_t n_shapes, bool own_qsplit) {
+// Rescore scratch from a workspace carver; ld = rows of query views the
+// masks are indexed by (total or maximum views).
+inline RescoreScratch take_rescore(Carver& c, int n_queries, int r, int64_t ld) {
   RescoreScratch s{};
   s.mask = c.take<unsigned long long>((size_t)r * ld);
   s.s1 = c.take<float>((size_t)r * ld);
   s.mark = c.take<uint8_t>((size_t)n_queries * r);
-  if (n_queries >= 8) {
-    const size_t slots = (size_t)n_queries * r;
-    const size_t max_units = (size_t)r * ((size_t)(ld + 63) / 64 + (size_t)n_queries);
-    if (own_qsplit) s.qsplit = c.take<uint8_t>((size_t)ld * dim * 4);
-    s.sort.first_pair = c.take<int32_t>((size_t)n_shapes);
-    s.sort.shape_rank = c.take<int32_t>((size_t)n_shapes);
-    s.sort.rank_shape = c.take<int32_t>(slots);
-    s.sort.ucnt = c.take<int32_t>(slots);
-    s.sort.ufill = c.take<int32_t>(slots);
-    s.sort.unit_off = c.take<int32_t>(slots + 1);
-    s.sort.item_off = c.take<int32_t>(slots + 1);
-    s.sort.item_rank = c.take<int32_t>(max_units);
-    s.sort.units = c.take<int64_t>(max_units);
-    s.sort.ctl = c.take<int32_t>(RS_CTL_WORDS);
-  }
   return s;
 }
 
-// sc.sort.units == nullptr: the query-major first phase only; else the
-// shape grouping runs and a device-side test picks the phase-1 kernel
-// (shape-major when the batch's pairs number at least twice its distinct
-// candidate shapes).  split_queries: split the query rows into sc.qsplit
-// first (else sc.qsplit already holds them).
-gift_status launch_rescore(const float* master, int n_views, int dim,
-                           const float* qviews, const int32_t* qoff, int n_queries,
-                           int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
-                           const int32_t* qwords, const int32_t* view_words, int ma,
-                           const int32_t* active, RescoreScratch sc, bool split_queries,
-                           int64_t n_shapes, float* s_hi, float* s_lo, hipStream_t st);
+void launch_rescore(const float* master, int n_views, int dim,
+                    const float* qviews, const int32_t* qoff, int n_queries,
+                    int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
+                    const int32_t* qwords, const int32_t* view_words, int ma,
+                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
+                    hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
 // id asc) and writes the top k; sets flags bit 0 when provably complete:

@@ -78,9 +78,7 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.sel_tmp = c.take<uint8_t>(select_top_ws(db->n_shapes, Bmax, r));
   w.s_hi = c.take<float>((size_t)Bmax * r);
   w.s_lo = c.take<float>((size_t)Bmax * r);
-  // the shape-major rescore reads the query rows the Q phase split
-  w.rs = take_rescore(c, Bmax, r, Vmax, db->dim, db->n_shapes, false);
-  w.rs.qsplit = w.qsplit;
+  w.rs = take_rescore(c, Bmax, r, Vmax);
   w.bytes = c.bytes();
   return w;
 }
@@ -118,11 +116,9 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   launch_select_top(p->ws.S, p->db.n_shapes, p->Bmax, p->r, active, p->ws.cand, p->ws.cand_s,
                     p->ws.sel_tmp, st);
   GIFT_LAUNCHED();
-  s = launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax,
-                     p->Vmax, p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim),
-                     p->ws.qwords, p->view_words, p->ma, active, p->ws.rs, false,
-                     p->db.n_shapes, p->ws.s_hi, p->ws.s_lo, st);
-  if (s != GIFT_OK) return s;
+  launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->Vmax,
+                 p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim), p->ws.qwords,
+                 p->view_words, p->ma, active, p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
                     p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim), p->qoff,

@@ -1,7 +1,5 @@
 // Ranking of Eq. 3 / Eq. 4 scores: block-level top-r selection, the exact
 // rescore of the candidates and the final (score desc, id asc) order.
-#include <mutex>
-
 #include "kernels.h"
 #include "mfma_tile.h"
 #include "quant.h"
@@ -287,10 +285,9 @@ void launch_select_top(const float* S, int64_t n, int n_queries, int r, const in
 }
 
 // ------------------------------------------------------------------ rescore
-// Work items in XCD-contiguous order: the chip runs blocks round-robin over
-// its 8 XCDs, so block `blk` runs on XCD blk % 8; giving XCD x the
-// contiguous item range [x c, x c + c), c = ceil(n / 8), lets the blocks
-// that share an XCD's L2 share their inputs.
+// Pairs handled by block `blk` when the chip runs blocks round-robin over its
+// 8 XCDs: XCD x takes the contiguous pair range [x c, x c + c), c = ceil(n / 8),
+// so the blocks running together on one XCD (and its L2) share a query.
 __device__ __forceinline__ int64_t xcd_contiguous(int64_t blk, int64_t n) {
   const int64_t c = (n + 7) / 8;
   return (blk & 7) * c + (blk >> 3);
@@ -364,18 +361,16 @@ __device__ __forceinline__ unsigned long long allowed_views(const int32_t* vw, i
 // With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
 // word of q_i is one of the `ma` words of p_j; a query view with no such
 // pair gets an empty mask and a maximum of 0.
-// Runs only when *use_shape_major is 0 (or the pointer is null).
 __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     int n_queries, const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
-    const int32_t* __restrict__ active, const int32_t* __restrict__ use_shape_major,
-    unsigned long long* __restrict__ mask, float* __restrict__ s1, int64_t ld) {
+    const int32_t* __restrict__ active, unsigned long long* __restrict__ mask,
+    float* __restrict__ s1, int64_t ld) {
   __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
   __shared__ int32_t vw[RS_CANDS][64 * 8];
 
-  if (use_shape_major != nullptr && *use_shape_major) return;
   const int groups = (r + RS_CANDS - 1) / RS_CANDS;
   const int64_t n_items = (int64_t)(active != nullptr ? *active : n_queries) * groups;
   const int64_t item = xcd_contiguous(blockIdx.x, n_items);
@@ -507,266 +502,6 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
       s1_chunk += v;
     }
     if (mine && lane == 0) s1[(int64_t)cslot * ld + q0 + it * 64] = s1_chunk;
-  }
-}
-
-// Phase 1, shape-major.  When many queries share candidate shapes (a large
-// batch), the (query, candidate) pairs are grouped by candidate shape, so
-// each shape's 64 float32 rows are read once per batch instead of once per
-// pair.  A unit is one 64-view chunk `it` of the query of pair p; units are
-// counted per shape, the shapes ranked by their first pair in (query,
-// candidate) order (so shapes first met by nearby queries are neighbours),
-// and the units listed rank by rank.  An item is up to 8 units of one
-// shape.
-//   rs_prep_kernel    first_pair[s] = INT_MAX, unit counters cleared
-//   rs_first_kernel   first_pair[s] = lowest pair with candidate s
-//   rs_rank_kernel    shape_rank / rank_shape in first-pair order; the
-//                     choice between the query-major and the shape-major
-//                     kernel (shape-major when pairs >= 2 x distinct shapes)
-//   rs_count_kernel   units per rank
-//   rs_offsets_kernel unit and item offsets per rank, item -> rank
-//   rs_scatter_kernel units listed rank by rank (any order within a rank)
-// Every kernel reads the batch size from *active (plans) or n_queries.
-__global__ __launch_bounds__(256) void rs_prep_kernel(RsSort s, int64_t n_shapes, int64_t n_slots) {
-  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x, step = (int64_t)gridDim.x * 256;
-  for (int64_t i = i0; i < n_shapes; i += step) s.first_pair[i] = 0x7fffffff;
-  for (int64_t i = i0; i < n_slots; i += step) { s.ucnt[i] = 0; s.ufill[i] = 0; }
-  if (i0 < RS_CTL_WORDS) s.ctl[i0] = 0;
-}
-
-__device__ __forceinline__ int64_t rs_pairs(const int32_t* active, int n_queries, int r) {
-  return (int64_t)(active != nullptr ? *active : n_queries) * r;
-}
-
-__global__ __launch_bounds__(256) void rs_first_kernel(RsSort s, const int32_t* __restrict__ cand,
-                                                       int r, const int32_t* active,
-                                                       int n_queries) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p < rs_pairs(active, n_queries, r)) atomicMin(&s.first_pair[cand[p]], (int32_t)p);
-}
-
-// Exclusive prefix over the 1024 threads of a block of per-thread counts;
-// returns the block total through `total`.
-__device__ inline int64_t block_excl_scan_1024(int64_t v, int64_t* wsum, int64_t& total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t t = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += t;
-  }
-  if (lane == 63) wsum[wave] = inc;
-  __syncthreads();
-  int64_t before = 0;
-  total = 0;
-  for (int w = 0; w < 16; ++w) {
-    if (w < wave) before += wsum[w];
-    total += wsum[w];
-  }
-  __syncthreads();
-  return before + inc - v;
-}
-
-__global__ __launch_bounds__(1024) void rs_rank_kernel(RsSort s, const int32_t* __restrict__ cand,
-                                                       int r, const int32_t* active,
-                                                       int n_queries) {
-  __shared__ int64_t wsum[16];
-  const int64_t n_pairs = rs_pairs(active, n_queries, r);
-  const int64_t per = (n_pairs + 1023) / 1024;
-  const int64_t p0 = threadIdx.x * per, p1 = p0 + per < n_pairs ? p0 + per : n_pairs;
-  int64_t cnt = 0;
-  for (int64_t p = p0; p < p1; ++p) cnt += s.first_pair[cand[p]] == (int32_t)p;
-  int64_t total;
-  int64_t run = block_excl_scan_1024(cnt, wsum, total);
-  for (int64_t p = p0; p < p1; ++p) {
-    const int32_t sh = cand[p];
-    if (s.first_pair[sh] == (int32_t)p) {
-      s.shape_rank[sh] = (int32_t)run;
-      s.rank_shape[run] = sh;
-      ++run;
-    }
-  }
-  if (threadIdx.x == 0) {
-    s.ctl[RS_CTL_DISTINCT] = (int32_t)total;
-    s.ctl[RS_CTL_SHAPE_MAJOR] = n_pairs > 0 && n_pairs >= 2 * total ? 1 : 0;
-  }
-}
-
-__global__ __launch_bounds__(256) void rs_count_kernel(RsSort s, const int32_t* __restrict__ cand,
-                                                       int r, const int32_t* __restrict__ qoff,
-                                                       const int32_t* active, int n_queries) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= rs_pairs(active, n_queries, r) || !s.ctl[RS_CTL_SHAPE_MAJOR]) return;
-  const int b = (int)(p / r);
-  const int chunks = (qoff[b + 1] - qoff[b] + 63) / 64;
-  if (chunks > 0) atomicAdd(&s.ucnt[s.shape_rank[cand[p]]], chunks);
-}
-
-__global__ __launch_bounds__(1024) void rs_offsets_kernel(RsSort s) {
-  __shared__ int64_t wsum[16];
-  if (!s.ctl[RS_CTL_SHAPE_MAJOR]) return;
-  const int64_t n = s.ctl[RS_CTL_DISTINCT];
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t k0 = threadIdx.x * per, k1 = k0 + per < n ? k0 + per : n;
-  int64_t cu = 0, ci = 0;
-  for (int64_t k = k0; k < k1; ++k) {
-    cu += s.ucnt[k];
-    ci += (s.ucnt[k] + RSS_UNITS - 1) / RSS_UNITS;
-  }
-  int64_t tu, ti;
-  int64_t ru = block_excl_scan_1024(cu, wsum, tu);
-  int64_t ri = block_excl_scan_1024(ci, wsum, ti);
-  for (int64_t k = k0; k < k1; ++k) {
-    const int c = s.ucnt[k], items = (c + RSS_UNITS - 1) / RSS_UNITS;
-    s.unit_off[k] = (int32_t)ru;
-    s.item_off[k] = (int32_t)ri;
-    for (int t = 0; t < items; ++t) s.item_rank[ri + t] = (int32_t)k;
-    ru += c;
-    ri += items;
-  }
-  if (threadIdx.x == 0) {
-    s.unit_off[n] = (int32_t)tu;
-    s.item_off[n] = (int32_t)ti;
-    s.ctl[RS_CTL_ITEMS] = (int32_t)ti;
-  }
-}
-
-__global__ __launch_bounds__(256) void rs_scatter_kernel(RsSort s, const int32_t* __restrict__ cand,
-                                                         int r, const int32_t* __restrict__ qoff,
-                                                         const int32_t* active, int n_queries) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= rs_pairs(active, n_queries, r) || !s.ctl[RS_CTL_SHAPE_MAJOR]) return;
-  const int b = (int)(p / r);
-  const int chunks = (qoff[b + 1] - qoff[b] + 63) / 64;
-  const int rk = s.shape_rank[cand[p]];
-  for (int it = 0; it < chunks; ++it)
-    s.units[s.unit_off[rk] + atomicAdd(&s.ufill[rk], 1)] = ((int64_t)p << 32) | (uint32_t)it;
-}
-
-// The shape-major phase-1 kernel (rescore_mask_shape_kernel): persistent
-// blocks of 8 waves, each XCD taking the items of its contiguous range in
-// order from its own counter.  Per item, the shape's 64 float32 rows are
-// read 128 bytes per row at a time, split into BF16 parts in registers and
-// stored to LDS once for the block; wave w multiplies them with unit w's 64
-// query rows, split once per call and loaded straight into LDS
-// (global_load_lds_dwordx4), on the split-row loop's MFMA step
-// (dma128_subtile_mfma): the products, order and bound of the query-major
-// kernel.  Two LDS stages: sub-tile kt + 1 loads while kt is multiplied.
-// Writes what the query-major kernel writes, for the same units.
-constexpr int RSS_THREADS = 64 * RSS_UNITS;
-constexpr int RSS_A_STAGE = 64 * DMA2_KSUB;              // the shape's rows
-constexpr int RSS_B_STAGE = 64 * RSS_UNITS * DMA2_KSUB;  // the units' query rows
-constexpr size_t RSS_LDS = 2 * (size_t)(RSS_A_STAGE + RSS_B_STAGE);
-
-__global__ __launch_bounds__(RSS_THREADS, 1) void rescore_mask_shape_kernel(
-    const float* __restrict__ master, int n_views, int dim, const uint8_t* __restrict__ qsplit,
-    const int32_t* __restrict__ qoff, const int32_t* __restrict__ cand, int r, float dot_err,
-    const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma, RsSort s,
-    unsigned long long* __restrict__ mask, float* __restrict__ s1, int64_t ld) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  __shared__ int32_t vw[64 * 8];
-  __shared__ int sh_item;
-  if (!s.ctl[RS_CTL_SHAPE_MAJOR]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
-  const int n_items = s.ctl[RS_CTL_ITEMS];
-  const int xcd = blockIdx.x & 7;
-  const int per_xcd = (n_items + 7) / 8;
-  const int lo_item = xcd * per_xcd, hi_item = min(n_items, lo_item + per_xcd);
-  const int row_bytes = dim * 4;  // float32 rows and split rows alike
-  const int n_kt = row_bytes / DMA2_KSUB;
-  lds_u8* l3 = (lds_u8*)lds;
-  for (;;) {
-    if (tid == 0) sh_item = lo_item + atomicAdd(&s.ctl[RS_CTL_XCD + xcd], 1);
-    __syncthreads();
-    const int item = sh_item;
-    if (item >= hi_item) break;
-    const int rk = s.item_rank[item];
-    const int64_t shape = s.rank_shape[rk];
-    const int u0 = s.unit_off[rk] + RSS_UNITS * (item - s.item_off[rk]);
-    const int nu = min(RSS_UNITS, s.unit_off[rk + 1] - u0);
-    const bool mine = wave < nu;
-    // this wave's unit: pair p = (query b, candidate slot c), chunk it
-    int b = 0, c = 0, v0 = 0, mi = 0;
-    if (mine) {
-      const int64_t code = s.units[u0 + wave];
-      const int64_t p = code >> 32;
-      const int it = (int)(code & 0xffffffff);
-      b = (int)(p / r);
-      c = (int)(p - (int64_t)b * r);
-      const int q0 = qoff[b];
-      v0 = q0 + 64 * it;
-      mi = min(64, qoff[b + 1] - v0);
-    }
-    if (qwords != nullptr)
-      for (int x = tid; x < n_views * ma; x += RSS_THREADS) vw[x] = view_words[shape * n_views * ma + x];
-    // A side: thread t stages bytes [16 (t & 7), +16) of row t >> 3 of each
-    // 128-byte sub-tile (zeros for rows past n_views)
-    const int ra = tid >> 3, pc = tid & 7;
-    const bool a_ok = ra < n_views;
-    const float* arow_g = master + (shape * n_views + (a_ok ? ra : 0)) * (int64_t)dim + pc * 4;
-    const int sw_a = dma2_swizzle(ra);
-    const int hi_off = ra * DMA2_KSUB + (((pc >> 1) ^ sw_a) * 16) + (pc & 1) * 8;
-    const int lo_off = ra * DMA2_KSUB + (((4 + (pc >> 1)) ^ sw_a) * 16) + (pc & 1) * 8;
-    // B side: lane l of wave w loads chunk slot l & 7 of rows 8 i + l / 8 of
-    // unit w (pad rows re-read the unit's first row)
-    uint32_t goff[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int row = 8 * i + (lane >> 3);
-      goff[i] = (uint32_t)((row < mi ? row : 0) * row_bytes) +
-                (uint32_t)(((lane & 7) ^ dma2_swizzle(row)) * 16);
-    }
-    const uint64_t gq = (uint64_t)(uintptr_t)(qsplit + (int64_t)v0 * row_bytes);
-    const uint32_t b_lds = (uint32_t)(uintptr_t)(l3 + 2 * RSS_A_STAGE + wave * 64 * DMA2_KSUB);
-    auto issue_b = [&](int kt) {
-      dma128_issue<8>(b_lds + (uint32_t)((kt & 1) * RSS_B_STAGE), gq + (uint64_t)(kt * DMA2_KSUB),
-                      goff);
-    };
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-    uint4 pre = a_ok ? *reinterpret_cast<const uint4*>(arow_g) : make_uint4(0, 0, 0, 0);
-    if (mine) issue_b(0);
-    for (int kt = 0; kt < n_kt; ++kt) {
-      uint8_t* sta = lds + (kt & 1) * RSS_A_STAGE;
-      uint2 hi, lo;
-      split_bf16x4(pre, hi, lo);
-      *reinterpret_cast<uint2*>(sta + hi_off) = hi;
-      *reinterpret_cast<uint2*>(sta + lo_off) = lo;
-      // this wave's query rows of sub-tile kt have landed; after the
-      // barrier every wave's have, and every wave is past sub-tile kt - 1
-      wait_vm_barrier<0>();
-      if (kt + 1 < n_kt) {
-        pre = a_ok ? *reinterpret_cast<const uint4*>(arow_g + (kt + 1) * 32) : make_uint4(0, 0, 0, 0);
-        if (mine) issue_b(kt + 1);
-      }
-      if (mine)
-        dma128_subtile_mfma<DMA_SPLIT_BF16, 2, 2, RSS_UNITS>(
-            sta, lds + 2 * RSS_A_STAGE + (kt & 1) * RSS_B_STAGE, acc);
-    }
-    wait_vm_barrier<0>();  // LDS is reused by the next item
-    if (mine) {
-      float s1_chunk = 0.f;
-#pragma unroll
-      for (int cj = 0; cj < 2; ++cj) {
-        const int i = cj * 32 + l32;
-        const bool live = i < mi;
-        const unsigned long long allowed = allowed_views(
-            vw, n_views, ma, qwords != nullptr, live && qwords ? qwords[v0 + i] : -1);
-        unsigned long long bits;
-        const float mx = view_max_mask(acc, cj, live || qwords == nullptr ? allowed : 0ull, dot_err,
-                                       bits);
-        if (half == 0 && live) mask[(int64_t)c * ld + v0 + i] = bits;
-        float v = (half == 0 && live && mx != -INFINITY) ? mx : 0.f;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        s1_chunk += v;
-      }
-      if (lane == 0) s1[(int64_t)c * ld + v0] = s1_chunk;
-    }
   }
 }
 
@@ -902,66 +637,24 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
   }
 }
 
-static int device_cus() {
-  static std::mutex mu;
-  static int cached[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  std::lock_guard<std::mutex> lock(mu);
-  if (cached[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 8)
-      n = 256;
-    cached[dev] = n;
-  }
-  return cached[dev];
-}
-
-gift_status launch_rescore(const float* master, int n_views, int dim,
-                           const float* qviews, const int32_t* qoff, int n_queries,
-                           int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
-                           const int32_t* qwords, const int32_t* view_words, int ma,
-                           const int32_t* active, RescoreScratch sc, bool split_queries,
-                           int64_t n_shapes, float* s_hi, float* s_lo, hipStream_t st) {
+void launch_rescore(const float* master, int n_views, int dim,
+                    const float* qviews, const int32_t* qoff, int n_queries,
+                    int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
+                    const int32_t* qwords, const int32_t* view_words, int ma,
+                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
+                    hipStream_t st) {
   const int64_t items = (int64_t)n_queries * ((r + RS_CANDS - 1) / RS_CANDS);
-  if (items <= 0) return GIFT_OK;
-  const int64_t slots = (int64_t)n_queries * r;
-  const bool shape_major = sc.sort.units != nullptr;  // batches large enough to share shapes
-  if (shape_major) {
-    if (split_queries) launch_split_rows(qviews, ld, dim, sc.qsplit, st);
-    const int64_t big = slots > n_shapes ? slots : n_shapes;
-    const unsigned g_prep = (unsigned)((big + 255) / 256 < 2048 ? (big + 255) / 256 : 2048);
-    const unsigned g_pairs = (unsigned)((slots + 255) / 256);
-    hipLaunchKernelGGL(rs_prep_kernel, dim3(g_prep), dim3(256), 0, st, sc.sort, n_shapes, slots);
-    hipLaunchKernelGGL(rs_first_kernel, dim3(g_pairs), dim3(256), 0, st, sc.sort, cand, r, active,
-                       n_queries);
-    hipLaunchKernelGGL(rs_rank_kernel, dim3(1), dim3(1024), 0, st, sc.sort, cand, r, active,
-                       n_queries);
-    hipLaunchKernelGGL(rs_count_kernel, dim3(g_pairs), dim3(256), 0, st, sc.sort, cand, r, qoff,
-                       active, n_queries);
-    hipLaunchKernelGGL(rs_offsets_kernel, dim3(1), dim3(1024), 0, st, sc.sort);
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3(g_pairs), dim3(256), 0, st, sc.sort, cand, r, qoff,
-                       active, n_queries);
-    const gift_status s = ensure_dynamic_lds(
-        reinterpret_cast<const void*>(rescore_mask_shape_kernel), RSS_LDS);
-    if (s != GIFT_OK) return s;
-    const int grid = device_cus() / 8 * 8;
-    hipLaunchKernelGGL(rescore_mask_shape_kernel, dim3(grid), dim3(RSS_THREADS), RSS_LDS, st,
-                       master, n_views, dim, sc.qsplit, qoff, cand, r, dot_err, qwords,
-                       view_words, ma, sc.sort, sc.mask, sc.s1, ld);
-  }
+  if (items <= 0) return;
   // grids cover every slot of the XCD-contiguous order
   hipLaunchKernelGGL(rescore_mask_kernel, dim3((unsigned)((items + 7) / 8 * 8)), dim3(RS_THREADS),
                      0, st, master, n_views, dim, qviews, qoff, n_queries, cand, r,
-                     dot_err, qwords, view_words, ma, active,
-                     shape_major ? sc.sort.ctl + RS_CTL_SHAPE_MAJOR : nullptr, sc.mask, sc.s1, ld);
+                     dot_err, qwords, view_words, ma, active, sc.mask, sc.s1, ld);
   hipLaunchKernelGGL(rescore_mark_kernel, dim3((unsigned)n_queries), dim3(256), 0, st, sc.s1, ld,
                      qoff, r, top_k, dot_err, active, sc.mark);
   const int64_t pairs = (int64_t)n_queries * r;
   hipLaunchKernelGGL(rescore_exact_kernel, dim3((unsigned)((pairs + 7) / 8 * 8)), dim3(256), 0, st,
                      master, n_views, dim, qviews, qoff, n_queries, cand, r, sc.mask, ld,
                      sc.mark, active, s_hi, s_lo);
-  return GIFT_OK;
 }
 
 // ------------------------------------------------------------------ final

@@ -295,15 +295,12 @@ def test_query_exhaustive_ranked_ids(L, dtype_name, case):
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
-def test_shape_major_rescore_equals_single_queries(L, dtype_name):
-    """A batch of 8 or more queries whose candidates repeat (here 16 x 60
-    pairs over 300 shapes) takes the shape-major first rescore phase, which
-    reads each candidate shape once for all its pairs; a query alone takes
-    the query-major one.  Both form the same products in the same order, so
-    each query's ids, scores and flag are identical alone and in the batch,
-    and the ranking is the oracle's.  Queries of 1..150 views (64-view
-    chunks), shapes of 64 views."""
-    _say(f"shape-major rescore {dtype_name}")
+def test_shared_candidates_batch_equals_single_queries(L, dtype_name):
+    """A 16-query batch whose candidates repeat across queries (16 x 60 pairs
+    over 300 shapes) against each query alone: ids, scores and flag are
+    identical (every kernel works per query, in a fixed order), and the
+    ranking is the oracle's.  Queries of 1..150 views (64-view chunks)."""
+    _say(f"shared-candidate batch {dtype_name}")
     w, db, q, qoff = _data(N=300, dim=128, B=16, m=(1, 150), seed=31)
     k, R = 10, 60
     dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]

@@ -312,12 +312,11 @@ def test_query_fif_shared_candidates(L, ma):
 
 
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16"])
-def test_query_fif_shape_major_rescore_equals_single_queries(L, dtype_name):
-    """Eq. 4 rescore of a 16-query batch whose candidates repeat (the
-    shape-major first phase, word-matched pairs only) against each query
-    alone (the query-major phase): identical ids, scores and flags, and the
-    oracle's ranking.  Queries of 1..150 views."""
-    _say(f"fif shape-major rescore {dtype_name}")
+def test_query_fif_shared_candidates_batch_equals_single_queries(L, dtype_name):
+    """Eq. 4 ranking of a 16-query batch whose candidates repeat against each
+    query alone: identical ids, scores and flags, and the oracle's ranking.
+    Queries of 1..150 views."""
+    _say(f"fif shared-candidate batch {dtype_name}")
     dt = {"f32": L.F32, "bf16": L.BF16}[dtype_name]
     w = _wl(n_shapes=240, dim=128, m_lo=1, m_hi=150, n_queries=16)
     db, q, qoff, cb, V, F, Q, (off, es, ev) = _fif_case(L, w, 12, 2, dt)
