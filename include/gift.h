@@ -314,6 +314,19 @@ gift_status gift_fuse_activations(int32_t n_rows, const int32_t* ids1,
                                   float* out_scores, int32_t k_out,
                                   void* stream);
 
+/* Self membership of queries outside the database through Eq. 11 and      */
+/* Eq. 9.  Such a query joins its own neighbour set under each measure     */
+/* with membership self1[b] / self2[b] (1 for unit-norm views, the Eq. 3   */
+/* self score); gift_augment_neighbours averages its row over n1[b] / n2[b] */
+/* members (its n_members output), so the own membership becomes self / n; */
+/* out[b] is the generalised mean with exponent alpha of the two, as       */
+/* gift_fuse_activations forms it for every other coordinate.  It is the   */
+/* q_self of gift_rerank_sif for the fused activation.  All arrays device, */
+/* [n_rows]; n <= 0 counts as membership 0.  alpha > 0.                    */
+gift_status gift_fuse_self(int32_t n_rows, const float* self1, const int32_t* n1,
+                           const float* self2, const int32_t* n2, float alpha, float* out,
+                           void* stream);
+
 /* Re-ranking by Eq. 8 evaluated through the S-IF (Eq. 13 and 14):        */
 /*   S'(q, p) = sum_i min(F_q[i], F_p[i]) / (||F_q||_1 + ||F_p||_1 - num),  */
 /* the numerator taken over the coordinates where both are non-zero.  The  */

@@ -86,6 +86,7 @@ _sig = {
     "gift_augment_neighbours": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P,
                                             C.c_int32, _P, _P, C.c_int32, _P, _P, C.c_int32, _P,
                                             _P]),
+    "gift_fuse_self": (C.c_int32, [C.c_int32, _P, _P, _P, _P, C.c_float, _P, _P]),
     "gift_fuse_activations": (C.c_int32, [C.c_int32, _P, _P, C.c_int32, _P, _P, C.c_int32,
                                           C.c_float, _P, _P, C.c_int32, _P]),
     "gift_rerank_sif": (C.c_int32, [C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P,
@@ -530,6 +531,15 @@ def gift_augment_neighbours(nbr_ids, nbr_scores, members, own_ids=None, own_scor
                                         _ptr(members), k2, _ptr(own_ids), _ptr(own_scores), k_own,
                                         _ptr(oi), _ptr(os_), k_out, _ptr(nm), _stream(stream)))
     return oi, os_, nm
+
+
+def gift_fuse_self(self1, n1, self2, n2, alpha=0.5, stream=None):
+    """Fused self membership [n] of outside queries (Eq. 11 then Eq. 9)."""
+    n = int(self1.shape[0])
+    out = torch.empty(n, dtype=torch.float32, device=self1.device)
+    _check(_lib.gift_fuse_self(n, _ptr(self1), _ptr(n1), _ptr(self2), _ptr(n2), float(alpha),
+                               _ptr(out), _stream(stream)))
+    return out
 
 
 def gift_fuse_activations(ids1, sc1, ids2, sc2, alpha=0.5, k_out=None, stream=None):

@@ -888,6 +888,17 @@ gift_status gift_fuse_activations(int32_t n_rows, const int32_t* ids1, const flo
   return GIFT_OK;
 }
 
+gift_status gift_fuse_self(int32_t n_rows, const float* self1, const int32_t* n1,
+                           const float* self2, const int32_t* n2, float alpha, float* out,
+                           void* stream) {
+  GIFT_CHECK(n_rows >= 0, GIFT_EINVAL, "n_rows < 0");
+  GIFT_CHECK(alpha > 0.f, GIFT_EINVAL, "alpha must be > 0");
+  GIFT_CHECK(n_rows == 0 || (self1 && n1 && self2 && n2 && out), GIFT_EINVAL, "null pointer");
+  launch_fuse_self(self1, n1, self2, n2, alpha, n_rows, out, (hipStream_t)stream);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
+}
+
 gift_status gift_rerank_sif(int64_t n_shapes, const float* l1, const int64_t* post_off,
                             const int32_t* post_id, const float* post_val, int32_t n_queries,
                             int32_t k1, const int32_t* q_ids, const float* q_scores,

@@ -180,6 +180,8 @@ void launch_augment(const int32_t* t_ids, const float* t_val, int64_t N, int k1,
                     const int32_t* members, int k2, const int32_t* own_ids, const float* own_val,
                     int k_own, int n_rows, int32_t* out_ids, float* out_val, int k_out,
                     int32_t* n_members, hipStream_t st);
+void launch_fuse_self(const float* self1, const int32_t* n1, const float* self2,
+                      const int32_t* n2, float alpha, int n_rows, float* out, hipStream_t st);
 void launch_fuse(const int32_t* i1, const float* v1, int k_a, const int32_t* i2, const float* v2,
                  int k_b, float alpha, int n_rows, int32_t* out_ids, float* out_val, int k_out,
                  hipStream_t st);

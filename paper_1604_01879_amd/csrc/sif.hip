@@ -574,6 +574,34 @@ __global__ __launch_bounds__(256) void fuse_kernel(
   }
 }
 
+// Self membership of outside queries through Eq. 11 then Eq. 9: under each
+// measure the query's own membership self / n after averaging over its n
+// members, then the generalised mean of the two with the fuse kernel's
+// arithmetic.
+__global__ __launch_bounds__(256) void fuse_self_kernel(const float* __restrict__ self1,
+                                                        const int32_t* __restrict__ n1,
+                                                        const float* __restrict__ self2,
+                                                        const int32_t* __restrict__ n2,
+                                                        float alpha, int n_rows,
+                                                        float* __restrict__ out) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n_rows) return;
+  const float inv_a = 1.f / alpha;
+  const float a = n1[b] > 0 ? self1[b] / (float)n1[b] : 0.f;
+  const float c = n2[b] > 0 ? self2[b] / (float)n2[b] : 0.f;
+  const float pa = a > 0.f ? powf(a, alpha) : 0.f;
+  const float pc = c > 0.f ? powf(c, alpha) : 0.f;
+  const float m = 0.5f * (pa + pc);
+  out[b] = m > 0.f ? powf(m, inv_a) : 0.f;
+}
+
+void launch_fuse_self(const float* self1, const int32_t* n1, const float* self2,
+                      const int32_t* n2, float alpha, int n_rows, float* out, hipStream_t st) {
+  if (n_rows <= 0) return;
+  hipLaunchKernelGGL(fuse_self_kernel, dim3((n_rows + 255) / 256), dim3(256), 0, st, self1, n1,
+                     self2, n2, alpha, n_rows, out);
+}
+
 void launch_fuse(const int32_t* i1, const float* v1, int k_a, const int32_t* i2, const float* v2,
                  int k_b, float alpha, int n_rows, int32_t* out_ids, float* out_val, int k_out,
                  hipStream_t st) {

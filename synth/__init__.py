@@ -28,7 +28,7 @@ import numpy as np
 
 # Order in which child seed streams are spawned from SeedSequence(seed).
 _STREAMS = ("centres", "db_classes", "db_noise", "q_classes", "q_counts",
-            "q_noise", "kmeans_init", "arrivals", "subcentres")
+            "q_noise", "kmeans_init", "arrivals", "subcentres", "centres2")
 _CHUNK = 2048  # views per noise chunk; each chunk has its own seed
 
 
@@ -188,13 +188,9 @@ def query_counts(w: Workload) -> np.ndarray:
     return rng.integers(w.m_lo, w.m_hi + 1, size=w.n_queries, dtype=np.int32)
 
 
-def make_queries(w: Workload, threads=None):
-    """Fresh query shapes drawn from the same generator on separate streams.
-
-    Returns (views float32 [sum m, d], offsets int32 [B+1], classes int32 [B]).
-    """
+def _query_labels(w: Workload):
+    """Query classes [B], view counts [B], offsets [B+1] and per-view classes."""
     st = _streams(w.seed)
-    centres = _centre_table(w)
     rng = np.random.Generator(np.random.PCG64(st["q_classes"]))
     qcls = rng.integers(0, w.n_classes, size=w.n_queries, dtype=np.int32)
     counts = query_counts(w)
@@ -205,6 +201,16 @@ def make_queries(w: Workload, threads=None):
         dis = rng.random(vclass.shape[0]) < w.p_dis
         shift = rng.integers(1, w.n_classes, size=vclass.shape[0], dtype=np.int32)
         vclass = np.where(dis, (vclass + shift) % w.n_classes, vclass).astype(np.int32)
+    return qcls, counts, offsets, vclass
+
+
+def make_queries(w: Workload, threads=None):
+    """Fresh query shapes drawn from the same generator on separate streams.
+
+    Returns (views float32 [sum m, d], offsets int32 [B+1], classes int32 [B]).
+    """
+    centres = _centre_table(w)
+    qcls, counts, offsets, vclass = _query_labels(w)
     out = np.empty((int(offsets[-1]), w.dim), dtype=np.float32)
     rows = vclass
     if w.n_sub > 0:
@@ -212,6 +218,31 @@ def make_queries(w: Workload, threads=None):
         rows = (vclass * w.n_sub + vpt).astype(np.int32)
     _fill_views(out, rows, centres, w.sigma, w.seed, 2, threads)
     return out, offsets, qcls
+
+
+def make_second_measure(w: Workload, dim: int = 256, sigma: float = 0.45, threads=None):
+    """Features of the same database and query views under a second
+    similarity measure, standing in for a second CNN layer (the paper fuses
+    two, Sec. 2.4 and 3).  The views keep their classes and distractor
+    pattern (they are the same rendered views), while the measure has its own
+    class centres (stream "centres2"), its own noise streams and a larger
+    noise scale, so it ranks less sharply than the first.
+
+    Returns (db views float32 [N*Nv, dim], query views float32 [sum m, dim],
+    query offsets int32 [B+1]).
+    """
+    st = _streams(w.seed)
+    rng = np.random.Generator(np.random.PCG64(st["centres2"]))
+    centres = rng.standard_normal((w.n_classes, dim), dtype=np.float32)
+    shape_cls = (np.arange(w.n_shapes) % w.n_classes).astype(np.int32)
+    vrng = np.random.Generator(np.random.PCG64(st["db_classes"]))
+    vclass = _view_classes(vrng, shape_cls, w.n_views, w.n_classes, w.p_dis)
+    db = np.empty((w.n_shapes * w.n_views, dim), dtype=np.float32)
+    _fill_views(db, vclass, centres, sigma, w.seed, 3, threads)
+    _, _, offsets, qvclass = _query_labels(w)
+    q = np.empty((int(offsets[-1]), dim), dtype=np.float32)
+    _fill_views(q, qvclass, centres, sigma, w.seed, 4, threads)
+    return db, q, offsets
 
 
 def kmeans_init_idx(n_train: int, K: int, seed: int) -> np.ndarray:

@@ -193,16 +193,21 @@ def test_neighbour_augmentation_matches_oracle(L):
     gi, gs, gn = L.gift_augment_neighbours(_t(ids), _t(sc), _t(mem), _t(qi), _t(qv))
     gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
     assert (gn.cpu().numpy() == k2).all()
+    # the oracle's Eq. 10 over the database rows with the queries appended as
+    # rows N..N+4, each query's member list being itself then `mem`
+    Fx = np.zeros((N + 5, N))
+    Fx[:N] = F
+    nbx = np.full((N + 5, k2), -1, np.int64)
+    nbx[:N] = ids[:, :k2]
     for b in range(5):
-        dense = np.zeros(N)
-        dense[qi[b]] += qv[b]
-        for i in mem[b]:
-            dense += F[i]
-        dense /= k2
+        Fx[N + b, qi[b]] = qv[b]
+        nbx[N + b] = [N + b] + mem[b].tolist()
+    ref_q = O.neighbour_augment(Fx, nbx, k2)[N:]
+    for b in range(5):
         got = np.zeros(N)
         valid = gi[b] >= 0
         got[gi[b][valid]] = gs[b][valid]
-        assert np.allclose(got, dense, rtol=1e-6, atol=1e-7)
+        assert np.allclose(got, ref_q[b], rtol=1e-6, atol=1e-7)
 
 
 def test_fusion_and_co_augmentation_match_oracle(L):

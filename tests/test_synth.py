@@ -75,3 +75,24 @@ def test_subcentres_group_views_by_viewpoint():
     base, _, _ = synth.make_db(synth.PRESETS["c1"].scaled(n_shapes=10, dim=32))
     again, _, _ = synth.make_db(synth.PRESETS["c1"].scaled(n_shapes=10, dim=32, n_sub=0))
     assert np.array_equal(base, again)
+
+
+def test_second_measure_same_views_own_features():
+    """The second measure describes the same views: same query offsets, and
+    views of one class (the first measure's labels) are closer to each other
+    than to other classes' views; its features are deterministic, unit-norm
+    and non-negative, and differ from the first measure's."""
+    w = synth.PRESETS["c1"].scaled(n_shapes=80, dim=64, n_queries=5, m_lo=4, m_hi=12,
+                                   p_dis=0.25, seed=3)
+    db1, _, vclass = synth.make_db(w)
+    _, qoff, _ = synth.make_queries(w)
+    db2, q2, qoff2 = synth.make_second_measure(w, dim=48)
+    again = synth.make_second_measure(w, dim=48)
+    assert np.array_equal(db2, again[0]) and np.array_equal(q2, again[1])
+    assert np.array_equal(qoff, qoff2) and q2.shape == (int(qoff[-1]), 48)
+    assert db2.shape == (db1.shape[0], 48) and (db2 >= 0).all()
+    assert np.allclose(np.linalg.norm(db2, axis=1), 1.0, atol=1e-6)
+    G = db2[:1000].astype(np.float64) @ db2[:1000].T.astype(np.float64)
+    same = vclass[:1000, None] == vclass[None, :1000]
+    off_diag = ~np.eye(1000, dtype=bool)
+    assert G[same & off_diag].mean() > G[~same].mean() + 0.1
