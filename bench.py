@@ -535,6 +535,7 @@ def scale_bench(args):
                     res = L.gift_rerank_sif(S, plan.ids, plan.scores, one, args.top_k,
                                             stream=plan.stream)
                 plan.stream.synchronize()
+                multi = int(((res[2] & 2) != 0).sum().item())
                 dt = (time.perf_counter() - t1) / args.steps
                 rr_ms, rr_n = L.gift_profile_read("rerank_sif")
                 L.gift_profile_enable(0)
@@ -547,7 +548,8 @@ def scale_bench(args):
             out[f"blocks_per_cu_{bpc}"] = {"ms_per_batch": round(dt * 1e3, 3),
                                            "queries_per_s": round(B / dt, 1),
                                            "eager_first_pass_ms": round(t_eager * 1e3, 3),
-                                           "rerank_ms": rr_ms / max(rr_n, 1), "queue_error": err,
+                                           "rerank_ms": rr_ms / max(rr_n, 1),
+                                           "multi_range_reranks": multi, "queue_error": err,
                                            "phase_block_ms": phases,
                                            "phase_end_us": dict(zip(_PHASES, (
                                                round(x, 1) for x in plan.phase_end_us())))}
@@ -592,25 +594,42 @@ def scale_bench(args):
         log(f"c5 plan alone: {nb} queries in {by_size[str(nb)]['ms_per_batch']} ms")
     plan.close()
     rates = [float(r) for r in args.serve_rates.split(",")]
-    srv = Server(V, F, S, top_k=args.top_k, k1=k1, rescore_r=64, max_queries=64,
-                 max_views=64 * 64, max_slots=3)
     queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
-    for v in queries[:8]:
-        srv.submit(v).result()
-    runs = {}
-    for rate in rates:
-        arr = synth.poisson_arrivals(rate, args.serve_seconds, w.seed + int(rate))
-        qs = [queries[i % len(queries)] for i in range(len(arr))]
-        b0 = srv.batches
-        _, lat, wall = replay_trace(srv, qs, arr)
-        runs[str(int(rate))] = {"offered_qps": rate, "completed": len(arr),
-                                "achieved_qps": round(len(arr) / wall, 1),
-                                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                                "batches": srv.batches - b0}
-        log(f"c5 serve {rate} qps: p50 {runs[str(int(rate))]['p50_ms']} ms, "
-            f"p99 {runs[str(int(rate))]['p99_ms']} ms")
-    n_slots = srv.n_slots
+
+    def serve_runs(srv, rate_list, label):
+        for v in queries[:8]:
+            srv.submit(v).result()
+        res = {}
+        for rate in rate_list:
+            arr = synth.poisson_arrivals(rate, args.serve_seconds, w.seed + int(rate))
+            qs = [queries[i % len(queries)] for i in range(len(arr))]
+            st0 = dict(srv.stats)
+            _, lat, wall = replay_trace(srv, qs, arr)
+            d = {k: srv.stats[k] - st0[k] for k in ("batches", "memory_waits",
+                                                     "multi_range_reranks", "slots_created",
+                                                     "slots_evicted")}
+            res[str(int(rate))] = {"offered_qps": rate, "completed": len(arr),
+                                   "achieved_qps": round(len(arr) / wall, 1),
+                                   "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                   "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                   "max_busy_slots": srv.stats["max_busy_slots"], **d}
+            log(f"c5 serve {label} {rate} qps: p50 {res[str(int(rate))]['p50_ms']} ms, "
+                f"p99 {res[str(int(rate))]['p99_ms']} ms over {len(arr)} queries")
+        return res
+
+    srv = Server(V, F, S, top_k=args.top_k, k1=k1, rescore_r=64, max_queries=64, max_m=w.m_hi,
+                 max_slots=3)
+    budget = srv.arena.size
+    slot_classes = {f"{q}x{v}": b for (q, v), b in zip(srv.classes, srv.slot_bytes)}
+    runs = serve_runs(srv, rates, "3 slots")
+    n_slots = len(srv.slots)
+    srv.close()
+    # the same load under a memory budget of one 16-query slot: batches wait
+    # for memory, and larger ones than fit are split
+    tight = srv.slot_bytes[srv.classes.index(next(c for c in srv.classes if c[0] >= 16))]
+    srv = Server(V, F, S, top_k=args.top_k, k1=k1, rescore_r=64, max_queries=64, max_m=w.m_hi,
+                 max_slots=3, mem_budget_bytes=tight + 256)
+    tight_runs = serve_runs(srv, [rates[len(rates) // 2]], "tight budget")
     srv.close()
     top = runs[str(int(rates[-1]))]
     return {"metric": f"serving queries/s and p50/p99 ms, F-IF + S-IF, 200k x 64-view {storage} DB",
@@ -618,8 +637,10 @@ def scale_bench(args):
             "higher_is_better": True, "dtype": storage, "data": "synthetic",
             "config": {"workload": f"c5: 200,000 shapes x 64 x 1024 {storage}, K=8192, k1=20, Poisson "
                        f"arrivals {args.serve_rates} q/s for {args.serve_seconds}s each, "
-                       "8..64 views per query", "slots": n_slots},
-            "build": build, "plan_alone_by_batch": by_size, "serving": runs}
+                       "8..64 views per query", "slots": n_slots,
+                       "memory_budget_bytes": budget, "slot_bytes_by_class": slot_classes},
+            "build": build, "plan_alone_by_batch": by_size, "serving": runs,
+            "serving_tight_memory": {"memory_budget_bytes": tight + 256, "runs": tight_runs}}
 
 
 def sweep_bench(args):

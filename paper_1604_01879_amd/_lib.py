@@ -440,6 +440,11 @@ def gift_autotune_score(db: Views, q: Queries, tiles, groups, reps=2, stream=Non
 
 
 # ---------------------------------------------------------------- plans
+def fif_plan_workspace(db: Views, fif: Fif, max_queries, max_views, top_k, rescore_r) -> int:
+    return int(_lib.gift_fif_plan_workspace(C.byref(db.c), C.byref(fif.c), max_queries,
+                                            max_views, top_k, rescore_r))
+
+
 class FifPlan:
     """A captured F-IF batch plan with its own input/output buffers.
 
@@ -449,19 +454,30 @@ class FifPlan:
     non-default stream."""
 
     def __init__(self, db: Views, fif: Fif, max_queries, max_views, max_views_per_query, top_k,
-                 rescore_r, blocks_per_cu=2, stream=None):
+                 rescore_r, blocks_per_cu=2, stream=None, ws=None, views=None):
+        """ws (uint8) and views (float32 [max_views, dim]) may be given as
+        caller-owned device tensors (e.g. carved from a memory pool); they
+        must outlive the plan."""
         dev = db.data.device
         self.db, self.fif = db, fif
         self.max_queries, self.max_views, self.top_k = max_queries, max_views, top_k
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
-        self.views = torch.zeros((max_views, db.dim), dtype=torch.float32, device=dev)
+        if views is not None:
+            assert views.shape == (max_views, db.dim) and views.dtype == torch.float32
+            self.views = views
+        else:
+            self.views = torch.zeros((max_views, db.dim), dtype=torch.float32, device=dev)
         self.offsets = torch.zeros(max_queries + 1, dtype=torch.int32, device=dev)
         self.ids = torch.zeros((max_queries, top_k), dtype=torch.int32, device=dev)
         self.scores = torch.zeros((max_queries, top_k), dtype=torch.float32, device=dev)
         self.flags = torch.zeros(max_queries, dtype=torch.int32, device=dev)
         need = _lib.gift_fif_plan_workspace(C.byref(db.c), C.byref(fif.c), max_queries,
                                             max_views, top_k, rescore_r)
-        self.ws = _workspace(need, dev)
+        if ws is not None:
+            assert ws.dtype == torch.uint8 and ws.numel() >= need
+            self.ws = ws
+        else:
+            self.ws = _workspace(need, dev)
         torch.cuda.synchronize(dev)
         self.handle = C.c_void_p()
         _check(_lib.gift_fif_plan_create(C.byref(db.c), C.byref(fif.c), max_queries, max_views,

@@ -1,17 +1,21 @@
-"""GPU test of the continuous-batching server: results are the same when a
-query runs alone and when it is batched with others under load, and equal
-those of the direct calls (F-IF top-(k1-1) + self, then S-IF re-rank)."""
+"""GPU tests of the continuous-batching server: each result is the same when
+a query runs alone and when it is batched with others under load, equals the
+direct calls (F-IF top-(k1-1) + self, then the S-IF re-rank) and the oracle
+pipeline (Eq. 4 lists, Eq. 7 S-IF, Eq. 8 re-ranking); and a memory budget
+that holds a single small slot makes queries wait and split into batches
+that fit it, with the same results."""
 import sys
-import time
 
 import numpy as np
 import pytest
 import torch
 
+import oracle as O
 import synth
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
+REL = 1e-5
 
 
 def _say(msg):
@@ -19,10 +23,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def test_server_alone_equals_mix():
+@pytest.fixture(scope="module")
+def setup():
+    """300 shapes in e4m3 storage, a 32-word F-IF (MA 1), and the S-IF of
+    every shape's top-k1 by Eq. 4 (every shape rescored, so each list is the
+    exact Eq. 4 top-k1)."""
     from paper_1604_01879_amd import _lib as L
-    from paper_1604_01879_amd.serve import Server, replay_trace
-    _say("server alone vs mix")
     w = synth.PRESETS["c1"].scaled(n_shapes=300, dim=128, n_queries=24, m_lo=8, m_hi=64,
                                    p_dis=0.2, seed=2)
     db, _, _ = synth.make_db(w)
@@ -30,34 +36,108 @@ def test_server_alone_equals_mix():
     master = torch.from_numpy(db).to(DEV)
     codes, scale = L.gift_quantize_views(master, L.FP8E4M3)
     V = L.Views(codes, w.n_views, L.FP8E4M3, scale, master)
-    cb = master[torch.from_numpy(synth.kmeans_init_idx(db.shape[0], 32, 1))].contiguous()
-    F = L.gift_build_fif(L.Views(master, w.n_views, L.F32), cb, 1)
-    k1, k = 8, 20
-    # S-IF from every database shape's top-k1 by Eq. 4
+    cb_np = db[synth.kmeans_init_idx(db.shape[0], 32, 1)]
+    F = L.gift_build_fif(L.Views(master, w.n_views, L.F32), torch.from_numpy(cb_np).to(DEV), 1)
+    k1, k, R = 8, 20, w.n_shapes
     Qdb = L.Queries(master, torch.arange(0, w.n_shapes + 1, dtype=torch.int32) * w.n_views)
-    nid, nsc, _ = L.gift_query_fif(V, F, Qdb, k1, 32)
+    nid, nsc, _ = L.gift_query_fif(V, F, Qdb, k1, R)
     S = L.gift_build_sif(nid, nsc)
-    queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
-    # direct calls
+    torch.cuda.synchronize()
+    return L, w, db, q, qoff, cb_np, V, F, S, k1, k, R
+
+
+def _oracle_pipeline(w, db, q, qoff, cb, k1, k):
+    """Eq. 4 top-k1 of every database shape (S-IF, Eq. 7) and top-(k1 - 1) of
+    every query plus itself, re-ranked by Eq. 8; memberships rounded to
+    float32 as the library returns scores."""
+    off, es, ev = O.build_fif(O.assign(db, cb, 1), len(cb), w.n_views)
+    N = w.n_shapes
+    Sdb = O.fif_scores(db, np.arange(N + 1) * w.n_views, db, w.n_views, cb, off, es, ev)
+    ids, sc = O.rank_topk(Sdb, k1)
+    l1, po, pid, pv = O.build_sif(ids, sc.astype(np.float32).astype(np.float64), N)
+    Sq = O.fif_scores(q, qoff, db, w.n_views, cb, off, es, ev)
+    qi, qv = O.rank_topk(Sq, k1 - 1)
+    out = []
+    for b in range(len(qoff) - 1):
+        _, _, Sfull = O.rerank_sif(l1, po, pid, pv, qi[b],
+                                   qv[b].astype(np.float32).astype(np.float64), 1.0, k)
+        out.append(Sfull)
+    return out
+
+
+def _assert_like_oracle(ids, sc, Sref, k, tie=1e-6):
+    ref_ids, ref_s = O.rank_topk(Sref[None], k)
+    ref_ids, ref_s = ref_ids[0], ref_s[0]
+    assert len(set(ids.tolist())) == k
+    assert np.allclose(sc, Sref[ids], rtol=REL, atol=1e-7)
+    assert np.all(np.abs(Sref[ids] - ref_s) <= tie)
+    gaps = np.abs(np.diff(ref_s))
+    near = np.zeros(k, bool)
+    near[:-1] |= gaps <= tie
+    near[1:] |= gaps <= tie
+    assert np.array_equal(ids[~near], ref_ids[~near])
+
+
+def _direct(L, w, q, qoff, V, F, S, k1, k, R):
     Q = L.Queries(torch.from_numpy(q).to(DEV), torch.from_numpy(qoff))
-    qi, qs, _ = L.gift_query_fif(V, F, Q, k1 - 1, 32)
+    qi, qs, _ = L.gift_query_fif(V, F, Q, k1 - 1, R)
     one = torch.ones(w.n_queries, dtype=torch.float32, device=DEV)
     ref_ids, ref_sc, _ = L.gift_rerank_sif(S, qi, qs, one, k)
     torch.cuda.synchronize()
-    ref_ids, ref_sc = ref_ids.cpu().numpy(), ref_sc.cpu().numpy()
-    srv = Server(V, F, S, top_k=k, k1=k1, rescore_r=32, max_queries=6, max_views=6 * 64,
-                 max_slots=2)
+    return ref_ids.cpu().numpy(), ref_sc.cpu().numpy()
+
+
+def test_server_alone_equals_mix_and_oracle(setup):
+    from paper_1604_01879_amd.serve import Server, replay_trace
+    L, w, db, q, qoff, cb, V, F, S, k1, k, R = setup
+    _say("server alone vs mix vs oracle")
+    ref_ids, ref_sc = _direct(L, w, q, qoff, V, F, S, k1, k, R)
+    Sref = _oracle_pipeline(w, db, q, qoff, cb, k1, k)
+    queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
+    srv = Server(V, F, S, top_k=k, k1=k1, rescore_r=R, max_queries=6, max_m=64, max_slots=2)
     try:
-        alone = []
-        for v in queries:
-            alone.append(srv.submit(v).result(timeout=60))
+        alone = [srv.submit(v).result(timeout=60) for v in queries]
         res, lat, wall = replay_trace(srv, queries, np.zeros(len(queries)))  # all at once
-        assert srv.batches < 2 * len(queries)  # the burst was batched
+        assert srv.stats["batches"] < 2 * len(queries)  # the burst was batched
         for b in range(w.n_queries):
             assert np.array_equal(alone[b][0], ref_ids[b])
             assert np.array_equal(alone[b][1], ref_sc[b])
             assert np.array_equal(res[b][0], alone[b][0])
             assert np.array_equal(res[b][1], alone[b][1])
+            _assert_like_oracle(res[b][0], res[b][1], Sref[b], k)
         assert (lat > 0).all()
+    finally:
+        srv.close()
+
+
+def test_server_memory_budget_makes_queries_wait(setup):
+    """A budget that holds one slot of the 4-query class (and nothing larger)
+    serves a burst of 24 queries of up to 64 views: the server creates that
+    one slot, queries wait for it (memory waits), batches hold at most 4
+    queries, and every result is the one the query gets alone."""
+    from paper_1604_01879_amd.serve import Server, replay_trace
+    L, w, db, q, qoff, cb, V, F, S, k1, k, R = setup
+    _say("server under a one-slot memory budget")
+    ref_ids, ref_sc = _direct(L, w, q, qoff, V, F, S, k1, k, R)
+    queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
+    probe = Server(V, F, S, top_k=k, k1=k1, rescore_r=R, max_queries=16, max_m=64, max_slots=1,
+                   prewarm=False)
+    classes, sizes = probe.classes, probe.slot_bytes
+    probe.close()
+    i4 = classes.index((4, 256))
+    budget = sizes[i4] + 256
+    assert budget < sizes[i4 + 1]  # no room for the 16-query class
+    srv = Server(V, F, S, top_k=k, k1=k1, rescore_r=R, max_queries=16, max_m=64, max_slots=3,
+                 mem_budget_bytes=budget)
+    try:
+        assert len(srv.slots) == 1 and srv.slots[0].q_cap == 4
+        res, lat, wall = replay_trace(srv, queries, np.zeros(len(queries)))
+        st = srv.stats
+        assert st["memory_waits"] > 0
+        assert st["batches"] >= len(queries) // 4
+        assert st["max_busy_slots"] == 1 and st["peak_bytes"] <= budget
+        for b in range(w.n_queries):
+            assert np.array_equal(res[b][0], ref_ids[b])
+            assert np.array_equal(res[b][1], ref_sc[b])
     finally:
         srv.close()
