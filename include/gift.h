@@ -370,8 +370,14 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* launches that graph for a batch occupying the first n_queries slots and  */
 /* n_views rows; outputs of unused slots are unspecified.  The first-pass */
 /* scores, ids, scores and flags equal those of gift_query_fif on the same */
-/* batch (the same tiles in the same order).  blocks_per_cu (1 or 2) sets */
-/* the persistent grid.  Create SYNCHRONISES `stream` (which must be a     */
+/* batch (the same tiles in the same order) under the default tuning.     */
+/* `tuning` (NULL: the defaults) sets the persistent grid (blocks_per_cu,   */
+/* 1 or 2; default 2), the list entries per scan item (list_tile, 32..128  */
+/* in steps of 32; default 128) and the largest query-view group that takes */
+/* the narrow scan tile (narrow_max, 0, 16 or 32; default 32).  Every      */
+/* tuning gives the same ids and exact scores; a first-pass value, and so  */
+/* a flag, may differ in the last bits between tunings.  The workspace     */
+/* size depends on list_tile.  Create SYNCHRONISES `stream` (which must be a */
 /* non-default stream not being captured); run is asynchronous.  A plan is */
 /* not thread-safe and its runs on different streams must not overlap.     */
 /* gift_fif_plan_first_pass copies the first-pass Eq. 4 scores of the     */
@@ -390,16 +396,24 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* queue reset to the end of the phase's last item (0: no item).           */
 /* ---------------------------------------------------------------------- */
 typedef struct gift_fif_plan gift_fif_plan;
+typedef struct gift_plan_tuning {
+  int32_t blocks_per_cu;  /* persistent blocks per CU: 1 or 2                */
+  int32_t list_tile;      /* list entries per scan item: 32, 64, 96 or 128   */
+  int32_t narrow_max;     /* groups of at most this many query views take
+                             the narrow scan tile: 0 (none), 16 or 32        */
+  int32_t reserved;       /* 0                                               */
+} gift_plan_tuning;
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,
                                int32_t max_queries, int64_t max_views,
-                               int32_t top_k, int32_t rescore_r);
+                               int32_t top_k, int32_t rescore_r,
+                               const gift_plan_tuning* tuning);
 gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif,
                                  int32_t max_queries, int64_t max_views,
                                  int32_t max_views_per_query, int32_t top_k,
                                  int32_t rescore_r, const float* q_views,
                                  int32_t* q_offsets, int32_t* ids,
                                  float* scores, int32_t* flags,
-                                 int32_t blocks_per_cu, void* ws,
+                                 const gift_plan_tuning* tuning, void* ws,
                                  size_t ws_bytes, void* stream,
                                  gift_fif_plan** plan);
 gift_status gift_fif_plan_run(gift_fif_plan* plan, int32_t n_queries,

@@ -52,6 +52,12 @@ class gift_fif(C.Structure):
 
 _P = C.c_void_p
 _FP = C.POINTER(gift_fif)
+class gift_plan_tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("list_tile", C.c_int32),
+                ("narrow_max", C.c_int32), ("reserved", C.c_int32)]
+
+
+_TP = C.POINTER(gift_plan_tuning)
 _VP = C.POINTER(gift_views)
 _QP = C.POINTER(gift_queries)
 _sig = {
@@ -97,9 +103,9 @@ _sig = {
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P,
                                         C.c_size_t, _P]),
     "gift_fif_plan_workspace": (C.c_size_t, [_VP, _FP, C.c_int32, C.c_int64, C.c_int32,
-                                             C.c_int32]),
+                                             C.c_int32, _TP]),
     "gift_fif_plan_create": (C.c_int32, [_VP, _FP, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
-                                         C.c_int32, _P, _P, _P, _P, _P, C.c_int32, _P,
+                                         C.c_int32, _P, _P, _P, _P, _P, _TP, _P,
                                          C.c_size_t, _P, C.POINTER(C.c_void_p)]),
     "gift_fif_plan_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
     "gift_fif_plan_run_eager": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
@@ -440,9 +446,15 @@ def gift_autotune_score(db: Views, q: Queries, tiles, groups, reps=2, stream=Non
 
 
 # ---------------------------------------------------------------- plans
-def fif_plan_workspace(db: Views, fif: Fif, max_queries, max_views, top_k, rescore_r) -> int:
+def plan_tuning(blocks_per_cu=2, list_tile=128, narrow_max=32):
+    return gift_plan_tuning(int(blocks_per_cu), int(list_tile), int(narrow_max), 0)
+
+
+def fif_plan_workspace(db: Views, fif: Fif, max_queries, max_views, top_k, rescore_r,
+                       tuning=None) -> int:
+    t = tuning if tuning is not None else plan_tuning()
     return int(_lib.gift_fif_plan_workspace(C.byref(db.c), C.byref(fif.c), max_queries,
-                                            max_views, top_k, rescore_r))
+                                            max_views, top_k, rescore_r, C.byref(t)))
 
 
 class FifPlan:
@@ -454,7 +466,8 @@ class FifPlan:
     non-default stream."""
 
     def __init__(self, db: Views, fif: Fif, max_queries, max_views, max_views_per_query, top_k,
-                 rescore_r, blocks_per_cu=2, stream=None, ws=None, views=None):
+                 rescore_r, blocks_per_cu=2, stream=None, ws=None, views=None, list_tile=128,
+                 narrow_max=32):
         """ws (uint8) and views (float32 [max_views, dim]) may be given as
         caller-owned device tensors (e.g. carved from a memory pool); they
         must outlive the plan."""
@@ -471,8 +484,8 @@ class FifPlan:
         self.ids = torch.zeros((max_queries, top_k), dtype=torch.int32, device=dev)
         self.scores = torch.zeros((max_queries, top_k), dtype=torch.float32, device=dev)
         self.flags = torch.zeros(max_queries, dtype=torch.int32, device=dev)
-        need = _lib.gift_fif_plan_workspace(C.byref(db.c), C.byref(fif.c), max_queries,
-                                            max_views, top_k, rescore_r)
+        self.tuning = plan_tuning(blocks_per_cu, list_tile, narrow_max)
+        need = fif_plan_workspace(db, fif, max_queries, max_views, top_k, rescore_r, self.tuning)
         if ws is not None:
             assert ws.dtype == torch.uint8 and ws.numel() >= need
             self.ws = ws
@@ -483,7 +496,8 @@ class FifPlan:
         _check(_lib.gift_fif_plan_create(C.byref(db.c), C.byref(fif.c), max_queries, max_views,
                                          max_views_per_query, top_k, rescore_r,
                                          _ptr(self.views), _ptr(self.offsets), _ptr(self.ids),
-                                         _ptr(self.scores), _ptr(self.flags), blocks_per_cu,
+                                         _ptr(self.scores), _ptr(self.flags),
+                                         C.byref(self.tuning),
                                          _ptr(self.ws), self.ws.numel(), _stream(self.stream),
                                          C.byref(self.handle)))
 

@@ -629,10 +629,12 @@ void launch_count_changes(const int32_t* a, const int32_t* b, int64_t n, int32_t
 }
 
 // ------------------------------------------------------------------ list scan
-// tile_off[w+1] - tile_off[w] = ceil(|L_w| / 128) list tiles (single block).
+// tile_off[w+1] - tile_off[w] = ceil(|L_w| / tile_len) list tiles (single block).
 __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restrict__ off, int K,
+                                                          int tile_len,
                                                           int64_t* __restrict__ tcount) {
-  for (int w = threadIdx.x; w < K; w += 1024) tcount[w] = (off[w + 1] - off[w] + 127) / 128;
+  for (int w = threadIdx.x; w < K; w += 1024)
+    tcount[w] = (off[w + 1] - off[w] + tile_len - 1) / tile_len;
 }
 
 // One block per list tile of 128 entries and the batch's query views whose
@@ -641,7 +643,10 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 // float32 rows), the per-shape maximum over
 // the tile's entries (entries of a shape are contiguous), and an atomic max
 // into mbuf[query view][shape] (row stride ldn; 0 = no matching view yet).
-// Tile b of list w (tile_off[w] <= b < tile_off[w + 1]).
+// Tile b of list w (tile_off[w] <= b < tile_off[w + 1]) holds entries
+// [tile_len (b - tile_off[w]), + tile_len) of the list (tile_len <= 128: the
+// MFMA tile's rows past it are padding).  Groups of at most narrow_max
+// (<= 32) query views take the narrow tile.
 // Scales: per-view float32 (BF16 / e4m3) or E8M0 rows (MX), null for float32.
 // NARROW_DMA: narrow tiles of whole 128-byte sub-tiles use the
 // direct-to-LDS gather pipeline instead of register staging.
@@ -652,7 +657,8 @@ __device__ __forceinline__ void scan_list_tile(
     const int32_t* __restrict__ ent_view, const int64_t* __restrict__ tile_off, int w,
     const int64_t* __restrict__ goff, const int32_t* __restrict__ gitems,
     const uint8_t* __restrict__ qv, const void* __restrict__ q_scale_v,
-    uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds) {
+    uint32_t* __restrict__ mbuf, int64_t ldn, int64_t b, uint8_t* lds, int tile_len = 128,
+    int narrow_max = 32) {
   using T = TileShape<2, 2>;
   constexpr bool MX = DT == GIFT_MXFP8 || DT == GIFT_MXFP4;
   constexpr bool SCALED = DT == GIFT_BF16 || DT == GIFT_FP8E4M3;
@@ -660,8 +666,8 @@ __device__ __forceinline__ void scan_list_tile(
   const float* q_scale = static_cast<const float*>(q_scale_v);
   const int64_t g0 = goff[w], g1 = goff[w + 1];
   if (g0 == g1) return;
-  const int64_t e0 = loff[w] + (b - tile_off[w]) * T::BM;
-  const int64_t e1 = e0 + T::BM < loff[w + 1] ? e0 + T::BM : loff[w + 1];
+  const int64_t e0 = loff[w] + (b - tile_off[w]) * tile_len;
+  const int64_t e1 = e0 + tile_len < loff[w + 1] ? e0 + tile_len : loff[w + 1];
   const int ne = (int)(e1 - e0);
   float* C = reinterpret_cast<float*>(lds);  // [128][129] after the main loop
   const int wave = threadIdx.x >> 6;
@@ -693,7 +699,7 @@ __device__ __forceinline__ void scan_list_tile(
     // number of 128-byte sub-tiles use the 128 x 128 tiles instead.
     const bool narrow_ok =
         DT != GIFT_BF16 || (NARROW_DMA && row_bytes % DMA2_KSUB == 0);
-    if (g1 - g0 <= NarrowShape::BN && narrow_ok) {
+    if (g1 - g0 <= narrow_max && narrow_ok) {
       using N = NarrowShape;
       f32x16 acc;
       if (NARROW_DMA && row_bytes % DMA2_KSUB == 0) {
@@ -884,7 +890,7 @@ gift_status launch_fif_scan(const gift_views* db, const int64_t* loff, const int
                             int64_t* tile_off, int64_t* tcount, const int64_t* goff,
                             const int32_t* gitems, const void* qv, const void* qscale,
                             uint32_t* mbuf, int64_t ldn, hipStream_t st) {
-  hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tcount);
+  hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, 128, tcount);
   GIFT_LAUNCHED();
   hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, st, tcount, K, tile_off);
   GIFT_LAUNCHED();
@@ -1298,7 +1304,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
                              a.ent_view, a.tile_off, a.tile_word[b], a.goff, a.gitems,
                              DT == GIFT_F32 ? reinterpret_cast<const uint8_t*>(a.qviews)
                                             : a.qcodes,
-                             a.qscale, a.mbuf, a.n_shapes, b, lds);
+                             a.qscale, a.mbuf, a.n_shapes, b, lds, a.tile_len, a.narrow_max);
           break;
         }
         case BP_RED: {
@@ -1392,9 +1398,9 @@ gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo
   return GIFT_OK;
 }
 
-gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64_t* tile_off,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tcount);
+gift_status launch_list_tiles(const int64_t* loff, int K, int tile_len, int64_t* tcount,
+                              int64_t* tile_off, hipStream_t st) {
+  hipLaunchKernelGGL(list_tiles_kernel, dim3(1), dim3(1024), 0, st, loff, K, tile_len, tcount);
   GIFT_LAUNCHED();
   hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, st, tcount, K, tile_off);
   GIFT_LAUNCHED();

@@ -155,6 +155,8 @@ struct BatchArgs {
   float gamma2;
   int64_t wait_ticks;        // wall-clock ticks a phase wait may take
   int64_t gemm_col_tiles;
+  int tile_len;              // list entries per scan item (<= 128)
+  int narrow_max;            // groups of at most this many views take the narrow tile
 };
 void launch_batch_reset(const BatchArgs& a, hipStream_t st);
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st);
@@ -162,7 +164,8 @@ gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo
 // n rows of dim float32 values split into BF16 parts, dim x 4 bytes per row:
 // per 32 values, 32 high parts then 32 low parts (split_rows_kernel).
 void launch_split_rows(const float* src, int64_t n, int dim, uint8_t* dst, hipStream_t st);
-gift_status launch_list_tiles(const int64_t* loff, int K, int64_t* tcount, int64_t* tile_off,
+gift_status launch_list_tiles(const int64_t* loff, int K, int tile_len, int64_t* tcount,
+                              int64_t* tile_off,
                               hipStream_t st);
 void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStream_t st);
 float assign_gamma2(int dim);

@@ -41,15 +41,15 @@ struct PlanWs {
 };
 
 static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, int Bmax,
-                         int64_t Vmax, int r) {
+                         int64_t Vmax, int r, int tile_len) {
   Carver c(base);
   PlanWs w{};
   w.nhi = c.take<float>((size_t)f->K);
   w.nlo = c.take<float>((size_t)f->K);
   w.tcount = c.take<int64_t>((size_t)f->K);
   w.tile_off = c.take<int64_t>((size_t)f->K + 1);
-  // list tiles: at most n_entries / 128 + K of them
-  const size_t max_tiles = (size_t)(f->n_entries / 128 + f->K + 1);
+  // list tiles: at most n_entries / tile_len + K of them
+  const size_t max_tiles = (size_t)(f->n_entries / tile_len + f->K + 1);
   w.tile_word = c.take<int32_t>(max_tiles);
   w.act_off = c.take<int32_t>((size_t)f->K);
   w.act_tile = c.take<int32_t>(max_tiles);
@@ -129,24 +129,44 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
 
 }  // namespace gift
 
+// The tuning a plan runs with: the given one, or the defaults (2 blocks per
+// CU, 128-entry list tiles, narrow tiles for groups of up to 32 views).
+static gift_plan_tuning plan_tuning(const gift_plan_tuning* t) {
+  if (t != nullptr) return *t;
+  gift_plan_tuning d{};
+  d.blocks_per_cu = 2;
+  d.list_tile = 128;
+  d.narrow_max = 32;
+  return d;
+}
+
+static bool tuning_ok(const gift_plan_tuning& t) {
+  return (t.blocks_per_cu == 1 || t.blocks_per_cu == 2) && t.list_tile >= 32 &&
+         t.list_tile <= 128 && t.list_tile % 32 == 0 &&
+         (t.narrow_max == 0 || t.narrow_max == 16 || t.narrow_max == 32);
+}
+
 using namespace gift;
 
 extern "C" {
 
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif, int32_t max_queries,
-                               int64_t max_views, int32_t top_k, int32_t rescore_r) {
+                               int64_t max_views, int32_t top_k, int32_t rescore_r,
+                               const gift_plan_tuning* tuning) {
   (void)top_k;
-  if (db == nullptr || fif == nullptr || max_queries < 1 || max_views < 1 || rescore_r < 1)
+  const gift_plan_tuning t = plan_tuning(tuning);
+  if (db == nullptr || fif == nullptr || max_queries < 1 || max_views < 1 || rescore_r < 1 ||
+      !tuning_ok(t))
     return 0;
-  return carve_plan(nullptr, db, fif, max_queries, max_views, rescore_r).bytes;
+  return carve_plan(nullptr, db, fif, max_queries, max_views, rescore_r, t.list_tile).bytes;
 }
 
 gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int32_t max_queries,
                                  int64_t max_views, int32_t max_views_per_query, int32_t top_k,
                                  int32_t rescore_r, const float* q_views, int32_t* q_offsets,
                                  int32_t* ids, float* scores, int32_t* flags,
-                                 int32_t blocks_per_cu, void* ws, size_t ws_bytes, void* stream,
-                                 gift_fif_plan** plan) {
+                                 const gift_plan_tuning* tuning, void* ws, size_t ws_bytes,
+                                 void* stream, gift_fif_plan** plan) {
   GIFT_CHECK(plan != nullptr, GIFT_EINVAL, "null plan pointer");
   *plan = nullptr;
   GIFT_CHECK(db && fif && db->data && db->master && fif->codebook && fif->offsets &&
@@ -163,7 +183,11 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
              "K must be 1..16384 and ma 1..8");
   GIFT_CHECK(fif->n_entries == (int64_t)fif->ma * db->n_shapes * db->n_views, GIFT_EINVAL,
              "n_entries must be ma * n_shapes * n_views");
-  GIFT_CHECK(fif->n_entries / 128 + fif->K + 1 < ((int64_t)1 << 31), GIFT_ECAPACITY,
+  const gift_plan_tuning tune = plan_tuning(tuning);
+  GIFT_CHECK(tuning_ok(tune), GIFT_EINVAL,
+             "tuning: blocks_per_cu 1 or 2, list_tile 32..128 in steps of 32, narrow_max 0, "
+             "16 or 32");
+  GIFT_CHECK(fif->n_entries / tune.list_tile + fif->K + 1 < ((int64_t)1 << 31), GIFT_ECAPACITY,
              "too many list tiles");
   GIFT_CHECK(max_queries >= 1 && max_views >= 1 && max_views < ((int64_t)1 << 31) &&
                  max_views_per_query >= 1,
@@ -176,9 +200,8 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
                  (reinterpret_cast<uintptr_t>(db->data) & 15) == 0 &&
                  (reinterpret_cast<uintptr_t>(db->master) & 15) == 0,
              GIFT_EINVAL, "views must be 16-byte aligned");
-  GIFT_CHECK(blocks_per_cu >= 1 && blocks_per_cu <= 2, GIFT_EINVAL, "blocks_per_cu must be 1 or 2");
   const hipStream_t st = (hipStream_t)stream;
-  PlanWs w = carve_plan(ws, db, fif, max_queries, max_views, rescore_r);
+  PlanWs w = carve_plan(ws, db, fif, max_queries, max_views, rescore_r, tune.list_tile);
   GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
 
@@ -203,7 +226,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
     delete p;
     return fail(GIFT_EHIP, "cannot query the device");
   }
-  p->grid = n_cu * blocks_per_cu;
+  p->grid = n_cu * tune.blocks_per_cu;
   int clock_khz = 0;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
       clock_khz <= 0) {
@@ -217,7 +240,8 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
     launch_split_rows(fif->codebook, fif->K, db->dim, w.cbsplit, st);
     if (hipGetLastError() != hipSuccess) s = fail(GIFT_EHIP, "codebook split launch failed");
   }
-  if (s == GIFT_OK) s = launch_list_tiles(fif->offsets, fif->K, w.tcount, w.tile_off, st);
+  if (s == GIFT_OK)
+    s = launch_list_tiles(fif->offsets, fif->K, tune.list_tile, w.tcount, w.tile_off, st);
   if (s == GIFT_OK) {
     launch_tile_word(w.tile_off, fif->K, w.tile_word, st);
     if (hipGetLastError() != hipSuccess) s = fail(GIFT_EHIP, "tile map launch failed");
@@ -270,6 +294,8 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.wait_ticks = (int64_t)clock_khz * 1000 * 5;  // five seconds per phase wait
   p->clock_khz = clock_khz;
   a.gemm_col_tiles = (fif->K + 127) / 128;
+  a.tile_len = tune.list_tile;
+  a.narrow_max = tune.narrow_max;
 
   // an empty batch run eagerly once (sets kernel attributes, checks launches)
   {

@@ -60,7 +60,7 @@ class _Slot:
         v_off = off + (ws_bytes + 255) // 256 * 256
         views = buf[v_off:v_off + v_cap * srv.dim * 4].view(torch.float32).view(v_cap, srv.dim)
         self.plan = L.FifPlan(srv.db, srv.fif, q_cap, v_cap, srv.max_m, srv.fif_k, srv.rescore_r,
-                              ws=ws, views=views)
+                              ws=ws, views=views, **srv.tuning)
         self.stream = self.plan.stream
         dev = srv.db.data.device
         self.staging = torch.empty((v_cap, srv.dim), dtype=torch.float32).pin_memory()
@@ -154,18 +154,21 @@ class Server:
     class) is the arena every slot is carved from; max_slots bounds the
     number of slots (streams).  prewarm creates slots of the largest class
     that fits while the budget and max_slots allow, so no graph is captured
-    while queries wait.
+    while queries wait.  tuning: the plans' settings (blocks_per_cu,
+    list_tile, narrow_max; e.g. from tune.tune_plan), default the library's.
     """
 
     def __init__(self, db, fif, sif=None, top_k=100, k1=20, rescore_r=200, max_queries=64,
-                 max_m=64, mem_budget_bytes=None, max_slots=3, prewarm=True):
+                 max_m=64, mem_budget_bytes=None, max_slots=3, prewarm=True, tuning=None):
         self.db, self.fif, self.sif = db, fif, sif
+        self.tuning = dict(tuning or {})
         self.top_k, self.max_m, self.dim = top_k, max_m, db.dim
         self.fif_k = (k1 - 1) if sif is not None else top_k
         self.rescore_r = max(rescore_r, self.fif_k)
         qs = sorted({q for q in (1, 4, 16, max_queries) if q <= max_queries})
         self.classes = [(q, q * max_m) for q in qs]
-        self.ws_bytes = [L.fif_plan_workspace(db, fif, q, v, self.fif_k, self.rescore_r)
+        t = L.plan_tuning(**self.tuning)
+        self.ws_bytes = [L.fif_plan_workspace(db, fif, q, v, self.fif_k, self.rescore_r, t)
                          for q, v in self.classes]
         self.slot_bytes = [(w + 255) // 256 * 256 + v * db.dim * 4
                            for w, (q, v) in zip(self.ws_bytes, self.classes)]
