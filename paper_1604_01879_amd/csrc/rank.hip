@@ -343,24 +343,28 @@ __device__ __forceinline__ unsigned long long allowed_views(const int32_t* vw, i
   return a;
 }
 
-// Candidate rescore, phase 1, query-major (rescore_mask_kernel): one block
-// (four waves) per (query, 4 consecutive candidates), blocks in
-// XCD-contiguous order, so the query's rows are staged once for four
-// candidates and the blocks sharing an XCD share the query.  Approximate
-// dot products of each candidate's views (rows, 64) with up to 64 query
-// views (columns) on MFMA; wave w owns candidate w, as 2 x 2 blocks of
-// 32 x 32.  Each float32 value is split as hi + lo + r (hi, lo bfloat16,
-// |r| <= 2^-16 |x|) and the dot is hi.hi' + hi.lo' + lo.hi' on BF16 MFMA
-// (products exact in float32), missing at most about 3 * 2^-16 sum |x y|.
-// Each 32-value K-tile is accumulated into a fresh register block and added
-// into a running total, which bounds the float32 accumulation depth; dot_err
-// bounds both.  For query view i of chunk `it` (views q0 + 64 it + i) the
-// kernel writes the mask of views within 2 dot_err of the approximate
-// maximum (bit j of mask[c][q0 + 64 it + i], candidate slot c) and the
-// chunk's sum of approximate maxima s1[c][q0 + 64 it].
+// Candidate rescore, phase 1 (rescore_mask_kernel): one block (four waves)
+// per (query, 4 consecutive candidates), blocks in XCD-contiguous order, so
+// the query's rows are staged once for four candidates and the blocks
+// sharing an XCD share the query.  Approximate dot products of each
+// candidate's views (rows) with up to 64 query views (columns) on MFMA;
+// wave w owns candidate w, as 2 x 2 blocks of 32 x 32.  Each float32 value
+// is split as hi + lo + r (hi, lo bfloat16, |r| <= 2^-16 |x|) and the dot is
+// hi.hi' + hi.lo' + lo.hi' on BF16 MFMA (products exact in float32), missing
+// at most about 3 * 2^-16 sum |x y|.  Each 32-value K-tile is accumulated
+// into a fresh register block and added into a running total, which bounds
+// the float32 accumulation depth; dot_err bounds both.  For query view i of
+// chunk `it` (views q0 + 64 it + i) the kernel writes the mask of views
+// within 2 dot_err of the approximate maximum (bit j of mask[c][q0 + 64 it +
+// i], candidate slot c) and the chunk's sum of approximate maxima
+// s1[c][q0 + 64 it].
 // With `qwords` set (Eq. 4), the pair (q_i, p_j) takes part only when the
 // word of q_i is one of the `ma` words of p_j; a query view with no such
-// pair gets an empty mask and a maximum of 0.
+// pair gets an empty mask and a maximum of 0.  Only the candidate views that
+// share a word with some view of the chunk are staged, compacted (staged row
+// r of candidate k is its view cu[k][r], r < nu[k]); the second block of 32
+// rows is skipped when at most 32 remain.  Most Eq. 4 candidates match a
+// query through a few views, so their rows are read for those views only.
 __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
@@ -370,6 +374,9 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     float* __restrict__ s1, int64_t ld) {
   __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
   __shared__ int32_t vw[RS_CANDS][64 * 8];
+  __shared__ int32_t qw_chunk[64];
+  __shared__ int8_t cu[RS_CANDS][64];
+  __shared__ int nu_sh[RS_CANDS];
 
   const int groups = (r + RS_CANDS - 1) / RS_CANDS;
   const int64_t n_items = (int64_t)(active != nullptr ? *active : n_queries) * groups;
@@ -381,6 +388,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const bool mine = wave < n_cand;  // this wave's candidate exists
+  const bool eq4 = qwords != nullptr;
   const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int row_bytes = dim * 4;
   const int64_t shape_bytes = (int64_t)n_views * row_bytes;
@@ -392,7 +400,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
   for (int k = 0; k < RS_CANDS; ++k) shape[k] = cand[(int64_t)b * r + c0 + min(k, n_cand - 1)];
   const int cslot = c0 + (mine ? wave : 0);
 
-  if (qwords != nullptr)
+  if (eq4)
 #pragma unroll
     for (int k = 0; k < RS_CANDS; ++k)
       for (int x = tid; x < n_views * ma; x += RS_THREADS)
@@ -400,8 +408,8 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
 
   // staging: thread t copies bytes [16 (t & 7), 16 (t & 7) + 16) of each
   // 128-byte K-tile of staged rows (t >> 3) + 32 p, p < RS_PIECES: rows
-  // 64 k + i of candidate k, then 64 RS_CANDS + i of the query chunk,
-  // addressed as 32-bit offsets from the row group's base
+  // 64 k + r of candidate k (its view cu[k][r]), then 64 RS_CANDS + i of the
+  // query chunk, addressed as 32-bit offsets from the row group's base
   uint32_t roff[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -409,19 +417,41 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
   gptr<uint8_t> gb[RS_CANDS + 1];
 #pragma unroll
   for (int k = 0; k < RS_CANDS; ++k) gb[k] = uniform_gptr(master_b + shape[k] * shape_bytes);
-  __syncthreads();
 
   for (int it = 0; it * 64 < m; ++it) {
     const int mi = min(64, m - it * 64);
+    __syncthreads();  // the previous chunk's epilogue is done with the tables
+    if (eq4 && tid < 64) qw_chunk[tid] = tid < mi ? qwords[q0 + it * 64 + tid] : -1;
+    __syncthreads();
+    {
+      // wave k lists candidate k's views that may pair with this chunk
+      // (lane j: view j) in ascending order
+      bool use = lane < n_views;
+      if (use && eq4) {
+        bool hit = false;
+        for (int a2 = 0; a2 < ma && !hit; ++a2) {
+          const int wj = vw[wave][lane * ma + a2];
+          for (int i = 0; i < mi; ++i)
+            if (qw_chunk[i] == wj) { hit = true; break; }
+        }
+        use = hit;
+      }
+      const unsigned long long U = __ballot(use);
+      if (use) cu[wave][__popcll(U & ((1ull << lane) - 1ull))] = (int8_t)lane;
+      if (lane == 0) nu_sh[wave] = __popcll(U);
+    }
+    __syncthreads();
     const float* qbase = qviews + (int64_t)(q0 + it * 64) * dim;
     gb[RS_CANDS] = uniform_gptr(reinterpret_cast<const uint8_t*>(qbase));
     unsigned valid = 0u;  // bit p: piece p lies in a present row
 #pragma unroll
     for (int p = 0; p < RS_PIECES; ++p) {
       const int g = p >> 1, row = (tid >> 3) + 32 * (p & 1);
-      const bool ok = g < RS_CANDS ? (g < n_cand && row < n_views) : row < mi;
+      const bool ok = g < RS_CANDS ? (g < n_cand && row < nu_sh[g]) : row < mi;
       valid |= (ok ? 1u : 0u) << p;
     }
+    const int nu = nu_sh[wave];
+    const bool two = nu > 32;  // the wave's second block of 32 rows has rows
     f32x16 tot[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -436,9 +466,14 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     uint4 pre[RS_PIECES];
     auto gload = [&](int k0) {
 #pragma unroll
-      for (int p = 0; p < RS_PIECES; ++p)
-        pre[p] = (valid >> p) & 1u ? load_at<uint4>(gb[p >> 1], roff[p & 1] + (uint32_t)k0)
+      for (int p = 0; p < RS_PIECES; ++p) {
+        const int g = p >> 1, row = (tid >> 3) + 32 * (p & 1);
+        uint32_t off = roff[p & 1];
+        if (g < RS_CANDS)
+          off = (uint32_t)cu[g][row & 63] * (uint32_t)row_bytes + (uint32_t)(tid & 7) * 16u;
+        pre[p] = (valid >> p) & 1u ? load_at<uint4>(gb[g], off + (uint32_t)k0)
                                    : make_uint4(0, 0, 0, 0);
+      }
     };
     gload(0);
     for (int k0 = 0; k0 < row_bytes; k0 += 128) {
@@ -463,6 +498,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
+          if (bi == 1 && !two) continue;  // rows 32..63 hold no view
           uint4 ah[2], al[2];
 #pragma unroll
           for (int st = 0; st < 2; ++st) {
@@ -491,11 +527,26 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     for (int cj = 0; cj < 2; ++cj) {
       const int i = cj * 32 + l32;
       const bool live = mine && i < mi;
-      const unsigned long long allowed = allowed_views(
-          vw[wave], n_views, ma, qwords != nullptr, live && qwords ? qwords[q0 + it * 64 + i] : -1);
+      unsigned long long allowed =
+          allowed_views(vw[wave], n_views, ma, eq4, live && eq4 ? qw_chunk[i] : -1);
+      if (eq4) {
+        // over the staged rows: row q allowed when its view cu[wave][q] is
+        unsigned long long ac = 0ull;
+        for (int q = 0; q < nu; ++q) ac |= ((allowed >> cu[wave][q]) & 1ull) << q;
+        allowed = live ? ac : 0ull;
+      }
       unsigned long long bits;
-      const float mx = view_max_mask(tot, cj, live || qwords == nullptr ? allowed : 0ull, dot_err,
-                                     bits);
+      const float mx = view_max_mask(tot, cj, allowed, dot_err, bits);
+      if (eq4) {
+        // staged rows back to views
+        unsigned long long vb = 0ull;
+        while (bits) {
+          const int q = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          vb |= 1ull << cu[wave][q];
+        }
+        bits = vb;
+      }
       if (half == 0 && live) mask[(int64_t)cslot * ld + q0 + it * 64 + i] = bits;
       float v = (half == 0 && i < mi && mx != -INFINITY) ? mx : 0.f;
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
