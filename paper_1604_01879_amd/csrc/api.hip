@@ -484,7 +484,8 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), nullptr,
-                 nullptr, 0, nullptr, w.rs, w.s_hi, w.s_lo, st);
+                 nullptr, 0, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim), w.rs, w.s_hi,
+                 w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
@@ -713,7 +714,8 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), w.qwords,
-                 fif->view_words, fif->ma, nullptr, w.rs, w.s_hi, w.s_lo, st);
+                 fif->view_words, fif->ma, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim),
+                 w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);

@@ -36,9 +36,11 @@ size_t select_top_ws(int64_t n, int n_queries, int r);
 void launch_select_top(const float* S, int64_t n, int n_queries, int r, const int32_t* active,
                        int32_t* out_id, float* out_s, void* tmp, hipStream_t st);
 
-// Exact rescore of candidates: split-BF16 dot products with a known error
-// bound give each view's candidate maxima and an approximate score; the
-// candidates that can still reach the top_k get a compensated
+// Exact rescore of candidates: candidates whose first-pass score (first_s
+// [queries][r], sorted desc) plus the first-pass bound first_err cannot
+// reach the top_k are dropped first; then split-BF16 dot products with a
+// known error bound give each view's candidate maxima and an approximate
+// score; the candidates that can still reach the top_k get a compensated
 // re-evaluation of every view pair that the bound cannot exclude as the
 // maximum, and their float-float score; the others score -inf.
 // With qwords != nullptr only pairs whose words match take part (Eq. 4).
@@ -62,8 +64,8 @@ void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
-                    hipStream_t st);
+                    const int32_t* active, const float* first_s, double first_err,
+                    RescoreScratch sc, float* s_hi, float* s_lo, hipStream_t st);
 
 // Orders the r rescored candidates of each query by (exact score desc,
 // id asc) and writes the top k; sets flags bit 0 when provably complete:

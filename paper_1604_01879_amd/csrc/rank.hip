@@ -298,6 +298,24 @@ constexpr int RS_THREADS = 64 * RS_CANDS;
 constexpr int RS_ROWS = 64 * (RS_CANDS + 1);        // staged rows: candidate views, then query views
 constexpr int RS_PIECES = RS_ROWS * 8 / RS_THREADS;  // 16-byte pieces per thread per K-tile
 
+// First-pass pruning.  Candidates come sorted by first-pass score (desc),
+// and each first-pass score is within e_b = (first_err + gamma_(m_b + 2)) *
+// 1.001 of the exact score (first_err: the storage bound for unit-norm
+// views, the same bound the completeness flag uses).  The k best candidates
+// all score at least T = first[k - 1] - e_b exactly, so a candidate with
+// first + e_b below T (less a relative 2.4e-7, which absorbs the float
+// rounding here and the rescore's own error) cannot be in the top k: it is
+// neither staged nor rescored and is ranked last.  Sorted order makes the
+// surviving candidates a prefix.  Storage with a loose bound (e4m3, MX)
+// prunes nothing.
+__device__ __forceinline__ bool first_pass_live(const float* first_row, int c, int k, int m,
+                                                float first_err) {
+  const float nm = (float)(m + 2) * 5.96046448e-08f;
+  const float eb = (first_err + nm / (1.f - nm)) * 1.001f;
+  const float T = first_row[k - 1] - eb;
+  return first_row[c] + eb >= T - fabsf(T) * 2.4e-7f;
+}
+
 // Approximate maximum and near-maximum mask of one query view (this lane's
 // column i of block cj) from a wave's 64 x 64 dot tile acc[bi][cj]
 // (candidate views in rows, query views in columns): the maximum over the
@@ -370,8 +388,8 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     int n_queries, const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
-    const int32_t* __restrict__ active, unsigned long long* __restrict__ mask,
-    float* __restrict__ s1, int64_t ld) {
+    const int32_t* __restrict__ active, const float* __restrict__ first_s, float first_err,
+    int top_k, unsigned long long* __restrict__ mask, float* __restrict__ s1, int64_t ld) {
   __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
   __shared__ int32_t vw[RS_CANDS][64 * 8];
   __shared__ int32_t qw_chunk[64];
@@ -384,12 +402,16 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
   if (item >= n_items) return;  // past the batch
   const int b = (int)(item / groups);
   const int c0 = (int)(item % groups) * RS_CANDS;
-  const int n_cand = min(RS_CANDS, r - c0);
+  const int q0 = qoff[b], m = qoff[b + 1] - q0;
+  // the block's candidates that survive first-pass pruning (a prefix)
+  int n_cand = 0;
+  for (int k = 0; k < min(RS_CANDS, r - c0); ++k)
+    n_cand += first_pass_live(first_s + (int64_t)b * r, c0 + k, top_k, m, first_err) ? 1 : 0;
+  if (n_cand == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const bool mine = wave < n_cand;  // this wave's candidate exists
   const bool eq4 = qwords != nullptr;
-  const int q0 = qoff[b], m = qoff[b + 1] - q0;
   const int row_bytes = dim * 4;
   const int64_t shape_bytes = (int64_t)n_views * row_bytes;
   const uint8_t* master_b = reinterpret_cast<const uint8_t*>(master);
@@ -566,7 +588,8 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
 // exact evaluation.
 __global__ __launch_bounds__(256) void rescore_mark_kernel(
     const float* __restrict__ s1c, int64_t ld, const int32_t* __restrict__ qoff, int r, int k,
-    float dot_err, const int32_t* __restrict__ active, uint8_t* __restrict__ mark) {
+    float dot_err, const int32_t* __restrict__ active, const float* __restrict__ first_s,
+    float first_err, uint8_t* __restrict__ mark) {
   __shared__ float lb[MAX_R], sv[MAX_R];
   const int b = blockIdx.x;
   if (active != nullptr && b >= *active) return;
@@ -578,9 +601,12 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
   for (int i = threadIdx.x; i < np2; i += 256) {
     float v = -INFINITY;
     if (i < r) {
-      float acc = 0.f;
-      for (int it = 0; it * 64 < m; ++it) acc += s1c[(int64_t)i * ld + q0 + it * 64];
-      v = m > 0 ? acc / (float)m : 0.f;
+      // a pruned candidate has no approximate score and is never marked
+      if (first_pass_live(first_s + base, i, k, m, first_err)) {
+        float acc = 0.f;
+        for (int it = 0; it * 64 < m; ++it) acc += s1c[(int64_t)i * ld + q0 + it * 64];
+        v = m > 0 ? acc / (float)m : 0.f;
+      }
       sv[i] = v;
     }
     lb[i] = i < r ? v - delta : -INFINITY;
@@ -601,7 +627,8 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
     }
   }
   const float T = lb[k - 1];
-  for (int i = threadIdx.x; i < r; i += 256) mark[base + i] = sv[i] + delta >= T ? 1 : 0;
+  for (int i = threadIdx.x; i < r; i += 256)
+    mark[base + i] = sv[i] != -INFINITY && sv[i] + delta >= T ? 1 : 0;
 }
 
 // Candidate rescore, phases 2 and 3 (rescore_exact_kernel): one block (four
@@ -692,16 +719,20 @@ void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
                     const int32_t* qwords, const int32_t* view_words, int ma,
-                    const int32_t* active, RescoreScratch sc, float* s_hi, float* s_lo,
-                    hipStream_t st) {
+                    const int32_t* active, const float* first_s, double first_err,
+                    RescoreScratch sc, float* s_hi, float* s_lo, hipStream_t st) {
   const int64_t items = (int64_t)n_queries * ((r + RS_CANDS - 1) / RS_CANDS);
   if (items <= 0) return;
+  // the storage bound as a float no smaller than it
+  float fe = (float)first_err;
+  if ((double)fe < first_err) fe = nextafterf(fe, INFINITY);
   // grids cover every slot of the XCD-contiguous order
   hipLaunchKernelGGL(rescore_mask_kernel, dim3((unsigned)((items + 7) / 8 * 8)), dim3(RS_THREADS),
                      0, st, master, n_views, dim, qviews, qoff, n_queries, cand, r,
-                     dot_err, qwords, view_words, ma, active, sc.mask, sc.s1, ld);
+                     dot_err, qwords, view_words, ma, active, first_s, fe, top_k, sc.mask, sc.s1,
+                     ld);
   hipLaunchKernelGGL(rescore_mark_kernel, dim3((unsigned)n_queries), dim3(256), 0, st, sc.s1, ld,
-                     qoff, r, top_k, dot_err, active, sc.mark);
+                     qoff, r, top_k, dot_err, active, first_s, fe, sc.mark);
   const int64_t pairs = (int64_t)n_queries * r;
   hipLaunchKernelGGL(rescore_exact_kernel, dim3((unsigned)((pairs + 7) / 8 * 8)), dim3(256), 0, st,
                      master, n_views, dim, qviews, qoff, n_queries, cand, r, sc.mask, ld,
