@@ -167,11 +167,11 @@ __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ cb
 }
 
 // ------------------------------------------------------------------ select
-// One wave per row.  d^_k = ||b_k||^2 - 2 D[k] in float32 with a per-k
-// bound e_k; U = the ma-th smallest d^_k + e_k bounds the true ma-th
-// smallest distance from above, so every k with d^_k - e_k <= U may belong
-// to the exact top-ma.  Those candidates are re-evaluated with compensated
-// arithmetic and the ma smallest (distance, index) are written.
+// d^_k = ||b_k||^2 - 2 D[k] in float32 with a per-k bound e_k; U = the
+// ma-th smallest d^_k + e_k bounds the true ma-th smallest distance from
+// above, so every k with d^_k - e_k <= U may belong to the exact top-ma.
+// Those candidates are re-evaluated with compensated arithmetic and the ma
+// smallest (distance, index) are written.
 constexpr int SEL_CAP = 256;   // candidates kept per row
 constexpr int MAX_MA = 8;
 constexpr int SEL_UNROLL = 16;  // codewords per lane with loads in flight together
@@ -182,24 +182,48 @@ __device__ inline bool dk_less(float ah, float al, int ak, float bh, float bl, i
   return ak < bk;
 }
 
-constexpr size_t SEL_LDS = 4 * SEL_CAP * 12;
+// d^_k and its bound e_k from the float32 dot dv and ||b_k||^2 (hi part) nv.
+__device__ __forceinline__ void sel_bounds(float dv, float nv, float c1, float c2, float& dk,
+                                           float& ek) {
+  dk = nv - 2.f * dv;
+  ek = c1 * sqrtf(fmaxf(nv, 0.f)) + c2 * (fabsf(dk) + 1.f);
+}
 
-// Rows r0 + 4*blk .. +3 (one wave each) of the chunk [r0, r1); D holds the
-// chunk's dots.  With `counts` set (ma == 1), the chosen word's counter is
-// incremented.
+// LDS of a selection item: per wave its candidates (index, lower bound,
+// compensated distance) and its ma smallest upper bounds and count, and a
+// block-wide candidate list for rows split over the four waves.
+struct SelLds {
+  int wk[4][SEL_CAP];
+  float wlb[4][SEL_CAP];
+  float chi[4][SEL_CAP], clo[4][SEL_CAP];
+  int cand[SEL_CAP];
+  float wub[4][MAX_MA];
+  int wn[4];
+};
+constexpr size_t SEL_LDS = sizeof(SelLds);
+
+// Certified ma nearest codewords of rows of the chunk [r0, r1); D holds the
+// chunk's dots.  SPLIT: one row per block (row r0 + blk), wave w scanning the
+// codewords [w kq, (w + 1) kq) (kq = K / 4 rounded up to 64), so the passes
+// over D are a quarter as long and the candidates' compensated dots run four
+// at a time.  Otherwise one row per wave (rows r0 + 4 blk + w; an idle wave
+// past the last row redoes it and writes nothing).  With `counts` set
+// (ma == 1), the chosen word's counter is incremented.  The word is stored,
+// and counted, through device-scope atomics.
+template <bool SPLIT>
 __device__ __forceinline__ void select_rows(const float* __restrict__ x, int64_t r0, int64_t r1,
-                            const float* __restrict__ cb, int K, int dim, int ma,
-                            const float* __restrict__ D, const float* __restrict__ nhi,
-                            const float* __restrict__ nlo, float gamma2,
-                            int32_t* __restrict__ words, int32_t* __restrict__ overflow,
-                            int32_t* __restrict__ counts, int64_t blk, uint8_t* smem) {
-  int (*cand)[SEL_CAP] = reinterpret_cast<int (*)[SEL_CAP]>(smem);
-  float (*chi)[SEL_CAP] = reinterpret_cast<float (*)[SEL_CAP]>(smem + 4 * SEL_CAP * 4);
-  float (*clo)[SEL_CAP] = reinterpret_cast<float (*)[SEL_CAP]>(smem + 8 * SEL_CAP * 4);
+                                            const float* __restrict__ cb, int K, int dim, int ma,
+                                            const float* __restrict__ D,
+                                            const float* __restrict__ nhi,
+                                            const float* __restrict__ nlo, float gamma2,
+                                            int32_t* __restrict__ words,
+                                            int32_t* __restrict__ overflow,
+                                            int32_t* __restrict__ counts, int64_t blk,
+                                            uint8_t* smem) {
+  SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r_raw = r0 + blk * 4 + wave;
-  // an idle wave (past the last row) redoes the last row and writes nothing,
-  // so every wave reaches the block barrier below
+  const int64_t r_raw = SPLIT ? r0 + blk : r0 + blk * 4 + wave;
+  if (SPLIT && r_raw >= r1) return;  // block-uniform
   const bool active = r_raw < r1;
   const int64_t r = active ? r_raw : r1 - 1;
   const float* xr = x + r * dim;
@@ -226,85 +250,191 @@ __device__ __forceinline__ void select_rows(const float* __restrict__ x, int64_t
   const float xn = sqrtf(ss) * 1.001f + 1e-30f;
   const float c1 = gamma2 * xn;
   const float c2 = 2.4e-7f;  // a few float32 roundings of d^_k itself
+  const int kq = SPLIT ? ((K + 3) / 4 + 63) / 64 * 64 : K;
+  const int kb = SPLIT ? min(K, wave * kq) : 0, ke = SPLIT ? min(K, kb + kq) : K;
 
-  // lane-local ma smallest upper bounds; SEL_UNROLL codewords per lane are
-  // loaded before any is used, so their loads overlap
-  float best[MAX_MA];
+  // This wave's candidates so far (n_w, the first SEL_CAP kept).
+  int n_w = 0;
+  bool rescan = true;  // collect this wave's candidates in a second pass
+  if (ma == 1) {
+    // One pass.  The running U (smallest upper bound so far, over whole
+    // blocks of 64 SEL_UNROLL codewords) never falls below the final U, so
+    // every final candidate passes the test against it and is kept, in
+    // ascending k, with its lower bound; the final U filters them below.
+    float Uw = INFINITY;
+    for (int k0 = kb; k0 < ke; k0 += 64 * SEL_UNROLL) {
+      float dv[SEL_UNROLL], nv[SEL_UNROLL], lb[SEL_UNROLL];
 #pragma unroll
-  for (int a = 0; a < MAX_MA; ++a) best[a] = INFINITY;
-  for (int k0 = lane; k0 < K; k0 += 64 * SEL_UNROLL) {
-    float dv[SEL_UNROLL], nv[SEL_UNROLL];
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        const int k = k0 + 64 * t + lane;
+        dv[t] = k < ke ? Dr[k] : 0.f;
+        nv[t] = k < ke ? nhi[k] : 0.f;
+      }
+      float umin = INFINITY;
 #pragma unroll
-    for (int t = 0; t < SEL_UNROLL; ++t) {
-      const int k = k0 + 64 * t;
-      dv[t] = k < K ? Dr[k] : 0.f;
-      nv[t] = k < K ? nhi[k] : 0.f;
-    }
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        lb[t] = INFINITY;
+        if (k0 + 64 * t + lane < ke) {
+          float dk, ek;
+          sel_bounds(dv[t], nv[t], c1, c2, dk, ek);
+          umin = fminf(umin, dk + ek);
+          lb[t] = dk - ek;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) umin = fminf(umin, __shfl_xor(umin, o, 64));
+      Uw = fminf(Uw, umin);
 #pragma unroll
-    for (int t = 0; t < SEL_UNROLL; ++t) {
-      if (k0 + 64 * t >= K) continue;
-      const float dk = nv[t] - 2.f * dv[t];
-      const float ek = c1 * sqrtf(fmaxf(nv[t], 0.f)) + c2 * (fabsf(dk) + 1.f);
-      float u = dk + ek;
-#pragma unroll
-      for (int a = 0; a < MAX_MA; ++a) {
-        if (a < ma && u < best[a]) { const float tt = best[a]; best[a] = u; u = tt; }
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        const bool f = lb[t] <= Uw;
+        const unsigned long long bal = __ballot(f);
+        const int pos = n_w + __popcll(bal & ((1ull << lane) - 1ull));
+        if (f && pos < SEL_CAP) {
+          L.wk[wave][pos] = k0 + 64 * t + lane;
+          L.wlb[wave][pos] = lb[t];
+        }
+        n_w += __popcll(bal);
       }
     }
+    if (lane == 0) L.wub[wave][0] = Uw;
+    rescan = n_w > SEL_CAP;
+  } else {
+    // lane-local ma smallest upper bounds; SEL_UNROLL codewords per lane are
+    // loaded before any is used, so their loads overlap
+    float best[MAX_MA];
+#pragma unroll
+    for (int a = 0; a < MAX_MA; ++a) best[a] = INFINITY;
+    for (int k0 = kb + lane; k0 < ke; k0 += 64 * SEL_UNROLL) {
+      float dv[SEL_UNROLL], nv[SEL_UNROLL];
+#pragma unroll
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        const int k = k0 + 64 * t;
+        dv[t] = k < ke ? Dr[k] : 0.f;
+        nv[t] = k < ke ? nhi[k] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        if (k0 + 64 * t >= ke) continue;
+        float dk, ek;
+        sel_bounds(dv[t], nv[t], c1, c2, dk, ek);
+        float u = dk + ek;
+#pragma unroll
+        for (int a = 0; a < MAX_MA; ++a) {
+          if (a < ma && u < best[a]) { const float tt = best[a]; best[a] = u; u = tt; }
+        }
+      }
+    }
+    // the wave's ma smallest upper bounds, ascending
+    int head = 0;
+    for (int a = 0; a < ma; ++a) {
+      float v = INFINITY;
+#pragma unroll
+      for (int q = 0; q < MAX_MA; ++q)
+        if (q == head) v = best[q];
+      float m = v;
+      int who = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const float om = __shfl_xor(m, o, 64);
+        const int ow = __shfl_xor(who, o, 64);
+        if (om < m || (om == m && ow < who)) { m = om; who = ow; }
+      }
+      if (lane == 0) L.wub[wave][a] = m;
+      if (lane == who) ++head;
+    }
   }
-  // wave-wide ma-th smallest of the upper bounds
+  __syncthreads();
+  // U: the ma-th smallest of the (four waves') ascending lists
   float U = INFINITY;
-  int head = 0;
-  for (int a = 0; a < ma; ++a) {
-    float v = head < ma ? best[0] : INFINITY;
+  {
+    int h[4] = {0, 0, 0, 0};
+    for (int a = 0; a < ma; ++a) {
+      int bw = 0;
+      float bv = INFINITY;
 #pragma unroll
-    for (int q = 0; q < MAX_MA; ++q)
-      if (q == head) v = best[q];
-    float m = v;
-    int who = lane;
-    for (int o = 32; o > 0; o >>= 1) {
-      const float om = __shfl_xor(m, o, 64);
-      const int ow = __shfl_xor(who, o, 64);
-      if (om < m || (om == m && ow < who)) { m = om; who = ow; }
-    }
-    U = m;
-    if (lane == who) ++head;
-  }
-  // candidates: d^_k - e_k <= U, in ascending k
-  int n_c = 0;
-  for (int kb = 0; kb < K; kb += 64 * SEL_UNROLL) {
-    float dv[SEL_UNROLL], nv[SEL_UNROLL];
-#pragma unroll
-    for (int t = 0; t < SEL_UNROLL; ++t) {
-      const int k = kb + 64 * t + lane;
-      dv[t] = k < K ? Dr[k] : 0.f;
-      nv[t] = k < K ? nhi[k] : 0.f;
-    }
-#pragma unroll
-    for (int t = 0; t < SEL_UNROLL; ++t) {
-      const int k = kb + 64 * t + lane;
-      bool f = false;
-      if (k < K) {
-        const float dk = nv[t] - 2.f * dv[t];
-        const float ek = c1 * sqrtf(fmaxf(nv[t], 0.f)) + c2 * (fabsf(dk) + 1.f);
-        f = dk - ek <= U;
+      for (int w = 0; w < 4; ++w) {
+        const bool mine = SPLIT || w == wave;
+        const float v = mine && h[w] < ma ? L.wub[w][h[w]] : INFINITY;
+        if (v < bv) { bv = v; bw = w; }
       }
-      const unsigned long long bal = __ballot(f);
-      const int pos = n_c + __popcll(bal & ((1ull << lane) - 1ull));
-      if (f && pos < SEL_CAP) cand[wave][pos] = k;
-      n_c += __popcll(bal);
+      U = bv;
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        if (w == bw) ++h[w];
     }
+  }
+  if (!rescan) {
+    // keep this wave's candidates within U, in order (each chunk of 64 is
+    // read before any of it is overwritten, and entries only move down)
+    int kept = 0;
+    for (int q = 0; q * 64 < n_w; ++q) {
+      const int c = q * 64 + lane;
+      const bool in = c < n_w;
+      const int kc = in ? L.wk[wave][c] : 0;
+      const bool f = in && L.wlb[wave][c] <= U;
+      const unsigned long long bal = __ballot(f);
+      if (f) L.wk[wave][kept + __popcll(bal & ((1ull << lane) - 1ull))] = kc;
+      kept += __popcll(bal);
+    }
+    n_w = kept;
+  } else {
+    // this wave's candidates: d^_k - e_k <= U, in ascending k
+    n_w = 0;
+    for (int k0 = kb; k0 < ke; k0 += 64 * SEL_UNROLL) {
+      float dv[SEL_UNROLL], nv[SEL_UNROLL];
+#pragma unroll
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        const int k = k0 + 64 * t + lane;
+        dv[t] = k < ke ? Dr[k] : 0.f;
+        nv[t] = k < ke ? nhi[k] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < SEL_UNROLL; ++t) {
+        const int k = k0 + 64 * t + lane;
+        bool f = false;
+        if (k < ke) {
+          float dk, ek;
+          sel_bounds(dv[t], nv[t], c1, c2, dk, ek);
+          f = dk - ek <= U;
+        }
+        const unsigned long long bal = __ballot(f);
+        const int pos = n_w + __popcll(bal & ((1ull << lane) - 1ull));
+        if (f && pos < SEL_CAP) L.wk[wave][pos] = k;
+        n_w += __popcll(bal);
+      }
+    }
+  }
+  // the candidate list: the waves' lists in wave order (ascending k) when
+  // the row is split, else the wave's own; the first SEL_CAP kept
+  int n_c = n_w;
+  const int* cand = L.wk[wave];
+  float* chi = L.chi[wave];
+  float* clo = L.clo[wave];
+  if (SPLIT) {
+    if (lane == 0) L.wn[wave] = n_w;
+    __syncthreads();
+    int before = 0;
+    n_c = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) before += L.wn[w];
+      n_c += L.wn[w];
+    }
+    for (int c = lane; c < min(n_w, SEL_CAP); c += 64)
+      if (before + c < SEL_CAP) L.cand[before + c] = L.wk[wave][c];
+    cand = L.cand;
+    chi = L.chi[0];
+    clo = L.clo[0];
   }
   if (n_c > SEL_CAP) {
-    if (lane == 0 && active) atomicAdd(overflow, 1);
+    if ((SPLIT ? threadIdx.x == 0 : lane == 0) && active) atomicAdd(overflow, 1);
     n_c = SEL_CAP;
   }
-  // compensated distances of the candidates, 8 float4 pieces of each row
-  // in flight per lane
-  for (int c = 0; c < n_c; ++c) {
-    const int k = cand[wave][c];
+  if (SPLIT) __syncthreads();
+  // compensated distances of the candidates (split rows: wave w takes
+  // candidates w, w + 4, ...), 8 float4 pieces of each row in flight per lane
+  for (int c = SPLIT ? wave : 0; c < n_c; c += SPLIT ? 4 : 1) {
+    const int k = cand[c];
     const float4* b4 = reinterpret_cast<const float4*>(cb + (int64_t)k * dim);
-    float s = 0.f, cc = 0.f;
+    float sd = 0.f, cc = 0.f;
     for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
       float4 xa[8], ba[8];
 #pragma unroll
@@ -315,48 +445,54 @@ __device__ __forceinline__ void select_rows(const float* __restrict__ x, int64_t
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        dot2_step(xa[q].x, ba[q].x, s, cc);
-        dot2_step(xa[q].y, ba[q].y, s, cc);
-        dot2_step(xa[q].z, ba[q].z, s, cc);
-        dot2_step(xa[q].w, ba[q].w, s, cc);
+        dot2_step(xa[q].x, ba[q].x, sd, cc);
+        dot2_step(xa[q].y, ba[q].y, sd, cc);
+        dot2_step(xa[q].z, ba[q].z, sd, cc);
+        dot2_step(xa[q].w, ba[q].w, sd, cc);
       }
     }
-    const ff dot = ff_wave_sum(s, cc);
+    const ff dot = ff_wave_sum(sd, cc);
     const ff d = ff_add(ff{nhi[k], nlo[k]}, ff{-2.f * dot.hi, -2.f * dot.lo});
-    if (lane == 0) { chi[wave][c] = d.hi; clo[wave][c] = d.lo; }
+    if (lane == 0) { chi[c] = d.hi; clo[c] = d.lo; }
   }
   __syncthreads();
-  // the ma smallest by (distance, index)
-  bool used[SEL_CAP / 64];
+  // the ma smallest by (distance, index): wave 0 for a split row, else each
+  // wave for its own
+  if (!SPLIT || wave == 0) {
+    bool used[SEL_CAP / 64];
 #pragma unroll
-  for (int q = 0; q < SEL_CAP / 64; ++q) used[q] = false;
-  for (int a = 0; a < ma; ++a) {
-    float bh = INFINITY, bl = INFINITY;
-    int bk = 0x7fffffff, bq = -1;
+    for (int q = 0; q < SEL_CAP / 64; ++q) used[q] = false;
+    for (int a = 0; a < ma; ++a) {
+      float bh = INFINITY, bl = INFINITY;
+      int bk = 0x7fffffff, bq = -1;
 #pragma unroll
-    for (int q = 0; q < SEL_CAP / 64; ++q) {
-      const int c = q * 64 + lane;
-      if (c < n_c && !used[q]) {
-        const int k = cand[wave][c];
-        if (dk_less(chi[wave][c], clo[wave][c], k, bh, bl, bk)) {
-          bh = chi[wave][c]; bl = clo[wave][c]; bk = k; bq = q;
+      for (int q = 0; q < SEL_CAP / 64; ++q) {
+        const int c = q * 64 + lane;
+        if (c < n_c && !used[q]) {
+          const int k = cand[c];
+          if (dk_less(chi[c], clo[c], k, bh, bl, bk)) {
+            bh = chi[c]; bl = clo[c]; bk = k; bq = q;
+          }
         }
       }
-    }
-    int who = lane;
-    for (int o = 32; o > 0; o >>= 1) {
-      const float oh = __shfl_xor(bh, o, 64), ol = __shfl_xor(bl, o, 64);
-      const int ok = __shfl_xor(bk, o, 64), ow = __shfl_xor(who, o, 64);
-      if (dk_less(oh, ol, ok, bh, bl, bk)) { bh = oh; bl = ol; bk = ok; who = ow; }
-    }
-    if (lane == who && bq >= 0) {
+      int who = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const float oh = __shfl_xor(bh, o, 64), ol = __shfl_xor(bl, o, 64);
+        const int ok = __shfl_xor(bk, o, 64), ow = __shfl_xor(who, o, 64);
+        if (dk_less(oh, ol, ok, bh, bl, bk)) { bh = oh; bl = ol; bk = ok; who = ow; }
+      }
+      if (lane == who && bq >= 0) {
 #pragma unroll
-      for (int q = 0; q < SEL_CAP / 64; ++q)
-        if (q == bq) used[q] = true;
-    }
-    if (lane == 0 && active) {
-      words[r * ma + a] = bk < K ? bk : -1;
-      if (counts != nullptr && bk < K) atomicAdd(&counts[bk], 1);
+        for (int q = 0; q < SEL_CAP / 64; ++q)
+          if (q == bq) used[q] = true;
+      }
+      if (lane == 0 && active) {
+        // performed where every XCD sees it, like the count: a batch item
+        // then needs no release fence, only the wait for its own stores
+        __hip_atomic_store(&words[r * ma + a], bk < K ? bk : -1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (counts != nullptr && bk < K) atomicAdd(&counts[bk], 1);
+      }
     }
   }
   __syncthreads();  // LDS is reused by the next item
@@ -368,8 +504,8 @@ __global__ __launch_bounds__(256) void assign_select_kernel(
     const float* __restrict__ nlo, float gamma2, int32_t* __restrict__ words,
     int32_t* __restrict__ overflow) {
   __shared__ __align__(16) uint8_t smem[SEL_LDS];
-  select_rows(x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow, nullptr,
-              blockIdx.x, smem);
+  select_rows<true>(x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow, nullptr,
+                    blockIdx.x, smem);
 }
 
 gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, int K, int ma,
@@ -396,7 +532,7 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
     hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st, xs,
                        r0, r1, cbs, K, dim, D, nr, nc);
     GIFT_LAUNCHED();
-    hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)((r1 - r0 + 3) / 4)), dim3(256), 0, st,
+    hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)(r1 - r0)), dim3(256), 0, st,
                        x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow);
     GIFT_LAUNCHED();
   }
@@ -1025,9 +1161,9 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // and every item is skipped, so every block exits.
 //
 // Memory ordering across blocks (the L2 of each XCD is private): every
-// thread of an item that produces data for later items makes its writes
-// visible at device scope (release fence) before the block barrier that
-// precedes the `done` increment.  A waiting item polls `done` with relaxed
+// wave of an item that produces data for later items waits for its own
+// writes, and after the block barrier thread 0 makes them visible at device
+// scope (one release fence) before the `done` increment.  A waiting item polls `done` with relaxed
 // loads, so the poll does not invalidate caches, and thread 0 takes one
 // device-scope acquire fence after the wait, before the block barrier.
 
@@ -1209,9 +1345,9 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           break;
         }
         case BP_SEL:
-          select_rows(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo, a.gamma2,
-                      a.qwords, a.overflow, a.counts, j, lds);
-          wrote = true;
+          // writes only through device-scope atomics (the word, its count)
+          select_rows<false>(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo,
+                             a.gamma2, a.qwords, a.overflow, a.counts, j, lds);
           break;
         case BP_PRE: {
           // group offsets (goff) and active-tile offsets (act_off) over
@@ -1333,16 +1469,19 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           break;
       }
     }
-    // Release what later items read with plain loads.  The list scan writes
-    // only through device-scope atomics, which are performed where every
-    // XCD sees them (as the queue counters are); each wave waits until its
-    // own have been performed (vmcnt 0), so thread 0's counter increment
-    // after the barrier cannot overtake them.  The per-query means are read
-    // only after the kernel.
-    if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    else if (ph == BP_SCAN) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // Release what later items read with plain loads.  Every wave waits
+    // until its own stores and atomics have been performed (vmcnt 0); after
+    // the barrier (a workgroup-scope release and acquire) thread 0 alone
+    // takes the device-scope release fence, which is cumulative: it covers
+    // the whole block's writes with one L2 write-back instead of one per
+    // wave.  The word selection and the list scan write only through
+    // device-scope atomics, which are performed where every XCD sees them
+    // (as the queue counters are), so they need no fence.  The per-query
+    // means are read only after the kernel.
+    if (wrote || ph == BP_SCAN || ph == BP_SEL) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (tid == 0) {
+      if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (ph == BP_Q) __hip_atomic_fetch_add(q_done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // no item waits for RED items, so they skip the shared counter
       if (ph != BP_RED) __hip_atomic_fetch_add(done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1368,6 +1507,7 @@ void launch_batch_reset(const BatchArgs& a, hipStream_t st) {
 
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st) {
   const size_t shmem = 128 * 129 * 4;  // the largest phase: the scan's C tile
+  static_assert(SEL_LDS <= 128 * 129 * 4, "word selection fits the batch kernel's LDS");
 #define GIFT_BATCH_LAUNCH(DTV)                                                                 \
   do {                                                                                         \
     const gift_status s_ = ensure_dynamic_lds(                                                 \
