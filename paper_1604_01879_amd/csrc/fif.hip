@@ -1088,30 +1088,42 @@ __device__ __forceinline__ float fif_mean(const uint32_t* __restrict__ mbuf, int
   return hi > lo ? acc / (float)(hi - lo) : 0.f;
 }
 
-// fif_mean of the 4 consecutive shapes p..p+3 (p and ldn multiples of 4,
-// mbuf 16-byte aligned): one 16-byte load per view, 16 views in flight.
-// Each shape's sum is taken in ascending view order, as in fif_mean, so the
-// results are the same bits.
-__device__ __forceinline__ float4 fif_mean4(const uint32_t* __restrict__ mbuf, int64_t ldn,
-                                            int64_t p, int lo, int hi) {
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int i = lo; i < hi; i += 16) {
-    uint4 u[16];
+// fif_mean of the 4 consecutive shapes p + 1024 s .. + 3 for s < 4 (those
+// below n; n, p and ldn multiples of 4, mbuf 16-byte aligned): 16-byte
+// loads, 8 views x 4 of them in flight.  Each shape's sum is taken in
+// ascending view order, as in fif_mean, so the results are the same bits.
+__device__ __forceinline__ void fif_mean16(const uint32_t* __restrict__ mbuf, int64_t ldn,
+                                           int64_t p, int64_t n, int lo, int hi,
+                                           float4 (&out)[4]) {
+  float acc[4][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t)
-      u[t] = i + t < hi ? *reinterpret_cast<const uint4*>(mbuf + (int64_t)(i + t) * ldn + p)
-                        : make_uint4(0u, 0u, 0u, 0u);
+  for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (u[t].x != 0u) acc[0] += order_float(u[t].x);
-      if (u[t].y != 0u) acc[1] += order_float(u[t].y);
-      if (u[t].z != 0u) acc[2] += order_float(u[t].z);
-      if (u[t].w != 0u) acc[3] += order_float(u[t].w);
-    }
+    for (int e = 0; e < 4; ++e) acc[s][e] = 0.f;
+  for (int i = lo; i < hi; i += 8) {
+    uint4 u[8][4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        u[t][s] = i + t < hi && p + 1024 * s < n
+                      ? *reinterpret_cast<const uint4*>(mbuf + (int64_t)(i + t) * ldn + p + 1024 * s)
+                      : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (u[t][s].x != 0u) acc[s][0] += order_float(u[t][s].x);
+        if (u[t][s].y != 0u) acc[s][1] += order_float(u[t][s].y);
+        if (u[t][s].z != 0u) acc[s][2] += order_float(u[t][s].z);
+        if (u[t][s].w != 0u) acc[s][3] += order_float(u[t][s].w);
+      }
   }
-  if (hi <= lo) return make_float4(0.f, 0.f, 0.f, 0.f);
   const float m = (float)(hi - lo);
-  return make_float4(acc[0] / m, acc[1] / m, acc[2] / m, acc[3] / m);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    out[s] = hi <= lo ? make_float4(0.f, 0.f, 0.f, 0.f)
+                      : make_float4(acc[s][0] / m, acc[s][1] / m, acc[s][2] / m, acc[s][3] / m);
 }
 
 __global__ __launch_bounds__(256) void reduce_fif_kernel(const uint32_t* __restrict__ mbuf,
@@ -1452,13 +1464,17 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           const int64_t p0 = (j - (int64_t)b * red_chunks) * BATCH_RED_SHAPES;
           const bool vec = (a.n_shapes & 3) == 0 &&
                            ((reinterpret_cast<uintptr_t>(a.mbuf) | reinterpret_cast<uintptr_t>(a.S)) & 15) == 0;
-          static_assert(BATCH_RED_SHAPES == 4 * 256, "one float4 of shapes per thread");
+          static_assert(BATCH_RED_SHAPES == 4 * 4 * 256, "four float4s of shapes per thread");
           if (vec) {
-            // 4 consecutive shapes per thread
+            // 4 consecutive shapes per thread in each of the item's 4 runs
+            // of 1,024 shapes
             const int64_t p = p0 + 4 * tid;
-            if (p < a.n_shapes)
-              *reinterpret_cast<float4*>(a.S + (int64_t)b * a.n_shapes + p) =
-                  fif_mean4(a.mbuf, a.n_shapes, p, lo, hi);
+            float4 m4[4];
+            fif_mean16(a.mbuf, a.n_shapes, p, a.n_shapes, lo, hi, m4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (p + 1024 * s < a.n_shapes)
+                *reinterpret_cast<float4*>(a.S + (int64_t)b * a.n_shapes + p + 1024 * s) = m4[s];
           } else {
             for (int64_t p = p0 + tid; p < p0 + BATCH_RED_SHAPES && p < a.n_shapes; p += 256)
               a.S[(int64_t)b * a.n_shapes + p] = fif_mean(a.mbuf, a.n_shapes, p, lo, hi);

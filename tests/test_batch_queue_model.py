@@ -34,7 +34,7 @@ import pytest
 # phases, in item order (the kernel's BatchPhase)
 Q, GEMM, FILL, SEL, PRE, SCAT, TILE, SCAN, RED = range(9)
 FILL_WORDS = 1 << 18      # match-buffer words cleared per clear item
-RED_SHAPES = 1024         # shapes of one query per mean item
+RED_SHAPES = 4096         # shapes of one query per mean item
 LIST_TILE = 128           # list entries per scan tile
 
 
