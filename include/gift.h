@@ -362,8 +362,9 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* before each run; q_offsets[0] = 0), and the outputs ids / scores        */
 /* [max_queries][top_k] and flags [max_queries] (NULL allowed).  The first */
 /* pass runs as ONE persistent kernel whose blocks take work items         */
-/* (split and quantize, dot tiles, clear, word selection, grouping, list   */
-/* tiles, per-query means) in order from a device queue; it is followed by */
+/* (split and quantize, dot tiles that also clear the match buffer, word  */
+/* selection, grouping, list tiles, per-query means) in order from a      */
+/* device queue; it is followed by                                        */
 /* the selection, rescore and final-ranking kernels, and the whole         */
 /* sequence is captured once into a HIP graph.                              */
 /* gift_fif_plan_run(n_queries, n_views)                                   */
@@ -389,8 +390,9 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* block-microseconds spent in each phase of the persistent kernel (sum    */
 /* over blocks of the wall time from the end of an item's wait for its     */
 /* inputs to the end of the item): out[9] = split and quantize, codeword   */
-/* dots, clear, word selection, word offsets, grouping, active-tile        */
-/* listing, list scan, per-query mean.                                     */
+/* dots, clear (no items of its own: the dot-tile items clear the match  */
+/* buffer, so it reads 0), word selection, word offsets, grouping,        */
+/* active-tile listing, list scan, per-query mean.                         */
 /* gift_fif_plan_phase_end_us (SYNCHRONISES) writes, for the last run and  */
 /* the same nine phases, the microseconds from the start of the run's      */
 /* queue reset to the end of the phase's last item (0: no item).           */

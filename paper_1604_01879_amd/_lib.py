@@ -517,7 +517,7 @@ class FifPlan:
         """Block-microseconds per phase of the last run, waits for inputs
         excluded (split and quantize, codeword dots, clear, word selection,
         word offsets, grouping, active-tile listing, list scan, per-query
-        mean)."""
+        mean; the clear runs inside the codeword-dot items and reads 0)."""
         out = (C.c_double * 9)()
         _check(_lib.gift_fif_plan_phase_us(self.handle, out, _stream(stream or self.stream)))
         return list(out)

@@ -101,6 +101,7 @@ __device__ __forceinline__ void split_row_wave(const float* __restrict__ x, int6
   const int lane = threadIdx.x & 63;
   const float* src = x + v * dim;
   uint8_t* row = dst + v * (int64_t)dim * 4;
+#pragma unroll 8
   for (int t = lane * 4; t < dim; t += 256) {
     uint2 hi, lo;
     split_bf16x4(*reinterpret_cast<const uint4*>(src + t), hi, lo);
@@ -1149,8 +1150,9 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // numbered phase by phase:
 //   Q    split 64 query views for the dot tiles and code them in the
 //        storage format
-//   GEMM query view x codeword dot tiles (MFMA)
-//   FILL clear rows [0, n_v) of mbuf
+//   GEMM query view x codeword dot tiles (MFMA); each item also clears its
+//        share of rows [0, n_v) of mbuf
+//   FILL (no items: the clear runs inside the GEMM items)
 //   SEL  certified nearest word of 4 query views; count views per word
 //   PRE  word offsets of the groups and of the active list tiles (one item)
 //   SCAT place every query view in its word's group
@@ -1164,7 +1166,7 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // order from an atomic counter.  An item of phase p first waits until every
 // item numbered below the first item of p has finished (one `done`
 // counter), except that GEMM waits for the Q items alone (a second
-// counter) and FILL waits for nothing; an item at or past the first SCAN
+// counter); an item at or past the first SCAN
 // item first waits for all of Q..TILE, and then knows the SCAN and RED
 // ranges.  The items waited for were all taken before by blocks that are
 // running, and the earliest unfinished item never waits, so the queue
@@ -1241,7 +1243,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     const int64_t n_items[BP_SCAN] = {
         (n_v + 63) / 64,                                                        // Q
         ((n_v + 127) / 128) * a.gemm_col_tiles,                                 // GEMM
-        (n_v * a.n_shapes + BATCH_FILL_WORDS - 1) / BATCH_FILL_WORDS,           // FILL
+        0,  // FILL: the clear runs inside the GEMM items                        // FILL
         (n_v + 3) / 4,                                                          // SEL
         1,                                                                      // PRE
         (n_v + 255) / 256,                                                      // SCAT
@@ -1336,20 +1338,22 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           wrote = true;
           break;
         }
-        case BP_FILL: {
-          // rows [0, n_v) of mbuf, BATCH_FILL_WORDS words per item
-          const int64_t e0 = j * BATCH_FILL_WORDS, lim = n_v * a.n_shapes;
-          const int64_t e1 = e0 + BATCH_FILL_WORDS < lim ? e0 + BATCH_FILL_WORDS : lim;
-          for (int64_t e = e0 + 4 * tid; e < e1; e += 1024) {
-            if (e + 4 <= e1)
-              *reinterpret_cast<uint4*>(a.mbuf + e) = make_uint4(0u, 0u, 0u, 0u);
-            else
-              for (int64_t t = e; t < e1; ++t) a.mbuf[t] = 0u;
-          }
-          wrote = true;
-          break;
-        }
         case BP_GEMM: {
+          // this item's share of clearing rows [0, n_v) of mbuf, stores that
+          // drain while the tile's MFMAs run (the release fence at the end of
+          // the item covers them)
+          {
+            const int64_t n_gemm = ((n_v + 127) / 128) * a.gemm_col_tiles;
+            const int64_t lim = n_v * a.n_shapes;
+            const int64_t per = ((lim + n_gemm - 1) / n_gemm + 1023) / 1024 * 1024;
+            const int64_t e0 = j * per, e1 = e0 + per < lim ? e0 + per : lim;
+            for (int64_t e = e0 + 4 * tid; e < e1; e += 1024) {
+              if (e + 4 <= e1)
+                *reinterpret_cast<uint4*>(a.mbuf + e) = make_uint4(0u, 0u, 0u, 0u);
+              else
+                for (int64_t t = e; t < e1; ++t) a.mbuf[t] = 0u;
+            }
+          }
           const int64_t rt = j / a.gemm_col_tiles;
           dots_split_tile(a.qsplit, n_v, a.cbsplit, a.K, a.dim, a.D, rt,
                           j - rt * a.gemm_col_tiles, lds);

@@ -114,7 +114,6 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 constexpr int BATCH_CTRL_WORDS = 8;
 enum BatchPhase { BP_Q = 0, BP_GEMM, BP_FILL, BP_SEL, BP_PRE, BP_SCAT, BP_TILE, BP_SCAN, BP_RED,
                   BP_END };
-constexpr int64_t BATCH_FILL_WORDS = (int64_t)1 << 18;  // mbuf words cleared per FILL item
 constexpr int64_t BATCH_RED_SHAPES = 4096;            // shapes of one query per RED item
 struct BatchArgs {
   const uint8_t* db;

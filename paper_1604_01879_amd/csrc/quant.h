@@ -79,25 +79,50 @@ __device__ inline void quantize_view_mx_wave(const float* __restrict__ src, int6
 }
 
 // One wave quantizes view v: scale = max|x| / Fmax (1 for an all-zero
-// view), code = round(x / scale).
+// view), code = round(x / scale).  dim is a multiple of 32: lane l takes the
+// float4 pieces l, l + 64, ..., eight pieces' loads in flight, in two passes
+// (the maximum, then the codes; the second reads the row from L2).
 __device__ inline void quantize_view_wave(const float* __restrict__ src, int64_t v, int dim,
                                           int dtype, uint8_t* __restrict__ dst,
                                           float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
-  const float* x = src + v * dim;
+  const float4* x4 = reinterpret_cast<const float4*>(src + v * dim);
+  const int n4 = dim >> 2;
   float amax = 0.f;
-  for (int t = lane; t < dim; t += 64) amax = fmaxf(amax, fabsf(x[t]));
+  for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
+    float4 xa[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      xa[k] = u0 + 64 * k < n4 ? x4[u0 + 64 * k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      amax = fmaxf(fmaxf(amax, fmaxf(fabsf(xa[k].x), fabsf(xa[k].y))),
+                   fmaxf(fabsf(xa[k].z), fabsf(xa[k].w)));
+  }
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
   const float fmax_ = dtype == GIFT_BF16 ? 1.0f : 448.0f;
   float s = amax / fmax_;
   if (s == 0.f) s = 1.f;
   if (lane == 0) scale[v] = s;
-  if (dtype == GIFT_BF16) {
-    uint16_t* d = reinterpret_cast<uint16_t*>(dst) + v * dim;
-    for (int t = lane; t < dim; t += 64) d[t] = bf16_rne(x[t] / s);
-  } else {
-    uint8_t* d = dst + v * dim;
-    for (int t = lane; t < dim; t += 64) d[t] = e4m3_rne_sat(x[t] / s);
+  for (int u0 = lane; u0 < n4; u0 += 64 * 8) {
+    float4 xa[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      xa[k] = u0 + 64 * k < n4 ? x4[u0 + 64 * k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int u = u0 + 64 * k;
+      if (u >= n4) continue;
+      if (dtype == GIFT_BF16) {
+        const uint32_t a = bf16_rne(xa[k].x / s) | ((uint32_t)bf16_rne(xa[k].y / s) << 16);
+        const uint32_t b = bf16_rne(xa[k].z / s) | ((uint32_t)bf16_rne(xa[k].w / s) << 16);
+        reinterpret_cast<uint2*>(dst + (v * dim) * 2)[u] = make_uint2(a, b);
+      } else {
+        reinterpret_cast<uint32_t*>(dst + v * dim)[u] =
+            (uint32_t)e4m3_rne_sat(xa[k].x / s) | ((uint32_t)e4m3_rne_sat(xa[k].y / s) << 8) |
+            ((uint32_t)e4m3_rne_sat(xa[k].z / s) << 16) | ((uint32_t)e4m3_rne_sat(xa[k].w / s) << 24);
+      }
+    }
   }
 }
 

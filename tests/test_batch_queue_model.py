@@ -3,9 +3,10 @@
 The persistent F-IF batch kernel numbers its work items phase by phase (split
 and quantize, codeword dots, clear, word selection, word offsets, grouping,
 active tiles, list scan, per-query mean) and lets blocks take them in
-increasing order from one counter.  An item waits until a `done` counter
-reaches the first item number of its phase (the dot tiles wait on a counter
-of finished split items instead; the clear waits for nothing), and the first
+increasing order from one counter; the clear of the match buffer has no
+items of its own but runs inside the dot-tile items.  An item waits until a
+`done` counter reaches the first item number of its phase (the dot tiles
+wait on a counter of finished split items instead), and the first
 item at or past the list scan waits for every item before the scan and then
 learns how many scan items there are.  Each block takes one acquire per phase
 after its wait; producers release before they count themselves done.
@@ -33,7 +34,6 @@ import pytest
 
 # phases, in item order (the kernel's BatchPhase)
 Q, GEMM, FILL, SEL, PRE, SCAT, TILE, SCAN, RED = range(9)
-FILL_WORDS = 1 << 18      # match-buffer words cleared per clear item
 RED_SHAPES = 4096         # shapes of one query per mean item
 LIST_TILE = 128           # list entries per scan tile
 
@@ -60,7 +60,7 @@ class Batch:
         n_items = [
             (self.n_v + self.qv - 1) // self.qv,
             ((self.n_v + 127) // 128) * gemm_col_tiles,
-            (self.n_v * n_shapes + FILL_WORDS - 1) // FILL_WORDS,
+            0,  # the clear runs inside the GEMM items
             (self.n_v + 3) // 4,
             1,
             (self.n_v + 255) // 256,
@@ -183,12 +183,19 @@ def check(b: Batch, log):
         for v in range(e["j"] * b.qv, min(e["j"] * b.qv + b.qv, b.n_v)):
             cover[v] += 1
     assert (cover == 1).all()
-    # the clear covers every word of rows [0, n_v) once
+    # the clear (a share of it in every GEMM item) covers every word of rows
+    # [0, n_v) once
     words = b.n_v * b.N
-    fill_cover = np.zeros((words + FILL_WORDS - 1) // FILL_WORDS, int)
-    for _, e in by_ph.get(FILL, []):
-        fill_cover[e["j"]] += 1
-    assert (fill_cover == 1).all() and len(by_ph.get(FILL, [])) * FILL_WORDS >= words
+    n_gemm = int(b.first[FILL] - b.first[GEMM])
+    per = ((words + n_gemm - 1) // n_gemm + 1023) // 1024 * 1024
+    assert not by_ph.get(FILL)
+    fill_cover = np.zeros(words, np.int8)
+    fill_end = np.full(words, -1.0)
+    for _, e in by_ph.get(GEMM, []):
+        e0, e1 = e["j"] * per, min(e["j"] * per + per, words)
+        fill_cover[e0:e1] += 1
+        fill_end[e0:e1] = e["end"]
+    assert (fill_cover == 1).all()
     # producers finish before consumers start, and the consumer's block
     # acquired after they finished
     producers = {GEMM: [Q], SEL: [Q, GEMM, FILL], PRE: [Q, GEMM, FILL, SEL],
@@ -202,15 +209,12 @@ def check(b: Batch, log):
             assert e["acq_t"] > last, (ph, it, "acquire before the producers finished")
     # clear of a row before any scan of that row; scans of (view, shape) before
     # the mean that reads them
-    fill_end = np.full(len(fill_cover), -1)
-    for _, e in by_ph.get(FILL, []):
-        fill_end[e["j"]] = e["end"]
     scan_end = {}
     for _, e in by_ph.get(SCAN, []):
         w, tt = b.act[e["j"]]
         for v in b.group[w]:
             w0, w1 = v * b.N, (v + 1) * b.N - 1
-            assert e["start"] > fill_end[w0 // FILL_WORDS: w1 // FILL_WORDS + 1].max()
+            assert e["start"] > fill_end[w0:w1 + 1].max()
             row = scan_end.setdefault(int(v), {})
             for p in b.tile_shapes[w][tt]:
                 row[int(p)] = max(row.get(int(p), -1), e["end"])
