@@ -561,7 +561,7 @@ def scale_bench(args):
         pairs = float((lens * counts).sum().item())
         gemm_flop = 2.0 * nvq * F.K * w.dim
         ideal_ms = (3 * gemm_flop / 2.5e15 + list_bytes / 8.0e12) * 1e3
-        return {"metric": "queries/s, batched F-IF (one persistent kernel in a HIP graph) + "
+        return {"metric": "queries/s, batched F-IF (persistent first-pass kernel in a HIP graph) + "
                           f"S-IF re-rank, 50k x 64-view {storage} DB",
                 "value": round(B / dt, 1), "unit": "queries/s", "n_gpus": 1,
                 "steps": args.steps, "higher_is_better": True, "dtype": storage,

@@ -375,7 +375,8 @@ gift_status gift_rerank_sif(int64_t n_shapes, const float* l1,
 /* `tuning` (NULL: the defaults) sets the persistent grid (blocks_per_cu,   */
 /* 1 or 2; default 2), the list entries per scan item (list_tile, 32..128  */
 /* in steps of 32; default 128) and the largest query-view group that takes */
-/* the narrow scan tile (narrow_max, 0, 16 or 32; default 32).  Every      */
+/* the narrow scan tile (narrow_max, 0, 16 or 32; default 32) and where   */
+/* the codeword GEMM runs (gemm, see gift_plan_tuning).  Every             */
 /* tuning gives the same ids and exact scores; a first-pass value, and so  */
 /* a flag, may differ in the last bits between tunings.  The workspace     */
 /* size depends on list_tile.  Create SYNCHRONISES `stream` (which must be a */
@@ -403,7 +404,11 @@ typedef struct gift_plan_tuning {
   int32_t list_tile;      /* list entries per scan item: 32, 64, 96 or 128   */
   int32_t narrow_max;     /* groups of at most this many query views take
                              the narrow scan tile: 0 (none), 16 or 32        */
-  int32_t reserved;       /* 0                                               */
+  int32_t gemm;           /* codeword GEMM: 0 auto (2 when max_views >=
+                             16384, else 1), 1 dot tiles inside the
+                             persistent kernel, 2 a separate 256 x 256 GEMM
+                             kernel before it (which also clears the match
+                             buffer)                                         */
 } gift_plan_tuning;
 size_t gift_fif_plan_workspace(const gift_views* db, const gift_fif* fif,
                                int32_t max_queries, int64_t max_views,

@@ -54,7 +54,7 @@ _P = C.c_void_p
 _FP = C.POINTER(gift_fif)
 class gift_plan_tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("list_tile", C.c_int32),
-                ("narrow_max", C.c_int32), ("reserved", C.c_int32)]
+                ("narrow_max", C.c_int32), ("gemm", C.c_int32)]
 
 
 _TP = C.POINTER(gift_plan_tuning)
@@ -446,8 +446,10 @@ def gift_autotune_score(db: Views, q: Queries, tiles, groups, reps=2, stream=Non
 
 
 # ---------------------------------------------------------------- plans
-def plan_tuning(blocks_per_cu=2, list_tile=128, narrow_max=32):
-    return gift_plan_tuning(int(blocks_per_cu), int(list_tile), int(narrow_max), 0)
+def plan_tuning(blocks_per_cu=2, list_tile=128, narrow_max=32, gemm=0):
+    """gemm: 0 placed by capacity, 1 inside the persistent kernel, 2 a
+    separate GEMM kernel."""
+    return gift_plan_tuning(int(blocks_per_cu), int(list_tile), int(narrow_max), int(gemm))
 
 
 def fif_plan_workspace(db: Views, fif: Fif, max_queries, max_views, top_k, rescore_r,
@@ -467,7 +469,7 @@ class FifPlan:
 
     def __init__(self, db: Views, fif: Fif, max_queries, max_views, max_views_per_query, top_k,
                  rescore_r, blocks_per_cu=2, stream=None, ws=None, views=None, list_tile=128,
-                 narrow_max=32):
+                 narrow_max=32, gemm=0):
         """ws (uint8) and views (float32 [max_views, dim]) may be given as
         caller-owned device tensors (e.g. carved from a memory pool); they
         must outlive the plan."""
@@ -484,7 +486,7 @@ class FifPlan:
         self.ids = torch.zeros((max_queries, top_k), dtype=torch.int32, device=dev)
         self.scores = torch.zeros((max_queries, top_k), dtype=torch.float32, device=dev)
         self.flags = torch.zeros(max_queries, dtype=torch.int32, device=dev)
-        self.tuning = plan_tuning(blocks_per_cu, list_tile, narrow_max)
+        self.tuning = plan_tuning(blocks_per_cu, list_tile, narrow_max, gemm)
         need = fif_plan_workspace(db, fif, max_queries, max_views, top_k, rescore_r, self.tuning)
         if ws is not None:
             assert ws.dtype == torch.uint8 and ws.numel() >= need

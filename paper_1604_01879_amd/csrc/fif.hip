@@ -37,9 +37,16 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
 // (row r at index r - r0).
 constexpr int SPLIT_TILE = 256;
 
+//
+// With n_rows_dev set, only rows [r0, r0 + *n_rows_dev) (at most r1) are
+// computed and blocks past them exit; with `clear` set, the blocks that
+// compute also zero words [0, rows * clear_row_words) of `clear` between
+// them, stores that drain under the MFMAs.
 __global__ __launch_bounds__(512, 1) void dots_split_kernel(
     const uint8_t* __restrict__ xs, int64_t r0, int64_t r1, const uint8_t* __restrict__ cbs, int K,
-    int dim, float* __restrict__ D, int64_t n_row_tiles, int64_t n_col_tiles) {
+    int dim, float* __restrict__ D, int64_t n_row_tiles, int64_t n_col_tiles,
+    const int32_t* __restrict__ n_rows_dev, uint32_t* __restrict__ clear,
+    int64_t clear_row_words) {
   constexpr int WM = 4, WN = 2, WC = 4;
   using S = Dma2Shape<WM, WN, WC, 2>;
   static_assert(S::BM == SPLIT_TILE && S::BN == SPLIT_TILE, "256 x 256 tiles");
@@ -52,6 +59,24 @@ __global__ __launch_bounds__(512, 1) void dots_split_kernel(
   const int64_t rows_in_group = n_row_tiles - gi * GROUP < GROUP ? n_row_tiles - gi * GROUP : GROUP;
   const int64_t row_tile = gi * GROUP + rem % rows_in_group;
   const int64_t col_tile = rem / rows_in_group;
+  if (n_rows_dev != nullptr) {
+    const int64_t nr = *n_rows_dev;
+    if (r0 + nr < r1) r1 = r0 + (nr > 0 ? nr : 0);
+    const int64_t act_rt = (r1 - r0 + SPLIT_TILE - 1) / SPLIT_TILE;
+    if (row_tile >= act_rt) return;  // block-uniform
+    if (clear != nullptr) {
+      const int64_t words = (r1 - r0) * clear_row_words, blocks = act_rt * n_col_tiles;
+      const int64_t per = ((words + blocks - 1) / blocks + 2047) / 2048 * 2048;
+      const int64_t e0 = (row_tile * n_col_tiles + col_tile) * per;
+      const int64_t e1 = e0 + per < words ? e0 + per : words;
+      for (int64_t e = e0 + 4 * threadIdx.x; e < e1; e += 2048) {
+        if (e + 4 <= e1)
+          *reinterpret_cast<uint4*>(clear + e) = make_uint4(0u, 0u, 0u, 0u);
+        else
+          for (int64_t t = e; t < e1; ++t) clear[t] = 0u;
+      }
+    }
+  }
   const int64_t rb = r0 + row_tile * SPLIT_TILE;  // first x row of the tile
   const int64_t cb0 = col_tile * SPLIT_TILE;      // first codeword
   const int row_bytes = dim * 4;
@@ -531,7 +556,7 @@ gift_status launch_assign(const float* x, int64_t n, int dim, const float* cb, i
     GIFT_LAUNCHED();
     const int64_t nr = (r1 - r0 + SPLIT_TILE - 1) / SPLIT_TILE;
     hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st, xs,
-                       r0, r1, cbs, K, dim, D, nr, nc);
+                       r0, r1, cbs, K, dim, D, nr, nc, nullptr, nullptr, (int64_t)0);
     GIFT_LAUNCHED();
     hipLaunchKernelGGL(assign_select_kernel, dim3((unsigned)(r1 - r0)), dim3(256), 0, st,
                        x, r0, r1, cb, K, dim, ma, D, nhi, nlo, gamma2, words, overflow);
@@ -1220,6 +1245,25 @@ __global__ __launch_bounds__(256) void tile_word_kernel(const int64_t* __restric
   for (int64_t b = tile_off[w]; b < tile_off[w + 1]; ++b) tile_word[b] = w;
 }
 
+// One wave splits query view v for the codeword GEMM and codes it in the
+// storage type for the list scan.
+template <int DT>
+__device__ __forceinline__ void batch_q_view(const BatchArgs& a, int64_t v) {
+  split_row_wave(a.qviews, v, a.dim, a.qsplit);
+  if constexpr (DT == GIFT_MXFP8 || DT == GIFT_MXFP4)
+    quantize_view_mx_wave(a.qviews, v, a.dim, DT, a.qcodes, static_cast<uint8_t*>(a.qscale));
+  else if constexpr (DT != GIFT_F32)
+    quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, static_cast<float*>(a.qscale));
+}
+
+// The Q work outside the persistent kernel: one wave per view of the
+// current batch (grid sized for Vmax).
+template <int DT>
+__global__ __launch_bounds__(256) void batch_q_kernel(BatchArgs a) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v < (int64_t)a.desc[1]) batch_q_view<DT>(a, v);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -1241,8 +1285,8 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   int64_t first[BP_SCAN + 1];
   {
     const int64_t n_items[BP_SCAN] = {
-        (n_v + 63) / 64,                                                        // Q
-        ((n_v + 127) / 128) * a.gemm_col_tiles,                                 // GEMM
+        a.ext_gemm ? 0 : (n_v + 63) / 64,                                       // Q
+        a.ext_gemm ? 0 : ((n_v + 127) / 128) * a.gemm_col_tiles,                // GEMM
         0,  // FILL: the clear runs inside the GEMM items                        // FILL
         (n_v + 3) / 4,                                                          // SEL
         1,                                                                      // PRE
@@ -1324,17 +1368,9 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     if (!sh_err) {
       switch (ph) {
         case BP_Q: {
-          // split the views for the codeword GEMM; code them in the storage
-          // type for the list scan
           const int wave = tid >> 6;
-          for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4) {
-            split_row_wave(a.qviews, v, a.dim, a.qsplit);
-            if constexpr (DT == GIFT_MXFP8 || DT == GIFT_MXFP4)
-              quantize_view_mx_wave(a.qviews, v, a.dim, DT, a.qcodes,
-                                    static_cast<uint8_t*>(a.qscale));
-            else if constexpr (DT != GIFT_F32)
-              quantize_view_wave(a.qviews, v, a.dim, DT, a.qcodes, static_cast<float*>(a.qscale));
-          }
+          for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4)
+            batch_q_view<DT>(a, v);
           wrote = true;
           break;
         }
@@ -1523,6 +1559,33 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
 
 void launch_batch_reset(const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, st, a);
+}
+
+gift_status launch_batch_pre(const BatchArgs& a, int dtype, hipStream_t st) {
+  const unsigned qgrid = (unsigned)((a.Vmax + 3) / 4);
+  switch (dtype) {
+    case GIFT_F32: hipLaunchKernelGGL(batch_q_kernel<GIFT_F32>, dim3(qgrid), dim3(256), 0, st, a); break;
+    case GIFT_BF16: hipLaunchKernelGGL(batch_q_kernel<GIFT_BF16>, dim3(qgrid), dim3(256), 0, st, a); break;
+    case GIFT_FP8E4M3:
+      hipLaunchKernelGGL(batch_q_kernel<GIFT_FP8E4M3>, dim3(qgrid), dim3(256), 0, st, a);
+      break;
+    case GIFT_MXFP8: hipLaunchKernelGGL(batch_q_kernel<GIFT_MXFP8>, dim3(qgrid), dim3(256), 0, st, a); break;
+    case GIFT_MXFP4: hipLaunchKernelGGL(batch_q_kernel<GIFT_MXFP4>, dim3(qgrid), dim3(256), 0, st, a); break;
+    default: return fail(GIFT_EUNSUPPORTED, "unsupported storage type");
+  }
+  GIFT_LAUNCHED();
+  const size_t split_lds = Dma2Shape<4, 2, 4, 2>::LDS_BYTES;
+  {
+    const gift_status s = ensure_dynamic_lds(reinterpret_cast<const void*>(dots_split_kernel), split_lds);
+    if (s != GIFT_OK) return s;
+  }
+  const int64_t nr = (a.Vmax + SPLIT_TILE - 1) / SPLIT_TILE;
+  const int64_t nc = (a.K + SPLIT_TILE - 1) / SPLIT_TILE;
+  hipLaunchKernelGGL(dots_split_kernel, dim3((unsigned)(nr * nc)), dim3(512), split_lds, st,
+                     a.qsplit, (int64_t)0, a.Vmax, a.cbsplit, a.K, a.dim, a.D, nr, nc, a.desc + 1,
+                     a.mbuf, a.n_shapes);
+  GIFT_LAUNCHED();
+  return GIFT_OK;
 }
 
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st) {

@@ -158,8 +158,16 @@ struct BatchArgs {
   int64_t gemm_col_tiles;
   int tile_len;              // list entries per scan item (<= 128)
   int narrow_max;            // groups of at most this many views take the narrow tile
+  // the split / quantize and codeword-dot work (and the match-buffer clear)
+  // runs in launch_batch_pre's kernels before the persistent kernel, which
+  // then has no Q or GEMM items
+  int ext_gemm;
 };
 void launch_batch_reset(const BatchArgs& a, hipStream_t st);
+// With ext_gemm: splits and codes the batch's query views and computes D
+// (256 x 256 tiles, clearing the match buffer on the way) for the
+// n_views = desc[1] rows of the current batch, grids sized for Vmax.
+gift_status launch_batch_pre(const BatchArgs& a, int dtype, hipStream_t st);
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st);
 gift_status launch_norms(const float* cb, int K, int dim, float* nhi, float* nlo, hipStream_t st);
 // n rows of dim float32 values split into BF16 parts, dim x 4 bytes per row:

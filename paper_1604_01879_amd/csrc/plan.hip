@@ -109,6 +109,10 @@ namespace gift {
 static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   launch_batch_reset(p->args, st);
   GIFT_LAUNCHED();
+  if (p->args.ext_gemm) {
+    const gift_status s0 = launch_batch_pre(p->args, p->db.dtype, st);
+    if (s0 != GIFT_OK) return s0;
+  }
   gift_status s = launch_fif_batch(p->args, p->db.dtype, p->grid, st);
   if (s != GIFT_OK) return s;
   // query slots past the batch (desc[0]) are skipped by every ranking kernel
@@ -131,21 +135,30 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
 }  // namespace gift
 
 // The tuning a plan runs with: the given one, or the defaults (2 blocks per
-// CU, 128-entry list tiles, narrow tiles for groups of up to 32 views).
+// CU, 128-entry list tiles, narrow tiles for groups of up to 32 views, the
+// codeword GEMM placed by capacity).
 static gift_plan_tuning plan_tuning(const gift_plan_tuning* t) {
   if (t != nullptr) return *t;
   gift_plan_tuning d{};
   d.blocks_per_cu = 2;
   d.list_tile = 128;
   d.narrow_max = 32;
+  d.gemm = 0;
   return d;
 }
 
 static bool tuning_ok(const gift_plan_tuning& t) {
   return (t.blocks_per_cu == 1 || t.blocks_per_cu == 2) && t.list_tile >= 32 &&
          t.list_tile <= 128 && t.list_tile % 32 == 0 &&
-         (t.narrow_max == 0 || t.narrow_max == 16 || t.narrow_max == 32);
+         (t.narrow_max == 0 || t.narrow_max == 16 || t.narrow_max == 32) && t.gemm >= 0 &&
+         t.gemm <= 2;
 }
+
+// Large batches take the separate 256 x 256 GEMM kernel (about half the
+// BF16 MFMA peak against a third for the persistent kernel's 128 x 128 dot
+// items); small ones keep the dot items, which spread one query's few row
+// tiles over more blocks.
+constexpr int64_t PLAN_EXT_GEMM_VIEWS = 16384;
 
 using namespace gift;
 
@@ -187,7 +200,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   const gift_plan_tuning tune = plan_tuning(tuning);
   GIFT_CHECK(tuning_ok(tune), GIFT_EINVAL,
              "tuning: blocks_per_cu 1 or 2, list_tile 32..128 in steps of 32, narrow_max 0, "
-             "16 or 32");
+             "16 or 32, gemm 0..2");
   GIFT_CHECK(fif->n_entries / tune.list_tile + fif->K + 1 < ((int64_t)1 << 31), GIFT_ECAPACITY,
              "too many list tiles");
   GIFT_CHECK(max_queries >= 1 && max_views >= 1 && max_views < ((int64_t)1 << 31) &&
@@ -297,6 +310,7 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   a.gemm_col_tiles = (fif->K + 127) / 128;
   a.tile_len = tune.list_tile;
   a.narrow_max = tune.narrow_max;
+  a.ext_gemm = tune.gemm == 2 || (tune.gemm == 0 && max_views >= PLAN_EXT_GEMM_VIEWS) ? 1 : 0;
 
   // an empty batch run eagerly once (sets kernel attributes, checks launches)
   {

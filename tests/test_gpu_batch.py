@@ -54,10 +54,12 @@ def _load(plan, q, qoff):
 
 
 # "bf16_263": a shape count that is not a multiple of 4 (the per-query mean
-# then reads one shape per load instead of four)
+# then reads one shape per load instead of four).  gemm 1: the codeword dots
+# as items of the persistent kernel; 2: a separate GEMM kernel before it.
+@pytest.mark.parametrize("gemm", [1, 2])
 @pytest.mark.parametrize("dtype_name", ["f32", "bf16", "fp8", "mxfp8", "mxfp4", "bf16_263"])
-def test_plan_equals_query_fif(L, dtype_name):
-    _say(f"plan vs query_fif {dtype_name}")
+def test_plan_equals_query_fif(L, dtype_name, gemm):
+    _say(f"plan vs query_fif {dtype_name} gemm {gemm}")
     name, _, ns = dtype_name.partition("_")
     dt = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3, "mxfp8": L.MXFP8,
           "mxfp4": L.MXFP4}[name]
@@ -66,7 +68,7 @@ def test_plan_equals_query_fif(L, dtype_name):
     _say("index built")
     k, R = 15, 60
     plan = L.FifPlan(V, F, max_queries=12, max_views=12 * 64, max_views_per_query=64, top_k=k,
-                     rescore_r=R)
+                     rescore_r=R, gemm=gemm)
     _say("plan created")
     S = O.fif_scores(q, qoff, db, w.n_views, cb, *O.build_fif(O.assign(db, cb, 2), 24,
                                                                 w.n_views))
