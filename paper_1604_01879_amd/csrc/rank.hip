@@ -10,7 +10,7 @@ namespace gift {
 constexpr int SEL_THREADS = 512;          // threads of a top-r selection block
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int SEL_UNROLL = 8;             // independent loads in flight per thread
-constexpr int P2_BATCH = 16;              // float4 loads per row per lane in a rescore batch
+constexpr int P2_BATCH = 8;               // float4 loads per row per lane in a rescore batch
 
 // Exclusive prefix count of `flag` over the threads of a block, in thread
 // order; returns the block total through `total`.
