@@ -1173,12 +1173,14 @@ void launch_reduce_fif(const uint32_t* mbuf, int64_t ldn, int64_t n_shapes, cons
 // One persistent kernel runs the whole first pass of a ragged query batch
 // (assign + group + scan + reduce) from a device work queue.  Items are
 // numbered phase by phase:
-//   Q    split 64 query views for the dot tiles and code them in the
-//        storage format
+//   Q    split 4 query views (one per wave) for the dot tiles and code
+//        them in the storage format
 //   GEMM query view x codeword dot tiles (MFMA); each item also clears its
 //        share of rows [0, n_v) of mbuf
 //   FILL (no items: the clear runs inside the GEMM items)
-//   SEL  certified nearest word of 4 query views; count views per word
+//   SEL  certified nearest word of one query view (batches of at most
+//        BATCH_SEL_SPLIT_MAX views, a whole block per view) or of 4 (one wave
+//        each); count views per word
 //   PRE  word offsets of the groups and of the active list tiles (one item)
 //   SCAT place every query view in its word's group
 //   TILE list the tiles of every list whose word has query views
@@ -1285,10 +1287,10 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   int64_t first[BP_SCAN + 1];
   {
     const int64_t n_items[BP_SCAN] = {
-        a.ext_gemm ? 0 : (n_v + 63) / 64,                                       // Q
+        a.ext_gemm ? 0 : (n_v + BATCH_Q_VIEWS - 1) / BATCH_Q_VIEWS,             // Q
         a.ext_gemm ? 0 : ((n_v + 127) / 128) * a.gemm_col_tiles,                // GEMM
         0,  // FILL: the clear runs inside the GEMM items                        // FILL
-        (n_v + 3) / 4,                                                          // SEL
+        n_v <= BATCH_SEL_SPLIT_MAX ? n_v : (n_v + 3) / 4,                       // SEL
         1,                                                                      // PRE
         (n_v + 255) / 256,                                                      // SCAT
         (int64_t)(a.K + 255) / 256};                                            // TILE
@@ -1369,7 +1371,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
       switch (ph) {
         case BP_Q: {
           const int wave = tid >> 6;
-          for (int64_t v = j * 64 + wave; v < j * 64 + 64 && v < n_v; v += 4)
+          for (int64_t v = j * BATCH_Q_VIEWS + wave; v < (j + 1) * BATCH_Q_VIEWS && v < n_v; v += 4)
             batch_q_view<DT>(a, v);
           wrote = true;
           break;
@@ -1398,8 +1400,12 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
         }
         case BP_SEL:
           // writes only through device-scope atomics (the word, its count)
-          select_rows<false>(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo,
-                             a.gamma2, a.qwords, a.overflow, a.counts, j, lds);
+          if (n_v <= BATCH_SEL_SPLIT_MAX)
+            select_rows<true>(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo,
+                              a.gamma2, a.qwords, a.overflow, a.counts, j, lds);
+          else
+            select_rows<false>(a.qviews, 0, n_v, a.cb, a.K, a.dim, 1, a.D, a.nhi, a.nlo,
+                               a.gamma2, a.qwords, a.overflow, a.counts, j, lds);
           break;
         case BP_PRE: {
           // group offsets (goff) and active-tile offsets (act_off) over
@@ -1408,20 +1414,38 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           int64_t* wsum = reinterpret_cast<int64_t*>(lds);  // [4] + [4]
           const int per = (a.K + 255) / 256;
           const int k0 = tid * per, k1 = k0 + per < a.K ? k0 + per : a.K;
+          // up to PRE_HOLD words per thread (K <= 8192) are read once, all
+          // loads in flight, and kept in registers for the write pass
+          constexpr int PRE_HOLD = 32;
+          const bool hold = per <= PRE_HOLD;
+          int ch[PRE_HOLD];
+          int64_t th[PRE_HOLD + 1];
           int64_t sum = 0, tsum = 0;
-          for (int k = k0; k < k1; k += 8) {
-            int c[8];
-            int64_t tl[8];
+          if (hold) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              c[q] = kk < k1 ? a.counts[kk] : 0;
-              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+            for (int q = 0; q < PRE_HOLD; ++q) ch[q] = k0 + q < k1 ? a.counts[k0 + q] : 0;
+#pragma unroll
+            for (int q = 0; q <= PRE_HOLD; ++q) th[q] = k0 + q <= k1 ? a.tile_off[k0 + q] : 0;
+#pragma unroll
+            for (int q = 0; q < PRE_HOLD; ++q) {
+              sum += ch[q];
+              if (ch[q] > 0) tsum += th[q + 1] - th[q];
             }
+          } else {
+            for (int k = k0; k < k1; k += 8) {
+              int c[8];
+              int64_t tl[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              sum += c[q];
-              if (c[q] > 0) tsum += tl[q];
+              for (int q = 0; q < 8; ++q) {
+                const int kk = k + q;
+                c[q] = kk < k1 ? a.counts[kk] : 0;
+                tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+              }
+#pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                sum += c[q];
+                if (c[q] > 0) tsum += tl[q];
+              }
             }
           }
           // inclusive scan within the wave, then across the 4 waves
@@ -1443,25 +1467,38 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
             __hip_atomic_store(n_active_w, (unsigned long long)(trun + tsum), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
           }
-          for (int k = k0; k < k1; k += 8) {
-            int c[8];
-            int64_t tl[8];
+          if (hold) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              c[q] = kk < k1 ? a.counts[kk] : 0;
-              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              if (kk < k1) {
-                a.goff[kk] = run;
-                a.act_off[kk] = (int32_t)trun;
-                a.fillc[kk] = 0;
+            for (int q = 0; q < PRE_HOLD; ++q) {
+              if (k0 + q < k1) {
+                a.goff[k0 + q] = run;
+                a.act_off[k0 + q] = (int32_t)trun;
+                a.fillc[k0 + q] = 0;
               }
-              run += c[q];
-              if (c[q] > 0) trun += tl[q];
+              run += ch[q];
+              if (ch[q] > 0) trun += th[q + 1] - th[q];
+            }
+          } else {
+            for (int k = k0; k < k1; k += 8) {
+              int c[8];
+              int64_t tl[8];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                const int kk = k + q;
+                c[q] = kk < k1 ? a.counts[kk] : 0;
+                tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+              }
+#pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                const int kk = k + q;
+                if (kk < k1) {
+                  a.goff[kk] = run;
+                  a.act_off[kk] = (int32_t)trun;
+                  a.fillc[kk] = 0;
+                }
+                run += c[q];
+                if (c[q] > 0) trun += tl[q];
+              }
             }
           }
           wrote = true;

@@ -115,6 +115,10 @@ constexpr int BATCH_CTRL_WORDS = 8;
 enum BatchPhase { BP_Q = 0, BP_GEMM, BP_FILL, BP_SEL, BP_PRE, BP_SCAT, BP_TILE, BP_SCAN, BP_RED,
                   BP_END };
 constexpr int64_t BATCH_RED_SHAPES = 4096;            // shapes of one query per RED item
+constexpr int64_t BATCH_Q_VIEWS = 4;                  // query views per Q item (one per wave)
+// batches of at most this many views select each view's word with a whole
+// block (one SEL item per view), larger ones with one wave per view
+constexpr int64_t BATCH_SEL_SPLIT_MAX = 512;
 struct BatchArgs {
   const uint8_t* db;
   const void* db_scale;      // per-view float32, E8M0 rows (MX) or null
