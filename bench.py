@@ -98,6 +98,8 @@ def main():
                     help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--fif", type=int, default=1, help="also measure the F-IF + S-IF path")
     ap.add_argument("--fif-steps", type=int, default=5)
+    ap.add_argument("--cpu-single", type=int, default=1,
+                    help="also time the oracle on one query with BLAS on one thread (0: skip)")
     ap.add_argument("--kmeans-iters", type=int, default=10)
     ap.add_argument("--workload", choices=["c3", "c4", "c5", "copy", "peaks", "sweep"],
                     default="c3",
@@ -350,13 +352,45 @@ def main():
         result["cpu_baseline"] = {
             "value": round(ns / dt, 4), "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"{ns} of the {B} queries against the full {w.n_shapes}-shape database, "
-                      f"float64 numpy (BLAS) exhaustive Eq. 3 + ranking, {dt:.1f}s"}
+                      f"float64 numpy (BLAS) exhaustive Eq. 3 + ranking, {dt:.1f}s",
+            "cpu_model": _cpu_model(), "blas": _blas_name()}
+        if args.cpu_single:
+            # the same oracle on one query with BLAS held to one thread
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t1 = time.time()
+                S1 = O.exhaustive_scores(q_np[:qoff_np[1]], qoff_np[:2], db_np, w.n_views)
+                O.rank_topk(S1, k)
+                dt1 = time.time() - t1
+            result["cpu_baseline"]["single_thread"] = {
+                "value": round(1.0 / dt1, 4), "unit": "queries/s",
+                "sample": f"1 query, BLAS limited to 1 thread, {dt1:.1f}s"}
         r64 = recall(main_run["ids"][:ns], ids64, min(100, k))
         result["recall"]["vs_fp64_oracle_sample"] = {"queries": ns, "at100_mean": r64[0],
                                                      "at100_min": r64[1]}
         result["recall"]["fp32_path_ids_equal_fp64_oracle_sample"] = bool(
             np.array_equal(exact_ids[:ns], ids64))
     print(json.dumps(result))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_name():
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg["Build Dependencies"]["blas"]
+        return f"{b.get('name', '?')} {b.get('version', '')}".strip()
+    except Exception:  # older numpy: no dict mode
+        return "unknown"
 
 
 # Vendor dense peaks of MI355X (TFLOP/s) and the probe's flop per MFMA.
