@@ -1414,38 +1414,20 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           int64_t* wsum = reinterpret_cast<int64_t*>(lds);  // [4] + [4]
           const int per = (a.K + 255) / 256;
           const int k0 = tid * per, k1 = k0 + per < a.K ? k0 + per : a.K;
-          // up to PRE_HOLD words per thread (K <= 8192) are read once, all
-          // loads in flight, and kept in registers for the write pass
-          constexpr int PRE_HOLD = 32;
-          const bool hold = per <= PRE_HOLD;
-          int ch[PRE_HOLD];
-          int64_t th[PRE_HOLD + 1];
           int64_t sum = 0, tsum = 0;
-          if (hold) {
+          for (int k = k0; k < k1; k += 8) {
+            int c[8];
+            int64_t tl[8];
 #pragma unroll
-            for (int q = 0; q < PRE_HOLD; ++q) ch[q] = k0 + q < k1 ? a.counts[k0 + q] : 0;
-#pragma unroll
-            for (int q = 0; q <= PRE_HOLD; ++q) th[q] = k0 + q <= k1 ? a.tile_off[k0 + q] : 0;
-#pragma unroll
-            for (int q = 0; q < PRE_HOLD; ++q) {
-              sum += ch[q];
-              if (ch[q] > 0) tsum += th[q + 1] - th[q];
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              c[q] = kk < k1 ? a.counts[kk] : 0;
+              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
             }
-          } else {
-            for (int k = k0; k < k1; k += 8) {
-              int c[8];
-              int64_t tl[8];
 #pragma unroll
-              for (int q = 0; q < 8; ++q) {
-                const int kk = k + q;
-                c[q] = kk < k1 ? a.counts[kk] : 0;
-                tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
-              }
-#pragma unroll
-              for (int q = 0; q < 8; ++q) {
-                sum += c[q];
-                if (c[q] > 0) tsum += tl[q];
-              }
+            for (int q = 0; q < 8; ++q) {
+              sum += c[q];
+              if (c[q] > 0) tsum += tl[q];
             }
           }
           // inclusive scan within the wave, then across the 4 waves
@@ -1467,38 +1449,25 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
             __hip_atomic_store(n_active_w, (unsigned long long)(trun + tsum), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
           }
-          if (hold) {
+          for (int k = k0; k < k1; k += 8) {
+            int c[8];
+            int64_t tl[8];
 #pragma unroll
-            for (int q = 0; q < PRE_HOLD; ++q) {
-              if (k0 + q < k1) {
-                a.goff[k0 + q] = run;
-                a.act_off[k0 + q] = (int32_t)trun;
-                a.fillc[k0 + q] = 0;
-              }
-              run += ch[q];
-              if (ch[q] > 0) trun += th[q + 1] - th[q];
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              c[q] = kk < k1 ? a.counts[kk] : 0;
+              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
             }
-          } else {
-            for (int k = k0; k < k1; k += 8) {
-              int c[8];
-              int64_t tl[8];
 #pragma unroll
-              for (int q = 0; q < 8; ++q) {
-                const int kk = k + q;
-                c[q] = kk < k1 ? a.counts[kk] : 0;
-                tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+            for (int q = 0; q < 8; ++q) {
+              const int kk = k + q;
+              if (kk < k1) {
+                a.goff[kk] = run;
+                a.act_off[kk] = (int32_t)trun;
+                a.fillc[kk] = 0;
               }
-#pragma unroll
-              for (int q = 0; q < 8; ++q) {
-                const int kk = k + q;
-                if (kk < k1) {
-                  a.goff[kk] = run;
-                  a.act_off[kk] = (int32_t)trun;
-                  a.fillc[kk] = 0;
-                }
-                run += c[q];
-                if (c[q] > 0) trun += tl[q];
-              }
+              run += c[q];
+              if (c[q] > 0) trun += tl[q];
             }
           }
           wrote = true;
