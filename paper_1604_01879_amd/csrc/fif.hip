@@ -1266,7 +1266,10 @@ __global__ __launch_bounds__(256) void batch_q_kernel(BatchArgs a) {
   if (v < (int64_t)a.desc[1]) batch_q_view<DT>(a, v);
 }
 
-template <int DT>
+// ITEMS: the kernel has the Q and GEMM items (plans that run them in the
+// kernels of launch_batch_pre use a copy without them, which needs fewer
+// registers).
+template <int DT, bool ITEMS>
 __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int64_t sh_item;
@@ -1370,6 +1373,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
     if (!sh_err) {
       switch (ph) {
         case BP_Q: {
+          if constexpr (!ITEMS) break;
           const int wave = tid >> 6;
           for (int64_t v = j * BATCH_Q_VIEWS + wave; v < (j + 1) * BATCH_Q_VIEWS && v < n_v; v += 4)
             batch_q_view<DT>(a, v);
@@ -1377,6 +1381,7 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           break;
         }
         case BP_GEMM: {
+          if constexpr (!ITEMS) break;
           // this item's share of clearing rows [0, n_v) of mbuf, stores that
           // drain while the tile's MFMAs run (the release fence at the end of
           // the item covers them)
@@ -1597,12 +1602,17 @@ gift_status launch_batch_pre(const BatchArgs& a, int dtype, hipStream_t st) {
 gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_t st) {
   const size_t shmem = 128 * 129 * 4;  // the largest phase: the scan's C tile
   static_assert(SEL_LDS <= 128 * 129 * 4, "word selection fits the batch kernel's LDS");
-#define GIFT_BATCH_LAUNCH(DTV)                                                                 \
+#define GIFT_BATCH_LAUNCH_1(DTV, IT)                                                           \
   do {                                                                                         \
     const gift_status s_ = ensure_dynamic_lds(                                                 \
-        reinterpret_cast<const void*>(fif_batch_kernel<DTV>), shmem);                          \
+        reinterpret_cast<const void*>(fif_batch_kernel<DTV, IT>), shmem);                      \
     if (s_ != GIFT_OK) return s_;                                                              \
-    hipLaunchKernelGGL(fif_batch_kernel<DTV>, dim3(grid), dim3(256), shmem, st, a);            \
+    hipLaunchKernelGGL((fif_batch_kernel<DTV, IT>), dim3(grid), dim3(256), shmem, st, a);      \
+  } while (0)
+#define GIFT_BATCH_LAUNCH(DTV)                                                                 \
+  do {                                                                                         \
+    if (a.ext_gemm) GIFT_BATCH_LAUNCH_1(DTV, false);                                           \
+    else GIFT_BATCH_LAUNCH_1(DTV, true);                                                       \
   } while (0)
   switch (dtype) {
     case GIFT_F32: GIFT_BATCH_LAUNCH(GIFT_F32); break;
@@ -1612,6 +1622,7 @@ gift_status launch_fif_batch(const BatchArgs& a, int dtype, int grid, hipStream_
     default: GIFT_BATCH_LAUNCH(GIFT_MXFP4); break;
   }
 #undef GIFT_BATCH_LAUNCH
+#undef GIFT_BATCH_LAUNCH_1
   GIFT_LAUNCHED();
   return GIFT_OK;
 }
