@@ -184,3 +184,37 @@ def test_plan_rejects_oversized_batch(L):
     with pytest.raises(L.GiftError):
         plan.run(2, 101)
     plan.close()
+
+
+@pytest.mark.parametrize("gemm", [1, 2])
+def test_plan_large_batch_equals_query_fif(L, gemm):
+    """A batch of more than 512 query views: the word selection takes one
+    wave per view instead of a whole block, and the per-query mean spans
+    several 4,096-shape items; first pass, ids and scores still equal
+    gift_query_fif's and the ids the oracle's."""
+    _say(f"plan large batch gemm {gemm}")
+    w, db, q, qoff, cb, V, F = _setup(L, L.BF16, n_shapes=4500, B=24, seed=9)
+    assert qoff[-1] > 512, "the batch must exceed the per-view selection limit"
+    k, R = 10, 40
+    plan = L.FifPlan(V, F, max_queries=24, max_views=24 * 64, max_views_per_query=64, top_k=k,
+                     rescore_r=R, gemm=gemm)
+    Q = L.Queries(torch.from_numpy(q).to(DEV), torch.from_numpy(qoff))
+    ref_ids, ref_sc, _ = L.gift_query_fif(V, F, Q, k, R)
+    ref_s1, _ = L.gift_score_fif(V, F, Q)
+    torch.cuda.synchronize()
+    n_q, n_v = _load(plan, q, qoff)
+    for _ in range(2):
+        plan.run(n_q, n_v)
+        plan.stream.synchronize()
+        assert plan.error() == 0
+        s1 = plan.first_pass(n_q)
+        plan.stream.synchronize()
+        assert torch.equal(s1, ref_s1), int((s1 != ref_s1).sum())
+        assert np.array_equal(plan.ids[:n_q].cpu().numpy(), ref_ids.cpu().numpy())
+        assert np.array_equal(plan.scores[:n_q].cpu().numpy(), ref_sc.cpu().numpy())
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, *O.build_fif(O.assign(db, cb, 2), 24, w.n_views))
+    ids, sc, fl = (t[:n_q].cpu().numpy() for t in (plan.ids, plan.scores, plan.flags))
+    for b in range(n_q):
+        if fl[b] & 1:
+            assert_ranked_equal(ids[b], sc[b], S[b], k)
+    plan.close()
