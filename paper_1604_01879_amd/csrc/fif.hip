@@ -837,18 +837,28 @@ __device__ __forceinline__ void scan_list_tile(
 
   // Per-shape maximum over this tile's entries for column c (rows [rbeg,
   // rend) of C, row stride ld), folded into mbuf for query view qi.
+  // The entries' shapes are read 8 at a time, all loads in flight, before
+  // they are used.
   auto fold = [&](int c, int ld, int rbeg, int rend, int qi) {
     const float cs = SCALED ? q_scale[qi] : 1.f;
     int cur = -1;
     float m = -INFINITY;
-    for (int r = rbeg; r < rend; ++r) {
-      const int shp = ent_shape[e0 + r];
-      if (shp != cur) {
-        if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
-        cur = shp;
-        m = -INFINITY;
+    for (int r0 = rbeg; r0 < rend; r0 += 8) {
+      int shp8[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) shp8[t] = r0 + t < rend ? ent_shape[e0 + r0 + t] : -1;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (r0 + t < rend) {
+          const int shp = shp8[t];
+          if (shp != cur) {
+            if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
+            cur = shp;
+            m = -INFINITY;
+          }
+          m = fmaxf(m, C[(r0 + t) * ld + c]);
+        }
       }
-      m = fmaxf(m, C[r * ld + c]);
     }
     if (cur >= 0) atomicMax(&mbuf[(int64_t)qi * ldn + cur], float_order(m * cs));
   };
