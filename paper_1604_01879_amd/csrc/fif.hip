@@ -834,6 +834,13 @@ __device__ __forceinline__ void scan_list_tile(
   float* C = reinterpret_cast<float*>(lds);  // [128][129] after the main loop
   const int wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
+  // the tile rows' view scales, read once per tile (the main loop's
+  // barriers order these writes before the epilogues' reads)
+  __shared__ float rscale[128];
+  if (SCALED && threadIdx.x < 128 && (int)threadIdx.x < ne) {
+    const int64_t en = e0 + threadIdx.x;
+    rscale[threadIdx.x] = db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
+  }
 
   // Per-shape maximum over this tile's entries for column c (rows [rbeg,
   // rend) of C, row stride ld), folded into mbuf for query view qi.
@@ -935,10 +942,7 @@ __device__ __forceinline__ void scan_list_tile(
       for (int e = 0; e < 16; ++e) {
         const int r = wave * 32 + acc_row(0, e);
         float v = acc[e];
-        if (SCALED && r < ne) {
-          const int64_t en = e0 + r;
-          v *= db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
-        }
+        if (SCALED && r < ne) v *= rscale[r];
         C[r * LD + acc_col(0)] = v;
       }
       __syncthreads();
@@ -1005,10 +1009,7 @@ __device__ __forceinline__ void scan_list_tile(
           const int r = wr * 64 + acc_row(i, e);
           const int c = wc * 64 + acc_col(j);
           float v = acc[i][j][e];
-          if (SCALED && r < ne) {
-            const int64_t en = e0 + r;
-            v *= db_scale[(int64_t)ent_shape[en] * n_views + ent_view[en]];
-          }
+          if (SCALED && r < ne) v *= rscale[r];
           C[r * 129 + c] = v;
         }
     __syncthreads();
