@@ -668,10 +668,17 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
   ff acc = {0.f, 0.f};
   for (int it = 0; it * 64 < m; ++it) {
     const int mi = min(64, m - it * 64);
+    // this wave's masks (query views wave, wave + 4, ...; lane i holds the
+    // i-th), read together instead of one round trip per query view
+    const int ivl = wave + 4 * lane;
+    const unsigned long long mk = lane < 16 && ivl < mi ? pmask[it * 64 + ivl] : 0ull;
     for (int iv = wave; iv < mi; iv += 4) {
       const float* qrow = qviews + (int64_t)(q0 + it * 64 + iv) * dim;
       const gptr<uint8_t> q4 = uniform_gptr(reinterpret_cast<const uint8_t*>(qrow));
-      unsigned long long bb = pmask[it * 64 + iv];
+      const int src = (iv - wave) >> 2;
+      unsigned long long bb =
+          ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(mk >> 32), src, 64) << 32) |
+          (uint32_t)__shfl((int)(uint32_t)mk, src, 64);
       ff best = {-INFINITY, 0.f};
       while (bb) {
         const int j = __builtin_ctzll(bb);
