@@ -75,23 +75,33 @@ static float rescore_dot_err(int dim) {
   return (float)((split + 1.02 * gamma_n(6.0 * 17 + dim / 32 + 2)) * 1.0001 + 1e-25);
 }
 
-// Bound on |first-pass score - exact Eq. 3 score| for unit-norm views,
-// without the mean's term.  Storage rounding: each stored value is within
-// u_s of the scaled value (u_s = 2^-8 for BF16, 2^-4 for e4m3), so a product
-// is within 2 u_s + u_s^2 relative; the MFMA accumulation is charged 2*dim
-// roundings.  The final ranking adds the mean over the query's own m views,
-// gamma_(m + 2), per query (so a query's certificate does not depend on the
-// other queries of its batch), and a 1.001 safety factor.
-static double first_pass_err(int dtype, int dim) {
+// Bound on |first-pass score - exact Eq. 3 / Eq. 4 score| for unit-norm
+// views, without the mean's term.  Storage rounding: each stored value is
+// within u_s of the scaled value (u_s = 2^-8 for BF16, 2^-4 for e4m3), so a
+// product is within 2 u_s + u_s^2 relative; the MFMA accumulation is
+// charged 2*dim roundings.  Float32 rows carry no storage error; in the
+// Eq. 4 list scan (`list_scan`) their tiles sum each 32-value K-tile into a
+// fresh block that is added into the running total, so a product is
+// rounded once, passes through at most 32 additions in its block (2 per
+// 32x32x2 MFMA, 4 per 16x16x4 MFMA) and at most dim / 32 into the total,
+// which 48 + dim / 32 + 2 roundings cover (the absolute term covers
+// products flushed to zero).  The final ranking adds the mean over the
+// query's own m views, gamma_(m + 2), per query (so a query's certificate
+// does not depend on the other queries of its batch), and a 1.001 safety
+// factor.
+static double first_pass_err(int dtype, int dim, bool list_scan) {
   // MX element errors are relative to the block maximum, not the element
   // (saturation can cost an eighth of it): no useful bound, so never certify
   if (dtype == GIFT_MXFP8 || dtype == GIFT_MXFP4) return 4.0;
+  if (dtype == GIFT_F32 && list_scan) return gamma_n(48.0 + (dim + 31) / 32 + 2) * 1.0001 + 1e-25;
   double us = dtype == GIFT_BF16 ? 1.0 / 256 : dtype == GIFT_FP8E4M3 ? 1.0 / 16 : 0.0;
   return (2 * us + us * us) + gamma_n(2.0 * dim + 4);
 }
 
 float rescore_dot_error(int dim) { return rescore_dot_err(dim); }
-double first_pass_error(int dtype, int dim) { return first_pass_err(dtype, dim); }
+double first_pass_error(int dtype, int dim, bool list_scan) {
+  return first_pass_err(dtype, dim, list_scan);
+}
 
 // Rows are read with 16-byte vector loads and scales with 4-byte loads.
 static bool aligned(const void* p, uintptr_t a) {
@@ -484,13 +494,13 @@ gift_status gift_query_exhaustive(const gift_views* db, const gift_queries* q,
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), nullptr,
-                 nullptr, 0, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim), w.rs, w.s_hi,
+                 nullptr, 0, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim, false), w.rs, w.s_hi,
                  w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
-                    db->n_shapes, first_pass_err(db->dtype, db->dim), q->offsets, nullptr,
+                    db->n_shapes, first_pass_err(db->dtype, db->dim, false), q->offsets, nullptr,
                     nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();
@@ -714,13 +724,13 @@ gift_status gift_query_fif(const gift_views* db, const gift_fif* fif, const gift
   prof_begin(P_RESCORE, st);
   launch_rescore(db->master, db->n_views, db->dim, q->views, q->offsets, q->n_queries,
                  q->total_views, w.cand, rescore_r, top_k, rescore_dot_err(db->dim), w.qwords,
-                 fif->view_words, fif->ma, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim),
+                 fif->view_words, fif->ma, nullptr, w.cand_s, first_pass_err(db->dtype, db->dim, true),
                  w.rs, w.s_hi, w.s_lo, st);
   prof_end(st);
   GIFT_LAUNCHED();
   prof_begin(P_FINAL, st);
   launch_final_rank(w.cand, w.cand_s, w.s_hi, w.s_lo, q->n_queries, rescore_r, top_k,
-                    db->n_shapes, first_pass_err(db->dtype, db->dim), q->offsets,
+                    db->n_shapes, first_pass_err(db->dtype, db->dim, true), q->offsets,
                     w.as.overflow, nullptr, ids, scores, flags, st);
   prof_end(st);
   GIFT_LAUNCHED();

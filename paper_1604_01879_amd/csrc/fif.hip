@@ -812,6 +812,9 @@ __global__ __launch_bounds__(1024) void list_tiles_kernel(const int64_t* __restr
 // Scales: per-view float32 (BF16 / e4m3) or E8M0 rows (MX), null for float32.
 // NARROW_DMA: narrow tiles of whole 128-byte sub-tiles use the
 // direct-to-LDS gather pipeline instead of register staging.
+// Float32 rows sum each K-tile into a fresh block (MFMA_F32_BLOCKED), so
+// every first-pass dot of the scan is within gamma(48 + d / 32 + 2)
+// sum |x y| of the exact one.
 template <int DT, bool NARROW_DMA = true>
 __device__ __forceinline__ void scan_list_tile(
     const uint8_t* __restrict__ db, const void* __restrict__ db_scale_v, int n_views,
@@ -824,6 +827,7 @@ __device__ __forceinline__ void scan_list_tile(
   using T = TileShape<2, 2>;
   constexpr bool MX = DT == GIFT_MXFP8 || DT == GIFT_MXFP4;
   constexpr bool SCALED = DT == GIFT_BF16 || DT == GIFT_FP8E4M3;
+  constexpr int MT = DT == GIFT_F32 ? MFMA_F32_BLOCKED : DT;  // MFMA form of the tiles
   const float* db_scale = static_cast<const float*>(db_scale_v);
   const float* q_scale = static_cast<const float*>(q_scale_v);
   const int64_t g0 = goff[w], g1 = goff[w + 1];
@@ -918,7 +922,7 @@ __device__ __forceinline__ void scan_list_tile(
             return;
           }
         }
-        mfma_tile_mainloop_narrow_dma<DT>(lds, src, row_bytes, acc);
+        mfma_tile_mainloop_narrow_dma<MT>(lds, src, row_bytes, acc);
       } else {
         const uint8_t* src[N::LOADS];
 #pragma unroll
@@ -935,7 +939,7 @@ __device__ __forceinline__ void scan_list_tile(
           }
           src[it] = p;
         }
-        mfma_tile_mainloop_narrow<DT>(lds, src, row_bytes, acc);
+        mfma_tile_mainloop_narrow<MT>(lds, src, row_bytes, acc);
       }
       constexpr int LD = N::BN + 1;
 #pragma unroll
@@ -998,7 +1002,7 @@ __device__ __forceinline__ void scan_list_tile(
       mfma_tile_mainloop_mx<DT == GIFT_MXFP8 ? 0 : 4, 2, 2>(lds, src, row_bytes, sa_row, sb_row,
                                                             acc);
     } else {
-      mfma_tile_mainloop<DT, 2, 2>(lds, src, row_bytes, acc);
+      mfma_tile_mainloop<MT, 2, 2>(lds, src, row_bytes, acc);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)

@@ -184,7 +184,7 @@ void launch_tile_word(const int64_t* tile_off, int K, int32_t* tile_word, hipStr
 float assign_gamma2(int dim);
 // error bounds of the rescore dot product and of the first pass (api.hip)
 float rescore_dot_error(int dim);
-double first_pass_error(int dtype, int dim);
+double first_pass_error(int dtype, int dim, bool list_scan);
 
 // ---- second inverted file
 // l1 [N][2] (compensated ||F_p||_1), post_off [N+1], post_id / post_val

@@ -35,7 +35,8 @@ struct Pair32 {
 
 template <>
 struct Mfma<GIFT_F32> {
-  // 16 steps of 32x32x2 per K-tile.
+  // 16 steps of 32x32x2 per K-tile, on one accumulation chain: a dot over d
+  // values is within gamma(2 d + 4) sum |x y| of the exact one.
   __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -44,6 +45,25 @@ struct Mfma<GIFT_F32> {
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].z), __builtin_bit_cast(float, b[s].z), c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a[s].w), __builtin_bit_cast(float, b[s].w), c, 0, 0, 0);
     }
+  }
+};
+
+// Pseudo storage type for float32 rows whose K-tiles are summed into a
+// fresh block that is then added into the running total: a product is
+// rounded once and passes through at most 32 additions in its block and
+// one per K-tile after it, so a dot over d values is within
+// gamma(48 + d / 32 + 2) sum |x y| of the exact one.  The list scan uses it
+// (its tighter first-pass bound lets the rescore drop more candidates);
+// the exhaustive float32 tile keeps one chain, whose 16 fewer live
+// registers per block keep it at 3 waves per SIMD.
+constexpr int MFMA_F32_BLOCKED = 17;
+
+template <>
+struct Mfma<MFMA_F32_BLOCKED> {
+  __device__ static __forceinline__ void run(const uint4 (&a)[4], const uint4 (&b)[4], f32x16& c) {
+    f32x16 p = {};
+    Mfma<GIFT_F32>::run(a, b, p);
+    c += p;
   }
 };
 
@@ -942,7 +962,14 @@ __device__ __forceinline__ void mfma_tile_mainloop_narrow16_dma_f32(
     for (int t = 0; t < 4; ++t) acc[bk][t] = 0.f;
   // LDS rows 32 w + 16 b + l16 (entries) and 128 + l16 (query views)
   const int swa0 = dma2_swizzle(l16), swa1 = dma2_swizzle(16 + l16), swb = dma2_swizzle(l16);
+  // each sub-tile's 8 MFMAs per block go into a fresh block (as in
+  // Mfma<MFMA_F32_BLOCKED>), added into the total during the next sub-tile
+  // so the addition does not wait for the MFMA chain before the barrier
+  f32x4 prev[2] = {};
   narrow_dma_pipeline(lds, src, row_bytes, [&](const uint8_t* st) {
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk) acc[bk] += prev[bk];
+    f32x4 part[2] = {};
     uint4 bq[2], aq[2][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -963,10 +990,14 @@ __device__ __forceinline__ void mfma_tile_mainloop_narrow16_dma_f32(
                              __builtin_bit_cast(float, aq[bk][h].z), __builtin_bit_cast(float, aq[bk][h].w)};
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          acc[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], acc[bk], 0, 0, 0);
+          part[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], part[bk], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk) prev[bk] = part[bk];
   });
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk) acc[bk] += prev[bk];
 }
 
 // Row (within the wave's WM*32 rows) and column of accumulator element e of

@@ -123,10 +123,10 @@ static gift_status enqueue_plan(gift_fif_plan* p, hipStream_t st) {
   launch_rescore(p->db.master, p->db.n_views, p->db.dim, p->qviews, p->qoff, p->Bmax, p->Vmax,
                  p->ws.cand, p->r, p->top_k, rescore_dot_error(p->db.dim), p->ws.qwords,
                  p->view_words, p->ma, active, p->ws.cand_s,
-                 first_pass_error(p->db.dtype, p->db.dim), p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
+                 first_pass_error(p->db.dtype, p->db.dim, true), p->ws.rs, p->ws.s_hi, p->ws.s_lo, st);
   GIFT_LAUNCHED();
   launch_final_rank(p->ws.cand, p->ws.cand_s, p->ws.s_hi, p->ws.s_lo, p->Bmax, p->r, p->top_k,
-                    p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim), p->qoff,
+                    p->db.n_shapes, first_pass_error(p->db.dtype, p->db.dim, true), p->qoff,
                     p->ws.overflow, active, p->ids, p->scores, p->flags, st);
   GIFT_LAUNCHED();
   return GIFT_OK;

@@ -265,7 +265,8 @@ def test_query_fif_ranked_ids(L, dtype_name, ma, R):
         assert_returned_exact(ids[b], sc[b], S[b], k)
         if dtype_name == "f32" or R == w.n_shapes or flags[b] & 1:
             assert_ranked_equal(ids[b], sc[b], S[b], k)
-    need = assert_flags_as_predicted(flags, S1, S, qoff, R, k, dtype_name, w.dim)
+    need = assert_flags_as_predicted(flags, S1, S, qoff, R, k, dtype_name, w.dim,
+                                     list_scan=True)
     assert (flags >> 1 == 0).all()  # every query word certified
     if R == w.n_shapes:
         assert (flags == 1).all()

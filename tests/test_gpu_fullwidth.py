@@ -131,4 +131,4 @@ def test_fullwidth_fif_ranked_ids(L, case, dtype_name, ma):
         dc, ds = O.quantize_views(db, dtype_name)
         S1 = O.fif_scores(O.dequantize(qc, qs), qoff, O.dequantize(dc, ds), w.n_views, cb,
                           off, es, ev, qwords=qw)
-    assert_flags_as_predicted(fl, S1, S, qoff, R, k, dtype_name, w.dim)
+    assert_flags_as_predicted(fl, S1, S, qoff, R, k, dtype_name, w.dim, list_scan=True)
