@@ -121,16 +121,33 @@ __device__ void select_block(const float* __restrict__ row, int64_t n, int64_t i
       sh.hist[d] = t;
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t cum = 0;
-      int d = 0;
-      for (; d < 255; ++d) {
-        if (cum + sh.hist[d] >= need) break;
-        cum += sh.hist[d];
+    // The digit of the need-th key: an inclusive scan of the 256 counts
+    // (digit d on thread d of the first four waves), then the one digit
+    // whose range (excl, incl] holds need, i.e. the first digit whose
+    // running count reaches need.
+    uint32_t h = 0, incl = 0;
+    if (tid < 256) {
+      const int lane = tid & 63;
+      h = sh.hist[tid];
+      incl = h;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += v;
       }
-      sh.need = need - cum;
-      sh.prefix = prefix | ((uint32_t)d << shift);
-      sh.eq = sh.hist[d];  // after the last pass: the keys equal to the r-th
+      if (lane == 63) sh.wsum[tid >> 6] = (int)incl;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      for (int w = 0; w < (tid >> 6); ++w) incl += (uint32_t)sh.wsum[w];
+      const uint32_t excl = incl - h;
+      // (thread 255 also when the counts fall short, as a sequential walk
+      // would end on the last digit; the counts always reach need)
+      if ((excl < need && need <= incl) || (tid == 255 && incl < need)) {
+        sh.need = need - excl;
+        sh.prefix = prefix | ((uint32_t)tid << shift);
+        sh.eq = h;  // after the last pass: the keys equal to the r-th
+      }
     }
     __syncthreads();
     need = sh.need;
@@ -233,7 +250,14 @@ __global__ __launch_bounds__(SEL_THREADS) void select_chunk_kernel(
   for (int i = threadIdx.x; i < r; i += SEL_THREADS) dst[i] = sh.keys[i];
 }
 
-// The r smallest of row b's n_keys chunk winners (at most SEL_MERGE_CAP).
+// The r smallest of row b's n_keys chunk winners (at most SEL_MERGE_CAP):
+// n_keys / r lists of r keys, each sorted ascending by select_chunk_kernel.
+// Keys are unique ((key, id) pairs), so a key's rank in the union is its
+// position in its own list plus, for every other list, the number of that
+// list's keys below it (a binary search); a key of rank < r is written at
+// its rank.  This replaces a sort of all the winners by one pass with no
+// barrier.  Pad keys (~0, chunks shorter than r) are skipped: the row holds
+// more than r scores, so they never rank below r.
 constexpr int SEL_MERGE_CAP = 4096;
 __global__ __launch_bounds__(SEL_THREADS) void select_merge_kernel(
     const uint64_t* __restrict__ tmp, int n_keys, int r, const int32_t* __restrict__ active,
@@ -241,16 +265,29 @@ __global__ __launch_bounds__(SEL_THREADS) void select_merge_kernel(
   __shared__ uint64_t keys[SEL_MERGE_CAP];
   const int b = blockIdx.x;
   if (active != nullptr && b >= *active) return;
-  int np2 = 1;
-  while (np2 < n_keys) np2 <<= 1;
   const uint64_t* src = tmp + (int64_t)b * n_keys;
-  for (int i = threadIdx.x; i < np2; i += SEL_THREADS) keys[i] = i < n_keys ? src[i] : ~0ull;
+  for (int i = threadIdx.x; i < n_keys; i += SEL_THREADS) keys[i] = src[i];
   __syncthreads();
-  bitonic_sort_u64(keys, np2);
-  for (int i = threadIdx.x; i < r; i += SEL_THREADS) {
-    const uint64_t k = keys[i];
-    out_id[(int64_t)b * r + i] = (int32_t)(k & 0xffffffffu);
-    out_s[(int64_t)b * r + i] = order_float(~(uint32_t)(k >> 32));
+  const int n_lists = n_keys / r;
+  for (int i = threadIdx.x; i < n_keys; i += SEL_THREADS) {
+    const uint64_t x = keys[i];
+    if (x == ~0ull) continue;
+    const int c = i / r;
+    int rank = i - c * r;
+    for (int c2 = 0; c2 < n_lists && rank < r; ++c2) {
+      if (c2 == c) continue;
+      const uint64_t* list = keys + (int64_t)c2 * r;
+      int lo = 0, hi = r;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (list[mid] < x) lo = mid + 1; else hi = mid;
+      }
+      rank += lo;
+    }
+    if (rank < r) {
+      out_id[(int64_t)b * r + rank] = (int32_t)(x & 0xffffffffu);
+      out_s[(int64_t)b * r + rank] = order_float(~(uint32_t)(x >> 32));
+    }
   }
 }
 
