@@ -1429,65 +1429,71 @@ __global__ __launch_bounds__(256, 2) void fif_batch_kernel(BatchArgs a) {
           break;
         case BP_PRE: {
           // group offsets (goff) and active-tile offsets (act_off) over
-          // words: each thread sums a contiguous range of words (8 words'
-          // loads in flight), then an exclusive scan over the 256 sums
+          // words.  Wave w covers a contiguous range of words, 64
+          // consecutive words per step (coalesced loads, 8 steps' loads in
+          // flight): pass 1 sums the range, the four wave sums are scanned
+          // through LDS, pass 2 scans each step across the wave (shuffles)
+          // and writes the offsets with coalesced stores.
           int64_t* wsum = reinterpret_cast<int64_t*>(lds);  // [4] + [4]
-          const int per = (a.K + 255) / 256;
-          const int k0 = tid * per, k1 = k0 + per < a.K ? k0 + per : a.K;
-          int64_t sum = 0, tsum = 0;
-          for (int k = k0; k < k1; k += 8) {
-            int c[8];
-            int64_t tl[8];
+          const int lane = tid & 63, wave = tid >> 6;
+          const int span = ((a.K + 255) / 256) * 64;  // words per wave
+          const int w0 = wave * span, w1 = w0 + span < a.K ? w0 + span : a.K;
+          auto load8 = [&](int k0, int (&c)[8], int64_t (&tl)[8]) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              c[q] = kk < k1 ? a.counts[kk] : 0;
-              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
+              const int kk = k0 + 64 * q + lane;
+              c[q] = kk < w1 ? a.counts[kk] : 0;
+              tl[q] = kk < w1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
             }
+          };
+          int64_t sum = 0, tsum = 0;
+          for (int k0 = w0; k0 < w1; k0 += 512) {
+            int c[8];
+            int64_t tl[8];
+            load8(k0, c, tl);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               sum += c[q];
               if (c[q] > 0) tsum += tl[q];
             }
           }
-          // inclusive scan within the wave, then across the 4 waves
-          const int lane = tid & 63, wave = tid >> 6;
-          int64_t is = sum, it = tsum;
 #pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const int64_t ps = __shfl_up(is, o, 64), pt = __shfl_up(it, o, 64);
-            if (lane >= o) { is += ps; it += pt; }
+          for (int o = 32; o > 0; o >>= 1) {
+            sum += __shfl_xor(sum, o, 64);
+            tsum += __shfl_xor(tsum, o, 64);
           }
-          if (lane == 63) { wsum[wave] = is; wsum[4 + wave] = it; }
+          if (lane == 0) { wsum[wave] = sum; wsum[4 + wave] = tsum; }
           __syncthreads();
-          int64_t run = is - sum, trun = it - tsum;
+          int64_t run = 0, trun = 0;
           for (int w = 0; w < wave; ++w) { run += wsum[w]; trun += wsum[4 + w]; }
-          if (tid == 255) {
-            a.goff[a.K] = run + sum;
+          if (tid == 0) {
+            a.goff[a.K] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
             // read with an atomic load by every block entering the scan
             // range: published the same way as the queue counters
-            __hip_atomic_store(n_active_w, (unsigned long long)(trun + tsum), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(n_active_w, (unsigned long long)(wsum[4] + wsum[5] + wsum[6] + wsum[7]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
-          for (int k = k0; k < k1; k += 8) {
+          for (int k0 = w0; k0 < w1; k0 += 512) {
             int c[8];
             int64_t tl[8];
+            load8(k0, c, tl);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              c[q] = kk < k1 ? a.counts[kk] : 0;
-              tl[q] = kk < k1 ? a.tile_off[kk + 1] - a.tile_off[kk] : 0;
-            }
+              const int kk = k0 + 64 * q + lane;
+              const int64_t x = c[q], t = c[q] > 0 ? tl[q] : 0;
+              int64_t xi = x, ti = t;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int kk = k + q;
-              if (kk < k1) {
-                a.goff[kk] = run;
-                a.act_off[kk] = (int32_t)trun;
+              for (int o = 1; o < 64; o <<= 1) {
+                const int64_t px = __shfl_up(xi, o, 64), pt = __shfl_up(ti, o, 64);
+                if (lane >= o) { xi += px; ti += pt; }
+              }
+              if (kk < w1) {
+                a.goff[kk] = run + xi - x;
+                a.act_off[kk] = (int32_t)(trun + ti - t);
                 a.fillc[kk] = 0;
               }
-              run += c[q];
-              if (c[q] > 0) trun += tl[q];
+              run += __shfl(xi, 63, 64);
+              trun += __shfl(ti, 63, 64);
             }
           }
           wrote = true;
