@@ -439,6 +439,18 @@ gift_status gift_fif_plan_phase_end_us(gift_fif_plan* plan, double* out /* host 
 gift_status gift_fif_plan_destroy(gift_fif_plan* plan);
 
 /* ---------------------------------------------------------------------- */
+/* Asynchronous copy of `bytes` bytes from src to dst on `stream`, each    */
+/* side host or device (the direction follows from the pointers; host     */
+/* memory must be pinned for the copy to stay asynchronous).  For callers */
+/* that stage batches through pinned host buffers, such as a serving loop,*/
+/* one call per buffer without a framework copy around it.  The caller    */
+/* owns both buffers and keeps them alive until the stream has passed the */
+/* copy.  GIFT_EINVAL for a null pointer with bytes > 0; GIFT_EHIP when   */
+/* the copy cannot be queued.  bytes == 0 does nothing.                    */
+/* ---------------------------------------------------------------------- */
+gift_status gift_copy_async(void* dst, const void* src, size_t bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Tuning of the first-pass scorer (host, process-wide, not thread-safe).  */
 /* tile (BF16 / FP8 storage; float32 always uses 128 x 128 and MX storage */
 /* 256 x 128), 0..8: for 0..3, bit 0 selects 256 database rows x 256 query */

@@ -62,6 +62,7 @@ _VP = C.POINTER(gift_views)
 _QP = C.POINTER(gift_queries)
 _sig = {
     "gift_version": (C.c_char_p, []),
+    "gift_copy_async": (C.c_int32, [_P, _P, C.c_size_t, _P]),
     "gift_last_error": (C.c_char_p, []),
     "gift_quantize_views": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P]),
     "gift_score_exhaustive_workspace": (C.c_size_t, [_VP, _QP]),
@@ -143,6 +144,15 @@ def _stream(stream):
 def _check(status):
     if status != OK:
         raise GiftError(status, _lib.gift_last_error().decode())
+
+
+def copy_async(dst, src, stream=None):
+    """Queues dst.copy_(src) on `stream` (device or pinned host tensors of
+    the same byte size, contiguous) through gift_copy_async."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or not (dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("copy_async needs contiguous tensors of the same byte size")
+    _check(_lib.gift_copy_async(_ptr(dst), _ptr(src), n, _stream(stream)))
 
 
 def _workspace(nbytes, device):

@@ -765,6 +765,13 @@ gift_status gift_score_fif(const gift_views* db, const gift_fif* fif, const gift
 }
 
 /* ------------------------------------------------------------ tuning */
+gift_status gift_copy_async(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes == 0) return GIFT_OK;
+  GIFT_CHECK(dst != nullptr && src != nullptr, GIFT_EINVAL, "null buffer");
+  GIFT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+  return GIFT_OK;
+}
+
 gift_status gift_set_score_tuning(int32_t dtype, int32_t tile, int32_t group) {
   return set_score_tuning(dtype, tile, group);
 }

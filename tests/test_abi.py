@@ -60,6 +60,16 @@ def test_argument_errors_need_no_device(lib):
     assert b"n_shapes" in lib.gift_last_error()
 
 
+def test_copy_async_argument_errors_need_no_device(lib):
+    # an empty copy does nothing, a null buffer is rejected on the host
+    lib.gift_copy_async.restype = ctypes.c_int32
+    lib.gift_copy_async.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]
+    assert lib.gift_copy_async(None, None, 0, None) == 0
+    assert lib.gift_copy_async(None, 1 << 20, 8, None) == -1
+    assert lib.gift_copy_async(1 << 20, None, 8, None) == -1
+
+
 def test_static_scratch_capacity_needs_no_device(lib):
     # gift_query_exhaustive_static sizes its batch against the 64 MiB static
     # scratch on the host: a batch too large for it fails with

@@ -141,3 +141,20 @@ def test_server_memory_budget_makes_queries_wait(setup):
             assert np.array_equal(res[b][1], ref_sc[b])
     finally:
         srv.close()
+
+
+def test_copy_async_round_trip():
+    """gift_copy_async moves bytes host -> device -> host on a stream, in
+    the order queued, for pinned host and device tensors."""
+    from paper_1604_01879_amd import _lib as L
+    print("[gpu] copy_async round trip", flush=True)
+    st = torch.cuda.Stream()
+    src = torch.arange(1 << 16, dtype=torch.int32).pin_memory()
+    dev = torch.empty(1 << 16, dtype=torch.int32, device="cuda:0")
+    back = torch.zeros(1 << 16, dtype=torch.int32).pin_memory()
+    L.copy_async(dev, src, st)
+    L.copy_async(back, dev, st)
+    st.synchronize()
+    assert torch.equal(back, src)
+    with pytest.raises(ValueError):
+        L.copy_async(back[:10], dev, st)
