@@ -12,6 +12,7 @@ resident in HBM before timing starts.
 Prints one JSON line (see the keys below).  Progress goes to stderr.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -658,6 +659,11 @@ def scale_bench(args):
     queries = [q[qoff[b]:qoff[b + 1]] for b in range(w.n_queries)]
 
     def serve_runs(srv, rate_list, label):
+        # the long-lived objects (index, plans, runtime) go to a generation
+        # the collector no longer walks, so a collection during the run does
+        # not stall the dispatcher for milliseconds
+        gc.collect()
+        gc.freeze()
         for v in queries[:8]:
             srv.submit(v).result()
         res = {}
