@@ -48,7 +48,22 @@ struct RescoreScratch {
   unsigned long long* mask;  // [r][ld] view masks (candidate slot, query view)
   float* s1;                 // [r][ld] per-chunk sums of approximate maxima
   uint8_t* mark;             // [queries][r] candidates that can reach the top k
+  // Split approximate phase (batches of at most RESCORE_SPLIT_ITEMS work
+  // items whose queries have at most 64 views, decided per run from the
+  // batch size): n_split blocks per work item each take a K range and
+  // write their partial dot tiles to `part` (rescore_split_floats floats),
+  // and a second kernel adds them in split order and builds the masks.
+  // n_split 0: one block per item over the whole K range, always.
+  float* part;
+  int n_split;
 };
+
+// Floats of the split approximate phase's partial tiles for a capacity of
+// n_queries x r candidates (work items of 4 candidates of one query; at
+// most RESCORE_SPLIT_ITEMS of them are split).
+size_t rescore_split_floats(int n_queries, int r);
+constexpr int RESCORE_SPLIT = 4;            // K ranges per work item when split
+constexpr int64_t RESCORE_SPLIT_ITEMS = 64;  // largest batch (in work items) that splits
 
 // Rescore scratch from a workspace carver; ld = rows of query views the
 // masks are indexed by (total or maximum views).

@@ -79,6 +79,10 @@ static PlanWs carve_plan(void* base, const gift_views* db, const gift_fif* f, in
   w.s_hi = c.take<float>((size_t)Bmax * r);
   w.s_lo = c.take<float>((size_t)Bmax * r);
   w.rs = take_rescore(c, Bmax, r, Vmax);
+  // partial tiles of the split approximate phase (used when the plan's
+  // queries have at most 64 views; see gift_fif_plan_create)
+  const size_t pf = rescore_split_floats(Bmax, r);
+  if (pf != 0) w.rs.part = c.take<float>(pf);
   w.bytes = c.bytes();
   return w;
 }
@@ -219,6 +223,15 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif, int3
   GIFT_CHECK(ws != nullptr && ws_bytes >= w.bytes, GIFT_EWORKSPACE,
              "workspace needs %zu bytes, got %zu", w.bytes, ws_bytes);
 
+  // When the plan's queries have at most 64 views, a batch of at most
+  // RESCORE_SPLIT_ITEMS work items (4 candidates of one query each: one
+  // query at r = 256, four at r = 64) splits the approximate rescore phase
+  // over K, 4 blocks per item of 2+ K-tiles each, so its K loop does not
+  // run on a handful of blocks; larger batches take the one-block-per-item
+  // kernel (the choice is made per run from the batch size)
+  w.rs.n_split = (w.rs.part != nullptr && max_views_per_query <= 64 && db->dim / 32 >= 2 * RESCORE_SPLIT)
+                     ? RESCORE_SPLIT
+                     : 0;
   auto* p = new gift_fif_plan();
   p->ws = w;
   p->db = *db;

@@ -420,13 +420,24 @@ __device__ __forceinline__ unsigned long long allowed_views(const int32_t* vw, i
 // r of candidate k is its view cu[k][r], r < nu[k]); the second block of 32
 // rows is skipped when at most 32 remain.  Most Eq. 4 candidates match a
 // query through a few views, so their rows are read for those views only.
+// MODE: RS_FULL, one block per item over the whole K range; RS_PART, block
+// (item, split) over K tiles [split kt, (split + 1) kt) of its rows, its
+// dot tiles written to `part`; RS_FINISH, one block per item adding the
+// n_split partial tiles in split order, then the masks and maxima.  The
+// split modes serve batches whose queries have at most 64 views (one
+// chunk).  Each split keeps the per-K-tile blocks and running total, and
+// the finish adds n_split - 1 more terms, so dot_err bounds them too.
+constexpr int RS_FULL = 0, RS_PART = 1, RS_FINISH = 2;
+
+template <int MODE>
 __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff,
     int n_queries, const int32_t* __restrict__ cand, int r, float dot_err,
     const int32_t* __restrict__ qwords, const int32_t* __restrict__ view_words, int ma,
     const int32_t* __restrict__ active, const float* __restrict__ first_s, float first_err,
-    int top_k, unsigned long long* __restrict__ mask, float* __restrict__ s1, int64_t ld) {
+    int top_k, unsigned long long* __restrict__ mask, float* __restrict__ s1, int64_t ld,
+    float* __restrict__ part, int n_split) {
   __shared__ __align__(16) uint8_t lds[RS_ROWS * LROW];
   __shared__ int32_t vw[RS_CANDS][64 * 8];
   __shared__ int32_t qw_chunk[64];
@@ -435,7 +446,21 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
 
   const int groups = (r + RS_CANDS - 1) / RS_CANDS;
   const int64_t n_items = (int64_t)(active != nullptr ? *active : n_queries) * groups;
-  const int64_t item = xcd_contiguous(blockIdx.x, n_items);
+  // With n_split set, the split kernels take batches of at most
+  // RESCORE_SPLIT_ITEMS items and this one the larger ones (the same graph
+  // serves every batch size up to the plan's capacity).
+  if (MODE == RS_FULL && n_split > 1 && n_items <= RESCORE_SPLIT_ITEMS) return;
+  if (MODE != RS_FULL && n_items > RESCORE_SPLIT_ITEMS) return;
+  int64_t item;
+  int split = 0;
+  if constexpr (MODE == RS_FULL) {
+    item = xcd_contiguous(blockIdx.x, n_items);
+  } else if constexpr (MODE == RS_PART) {
+    item = blockIdx.x / n_split;
+    split = (int)(blockIdx.x - item * n_split);
+  } else {
+    item = blockIdx.x;
+  }
   if (item >= n_items) return;  // past the batch
   const int b = (int)(item / groups);
   const int c0 = (int)(item % groups) * RS_CANDS;
@@ -478,6 +503,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
   for (int k = 0; k < RS_CANDS; ++k) gb[k] = uniform_gptr(master_b + shape[k] * shape_bytes);
 
   for (int it = 0; it * 64 < m; ++it) {
+    if (MODE != RS_FULL && it > 0) break;  // split batches hold queries of at most 64 views
     const int mi = min(64, m - it * 64);
     __syncthreads();  // the previous chunk's epilogue is done with the tables
     if (eq4 && tid < 64) qw_chunk[tid] = tid < mi ? qwords[q0 + it * 64 + tid] : -1;
@@ -534,8 +560,15 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
                                    : make_uint4(0, 0, 0, 0);
       }
     };
-    gload(0);
-    for (int k0 = 0; k0 < row_bytes; k0 += 128) {
+    // this block's K range (bytes of each row)
+    int kb = 0, ke = row_bytes;
+    if constexpr (MODE == RS_PART) {
+      const int kt = ((row_bytes + 127) / 128 + n_split - 1) / n_split;
+      kb = split * kt * 128;
+      ke = min(row_bytes, kb + kt * 128);
+    }
+    if (MODE != RS_FINISH && kb < ke) gload(kb);
+    for (int k0 = kb; MODE != RS_FINISH && k0 < ke; k0 += 128) {
       __syncthreads();
 #pragma unroll
       for (int p = 0; p < RS_PIECES; ++p) {
@@ -546,7 +579,7 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
         *reinterpret_cast<uint2*>(row + 64) = lo;
       }
       __syncthreads();
-      if (k0 + 128 < row_bytes) gload(k0 + 128);  // in flight during the MFMAs
+      if (k0 + 128 < ke) gload(k0 + 128);  // in flight during the MFMAs
 #pragma unroll
       for (int cj = 0; cj < 2; ++cj) {
         uint4 bh[2], bl[2];
@@ -578,6 +611,30 @@ __global__ __launch_bounds__(RS_THREADS, 2) void rescore_mask_kernel(
           }
 #pragma unroll
           for (int e = 0; e < 16; ++e) tot[bi][cj][e] += part[e];
+        }
+      }
+    }
+    if constexpr (MODE != RS_FULL) {
+      // partial tiles: [item][split][wave][(bi, cj, e)][lane]
+      const int64_t slab = (int64_t)RS_CANDS * 64 * 64;
+      if constexpr (MODE == RS_PART) {
+        float* dst = part + (item * n_split + split) * slab + (int64_t)wave * 64 * 64 + lane;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dst[((bi * 2 + cj) * 16 + e) * 64] = tot[bi][cj][e];
+        continue;
+      } else {
+        for (int sp = 0; sp < n_split; ++sp) {
+          const float* src = part + (item * n_split + sp) * slab + (int64_t)wave * 64 * 64 + lane;
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+              for (int e = 0; e < 16; ++e) tot[bi][cj][e] += src[((bi * 2 + cj) * 16 + e) * 64];
         }
       }
     }
@@ -759,6 +816,12 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
   }
 }
 
+size_t rescore_split_floats(int n_queries, int r) {
+  const int64_t items = (int64_t)n_queries * ((r + RS_CANDS - 1) / RS_CANDS);
+  if (items <= 0) return 0;
+  return (size_t)min(items, RESCORE_SPLIT_ITEMS) * RESCORE_SPLIT * RS_CANDS * 64 * 64;
+}
+
 void launch_rescore(const float* master, int n_views, int dim,
                     const float* qviews, const int32_t* qoff, int n_queries,
                     int64_t ld, const int32_t* cand, int r, int top_k, float dot_err,
@@ -770,11 +833,26 @@ void launch_rescore(const float* master, int n_views, int dim,
   // the storage bound as a float no smaller than it
   float fe = (float)first_err;
   if ((double)fe < first_err) fe = nextafterf(fe, INFINITY);
-  // grids cover every slot of the XCD-contiguous order
-  hipLaunchKernelGGL(rescore_mask_kernel, dim3((unsigned)((items + 7) / 8 * 8)), dim3(RS_THREADS),
-                     0, st, master, n_views, dim, qviews, qoff, n_queries, cand, r,
-                     dot_err, qwords, view_words, ma, active, first_s, fe, top_k, sc.mask, sc.s1,
-                     ld);
+  const bool split = sc.part != nullptr && sc.n_split > 1;
+  if (split) {
+    // batches of at most RESCORE_SPLIT_ITEMS items (the kernels read the
+    // batch size; the full kernel below takes the others)
+    const int64_t si = min(items, RESCORE_SPLIT_ITEMS);
+    hipLaunchKernelGGL(rescore_mask_kernel<RS_PART>, dim3((unsigned)(si * sc.n_split)),
+                       dim3(RS_THREADS), 0, st, master, n_views, dim, qviews, qoff, n_queries,
+                       cand, r, dot_err, qwords, view_words, ma, active, first_s, fe, top_k,
+                       sc.mask, sc.s1, ld, sc.part, sc.n_split);
+    hipLaunchKernelGGL(rescore_mask_kernel<RS_FINISH>, dim3((unsigned)si), dim3(RS_THREADS), 0,
+                       st, master, n_views, dim, qviews, qoff, n_queries, cand, r, dot_err,
+                       qwords, view_words, ma, active, first_s, fe, top_k, sc.mask, sc.s1, ld,
+                       sc.part, sc.n_split);
+  }
+  if (!split || items > RESCORE_SPLIT_ITEMS)
+    // grids cover every slot of the XCD-contiguous order
+    hipLaunchKernelGGL(rescore_mask_kernel<RS_FULL>, dim3((unsigned)((items + 7) / 8 * 8)),
+                       dim3(RS_THREADS), 0, st, master, n_views, dim, qviews, qoff, n_queries,
+                       cand, r, dot_err, qwords, view_words, ma, active, first_s, fe, top_k,
+                       sc.mask, sc.s1, ld, nullptr, split ? sc.n_split : 0);
   hipLaunchKernelGGL(rescore_mark_kernel, dim3((unsigned)n_queries), dim3(256), 0, st, sc.s1, ld,
                      qoff, r, top_k, dot_err, active, first_s, fe, sc.mark);
   const int64_t pairs = (int64_t)n_queries * r;

@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 import synth
-from test_gpu_exhaustive import assert_ranked_equal
+from test_gpu_exhaustive import assert_ranked_equal, assert_returned_exact
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -217,4 +217,41 @@ def test_plan_large_batch_equals_query_fif(L, gemm):
     for b in range(n_q):
         if fl[b] & 1:
             assert_ranked_equal(ids[b], sc[b], S[b], k)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "fp8"])
+def test_small_plan_split_rescore_equals_query_fif(L, dtype_name):
+    """A plan of at most 4 queries of up to 64 views splits the approximate
+    rescore phase over K (4 blocks per work item, partial tiles added in
+    split order): ids, scores and flags still equal gift_query_fif's (one
+    block per item over the whole K range), and the ids the oracle's."""
+    _say(f"small plan split rescore {dtype_name}")
+    dt = {"f32": L.F32, "fp8": L.FP8E4M3}[dtype_name]
+    w, db, q, qoff, cb, V, F = _setup(L, dt, n_shapes=300, dim=512, B=4, seed=11)
+    k, R = 10, 40
+    plan = L.FifPlan(V, F, max_queries=4, max_views=4 * 64, max_views_per_query=64, top_k=k,
+                     rescore_r=R)
+    S = O.fif_scores(q, qoff, db, w.n_views, cb, *O.build_fif(O.assign(db, cb, 2), 24,
+                                                                w.n_views))
+    for sub in (4, 1):
+        qo = qoff[:sub + 1]
+        qq = q[:qo[-1]]
+        Q = L.Queries(torch.from_numpy(qq).to(DEV), torch.from_numpy(qo))
+        ref_ids, ref_sc, ref_fl = L.gift_query_fif(V, F, Q, k, R)
+        torch.cuda.synchronize()
+        n_q, n_v = _load(plan, qq, qo)
+        for _ in range(2):
+            plan.run(n_q, n_v)
+            plan.stream.synchronize()
+            assert plan.error() == 0
+            ids, sc = plan.ids[:n_q].cpu().numpy(), plan.scores[:n_q].cpu().numpy()
+            assert np.array_equal(ids, ref_ids.cpu().numpy())
+            assert np.array_equal(sc, ref_sc.cpu().numpy())
+            assert np.array_equal(plan.flags[:n_q].cpu().numpy(), ref_fl.cpu().numpy())
+        fl = plan.flags[:n_q].cpu().numpy()
+        for b in range(n_q):
+            assert_returned_exact(ids[b], sc[b], S[b], k)
+            if dt == L.F32 or fl[b] & 1:
+                assert_ranked_equal(ids[b], sc[b], S[b], k)
     plan.close()
