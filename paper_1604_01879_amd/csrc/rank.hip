@@ -1,5 +1,6 @@
 // Ranking of Eq. 3 / Eq. 4 scores: block-level top-r selection, the exact
 // rescore of the candidates and the final (score desc, id asc) order.
+#include "bitonic.h"
 #include "kernels.h"
 #include "mfma_tile.h"
 #include "quant.h"
@@ -32,19 +33,9 @@ __device__ inline int block_excl_count(bool flag, int* wsum, int& total) {
 
 // Bitonic sort of `n` (power of two, <= 4096) 64-bit keys in LDS, ascending.
 __device__ inline void bitonic_sort_u64(uint64_t* key, int n) {
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const bool up = (i & k) == 0;
-          const uint64_t a = key[i], b = key[ix];
-          if ((a > b) == up) { key[i] = b; key[ix] = a; }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  block_bitonic_sort(
+      key, n, [](uint64_t a, uint64_t b) { return a < b; },
+      [](uint64_t v, int j) { return (uint64_t)__shfl_xor((unsigned long long)v, j, 64); });
 }
 
 // ------------------------------------------------------------------ top-r
@@ -707,19 +698,9 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
   }
   __syncthreads();
   // bitonic sort, descending
-  for (int kk = 2; kk <= np2; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < np2; i += 256) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const bool down = (i & kk) == 0;
-          const float a = lb[i], d = lb[ix];
-          if ((d > a) == down) { lb[i] = d; lb[ix] = a; }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  block_bitonic_sort(
+      lb, np2, [](float a, float b) { return a > b; },
+      [](float v, int j) { return __shfl_xor(v, j, 64); });
   const float T = lb[k - 1];
   for (int i = threadIdx.x; i < r; i += 256)
     mark[base + i] = sv[i] != -INFINITY && sv[i] + delta >= T ? 1 : 0;
@@ -891,19 +872,11 @@ __global__ __launch_bounds__(256) void final_rank_kernel(
     else c[i] = Cand{-INFINITY, -INFINITY, 0x7fffffff};
   }
   __syncthreads();
-  for (int kk = 2; kk <= np2; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < np2; i += 256) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const bool up = (i & kk) == 0;
-          const Cand a = c[i], d = c[ix];
-          if (cand_before(d, a) == up) { c[i] = d; c[ix] = a; }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  block_bitonic_sort(
+      c, np2, [](const Cand& a, const Cand& b) { return cand_before(a, b); },
+      [](const Cand& v, int j) {
+        return Cand{__shfl_xor(v.hi, j, 64), __shfl_xor(v.lo, j, 64), __shfl_xor(v.id, j, 64)};
+      });
   for (int i = threadIdx.x; i < k; i += 256) {
     ids[(int64_t)b * k + i] = c[i].id;
     scores[(int64_t)b * k + i] = c[i].hi;

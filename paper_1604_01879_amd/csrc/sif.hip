@@ -2,6 +2,7 @@
 // L1 norms, the postings of Fig. 3, and re-ranking by the fuzzy Jaccard
 // similarity of Eq. 8 evaluated through Eq. 13 (numerator over shared
 // non-zero coordinates) and Eq. 14 (denominator from the L1 norms).
+#include "bitonic.h"
 #include "kernels.h"
 
 namespace gift {
@@ -284,19 +285,9 @@ __global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     while (np2 < L) np2 <<= 1;
     for (int s = L + tid; s < np2; s += SIF_THREADS) key[s] = ~0ull;
     __syncthreads();
-    for (int kk = 2; kk <= np2; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < np2; i += SIF_THREADS) {
-          const int ix = i ^ j;
-          if (ix > i) {
-            const bool up = (i & kk) == 0;
-            const uint64_t x = key[i], y = key[ix];
-            if ((x > y) == up) { key[i] = y; key[ix] = x; }
-          }
-        }
-        __syncthreads();
-      }
-    }
+    block_bitonic_sort(
+        key, np2, [](uint64_t a, uint64_t b) { return a < b; },
+        [](uint64_t v, int j) { return (uint64_t)__shfl_xor((unsigned long long)v, j, 64); });
     // one candidate per distinct shape, in ascending shape order
     int base_u = 0;
     for (int s0 = 0; s0 < L; s0 += SIF_THREADS) {
@@ -331,19 +322,11 @@ __global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     while (np2u < U) np2u <<= 1;
     for (int i = U + tid; i < np2u; i += SIF_THREADS) cand[i] = SCand{-INFINITY, -INFINITY, 0x7fffffff};
     __syncthreads();
-    for (int kk = 2; kk <= np2u; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < np2u; i += SIF_THREADS) {
-          const int ix = i ^ j;
-          if (ix > i) {
-            const bool up = (i & kk) == 0;
-            const SCand x = cand[i], y = cand[ix];
-            if (scand_before(y, x) == up) { cand[i] = y; cand[ix] = x; }
-          }
-        }
-        __syncthreads();
-      }
-    }
+    block_bitonic_sort(
+        cand, np2u, [](const SCand& a, const SCand& b) { return scand_before(a, b); },
+        [](const SCand& v, int j) {
+          return SCand{__shfl_xor(v.hi, j, 64), __shfl_xor(v.lo, j, 64), __shfl_xor(v.id, j, 64)};
+        });
     // merge the pass's best min(U, k) into the running top k: an element's
     // output rank is its rank in its own list plus the number of elements of
     // the other list ordered before it (shapes of different passes differ)
@@ -386,19 +369,9 @@ __global__ __launch_bounds__(SIF_THREADS) void rerank_sif_kernel(
     for (int i = tid; i < np2k; i += SIF_THREADS)
       key[i] = i < kp ? (uint64_t)(uint32_t)best[i].id : ~0ull;
     __syncthreads();
-    for (int kk = 2; kk <= np2k; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < np2k; i += SIF_THREADS) {
-          const int ix = i ^ j;
-          if (ix > i) {
-            const bool up = (i & kk) == 0;
-            const uint64_t x = key[i], y = key[ix];
-            if ((x > y) == up) { key[i] = y; key[ix] = x; }
-          }
-        }
-        __syncthreads();
-      }
-    }
+    block_bitonic_sort(
+        key, np2k, [](uint64_t a, uint64_t b) { return a < b; },
+        [](uint64_t v, int j) { return (uint64_t)__shfl_xor((unsigned long long)v, j, 64); });
     if (tid == 0) {
       // zero-score shapes in id order, skipping the candidates
       int pos = kp, c = 0;
