@@ -11,7 +11,6 @@ namespace gift {
 constexpr int SEL_THREADS = 512;          // threads of a top-r selection block
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int SEL_UNROLL = 8;             // independent loads in flight per thread
-constexpr int P2_BATCH = 8;               // float4 loads per row per lane in a rescore batch
 
 // Exclusive prefix count of `flag` over the threads of a block, in thread
 // order; returns the block total through `total`.
@@ -711,15 +710,23 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
 // masked pair (q_i, p_j) is re-evaluated with the compensated dot product
 // of Ogita, Rump and Oishi (Dot2: error-free products by FMA, error-free
 // sums, the errors summed alongside), in float32 arithmetic, and the exact
-// maximum kept (wave w takes query views w, w + 4, ...); the block then
-// forms the compensated mean over the query views in ascending order.  A
-// query view with an empty mask contributes 0.  Lane l takes the float4
-// pieces l, l + 64, ... of both rows: a 4096-value row pair is one batch of
-// 16 + 16 loads in flight per lane, summed in four compensated chains of
-// at most 16 products (piece k goes to chain k % 4), then across the lane's
-// chains and the wave in float-float arithmetic.  The pair (hi, lo) is then
-// within about gamma(16)^2 sum |x y| + 16 u^2 sum |x y| of the exact dot
-// (about 1e-12 for unit-norm rows at d = 4096).
+// maximum over each query view's masked views kept; the block then forms
+// the compensated mean over the query views in ascending order.  A query
+// view with an empty mask contributes 0.  Lane l takes the float4 pieces
+// l, l + 64, ... of both rows, four at a time, summed in four compensated
+// chains of at most 16 products (piece k goes to chain k % 4), then across
+// the lane's chains and the wave in float-float arithmetic.  The pair (hi,
+// lo) is then within about gamma(16)^2 sum |x y| + 16 u^2 sum |x y| of the
+// exact dot (about 1e-12 for unit-norm rows at d = 4096).
+// Work units pair one candidate view with up to two of the query views
+// whose masks hold it, so a view that is the near-maximum of several query
+// views (a dozen distinct views cover the 64 query views of a headline
+// candidate) is read once per two of them instead of once per query view;
+// waves take the units in turn, and each pair's maximum is kept with an
+// LDS atomic maximum on its (hi, lo) order key, so the result does not
+// depend on the order of the units.
+constexpr int EX_BATCH = 4;  // float4 pieces per row per lane in flight per step
+
 __global__ __launch_bounds__(256) void rescore_exact_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff, int n_queries,
@@ -727,6 +734,10 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
     int64_t ld, const uint8_t* __restrict__ mark, const int32_t* __restrict__ active,
     float* __restrict__ s_hi, float* __restrict__ s_lo) {
   __shared__ float mff_hi[64], mff_lo[64];
+  __shared__ unsigned long long msk_s[64];   // the chunk's masks, by query view
+  __shared__ unsigned long long best_k[64];  // order key of each query view's maximum
+  __shared__ uint32_t units[64 * 33];        // j | i0 << 8 | i1 << 16 (i1 255: none)
+  __shared__ int n_units;
   const int64_t n_pairs = (int64_t)(active != nullptr ? *active : n_queries) * r;
   const int64_t pair = xcd_contiguous(blockIdx.x, n_pairs);
   if (pair >= n_pairs) return;  // past the batch
@@ -736,60 +747,97 @@ __global__ __launch_bounds__(256) void rescore_exact_kernel(
   }
   const int b = (int)(pair / r);
   const int q0 = qoff[b], m = qoff[b + 1] - q0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float* pbase = master + (int64_t)cand[pair] * n_views * dim;
   const unsigned long long* pmask = mask + (pair - (int64_t)b * r) * ld + q0;
   const int n4 = dim >> 2;
   ff acc = {0.f, 0.f};
   for (int it = 0; it * 64 < m; ++it) {
     const int mi = min(64, m - it * 64);
-    // this wave's masks (query views wave, wave + 4, ...; lane i holds the
-    // i-th), read together instead of one round trip per query view
-    const int ivl = wave + 4 * lane;
-    const unsigned long long mk = lane < 16 && ivl < mi ? pmask[it * 64 + ivl] : 0ull;
-    for (int iv = wave; iv < mi; iv += 4) {
-      const float* qrow = qviews + (int64_t)(q0 + it * 64 + iv) * dim;
-      const gptr<uint8_t> q4 = uniform_gptr(reinterpret_cast<const uint8_t*>(qrow));
-      const int src = (iv - wave) >> 2;
-      unsigned long long bb =
-          ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(mk >> 32), src, 64) << 32) |
-          (uint32_t)__shfl((int)(uint32_t)mk, src, 64);
-      ff best = {-INFINITY, 0.f};
-      while (bb) {
-        const int j = __builtin_ctzll(bb);
-        bb &= bb - 1;
-        const gptr<uint8_t> p4 = uniform_gptr(reinterpret_cast<const uint8_t*>(pbase + (int64_t)j * dim));
-        float s[4] = {0.f, 0.f, 0.f, 0.f}, cc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int u0 = lane; u0 < n4; u0 += 64 * P2_BATCH) {
-          float4 qa[P2_BATCH], pa[P2_BATCH];
-#pragma unroll
-          for (int k = 0; k < P2_BATCH; ++k) {
-            const uint32_t u = (uint32_t)(u0 + 64 * k);
-            qa[k] = u < (uint32_t)n4 ? load_at<float4>(q4, u * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
-            pa[k] = u < (uint32_t)n4 ? load_at<float4>(p4, u * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int k = 0; k < P2_BATCH; ++k) {
-            dot2_step(qa[k].x, pa[k].x, s[k & 3], cc[k & 3]);
-            dot2_step(qa[k].y, pa[k].y, s[k & 3], cc[k & 3]);
-            dot2_step(qa[k].z, pa[k].z, s[k & 3], cc[k & 3]);
-            dot2_step(qa[k].w, pa[k].w, s[k & 3], cc[k & 3]);
-          }
+    __syncthreads();  // the previous chunk is done with the tables
+    if (tid < 64) {
+      msk_s[tid] = tid < mi ? pmask[it * 64 + tid] : 0ull;
+      best_k[tid] = 0ull;
+    }
+    if (tid == 0) n_units = 0;
+    __syncthreads();
+    // units: view j with the query views whose masks hold it, two at a time
+    for (int j = wave; j < n_views; j += 4) {
+      unsigned long long qm = __ballot(lane < mi && ((msk_s[lane] >> j) & 1ull));
+      while (qm) {
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(qm);
+        qm &= qm - 1;
+        uint32_t i1 = 255u;
+        if (qm) {
+          i1 = (uint32_t)__builtin_ctzll(qm);
+          qm &= qm - 1;
         }
-        const ff lane_sum = ff_add(ff_add(ff_norm(s[0], cc[0]), ff_norm(s[1], cc[1])),
-                                   ff_add(ff_norm(s[2], cc[2]), ff_norm(s[3], cc[3])));
-        const ff v = ff_wave_sum(lane_sum.hi, lane_sum.lo);
-        if (ff_gt(v, best)) best = v;
+        if (lane == 0) units[atomicAdd(&n_units, 1)] = (uint32_t)j | (i0 << 8) | (i1 << 16);
       }
-      if (best.hi == -INFINITY) best = ff{0.f, 0.f};  // no matching view
-      if (lane == 0) { mff_hi[iv] = best.hi; mff_lo[iv] = best.lo; }
     }
     __syncthreads();
-    if (threadIdx.x == 0)
-      for (int iv = 0; iv < mi; ++iv) acc = ff_add(acc, ff{mff_hi[iv], mff_lo[iv]});
+    const int nu = n_units;
+    for (int u = wave; u < nu; u += 4) {
+      const uint32_t w = units[u];
+      const int j = (int)(w & 255u), i0 = (int)((w >> 8) & 255u), i1 = (int)((w >> 16) & 255u);
+      const bool two = i1 != 255;  // uniform in the wave
+      const gptr<uint8_t> p4 = uniform_gptr(reinterpret_cast<const uint8_t*>(pbase + (int64_t)j * dim));
+      const gptr<uint8_t> qa4 = uniform_gptr(
+          reinterpret_cast<const uint8_t*>(qviews + (int64_t)(q0 + it * 64 + i0) * dim));
+      const gptr<uint8_t> qb4 = uniform_gptr(
+          reinterpret_cast<const uint8_t*>(qviews + (int64_t)(q0 + it * 64 + (two ? i1 : i0)) * dim));
+      float sa[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
+      float sb[4] = {0.f, 0.f, 0.f, 0.f}, cb[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int u0 = lane; u0 < n4; u0 += 64 * EX_BATCH) {
+        float4 pa[EX_BATCH], qa[EX_BATCH], qb[EX_BATCH];
+#pragma unroll
+        for (int k = 0; k < EX_BATCH; ++k) {
+          const uint32_t uu = (uint32_t)(u0 + 64 * k);
+          const bool in = uu < (uint32_t)n4;
+          pa[k] = in ? load_at<float4>(p4, uu * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
+          qa[k] = in ? load_at<float4>(qa4, uu * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
+          qb[k] = in && two ? load_at<float4>(qb4, uu * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < EX_BATCH; ++k) {
+          dot2_step(qa[k].x, pa[k].x, sa[k], ca[k]);
+          dot2_step(qa[k].y, pa[k].y, sa[k], ca[k]);
+          dot2_step(qa[k].z, pa[k].z, sa[k], ca[k]);
+          dot2_step(qa[k].w, pa[k].w, sa[k], ca[k]);
+        }
+        if (two) {
+#pragma unroll
+          for (int k = 0; k < EX_BATCH; ++k) {
+            dot2_step(qb[k].x, pa[k].x, sb[k], cb[k]);
+            dot2_step(qb[k].y, pa[k].y, sb[k], cb[k]);
+            dot2_step(qb[k].z, pa[k].z, sb[k], cb[k]);
+            dot2_step(qb[k].w, pa[k].w, sb[k], cb[k]);
+          }
+        }
+      }
+      auto finish = [&](const float (&s)[4], const float (&c)[4], int iv) {
+        const ff lane_sum = ff_add(ff_add(ff_norm(s[0], c[0]), ff_norm(s[1], c[1])),
+                                   ff_add(ff_norm(s[2], c[2]), ff_norm(s[3], c[3])));
+        const ff v = ff_wave_sum(lane_sum.hi, lane_sum.lo);
+        // (hi, lo) in lexicographic order, as ff_gt compares them
+        if (lane == 0)
+          atomicMax(&best_k[iv], ((unsigned long long)float_order(v.hi) << 32) | float_order(v.lo));
+      };
+      finish(sa, ca, i0);
+      if (two) finish(sb, cb, i1);
+    }
     __syncthreads();
+    if (tid < mi) {
+      const unsigned long long k = best_k[tid];
+      // no masked view: 0
+      mff_hi[tid] = k != 0ull ? order_float((uint32_t)(k >> 32)) : 0.f;
+      mff_lo[tid] = k != 0ull ? order_float((uint32_t)k) : 0.f;
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int iv = 0; iv < mi; ++iv) acc = ff_add(acc, ff{mff_hi[iv], mff_lo[iv]});
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     ff res = {0.f, 0.f};
     if (m > 0) res = ff_div_int(acc, m);
     s_hi[pair] = res.hi;
