@@ -725,9 +725,11 @@ __global__ __launch_bounds__(256) void rescore_mark_kernel(
 // waves take the units in turn, and each pair's maximum is kept with an
 // LDS atomic maximum on its (hi, lo) order key, so the result does not
 // depend on the order of the units.
+// At 5 waves per SIMD (96 VGPRs, no spills) instead of the 4 that the
+// kernel's 102 VGPRs would allow, more units' loads are in flight per CU.
 constexpr int EX_BATCH = 4;  // float4 pieces per row per lane in flight per step
 
-__global__ __launch_bounds__(256) void rescore_exact_kernel(
+__global__ __launch_bounds__(256, 5) void rescore_exact_kernel(
     const float* __restrict__ master, int n_views, int dim,
     const float* __restrict__ qviews, const int32_t* __restrict__ qoff, int n_queries,
     const int32_t* __restrict__ cand, int r, const unsigned long long* __restrict__ mask,
