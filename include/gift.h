@@ -425,6 +425,29 @@ gift_status gift_fif_plan_create(const gift_views* db, const gift_fif* fif,
                                  gift_fif_plan** plan);
 gift_status gift_fif_plan_run(gift_fif_plan* plan, int32_t n_queries,
                               int64_t n_views, void* stream);
+/* One serving launch in one call, for host loops that stage each batch   */
+/* in pinned host memory: copies n_views x dim query views and the        */
+/* n_queries + 1 offsets from the host buffers into the plan's q_views /  */
+/* q_offsets, runs the plan (as gift_fif_plan_run), then, when l1 is not  */
+/* NULL, re-ranks the plan's ids / scores [n_queries][top_k of the plan]  */
+/* by Eq. 8 as gift_rerank_sif does (the S-IF arrays, q_self and top_k as */
+/* there; rr_ids / rr_scores [n_queries][top_k] and rr_flags [n_queries]  */
+/* are device buffers the caller owns), and copies the final ids, scores  */
+/* and flags to host_ids / host_scores / host_flags ([n_queries][k] with  */
+/* k the re-rank's top_k, else the plan's; host_flags may be NULL without */
+/* a re-rank).  Everything is queued on `stream`; the caller keeps the    */
+/* host buffers alive and unmodified until the stream has passed the     */
+/* copies (record an event after the call).  GIFT_EINVAL for a null plan  */
+/* or host buffer or incomplete re-rank arguments, GIFT_ECAPACITY as for   */
+/* gift_fif_plan_run; n_queries == 0 queues nothing.                      */
+gift_status gift_fif_plan_serve(gift_fif_plan* plan, const float* host_views,
+                                const int32_t* host_offsets, int32_t n_queries,
+                                int64_t n_views, int64_t n_shapes, const float* l1,
+                                const int64_t* post_off, const int32_t* post_id,
+                                const float* post_val, const float* q_self,
+                                int32_t top_k, int32_t* rr_ids, float* rr_scores,
+                                int32_t* rr_flags, int32_t* host_ids, float* host_scores,
+                                int32_t* host_flags, void* stream);
 /* The same sequence launched kernel by kernel (no graph), for comparison. */
 gift_status gift_fif_plan_run_eager(gift_fif_plan* plan, int32_t n_queries,
                                     int64_t n_views, void* stream);

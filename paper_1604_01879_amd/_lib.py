@@ -109,6 +109,9 @@ _sig = {
                                          C.c_int32, _P, _P, _P, _P, _P, _TP, _P,
                                          C.c_size_t, _P, C.POINTER(C.c_void_p)]),
     "gift_fif_plan_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
+    "gift_fif_plan_serve": (C.c_int32, [C.c_void_p, _P, _P, C.c_int32, C.c_int64, C.c_int64,
+                                        _P, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P, _P,
+                                        _P, _P]),
     "gift_fif_plan_run_eager": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, _P]),
     "gift_fif_plan_first_pass": (C.c_int32, [C.c_void_p, C.c_int32, _P, _P]),
     "gift_fif_plan_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), _P]),
@@ -153,6 +156,13 @@ def copy_async(dst, src, stream=None):
     if dst.numel() * dst.element_size() != n or not (dst.is_contiguous() and src.is_contiguous()):
         raise ValueError("copy_async needs contiguous tensors of the same byte size")
     _check(_lib.gift_copy_async(_ptr(dst), _ptr(src), n, _stream(stream)))
+
+
+def fif_plan_serve(*args):
+    """gift_fif_plan_serve with its 19 arguments already as C-compatible
+    values (handles, integer addresses, sizes): a serving loop computes the
+    fixed ones once per slot and passes them with the batch sizes."""
+    _check(_lib.gift_fif_plan_serve(*args))
 
 
 def _workspace(nbytes, device):

@@ -384,6 +384,54 @@ gift_status gift_fif_plan_run(gift_fif_plan* p, int32_t n_queries, int64_t n_vie
   return GIFT_OK;
 }
 
+gift_status gift_fif_plan_serve(gift_fif_plan* p, const float* host_views,
+                                const int32_t* host_offsets, int32_t n_queries, int64_t n_views,
+                                int64_t n_shapes, const float* l1, const int64_t* post_off,
+                                const int32_t* post_id, const float* post_val,
+                                const float* q_self, int32_t top_k, int32_t* rr_ids,
+                                float* rr_scores, int32_t* rr_flags, int32_t* host_ids,
+                                float* host_scores, int32_t* host_flags, void* stream) {
+  GIFT_CHECK(p != nullptr && host_views != nullptr && host_offsets != nullptr &&
+                 host_ids != nullptr && host_scores != nullptr,
+             GIFT_EINVAL, "null plan or host buffer");
+  GIFT_CHECK(n_queries >= 0 && n_queries <= p->Bmax && n_views >= 0 && n_views <= p->Vmax,
+             GIFT_ECAPACITY, "batch of %d queries / %lld views exceeds the plan (%d / %lld)",
+             n_queries, (long long)n_views, p->Bmax, (long long)p->Vmax);
+  const bool rerank = l1 != nullptr;
+  GIFT_CHECK(!rerank || (post_off && post_id && post_val && rr_ids && rr_scores && rr_flags &&
+                         host_flags && top_k >= 1 && n_shapes >= 1),
+             GIFT_EINVAL, "incomplete S-IF re-rank arguments");
+  if (n_queries == 0) return GIFT_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  GIFT_HIP(hipMemcpyAsync(const_cast<float*>(p->qviews), host_views,
+                          (size_t)n_views * p->db.dim * sizeof(float), hipMemcpyHostToDevice, st));
+  GIFT_HIP(hipMemcpyAsync(p->qoff, host_offsets, (size_t)(n_queries + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+  const gift_status s = gift_fif_plan_run(p, n_queries, n_views, stream);
+  if (s != GIFT_OK) return s;
+  const int32_t* ids = p->ids;
+  const float* sc = p->scores;
+  const int32_t* fl = p->flags;
+  int32_t k = p->top_k;
+  if (rerank) {
+    const gift_status r = gift_rerank_sif(n_shapes, l1, post_off, post_id, post_val, n_queries,
+                                          p->top_k, p->ids, p->scores, q_self, top_k, rr_ids,
+                                          rr_scores, rr_flags, stream);
+    if (r != GIFT_OK) return r;
+    ids = rr_ids;
+    sc = rr_scores;
+    fl = rr_flags;
+    k = top_k;
+  }
+  const size_t n_out = (size_t)n_queries * k;
+  GIFT_HIP(hipMemcpyAsync(host_ids, ids, n_out * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  GIFT_HIP(hipMemcpyAsync(host_scores, sc, n_out * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (host_flags != nullptr && fl != nullptr)
+    GIFT_HIP(hipMemcpyAsync(host_flags, fl, (size_t)n_queries * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+  return GIFT_OK;
+}
+
 gift_status gift_fif_plan_run_eager(gift_fif_plan* p, int32_t n_queries, int64_t n_views,
                                     void* stream) {
   GIFT_CHECK(p != nullptr, GIFT_EINVAL, "null plan");

@@ -78,6 +78,20 @@ class _Slot:
             self.host_flags = torch.zeros(q_cap, dtype=torch.int32).pin_memory()
         self.host_ids = torch.zeros((q_cap, k), dtype=torch.int32).pin_memory()
         self.host_sc = torch.zeros((q_cap, k), dtype=torch.float32).pin_memory()
+        # the arguments of gift_fif_plan_serve that do not change per batch
+        sp = self.stream.cuda_stream
+        self.serve_head = (self.plan.handle, self.staging.data_ptr(), self.off_host.data_ptr())
+        if srv.sif is not None:
+            sif = srv.sif
+            self.serve_tail = (sif.n_shapes, sif.l1.data_ptr(), sif.post_off.data_ptr(),
+                               sif.post_id.data_ptr(), sif.post_val.data_ptr(),
+                               self.self_m.data_ptr(), k, self.out_ids.data_ptr(),
+                               self.out_sc.data_ptr(), self.out_flags.data_ptr(),
+                               self.host_ids.data_ptr(), self.host_sc.data_ptr(),
+                               self.host_flags.data_ptr(), sp)
+        else:
+            self.serve_tail = (0, None, None, None, None, None, 0, None, None, None,
+                               self.host_ids.data_ptr(), self.host_sc.data_ptr(), None, sp)
         self.event = torch.cuda.Event(blocking=True)
         self.busy = False
         self.last_used = 0.0
@@ -94,21 +108,9 @@ class _Slot:
             views += r.m
             self.off_np[i + 1] = views
         n = len(reqs)
-        L.copy_async(self.plan.views[:views], self.staging[:views], self.stream)
-        L.copy_async(self.plan.offsets[:n + 1], self.off_host[:n + 1], self.stream)
-        self.plan.run(n, views, stream=self.stream)
-        if self.srv.sif is not None:
-            # re-rank with the batch's F-IF neighbours plus the query itself
-            _rerank_into(self.srv.sif, self.plan.ids[:n], self.plan.scores[:n], self.self_m[:n],
-                         self.srv.top_k, self.stream, self.out_ids[:n], self.out_sc[:n],
-                         self.out_flags[:n])
-            ids, sc = self.out_ids[:n], self.out_sc[:n]
-        else:
-            ids, sc = self.plan.ids[:n], self.plan.scores[:n]
-        L.copy_async(self.host_ids[:n], ids, self.stream)
-        L.copy_async(self.host_sc[:n], sc, self.stream)
-        if self.srv.sif is not None:
-            L.copy_async(self.host_flags[:n], self.out_flags[:n], self.stream)
+        # copies in, the plan, the re-rank with the batch's F-IF neighbours
+        # plus the query itself, copies out: one library call
+        L.fif_plan_serve(*self.serve_head, n, views, *self.serve_tail)
         self.event.record(self.stream)
         self.jobs.put(reqs)
 
@@ -132,17 +134,6 @@ class _Slot:
         self.jobs.put(None)
         self.thread.join()
         self.plan.close()
-
-
-def _rerank_into(sif, q_ids, q_sc, self_m, top_k, stream, out_ids, out_sc, flags):
-    """gift_rerank_sif on `stream` into buffers owned by the slot."""
-    import ctypes as C
-    B, k1 = q_ids.shape
-    L._check(L._lib.gift_rerank_sif(sif.n_shapes, L._ptr(sif.l1), L._ptr(sif.post_off),
-                                    L._ptr(sif.post_id), L._ptr(sif.post_val), B, k1,
-                                    L._ptr(q_ids), L._ptr(q_sc), L._ptr(self_m), top_k,
-                                    L._ptr(out_ids), L._ptr(out_sc), L._ptr(flags),
-                                    C.c_void_p(stream.cuda_stream)))
 
 
 class Server:

@@ -70,6 +70,21 @@ def test_copy_async_argument_errors_need_no_device(lib):
     assert lib.gift_copy_async(1 << 20, None, 8, None) == -1
 
 
+def test_plan_serve_argument_errors_need_no_device(lib):
+    # a null plan or host buffer is rejected on the host, before any copy
+    P = ctypes.c_void_p
+    lib.gift_fif_plan_serve.restype = ctypes.c_int32
+    lib.gift_fif_plan_serve.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                        P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P]
+    tail = (0, None, None, None, None, None, 0, None, None, None)
+    assert lib.gift_fif_plan_serve(None, 1 << 20, 1 << 20, 1, 8, *tail, 1 << 20, 1 << 20,
+                                   None, None) == -1
+    assert lib.gift_fif_plan_serve(1 << 20, None, 1 << 20, 1, 8, *tail, 1 << 20, 1 << 20,
+                                   None, None) == -1
+    assert lib.gift_fif_plan_serve(1 << 20, 1 << 20, 1 << 20, 1, 8, *tail, None, 1 << 20,
+                                   None, None) == -1
+
+
 def test_static_scratch_capacity_needs_no_device(lib):
     # gift_query_exhaustive_static sizes its batch against the 64 MiB static
     # scratch on the host: a batch too large for it fails with

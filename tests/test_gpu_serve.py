@@ -158,3 +158,67 @@ def test_copy_async_round_trip():
     assert torch.equal(back, src)
     with pytest.raises(ValueError):
         L.copy_async(back[:10], dev, st)
+
+
+def test_plan_serve_equals_separate_calls(setup):
+    """gift_fif_plan_serve (copies in, plan, optional S-IF re-rank, copies
+    out, one call) returns what the separate calls return, bit for bit: two
+    batches in a row, the second smaller, without and with the re-rank."""
+    L, w, db, q, qoff, cb, V, F, S, k1, k, R = setup
+    GiftError = L.GiftError
+    _say("plan serve vs separate calls")
+    kp = k1 - 1
+    plan = L.FifPlan(V, F, 6, 6 * 64, 64, kp, R)
+    st = plan.stream
+    hv = torch.zeros((6 * 64, w.dim), dtype=torch.float32).pin_memory()
+    ho = torch.zeros(7, dtype=torch.int32).pin_memory()
+    hid = torch.zeros((6, k), dtype=torch.int32).pin_memory()
+    hsc = torch.zeros((6, k), dtype=torch.float32).pin_memory()
+    hfl = torch.zeros(6, dtype=torch.int32).pin_memory()
+    one = torch.ones(6, dtype=torch.float32, device=DEV)
+    rr_ids = torch.zeros((6, k), dtype=torch.int32, device=DEV)
+    rr_sc = torch.zeros((6, k), dtype=torch.float32, device=DEV)
+    rr_fl = torch.zeros(6, dtype=torch.int32, device=DEV)
+    head = (plan.handle, hv.data_ptr(), ho.data_ptr())
+    no_rr = (0, None, None, None, None, None, 0, None, None, None)
+    rr = (S.n_shapes, S.l1.data_ptr(), S.post_off.data_ptr(), S.post_id.data_ptr(),
+          S.post_val.data_ptr(), one.data_ptr(), k, rr_ids.data_ptr(), rr_sc.data_ptr(),
+          rr_fl.data_ptr())
+    for b0, b1 in ((0, 5), (5, 7)):
+        n = b1 - b0
+        v0, v1 = int(qoff[b0]), int(qoff[b1])
+        nv = v1 - v0
+        hv[:nv] = torch.from_numpy(q[v0:v1])
+        ho[:n + 1] = torch.from_numpy((qoff[b0:b1 + 1] - v0).astype(np.int32))
+        # without the re-rank: the plan's own top-kp, scores and flags
+        L.fif_plan_serve(*head, n, nv, *no_rr, hid.data_ptr(), hsc.data_ptr(), hfl.data_ptr(),
+                         st.cuda_stream)
+        st.synchronize()
+        got = (hid.view(-1)[:n * kp].clone(), hsc.view(-1)[:n * kp].clone(), hfl[:n].clone())
+        plan.views[:nv].copy_(hv[:nv].to(DEV))
+        plan.offsets[:n + 1].copy_(ho[:n + 1].to(DEV))
+        torch.cuda.synchronize()
+        plan.run(n, nv)
+        st.synchronize()
+        assert torch.equal(got[0], plan.ids[:n].reshape(-1).cpu())
+        assert torch.equal(got[1], plan.scores[:n].reshape(-1).cpu())
+        assert torch.equal(got[2], plan.flags[:n].cpu())
+        ref_ids, ref_sc, ref_fl = L.gift_rerank_sif(S, plan.ids[:n], plan.scores[:n], one[:n], k)
+        torch.cuda.synchronize()
+        # with the re-rank
+        L.fif_plan_serve(*head, n, nv, *rr, hid.data_ptr(), hsc.data_ptr(), hfl.data_ptr(),
+                         st.cuda_stream)
+        st.synchronize()
+        assert torch.equal(hid[:n], ref_ids.cpu())
+        assert torch.equal(hsc[:n], ref_sc.cpu())
+        assert torch.equal(hfl[:n], ref_fl.cpu())
+    # host-side argument checks (nothing is queued)
+    with pytest.raises(GiftError) as e:
+        L.fif_plan_serve(*head, 7, 64, *no_rr, hid.data_ptr(), hsc.data_ptr(), hfl.data_ptr(),
+                         st.cuda_stream)
+    assert e.value.status == L.ECAPACITY
+    bad = rr[:7] + (None,) + rr[8:]
+    with pytest.raises(GiftError) as e:
+        L.fif_plan_serve(*head, 1, 8, *bad, hid.data_ptr(), hsc.data_ptr(), hfl.data_ptr(),
+                         st.cuda_stream)
+    assert e.value.status == L.EINVAL
